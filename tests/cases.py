@@ -1,0 +1,79 @@
+"""Small analytic test problems shared by the oracle pins and GPU parity tests.
+
+Everything here is input generation (initial conditions and refinement
+thresholds); none of the hydro method's arithmetic lives here.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import workloads as W
+
+
+def cell_centres(level: int, ijk: np.ndarray, n_at_level: int) -> np.ndarray:
+    return (ijk.astype(np.float64) + 0.5) / n_at_level
+
+
+def analytic_problem(name, level_min, level_max, state_fn, rho_thr=None, theta=None, gamma=1.4,
+                     bc=(W.BC_PERIODIC,) * 6, cfl=0.8):
+    """Problem whose every level takes point values state_fn(pos[n,3]) ->
+    (rho, vx, vy, vz, p) at cell centres; refinement by mass threshold or
+    gradient criterion."""
+    n0 = 1 << level_min
+
+    def values(level, ijk):
+        pos = cell_centres(level, ijk, 1 << level)
+        rho, vx, vy, vz, p = state_fn(pos)
+        return W.conserved(rho, vx, vy, vz, p, gamma)
+
+    idx = np.indices((n0, n0, n0))
+    ijk = np.stack([idx[2].ravel(), idx[1].ravel(), idx[0].ravel()], axis=1).astype(np.int32)
+    Ub = values(level_min, ijk).reshape(5, n0, n0, n0)
+    refine, param = W.REFINE_NONE, 0.0
+    if rho_thr is not None:
+        refine, param = W.REFINE_MASS, rho_thr
+    elif theta is not None:
+        refine, param = W.REFINE_GRAD, theta
+    return W.Problem(name, level_min, level_max, (n0, n0, n0), gamma, Ub, cfl=cfl, bc=bc,
+                     refine=refine, refine_param=param, fill=values)
+
+
+def _pdist(pos, c):
+    d = pos - np.asarray(c)
+    return d - np.round(d)
+
+
+def blob_state(pos, centre=(0.06, 0.92, 0.5), amp=60.0, width=0.08, mach=0.9, lshape=True):
+    """Density blob (wrapping across periodic faces) plus an L-shaped slab,
+    smooth swirling velocity, smoothly varying pressure."""
+    d = _pdist(pos, centre)
+    r2 = (d * d).sum(axis=1)
+    rho = 1.0 + amp * np.exp(-r2 / (2 * width * width))
+    if lshape:
+        x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
+        inz = (z > 0.3) & (z < 0.7)
+        arm1 = (x > 0.25) & (x < 0.75) & (y > 0.25) & (y < 0.40)
+        arm2 = (x > 0.25) & (x < 0.40) & (y > 0.25) & (y < 0.75)
+        rho = rho + 4.0 * (inz & (arm1 | arm2))
+    tp = 2 * math.pi
+    vx = mach * np.sin(tp * pos[:, 1]) * np.cos(tp * pos[:, 2])
+    vy = mach * np.sin(tp * pos[:, 2] + 0.3) * np.cos(tp * pos[:, 0])
+    vz = 0.5 * mach * np.sin(tp * pos[:, 0] + 0.7)
+    p = 1.0 + 0.3 * np.cos(tp * (pos[:, 0] + 2 * pos[:, 1])) * np.sin(tp * pos[:, 2])
+    return rho, vx, vy, vz, p
+
+
+def amr_blob(level_min=3, level_max=5, rho_thr=1.5, bc=(W.BC_PERIODIC,) * 6, **kw):
+    return analytic_problem(f"blob{level_min}-{level_max}", level_min, level_max,
+                            lambda pos: blob_state(pos, **kw), rho_thr=rho_thr, bc=bc)
+
+
+def rel_err(a, b, floor_frac=1e-3):
+    """Per-variable relative error |a-b| / max(|b|, floor_frac * max|b_v|)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    scale = np.maximum(np.abs(b), floor_frac * np.abs(b).max(axis=-1, keepdims=True))
+    scale = np.where(scale == 0, 1.0, scale)
+    return float((np.abs(a - b) / scale).max())

@@ -1,0 +1,264 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only generates initial conditions (density, velocity and
+pressure fields turned into conserved variables, and point-value fill
+functions for refined levels).  It holds none of the hydro method's
+arithmetic; both the GPU library and the CPU oracle consume the identical
+bytes it produces.
+
+Recipes (seed = 1000 * config + field; field 0 = ln rho, 1..3 = v_x, v_y,
+v_z; box b of the batched workload uses 5000 + 10 b + field):
+
+* sod      -- 32^3, gamma 1.4, left state (rho, p) = (1, 1) for cells with
+              centre x < 0.5, right state (0.125, 0.1), at rest, outflow.
+* uniform  -- 128^3 periodic, gamma 5/3, p = 1, ln rho = white noise
+              smoothed with a periodic Gaussian of sigma = 4 cells and
+              renormalised to zero mean / unit variance; three velocity
+              fields made the same way, scaled to rms Mach 1 against
+              c0 = sqrt(gamma).
+* twolevel -- the uniform generator at 128^3; the 64^3 base is the
+              8-cell mean of the 128^3 conserved field, refined cells take
+              the 128^3 values (gradient criterion, theta 0.70 or 0.1).
+* zoom     -- levels 7-12, lognormal background (sigma 1.5), 64 Gaussian
+              clumps in 8 clusters with peak contrast 1e3, p = rho, a
+              smooth velocity field scaled to a maximum Mach number of 5,
+              refined cells take point values (trilinear background plus
+              analytic clumps), mass criterion.
+* batch    -- 512 periodic boxes with sides in {16,24,32,40,48}, per box
+              sigma ~ U(0.5, 1.5), rms Mach ~ U(0.5, 3), gamma 5/3, p = 1.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, List, Optional
+
+import numpy as np
+
+BC_PERIODIC, BC_OUTFLOW = 0, 1
+REFINE_NONE, REFINE_GRAD, REFINE_MASS = 0, 1, 2
+
+FillFn = Callable[[int, np.ndarray], np.ndarray]
+
+
+@dataclasses.dataclass
+class Problem:
+    """One hydro problem: mesh/config parameters plus initial data."""
+    name: str
+    level_min: int
+    level_max: int
+    nbase: tuple
+    gamma: float
+    U_base: np.ndarray            # (5, nz, ny, nx) float64, conserved variables
+    boxlen: float = 1.0
+    cfl: float = 0.8
+    bc: tuple = (BC_PERIODIC,) * 6
+    refine: int = REFINE_NONE
+    refine_param: float = 0.0
+    rho_floor: float = 1e-10
+    p_floor: float = 1e-10
+    fill: Optional[FillFn] = None  # (level, ijk[n,3] int32) -> U[5, n] float64
+    t_end: float = math.inf
+    n_steps: int = 10
+
+    def base_flat(self) -> np.ndarray:
+        """U_base as 5 contiguous planes, x fastest."""
+        return np.ascontiguousarray(self.U_base.reshape(5, -1), dtype=np.float64)
+
+
+def conserved(rho, vx, vy, vz, p, gamma):
+    """Conserved variables (rho, rho v, E) of an ideal gas state."""
+    E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    return np.stack([rho, rho * vx, rho * vy, rho * vz, E]).astype(np.float64)
+
+
+def smooth_gaussian_field(n: int, seed: int, sigma_cells: float) -> np.ndarray:
+    """Periodic white noise smoothed by a Gaussian of `sigma_cells`, then
+    renormalised to zero mean and unit variance.  Array axes are (z, y, x)."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((n, n, n))
+    k = 2.0 * np.pi * np.fft.fftfreq(n)
+    kz = k[:, None, None]
+    ky = k[None, :, None]
+    kx = k[None, None, : n // 2 + 1]
+    filt = np.exp(-0.5 * sigma_cells ** 2 * (kx * kx + ky * ky + kz * kz))
+    g = np.fft.irfftn(np.fft.rfftn(w) * filt, s=(n, n, n), axes=(0, 1, 2))
+    g = g - g.mean()
+    g = g / g.std()
+    return g
+
+
+def lognormal_fields(n, seed0, sigma_ln, mach_rms, gamma, smooth=4.0):
+    rho = np.exp(sigma_ln * smooth_gaussian_field(n, seed0 + 0, smooth))
+    v = [smooth_gaussian_field(n, seed0 + f, smooth) for f in (1, 2, 3)]
+    c0 = math.sqrt(gamma)
+    vrms = math.sqrt(float(np.mean(v[0] ** 2 + v[1] ** 2 + v[2] ** 2)))
+    s = mach_rms * c0 / vrms
+    p = np.ones_like(rho)
+    return rho, v[0] * s, v[1] * s, v[2] * s, p
+
+
+# ---------------------------------------------------------------------------
+# config 1: Sod shock tube
+# ---------------------------------------------------------------------------
+def sod(n: int = 32, gamma: float = 1.4, t_end: float = 0.1) -> Problem:
+    x = (np.arange(n) + 0.5) / n
+    left = (x < 0.5)[None, None, :] * np.ones((n, n, 1), dtype=bool)
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    z = np.zeros_like(rho)
+    U = conserved(rho, z, z, z, p, gamma)
+    lvl = int(round(math.log2(n)))
+    return Problem("sod", lvl, lvl, (n, n, n), gamma, U, bc=(BC_OUTFLOW,) * 6,
+                   t_end=t_end, n_steps=1000)
+
+
+# ---------------------------------------------------------------------------
+# config 2: uniform periodic lognormal box
+# ---------------------------------------------------------------------------
+def uniform(n: int = 128, seed_cfg: int = 2, sigma_ln: float = 1.0, mach_rms: float = 1.0,
+            gamma: float = 5.0 / 3.0, n_steps: int = 10) -> Problem:
+    rho, vx, vy, vz, p = lognormal_fields(n, 1000 * seed_cfg, sigma_ln, mach_rms, gamma)
+    U = conserved(rho, vx, vy, vz, p, gamma)
+    lvl = int(round(math.log2(n)))
+    return Problem(f"uniform{n}", lvl, lvl, (n, n, n), gamma, U, n_steps=n_steps)
+
+
+# ---------------------------------------------------------------------------
+# config 3: two-level AMR from a 128^3 field
+# ---------------------------------------------------------------------------
+def tree_mean(U: np.ndarray) -> np.ndarray:
+    """8-cell mean of a (5, 2n, 2n, 2n) field -> (5, n, n, n)."""
+    c = [U[:, iz::2, iy::2, ix::2] for iz in (0, 1) for iy in (0, 1) for ix in (0, 1)]
+    return 0.125 * (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])))
+
+
+def twolevel(n_fine: int = 128, theta: float = 0.70, gamma: float = 5.0 / 3.0,
+             n_steps: int = 10) -> Problem:
+    rho, vx, vy, vz, p = lognormal_fields(n_fine, 3000, 1.0, 1.0, gamma)
+    Uf = conserved(rho, vx, vy, vz, p, gamma)
+    Ub = tree_mean(Uf)
+    lf = int(round(math.log2(n_fine)))
+
+    def fill(level: int, ijk: np.ndarray) -> np.ndarray:
+        assert level == lf
+        return Uf[:, ijk[:, 2], ijk[:, 1], ijk[:, 0]]
+
+    nb = n_fine // 2
+    return Problem(f"twolevel{n_fine}_t{theta}", lf - 1, lf, (nb, nb, nb), gamma, Ub,
+                   refine=REFINE_GRAD, refine_param=theta, fill=fill, n_steps=n_steps)
+
+
+# ---------------------------------------------------------------------------
+# config 4: zoom-shaped AMR
+# ---------------------------------------------------------------------------
+ZOOM_RHO_THR = 4.0     # mass criterion threshold at the base level
+ZOOM_R_CLUMP = 0.012   # clump radius (box units)
+
+
+class ZoomField:
+    """Analytic density/velocity field of the zoom workload (point values)."""
+
+    def __init__(self, n: int = 128, r_clump: float = ZOOM_R_CLUMP, gamma: float = 5.0 / 3.0,
+                 mach_max: float = 5.0):
+        self.n = n
+        self.gamma = gamma
+        self.rc = r_clump
+        self.lnbg = 1.5 * smooth_gaussian_field(n, 4000, 4.0)
+        vel = [smooth_gaussian_field(n, 4000 + f, 8.0) for f in (1, 2, 3)]
+        vmax = float(np.sqrt(vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2).max())
+        s = mach_max * math.sqrt(gamma) / vmax
+        self.vel = [v * s for v in vel]
+        rng = np.random.default_rng(4004)
+        centres = rng.random((8, 3))
+        offs = rng.normal(0.0, 1.0 / 32.0, size=(8, 8, 3))
+        self.clumps = np.mod(centres[:, None, :] + offs, 1.0).reshape(64, 3)
+
+    def _trilinear(self, g: np.ndarray, pos: np.ndarray) -> np.ndarray:
+        n = self.n
+        s = pos * n - 0.5                         # grid coordinates (cell centred)
+        i0 = np.floor(s).astype(np.int64)
+        f = s - i0
+        out = np.zeros(pos.shape[0])
+        for dz in (0, 1):
+            wz = f[:, 2] if dz else 1.0 - f[:, 2]
+            iz = (i0[:, 2] + dz) % n
+            for dy in (0, 1):
+                wy = f[:, 1] if dy else 1.0 - f[:, 1]
+                iy = (i0[:, 1] + dy) % n
+                for dx in (0, 1):
+                    wx = f[:, 0] if dx else 1.0 - f[:, 0]
+                    ix = (i0[:, 0] + dx) % n
+                    out += (wz * wy * wx) * g[iz, iy, ix]
+        return out
+
+    def values(self, level: int, ijk: np.ndarray, base_level: int = 7) -> np.ndarray:
+        ncell = self.n << (level - base_level)
+        pos = (ijk.astype(np.float64) + 0.5) / ncell
+        rho_bg = np.exp(self._trilinear(self.lnbg, pos))
+        boost = np.zeros(pos.shape[0])
+        inv2 = 1.0 / (2.0 * self.rc * self.rc)
+        for c in self.clumps:
+            d = pos - c
+            d -= np.round(d)
+            r2 = np.einsum("ij,ij->i", d, d)
+            m = r2 < 80.0 * self.rc * self.rc
+            if m.any():
+                boost[m] += np.exp(-r2[m] * inv2)
+        rho = rho_bg * (1.0 + 1.0e3 * boost)
+        vx, vy, vz = (self._trilinear(v, pos) for v in self.vel)
+        return conserved(rho, vx, vy, vz, rho.copy(), self.gamma)
+
+
+def zoom(level_min: int = 7, level_max: int = 12, rho_thr: float = ZOOM_RHO_THR,
+         r_clump: float = ZOOM_R_CLUMP, n_steps: int = 10) -> Problem:
+    n = 1 << level_min
+    zf = ZoomField(n, r_clump)
+    idx = np.indices((n, n, n))  # (3, z, y, x)
+    ijk = np.stack([idx[2].ravel(), idx[1].ravel(), idx[0].ravel()], axis=1).astype(np.int32)
+    Ub = zf.values(level_min, ijk, level_min).reshape(5, n, n, n)
+
+    def fill(level: int, ijk: np.ndarray) -> np.ndarray:
+        return zf.values(level, ijk, level_min)
+
+    return Problem(f"zoom{level_min}-{level_max}", level_min, level_max, (n, n, n), 5.0 / 3.0, Ub,
+                   refine=REFINE_MASS, refine_param=rho_thr, fill=fill, n_steps=n_steps)
+
+
+# ---------------------------------------------------------------------------
+# config 5: batched uneven periodic boxes
+# ---------------------------------------------------------------------------
+BATCH_SIDES = (16, 24, 32, 40, 48)
+
+
+def batch_box(b: int, side: int, sigma_ln: float, mach: float, gamma: float = 5.0 / 3.0) -> Problem:
+    rho, vx, vy, vz, p = lognormal_fields(side, 5000 + 10 * b, sigma_ln, mach, gamma)
+    U = conserved(rho, vx, vy, vz, p, gamma)
+    return Problem(f"box{b}", 1, 1, (side, side, side), gamma, U, n_steps=20)
+
+
+def batch(nbox: int = 512) -> List[Problem]:
+    rng = np.random.default_rng(5000)
+    sides = rng.choice(np.array(BATCH_SIDES), size=nbox)
+    sig = rng.uniform(0.5, 1.5, size=nbox)
+    mach = rng.uniform(0.5, 3.0, size=nbox)
+    return [batch_box(b, int(sides[b]), float(sig[b]), float(mach[b])) for b in range(nbox)]
+
+
+# ---------------------------------------------------------------------------
+# small cases used by the tests
+# ---------------------------------------------------------------------------
+def uniform_state(n=8, rho=1.3, v=(0.3, -0.2, 0.1), p=0.7, gamma=1.4, bc=(BC_PERIODIC,) * 6) -> Problem:
+    shape = (n, n, n)
+    U = conserved(np.full(shape, rho), np.full(shape, v[0]), np.full(shape, v[1]),
+                  np.full(shape, v[2]), np.full(shape, p), gamma)
+    lvl = int(round(math.log2(n)))
+    return Problem("uniform_state", lvl, lvl, shape, gamma, U, bc=bc)
+
+
+def random_smooth(n=16, seed=7, sigma_ln=0.5, mach=0.8, gamma=1.4, smooth=2.0) -> Problem:
+    rho, vx, vy, vz, p = lognormal_fields(n, seed, sigma_ln, mach, gamma, smooth)
+    p = p * np.exp(0.3 * smooth_gaussian_field(n, seed + 7, smooth))
+    U = conserved(rho, vx, vy, vz, p, gamma)
+    lvl = int(round(math.log2(n)))
+    return Problem(f"random{n}", lvl, lvl, (n, n, n), gamma, U)
