@@ -1,0 +1,218 @@
+"""Benchmark of the octree hydro step on one MI355X.
+
+Prints ONE JSON line.  Headline: FP64 hydro cell-updates/s on the uniform
+128^3 periodic lognormal box (262144 octs, gamma 5/3, CFL 0.8); a step is
+one coarse step of the whole hot path (device CFL/dt, the fused per-tile
+MUSCL-Hancock/HLLC update with its CFL epilogue).  Also reported: the mixed
+FP32/FP64 form on the same box, the zoom-shaped AMR workload (levels 7-12,
+both forms), the roofline of the dominant (hydro) kernel from HIP events on
+its launch stream, and the CPU oracle timed on the host as a baseline.
+
+A cell-update is one leaf cell advanced by one step of its own level;
+algorithmic HBM bytes are 80 per cell-update (5 FP64 read + 5 written).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL_UPDATE = 80
+METRIC = "hydro cell-updates/s (FP64 vs mixed FP32) + % HBM roofline, 128^3 and zoom AMR"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ry_internal.h"):
+        with open(os.path.join(ROOT, "paper_2411_14631_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload_key):
+    """HBM bytes per hydro launch measured with rocprofv3 counters, if they
+    were taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "hydro_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(workload_key)
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_advance(h, steps, warmup, timing):
+    import torch
+    h.set_timing(timing)
+    if warmup:
+        h.advance(warmup)
+    if timing:
+        h.set_timing(False)
+        h.set_timing(True)          # reset the per-kernel accumulators
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.advance(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = h.kernel_time("hydro") if timing else (0, 0.0)
+    h.set_timing(False)
+    return dt, kt
+
+
+def cell_updates_per_coarse_step(h):
+    tot = 0
+    for k, lv in enumerate(h.levels):
+        _, leaf = h.level_info(lv)
+        tot += leaf << k
+    return tot
+
+
+def run_uniform(precision, steps, warmup, tune):
+    import workloads as W
+    from paper_2411_14631_amd import Hydro
+    prob = W.uniform(128)
+    h = Hydro(prob, precision)
+    tuning = None
+    if tune:
+        tuning, _ = h.autotune()
+    cups = cell_updates_per_coarse_step(h)
+    dt_graph, _ = time_advance(h, steps, warmup, timing=False)
+    dt_ev, (nl, ms) = time_advance(h, steps, 0, timing=True)
+    return dict(prob=prob, h=h, cups=cups, dt_graph=dt_graph, dt_timed=dt_ev, launches=nl, kernel_ms=ms,
+                tuning=tuning or h.tuning(), floors=h.floors())
+
+
+def run_zoom(precision, steps, tune):
+    import workloads as W
+    from paper_2411_14631_amd import Hydro
+    prob = W.zoom()
+    t0 = time.perf_counter()
+    h = Hydro(prob, precision)
+    build_s = time.perf_counter() - t0
+    if tune:
+        h.autotune()
+    cups = cell_updates_per_coarse_step(h)
+    noct = sum(h.level_info(lv)[0] for lv in h.levels)
+    dt_graph, _ = time_advance(h, steps, 1, timing=False)
+    return dict(h=h, cups=cups, noct=noct, dt=dt_graph, build_s=build_s,
+                levels={lv: h.level_info(lv) for lv in h.levels})
+
+
+def cpu_baseline(budget_s=15.0):
+    """The oracle, as it is, on the host: 128^3 uniform box, whole steps
+    until about budget_s of wall time."""
+    import workloads as W
+    from oracle.ryo import Oracle, lib
+    prob = W.uniform(128)
+    o = Oracle(prob)
+    cores = lib().ryo_num_threads()
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        o.advance(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 10:
+            break
+    cups = 128 ** 3 * n / el
+    return {"value": cups, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"uniform 128^3 periodic box, {n} whole coarse steps ({el:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-zoom", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design only", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    tune = not args.no_tune
+
+    log("bench: uniform 128^3 fp64")
+    f = run_uniform("fp64", args.steps, args.warmup, tune)
+    log("bench: uniform 128^3 mixed")
+    m = run_uniform("mixed", args.steps, args.warmup, tune)
+
+    value = f["cups"] * args.steps / f["dt_timed"]
+    ms_per_step = 1e3 * f["dt_timed"] / args.steps
+    kernel_avg_ms = f["kernel_ms"] / max(f["launches"], 1)
+    alg_bytes = BYTES_PER_CELL_UPDATE * f["cups"]          # one launch per coarse step
+    achieved = alg_bytes / (kernel_avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles("uniform128_fp64")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "hydro_kernel<double>", "kernel_avg_ms": round(kernel_avg_ms, 5),
+                "alg_bytes_per_launch": alg_bytes}
+
+    m_kernel_ms = m["kernel_ms"] / max(m["launches"], 1)
+    mixed = {"value": m["cups"] * args.steps / m["dt_timed"], "unit": "cell-updates/s",
+             "kernel_avg_ms": round(m_kernel_ms, 5),
+             "hbm_frac": round(BYTES_PER_CELL_UPDATE * m["cups"] / (m_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "graph_value": m["cups"] * args.steps / m["dt_graph"], "tuning": m["tuning"]}
+    # mixed vs fp64 after the same number of steps (both ran warmup + 2 x steps)
+    import numpy as np
+    rf = f["h"].download(7)
+    rm = m["h"].download(7)
+    mixed["l1_rho_rel_vs_fp64"] = float(np.abs(rm[0] - rf[0]).sum() / np.abs(rf[0]).sum())
+    mixed["steps_compared"] = args.warmup + 2 * args.steps
+    del f["h"], m["h"]
+    torch.cuda.empty_cache()
+
+    zoom = None
+    if not args.no_zoom:
+        zoom = {}
+        for prec in ("fp64", "mixed"):
+            log(f"bench: zoom AMR {prec}")
+            z = run_zoom(prec, 3, tune)
+            zoom[prec] = {"value": z["cups"] * 3 / z["dt"], "unit": "cell-updates/s",
+                          "hbm_frac": round(BYTES_PER_CELL_UPDATE * z["cups"] * 3 / z["dt"] / 1e9 / HBM_PEAK_GBS, 4),
+                          "cell_updates_per_coarse_step": z["cups"], "octs": z["noct"],
+                          "ms_per_coarse_step": round(1e3 * z["dt"] / 3, 3), "build_s": round(z["build_s"], 1)}
+            zoom["levels"] = {str(k): v for k, v in z["levels"].items()}
+            del z
+            torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        log("bench: cpu oracle baseline")
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "uniform 128^3 periodic lognormal box (262144 octs), FP64, gamma 5/3, CFL 0.8",
+                   "cells": 128 ** 3, "cell_updates_per_step": f["cups"], "tuning": f["tuning"],
+                   "graph_value": f["cups"] * args.steps / f["dt_graph"], "floor_activations": f["floors"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "mixed": mixed,
+        "zoom_amr": zoom,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

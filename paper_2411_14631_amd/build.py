@@ -1,0 +1,58 @@
+"""Build the HIP library (gfx950) in-tree: paper_2411_14631_amd/libry.so.
+
+All sources go through hipcc.  Host code is compiled without floating-point
+contraction (the refinement map must be a pure function of the input
+bytes); the kernels opt into contraction locally.  Packed FP32 instructions
+are disabled for all device code.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libry.so")
+SOURCES = ["mesh.cpp", "api.cpp", "kernels.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def flags():
+    return ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument", "-Wno-unused-value"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    # the host pass of hipcc does not know the device-only feature flag
+    noise = "'-packed-fp32-ops' is not a recognized feature"
+    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"build failed: {' '.join(cmd)}\n{out}")
+    if out.strip():
+        print(out)
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    objs = []
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    for s in SOURCES:
+        src = os.path.join(CSRC, s)
+        obj = os.path.join(bdir, s + ".o")
+        cmd = [HIPCC] + flags() + (extra or []) + ["-c", src, "-o", obj]
+        if s.endswith(".cpp"):
+            cmd = [HIPCC, "-x", "hip"] + cmd[1:]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        _run(cmd)
+        objs.append(obj)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    _run(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

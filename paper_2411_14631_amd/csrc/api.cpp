@@ -1,0 +1,1050 @@
+// C ABI of the octree hydro library: context lifetime, device buffers,
+// subcycling driver, graph capture, batched boxes, autotuning, diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ry_internal.h"
+
+using namespace ry;
+
+namespace {
+
+struct DevLevel {
+  int64_t n_oct = 0, n_ghost = 0, n_ext = 0, n_leaf = 0;
+  int32_t n_tile = 0;
+  double* U[2] = {nullptr, nullptr};
+  int cur = 0;
+  int32_t* tab = nullptr;
+  uint32_t* tflag = nullptr;
+  uint8_t* refined = nullptr;
+  int32_t* child = nullptr;
+  double* reg = nullptr;
+  int64_t* gsrc = nullptr;
+  int32_t* parent_cell = nullptr;
+  int32_t* tile_box = nullptr;
+  int32_t* oct_box = nullptr;
+  std::vector<uint64_t> keys;
+  std::vector<uint8_t> refined_host;
+  int64_t plane() const { return 8 * n_ext; }
+};
+
+struct TimedLaunch {
+  std::string name;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct ry_ctx {
+  ry_config cfg{};
+  DomainSpec dom;
+  int nlev = 0;
+  bool built = false;
+  bool batch = false;
+  std::vector<DevLevel> lev;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int num_cu = 256;
+  ry_tuning tune{1, 0, 4, 1};
+  // device scalars
+  unsigned long long* d_smax = nullptr;   // per level / per box
+  double* d_lam = nullptr;                // 1 / per box
+  double* d_t = nullptr;                  // 1 / per box
+  int32_t* d_flags = nullptr;             // [0]=skip [1]=done [2]=nstep [3]=err
+  unsigned long long* d_floors = nullptr;
+  unsigned int* d_queue = nullptr;        // 8 counters
+  double* d_partial = nullptr;
+  double* d_tot = nullptr;
+  double* d_dx_box = nullptr;
+  bool slots_valid = false;
+  // subcycling order state for ry_hydro_step
+  int count[RY_MAX_LEVELS] = {0};
+  double dt_of[RY_MAX_LEVELS] = {0};
+  // graphs: key = parity of the base level buffer
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  std::vector<int> graph_par[2];
+  double graph_tend[2] = {0, 0};
+  // batch
+  int nbox = 0;
+  std::vector<int64_t> box_off, box_noct;
+  std::vector<double> box_dx;
+  hipGraphExec_t bgraph = nullptr;
+  int bgraph_steps = -1, bgraph_par = -1;
+  // timing
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  std::map<std::string, std::pair<int64_t, double>> ktime;
+  // memory
+  std::vector<void*> allocs;
+  std::string err;
+};
+
+namespace {
+
+ry_status fail(ry_ctx* c, ry_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIPCHK(c, call)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail((c), RY_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+void* dalloc(ry_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (c->cfg.dev_alloc) {
+    p = c->cfg.dev_alloc(bytes, c->cfg.alloc_user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->allocs.push_back(p);
+  return p;
+}
+
+void free_all(ry_ctx* c) {
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) {
+    if (c->cfg.dev_free) c->cfg.dev_free(p, c->cfg.alloc_user);
+    else if (!c->cfg.dev_alloc) hipFree(p);
+  }
+  c->allocs.clear();
+  for (auto& g : c->graph)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  if (c->bgraph) {
+    hipGraphExecDestroy(c->bgraph);
+    c->bgraph = nullptr;
+  }
+  c->lev.clear();
+}
+
+template <typename T>
+T* upload_vec(ry_ctx* c, const std::vector<T>& v, bool& ok) {
+  T* p = static_cast<T*>(dalloc(c, v.size() * sizeof(T)));
+  if (!p) {
+    ok = false;
+    return nullptr;
+  }
+  if (!v.empty() && hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    ok = false;
+  return p;
+}
+
+ry_status validate(const ry_config* cfg, bool single_level) {
+  if (!cfg) return RY_EINVAL;
+  if (cfg->level_min < 0 || cfg->level_max < cfg->level_min ||
+      cfg->level_max - cfg->level_min + 1 > RY_MAX_LEVELS || cfg->level_max > 20)
+    return RY_EINVAL;
+  if (single_level && cfg->level_max != cfg->level_min) return RY_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (cfg->nbase[a] < 4 || (cfg->nbase[a] % 4) != 0) return RY_EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    const int lo = cfg->bc[2 * a], hi = cfg->bc[2 * a + 1];
+    if (lo != RY_BC_PERIODIC && lo != RY_BC_OUTFLOW) return RY_EINVAL;
+    if (hi != RY_BC_PERIODIC && hi != RY_BC_OUTFLOW) return RY_EINVAL;
+    if ((lo == RY_BC_PERIODIC) != (hi == RY_BC_PERIODIC)) return RY_EINVAL;
+  }
+  if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0) || !(cfg->boxlen > 0.0)) return RY_EINVAL;
+  if (!(cfg->rho_floor > 0.0) || !(cfg->p_floor > 0.0)) return RY_EINVAL;
+  if (cfg->precision != RY_FP64 && cfg->precision != RY_MIXED) return RY_EINVAL;
+  if (cfg->refine < RY_REFINE_NONE || cfg->refine > RY_REFINE_MASS) return RY_EINVAL;
+  if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return RY_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if ((int64_t(cfg->nbase[a] / 2) << (cfg->level_max - cfg->level_min)) >= (int64_t(1) << 21)) return RY_EINVAL;
+  return RY_OK;
+}
+
+DomainSpec make_dom(const ry_config& cfg) {
+  DomainSpec d;
+  d.lmin = cfg.level_min;
+  d.lmax = cfg.level_max;
+  for (int a = 0; a < 3; ++a) d.nbase[a] = cfg.nbase[a];
+  for (int i = 0; i < 6; ++i) d.bc[i] = cfg.bc[i];
+  d.refine = cfg.refine;
+  d.refine_param = cfg.refine_param;
+  int m = std::max(cfg.nbase[0], std::max(cfg.nbase[1], cfg.nbase[2])) / 2, bits = 0;
+  while ((1 << bits) < m) ++bits;
+  d.hbits0 = bits;
+  return d;
+}
+
+double level_dx(const ry_ctx* c, int l) {
+  return c->cfg.boxlen / double(int64_t(c->cfg.nbase[0]) << (l - c->cfg.level_min));
+}
+
+ry_status init_common(ry_ctx* c) {
+  if (c->cfg.stream) {
+    c->stream = (hipStream_t)c->cfg.stream;
+  } else {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    c->num_cu = ncu;
+  return RY_OK;
+}
+
+ry_status alloc_scalars(ry_ctx* c, int nslot) {
+  c->d_smax = static_cast<unsigned long long*>(dalloc(c, sizeof(unsigned long long) * nslot));
+  c->d_lam = static_cast<double*>(dalloc(c, sizeof(double) * nslot));
+  c->d_t = static_cast<double*>(dalloc(c, sizeof(double) * nslot));
+  c->d_flags = static_cast<int32_t*>(dalloc(c, sizeof(int32_t) * 8));
+  c->d_floors = static_cast<unsigned long long*>(dalloc(c, sizeof(unsigned long long)));
+  c->d_queue = static_cast<unsigned int*>(dalloc(c, sizeof(unsigned int) * 8));
+  c->d_partial = static_cast<double*>(dalloc(c, sizeof(double) * NVAR * totals_blocks()));
+  c->d_tot = static_cast<double*>(dalloc(c, sizeof(double) * NVAR));
+  if (!c->d_smax || !c->d_lam || !c->d_t || !c->d_flags || !c->d_floors || !c->d_queue || !c->d_partial || !c->d_tot)
+    return RY_ENOMEM;
+  HIPCHK(c, hipMemsetAsync(c->d_smax, 0, sizeof(unsigned long long) * nslot, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_lam, 0, sizeof(double) * nslot, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_t, 0, sizeof(double) * nslot, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_flags, 0, sizeof(int32_t) * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_floors, 0, sizeof(unsigned long long), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_queue, 0, sizeof(unsigned int) * 8, c->stream));
+  return RY_OK;
+}
+
+int32_t* skip_ptr(ry_ctx* c) { return c->d_flags + 0; }
+int32_t* done_ptr(ry_ctx* c) { return c->d_flags + 1; }
+int32_t* nstep_ptr(ry_ctx* c) { return c->d_flags + 2; }
+int32_t* err_ptr(ry_ctx* c) { return c->d_flags + 3; }
+
+bool level_nonempty(const ry_ctx* c, int l) {
+  return l >= c->cfg.level_min && l <= c->cfg.level_max && c->lev[l - c->cfg.level_min].n_oct > 0;
+}
+
+// --- timing helpers -------------------------------------------------------
+void time_begin(ry_ctx* c, const char* name, TimedLaunch& tl) {
+  tl.name = name;
+  hipEventCreate(&tl.a);
+  hipEventCreate(&tl.b);
+  hipEventRecord(tl.a, c->stream);
+}
+void time_end(ry_ctx* c, TimedLaunch& tl) {
+  hipEventRecord(tl.b, c->stream);
+  c->pending.push_back(tl);
+}
+void time_collect(ry_ctx* c) {
+  for (auto& tl : c->pending) {
+    float ms = 0.f;
+    hipEventSynchronize(tl.b);
+    hipEventElapsedTime(&ms, tl.a, tl.b);
+    auto& e = c->ktime[tl.name];
+    e.first += 1;
+    e.second += ms;
+    hipEventDestroy(tl.a);
+    hipEventDestroy(tl.b);
+  }
+  c->pending.clear();
+}
+
+// --- kernel enqueue helpers -------------------------------------------------
+ry_status enqueue_cfl_all(ry_ctx* c) {
+  if (launch_zero_u64(c->d_smax, c->batch ? c->nbox : c->nlev, c->stream)) return fail(c, RY_EHIP, "zero kernel");
+  for (int k = 0; k < c->nlev; ++k) {
+    DevLevel& L = c->lev[k];
+    if (L.n_oct == 0) continue;
+    if (c->batch) {
+      // one slot per box: reuse the CFL kernel per box range
+      for (int b = 0; b < c->nbox; ++b) {
+        const int64_t off = c->box_off[b] * 8;
+        if (launch_cfl(L.U[L.cur] + off, L.plane(), c->box_noct[b], L.refined + c->box_off[b], c->cfg.gamma,
+                       c->cfg.rho_floor, c->cfg.p_floor, c->d_smax + b, err_ptr(c), c->stream))
+          return fail(c, RY_EHIP, "cfl kernel");
+      }
+    } else if (launch_cfl(L.U[L.cur], L.plane(), L.n_oct, L.refined, c->cfg.gamma, c->cfg.rho_floor,
+                          c->cfg.p_floor, c->d_smax + k, err_ptr(c), c->stream)) {
+      return fail(c, RY_EHIP, "cfl kernel");
+    }
+  }
+  c->slots_valid = true;
+  return RY_OK;
+}
+
+ry_status enqueue_ghost(ry_ctx* c, int l, const int32_t* skip) {
+  DevLevel& L = c->lev[l - c->cfg.level_min];
+  if (L.n_ghost == 0) return RY_OK;
+  GhostArgs g{};
+  for (int k = 0; k < RY_MAX_LEVELS; ++k) {
+    const int lc = l - 1 - k;
+    if (lc < c->cfg.level_min) break;
+    DevLevel& C = c->lev[lc - c->cfg.level_min];
+    g.src[k] = C.U[C.cur];
+    g.src_plane[k] = C.plane();
+  }
+  g.gsrc = L.gsrc;
+  g.n_ghost = L.n_ghost;
+  g.n_oct = L.n_oct;
+  g.dst0 = L.U[0];
+  g.dst1 = L.U[1];
+  g.plane = L.plane();
+  g.skip = skip;
+  TimedLaunch tl;
+  if (c->timing) time_begin(c, "ghost", tl);
+  if (launch_ghost(g, c->stream)) return fail(c, RY_EHIP, "ghost kernel");
+  if (c->timing) time_end(c, tl);
+  return RY_OK;
+}
+
+HydroArgs hydro_args(ry_ctx* c, int l, int substep) {
+  DevLevel& L = c->lev[l - c->cfg.level_min];
+  HydroArgs a{};
+  a.U = L.U[L.cur];
+  a.Un = L.U[L.cur ^ 1];
+  a.plane = L.plane();
+  a.n_oct = int32_t(L.n_oct);
+  a.n_tile = L.n_tile;
+  a.tab = L.tab;
+  a.tflag = L.tflag;
+  a.refined = L.refined;
+  const bool fine = level_nonempty(c, l + 1);
+  a.child = fine ? L.child : nullptr;
+  a.reg_fine = fine ? c->lev[l + 1 - c->cfg.level_min].reg : nullptr;
+  a.reg_own = L.reg;
+  a.substep = substep;
+  a.record_reg = (l > c->cfg.level_min) ? 1 : 0;
+  a.gamma = c->cfg.gamma;
+  a.rho_floor = c->cfg.rho_floor;
+  a.p_floor = c->cfg.p_floor;
+  a.floors = c->d_floors;
+  a.err = err_ptr(c);
+  a.queue = c->d_queue;
+  a.tile_box = L.tile_box;
+  return a;
+}
+
+ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a) {
+  if (c->tune.persistent && launch_zero_u32(c->d_queue, 8, c->stream)) return fail(c, RY_EHIP, "zero kernel");
+  TimedLaunch tl;
+  if (c->timing) time_begin(c, "hydro", tl);
+  if (launch_hydro(a, c->cfg.precision, c->tune, c->num_cu, c->stream)) return fail(c, RY_EHIP, "hydro kernel");
+  if (c->timing) time_end(c, tl);
+  return RY_OK;
+}
+
+ry_status enqueue_restrict(ry_ctx* c, int l, const int32_t* skip) {
+  DevLevel& L = c->lev[l - c->cfg.level_min];
+  DevLevel& F = c->lev[l + 1 - c->cfg.level_min];
+  if (launch_restrict(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur ^ 1], L.plane(), skip, c->stream))
+    return fail(c, RY_EHIP, "restrict kernel");
+  return RY_OK;
+}
+
+// Fine-first recursion of one parent step of level l (device lambda).
+ry_status enqueue_level(ry_ctx* c, int l, int substep, bool last) {
+  ry_status s;
+  const bool fine = level_nonempty(c, l + 1);
+  if (fine) {
+    if ((s = enqueue_ghost(c, l + 1, skip_ptr(c)))) return s;
+    if ((s = enqueue_level(c, l + 1, 0, false))) return s;
+    if ((s = enqueue_level(c, l + 1, 1, last))) return s;
+  }
+  HydroArgs a = hydro_args(c, l, substep);
+  a.lam_dev = c->d_lam;
+  a.skip = skip_ptr(c);
+  a.smax = last ? c->d_smax + (l - c->cfg.level_min) : nullptr;
+  if ((s = enqueue_hydro(c, a))) return s;
+  if (fine && (s = enqueue_restrict(c, l, skip_ptr(c)))) return s;
+  DevLevel& L = c->lev[l - c->cfg.level_min];
+  L.cur ^= 1;
+  return RY_OK;
+}
+
+ry_status enqueue_coarse_step(ry_ctx* c, double t_end) {
+  FinalizeArgs f{};
+  f.smax = c->d_smax;
+  f.nslot = c->nlev;
+  f.cfl = c->cfg.cfl;
+  for (int k = 0; k < c->nlev; ++k) f.dx[k] = level_dx(c, c->cfg.level_min + k);
+  f.t_end = t_end;
+  f.t = c->d_t;
+  f.lam = c->d_lam;
+  f.skip = skip_ptr(c);
+  f.done = done_ptr(c);
+  f.nstep = nstep_ptr(c);
+  f.clear = c->d_smax;
+  f.batch = 0;
+  if (launch_finalize(f, c->stream)) return fail(c, RY_EHIP, "finalize kernel");
+  return enqueue_level(c, c->cfg.level_min, 0, true);
+}
+
+ry_status sync_and_check(ry_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) time_collect(c);
+  int32_t e = 0;
+  HIPCHK(c, hipMemcpy(&e, err_ptr(c), sizeof e, hipMemcpyDeviceToHost));
+  if (e) return fail(c, RY_ENUMERIC, "non-finite or non-positive density/energy latched on the device");
+  return RY_OK;
+}
+
+ry_status upload_level_state(ry_ctx* c, DevLevel& D, const double* U_host) {
+  for (int b = 0; b < 2; ++b)
+    for (int v = 0; v < NVAR; ++v)
+      HIPCHK(c, hipMemcpyAsync(D.U[b] + v * D.plane(), U_host + size_t(v) * 8 * D.n_oct,
+                               sizeof(double) * 8 * D.n_oct, hipMemcpyHostToDevice, c->stream));
+  return RY_OK;
+}
+
+void drop_graphs(ry_ctx* c) {
+  for (auto& g : c->graph)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+ry_status ry_create(const ry_config* cfg, ry_ctx** out) {
+  if (!out) return RY_EINVAL;
+  *out = nullptr;
+  ry_status s = validate(cfg, false);
+  if (s) return s;
+  ry_ctx* c = new (std::nothrow) ry_ctx();
+  if (!c) return RY_ENOMEM;
+  c->cfg = *cfg;
+  c->dom = make_dom(*cfg);
+  c->nlev = cfg->level_max - cfg->level_min + 1;
+  if ((s = init_common(c))) {
+    delete c;
+    return s;
+  }
+  *out = c;
+  return RY_OK;
+}
+
+void ry_destroy(ry_ctx* c) {
+  if (!c) return;
+  free_all(c);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  for (auto& tl : c->pending) {
+    hipEventDestroy(tl.a);
+    hipEventDestroy(tl.b);
+  }
+  delete c;
+}
+
+const char* ry_last_error(const ry_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* user) {
+  if (!c || !U_base || c->batch) return RY_EINVAL;
+  if (c->cfg.level_max > c->cfg.level_min && c->cfg.refine != RY_REFINE_NONE && !fill)
+    return fail(c, RY_EINVAL, "fill callback required when level_max > level_min");
+  free_all(c);
+  c->built = false;
+  std::vector<HostLevel> H;
+  std::string e = build_mesh(c->dom, U_base, fill, user, H);
+  if (!e.empty()) return fail(c, RY_EINVAL, "%s", e.c_str());
+  std::vector<LevelTables> T;
+  e = build_tables(c->dom, H, T);
+  if (!e.empty()) return fail(c, RY_EINVAL, "%s", e.c_str());
+  c->lev.assign(c->nlev, DevLevel());
+  bool ok = true;
+  for (int k = 0; k < c->nlev && ok; ++k) {
+    DevLevel& D = c->lev[k];
+    LevelTables& t = T[k];
+    D.n_oct = t.n_oct;
+    D.n_ghost = t.n_ghost;
+    D.n_ext = t.n_oct + t.n_ghost;
+    D.n_leaf = t.n_leaf;
+    D.n_tile = t.n_tile;
+    D.keys = H[k].key;
+    D.refined_host = H[k].refined;
+    if (D.n_oct == 0) continue;
+    for (int b = 0; b < 2; ++b) {
+      D.U[b] = static_cast<double*>(dalloc(c, sizeof(double) * NVAR * 8 * D.n_ext));
+      if (!D.U[b]) ok = false;
+    }
+    if (!ok) break;
+    if (upload_level_state(c, D, H[k].U.data())) return c->err.empty() ? RY_EHIP : RY_EHIP;
+    D.tab = upload_vec(c, t.tab, ok);
+    D.tflag = upload_vec(c, t.tflag, ok);
+    D.refined = upload_vec(c, t.refined_ext, ok);
+    if (!t.child.empty()) D.child = upload_vec(c, t.child, ok);
+    if (!t.parent_cell.empty()) D.parent_cell = upload_vec(c, t.parent_cell, ok);
+    if (!t.gsrc.empty()) D.gsrc = upload_vec(c, t.gsrc, ok);
+    std::vector<double> zeros(size_t(D.n_oct) * REG_PER_OCT, 0.0);
+    if (k > 0) D.reg = upload_vec(c, zeros, ok);
+  }
+  if (!ok) {
+    free_all(c);
+    return fail(c, RY_ENOMEM, "device allocation failed");
+  }
+  ry_status s = alloc_scalars(c, std::max(c->nlev, 1));
+  if (s) {
+    free_all(c);
+    return fail(c, s, "device allocation failed");
+  }
+  std::fill(std::begin(c->count), std::end(c->count), 0);
+  if ((s = enqueue_cfl_all(c))) return s;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->built = true;
+  return RY_OK;
+}
+
+ry_status ry_level_info(const ry_ctx* c, int32_t level, int64_t* n_oct, int64_t* n_leaf) {
+  if (!c || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
+  const DevLevel& D = c->lev[level - c->cfg.level_min];
+  if (n_oct) *n_oct = D.n_oct;
+  if (n_leaf) *n_leaf = D.n_leaf;
+  return RY_OK;
+}
+
+ry_status ry_get_mesh(const ry_ctx* c, int32_t level, uint64_t* keys, uint8_t* refined) {
+  if (!c || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
+  const DevLevel& D = c->lev[level - c->cfg.level_min];
+  if (keys && D.n_oct) std::memcpy(keys, D.keys.data(), sizeof(uint64_t) * D.n_oct);
+  if (refined && D.n_oct) std::memcpy(refined, D.refined_host.data(), D.n_oct);
+  return RY_OK;
+}
+
+ry_status ry_cfl_dt(ry_ctx* c, double* dt) {
+  if (!c || !dt || !c->built || c->batch) return RY_EINVAL;
+  ry_status s = enqueue_cfl_all(c);
+  if (s) return s;
+  if ((s = sync_and_check(c))) return s;
+  std::vector<unsigned long long> sm(c->nlev);
+  HIPCHK(c, hipMemcpy(sm.data(), c->d_smax, sizeof(unsigned long long) * c->nlev, hipMemcpyDeviceToHost));
+  double best = INFINITY;
+  for (int k = 0; k < c->nlev; ++k) {
+    double smax;
+    std::memcpy(&smax, &sm[k], sizeof smax);
+    if (!(smax > 0.0)) continue;
+    const double dtl = c->cfg.cfl * level_dx(c, c->cfg.level_min + k) / smax;
+    const double cand = std::ldexp(dtl, k);
+    if (cand < best) best = cand;
+  }
+  *dt = best;
+  return RY_OK;
+}
+
+ry_status ry_hydro_step(ry_ctx* c, int32_t level, double dt) {
+  if (!c || c->batch) return RY_EINVAL;
+  if (!c->built) return fail(c, RY_ESTATE, "not built");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !level_nonempty(c, level)) return fail(c, RY_EINVAL, "bad level or dt");
+  const int lmin = c->cfg.level_min;
+  const int k = level - lmin;
+  const bool fine = level_nonempty(c, level + 1);
+  if (fine) {
+    if (c->count[k + 1] != 2) return fail(c, RY_ESTATE, "level %d needs two steps of level %d first", level, level + 1);
+    if (dt != 2.0 * c->dt_of[k + 1]) return fail(c, RY_EINVAL, "dt must be twice the finer level's dt");
+  }
+  if (level > lmin) {
+    if (c->count[k] >= 2) return fail(c, RY_ESTATE, "level %d already took two substeps", level);
+    if (c->count[k] == 1 && dt != c->dt_of[k]) return fail(c, RY_EINVAL, "both substeps need the same dt");
+  }
+  ry_status s;
+  if (level > lmin && c->count[k] == 0 && (s = enqueue_ghost(c, level, nullptr))) return s;
+  HydroArgs a = hydro_args(c, level, level > lmin ? c->count[k] : 0);
+  a.lam_dev = nullptr;
+  a.lam_host = dt / level_dx(c, level);
+  a.skip = nullptr;
+  a.smax = nullptr;
+  if ((s = enqueue_hydro(c, a))) return s;
+  if (fine && (s = enqueue_restrict(c, level, nullptr))) return s;
+  c->lev[k].cur ^= 1;
+  c->dt_of[k] = dt;
+  if (level > lmin) c->count[k] += 1;
+  if (fine) c->count[k + 1] = 0;
+  c->slots_valid = false;
+  drop_graphs(c);
+  return RY_OK;
+}
+
+static ry_status capture_step(ry_ctx* c, int par, double t_end) {
+  if (c->graph[par]) {
+    hipGraphExecDestroy(c->graph[par]);
+    c->graph[par] = nullptr;
+  }
+  std::vector<int> saved;
+  for (auto& L : c->lev) saved.push_back(L.cur);
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  ry_status s = enqueue_coarse_step(c, t_end);
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  for (size_t i = 0; i < c->lev.size(); ++i) c->lev[i].cur = saved[i];
+  if (s) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(c, RY_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->graph[par], g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(c, RY_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  c->graph_par[par] = saved;
+  c->graph_tend[par] = t_end;
+  return RY_OK;
+}
+
+ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
+  if (!c || !t_io || c->batch || n_coarse < 0) return RY_EINVAL;
+  if (!c->built) return fail(c, RY_ESTATE, "not built");
+  for (int k = 1; k < c->nlev; ++k)
+    if (c->count[k] != 0) return fail(c, RY_ESTATE, "ry_advance called inside a coarse step");
+  ry_status s;
+  if (!c->slots_valid && (s = enqueue_cfl_all(c))) return s;
+  const double t0 = *t_io;
+  HIPCHK(c, hipMemcpyAsync(c->d_t, &t0, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (launch_zero_u32(reinterpret_cast<unsigned int*>(c->d_flags), 3, c->stream))
+    return fail(c, RY_EHIP, "zero kernel");
+  const bool use_graph = !c->timing;
+  for (int32_t i = 0; i < n_coarse; ++i) {
+    if (use_graph) {
+      const int par = c->lev[0].cur;
+      std::vector<int> now;
+      for (auto& L : c->lev) now.push_back(L.cur);
+      if (!c->graph[par] || c->graph_par[par] != now || c->graph_tend[par] != t_end)
+        if ((s = capture_step(c, par, t_end))) return s;
+      HIPCHK(c, hipGraphLaunch(c->graph[par], c->stream));
+      c->lev[0].cur ^= 1;
+    } else if ((s = enqueue_coarse_step(c, t_end))) {
+      return s;
+    }
+  }
+  c->slots_valid = true;
+  if ((s = sync_and_check(c))) return s;
+  HIPCHK(c, hipMemcpy(t_io, c->d_t, sizeof(double), hipMemcpyDeviceToHost));
+  return RY_OK;
+}
+
+ry_status ry_conserved_totals(ry_ctx* c, double tot[5]) {
+  if (!c || !tot || !c->built || c->batch) return RY_EINVAL;
+  const int nb = totals_blocks();
+  if (launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_partial), int64_t(NVAR) * nb, c->stream))
+    return fail(c, RY_EHIP, "zero kernel");
+  for (int k = 0; k < c->nlev; ++k) {
+    DevLevel& L = c->lev[k];
+    if (!L.n_oct) continue;
+    const double dx = level_dx(c, c->cfg.level_min + k);
+    if (launch_totals(L.U[L.cur], L.plane(), L.n_oct, L.refined, dx * dx * dx, c->d_partial, nb, c->stream))
+      return fail(c, RY_EHIP, "totals kernel");
+  }
+  if (launch_totals_final(c->d_partial, nb, c->d_tot, c->stream)) return fail(c, RY_EHIP, "totals kernel");
+  ry_status s = sync_and_check(c);
+  if (s) return s;
+  HIPCHK(c, hipMemcpy(tot, c->d_tot, sizeof(double) * NVAR, hipMemcpyDeviceToHost));
+  return RY_OK;
+}
+
+ry_status ry_download(ry_ctx* c, int32_t level, double* U) {
+  if (!c || !U || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
+  DevLevel& D = c->lev[level - c->cfg.level_min];
+  for (int v = 0; v < NVAR && D.n_oct; ++v)
+    HIPCHK(c, hipMemcpyAsync(U + size_t(v) * 8 * D.n_oct, D.U[D.cur] + v * D.plane(), sizeof(double) * 8 * D.n_oct,
+                             hipMemcpyDeviceToHost, c->stream));
+  return sync_and_check(c);
+}
+
+ry_status ry_upload(ry_ctx* c, int32_t level, const double* U) {
+  if (!c || !U || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
+  DevLevel& D = c->lev[level - c->cfg.level_min];
+  if (!D.n_oct) return RY_OK;
+  ry_status s = upload_level_state(c, D, U);
+  if (s) return s;
+  HIPCHK(c, hipMemsetAsync(err_ptr(c), 0, sizeof(int32_t), c->stream));
+  if ((s = enqueue_cfl_all(c))) return s;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RY_OK;
+}
+
+// --------------------------------------------------------------- batching
+ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* const* U0, ry_ctx** out) {
+  if (!out || !cfgs || !U0 || nbox <= 0) return RY_EINVAL;
+  *out = nullptr;
+  for (int b = 0; b < nbox; ++b) {
+    ry_status s = validate(&cfgs[b], true);
+    if (s) return s;
+    if (!U0[b]) return RY_EINVAL;
+    if (cfgs[b].gamma != cfgs[0].gamma || cfgs[b].cfl != cfgs[0].cfl || cfgs[b].rho_floor != cfgs[0].rho_floor ||
+        cfgs[b].p_floor != cfgs[0].p_floor || cfgs[b].precision != cfgs[0].precision)
+      return RY_EINVAL;
+  }
+  ry_ctx* c = new (std::nothrow) ry_ctx();
+  if (!c) return RY_ENOMEM;
+  c->cfg = cfgs[0];
+  c->batch = true;
+  c->nlev = 1;
+  c->nbox = nbox;
+  c->tune.persistent = 1;
+  c->tune.batch = 4;
+  ry_status s = init_common(c);
+  if (s) {
+    delete c;
+    return s;
+  }
+  LevelTables all;
+  std::vector<double> Uall;
+  std::vector<int32_t> oct_box;
+  std::vector<std::vector<double>> Ubox(nbox);
+  int64_t off = 0;
+  for (int b = 0; b < nbox; ++b) {
+    DomainSpec d = make_dom(cfgs[b]);
+    std::vector<HostLevel> H;
+    std::string e = build_mesh(d, U0[b], nullptr, nullptr, H);
+    std::vector<LevelTables> T;
+    if (e.empty()) e = build_tables(d, H, T);
+    if (!e.empty()) {
+      ry_destroy(c);
+      return RY_EINVAL;
+    }
+    const LevelTables& t = T[0];
+    c->box_off.push_back(off);
+    c->box_noct.push_back(t.n_oct);
+    c->box_dx.push_back(cfgs[b].boxlen / double(cfgs[b].nbase[0]));
+    for (int32_t i = 0; i < t.n_tile; ++i) {
+      for (int j = 0; j < TILE_TAB; ++j) {
+        const int32_t v = t.tab[size_t(i) * TILE_TAB + j];
+        all.tab.push_back(v >= 0 ? int32_t(v + off) : -1);
+      }
+      all.tflag.push_back(t.tflag[i]);
+      all.tile_box.push_back(b);
+    }
+    for (int64_t o = 0; o < t.n_oct; ++o) oct_box.push_back(b);
+    Ubox[b] = H[0].U;
+    off += t.n_oct;
+  }
+  all.n_oct = off;
+  all.n_tile = int32_t(all.tflag.size());
+  all.refined_ext.assign(off, 0);
+  c->lev.assign(1, DevLevel());
+  DevLevel& D = c->lev[0];
+  D.n_oct = off;
+  D.n_ext = off;
+  D.n_leaf = off * 8;
+  D.n_tile = all.n_tile;
+  bool ok = true;
+  for (int b = 0; b < 2; ++b) {
+    D.U[b] = static_cast<double*>(dalloc(c, sizeof(double) * NVAR * 8 * D.n_ext));
+    if (!D.U[b]) ok = false;
+  }
+  if (ok) {
+    for (int b = 0; b < nbox; ++b)
+      for (int buf = 0; buf < 2; ++buf)
+        for (int v = 0; v < NVAR; ++v)
+          if (hipMemcpyAsync(D.U[buf] + v * D.plane() + c->box_off[b] * 8, Ubox[b].data() + size_t(v) * 8 * c->box_noct[b],
+                             sizeof(double) * 8 * c->box_noct[b], hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            ok = false;
+    D.tab = upload_vec(c, all.tab, ok);
+    D.tflag = upload_vec(c, all.tflag, ok);
+    D.refined = upload_vec(c, all.refined_ext, ok);
+    D.tile_box = upload_vec(c, all.tile_box, ok);
+    D.oct_box = upload_vec(c, oct_box, ok);
+    c->d_dx_box = upload_vec(c, c->box_dx, ok);
+  }
+  if (!ok || alloc_scalars(c, nbox)) {
+    ry_destroy(c);
+    return RY_ENOMEM;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    ry_destroy(c);
+    return RY_EHIP;
+  }
+  c->built = true;
+  *out = c;
+  return RY_OK;
+}
+
+static ry_status enqueue_batch_step(ry_ctx* c) {
+  DevLevel& L = c->lev[0];
+  FinalizeArgs f{};
+  f.smax = c->d_smax;
+  f.nslot = c->nbox;
+  f.cfl = c->cfg.cfl;
+  f.dx_box = c->d_dx_box;
+  f.t = c->d_t;
+  f.lam = c->d_lam;
+  f.nstep = nstep_ptr(c);
+  f.clear = c->d_smax;
+  f.batch = 1;
+  if (launch_finalize(f, c->stream)) return fail(c, RY_EHIP, "finalize kernel");
+  HydroArgs a = hydro_args(c, c->cfg.level_min, 0);
+  a.child = nullptr;
+  a.reg_fine = nullptr;
+  a.reg_own = nullptr;
+  a.record_reg = 0;
+  a.lam_dev = c->d_lam;
+  a.tile_box = L.tile_box;
+  a.smax = c->d_smax;
+  a.skip = nullptr;
+  ry_status s = enqueue_hydro(c, a);
+  if (s) return s;
+  L.cur ^= 1;
+  return RY_OK;
+}
+
+ry_status ry_batch_run(ry_ctx* c, int32_t nsteps) {
+  if (!c || !c->batch || !c->built || nsteps < 0) return RY_EINVAL;
+  ry_status s;
+  if (!c->slots_valid && (s = enqueue_cfl_all(c))) return s;
+  DevLevel& L = c->lev[0];
+  if (c->timing) {
+    for (int i = 0; i < nsteps; ++i)
+      if ((s = enqueue_batch_step(c))) return s;
+  } else if (nsteps > 0) {
+    if (!c->bgraph || c->bgraph_steps != nsteps || c->bgraph_par != L.cur) {
+      if (c->bgraph) {
+        hipGraphExecDestroy(c->bgraph);
+        c->bgraph = nullptr;
+      }
+      const int saved = L.cur;
+      hipGraph_t g = nullptr;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < nsteps && !s; ++i) s = enqueue_batch_step(c);
+      hipError_t e = hipStreamEndCapture(c->stream, &g);
+      L.cur = saved;
+      if (s) {
+        if (g) hipGraphDestroy(g);
+        return s;
+      }
+      if (e != hipSuccess) return fail(c, RY_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&c->bgraph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(c, RY_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      c->bgraph_steps = nsteps;
+      c->bgraph_par = saved;
+    }
+    HIPCHK(c, hipGraphLaunch(c->bgraph, c->stream));
+    if (nsteps & 1) L.cur ^= 1;
+  }
+  c->slots_valid = true;
+  return sync_and_check(c);
+}
+
+ry_status ry_batch_box_info(const ry_ctx* c, int32_t box, int64_t* n_oct, double* t) {
+  if (!c || !c->batch || box < 0 || box >= c->nbox) return RY_EINVAL;
+  if (n_oct) *n_oct = c->box_noct[box];
+  if (t && hipMemcpy(t, c->d_t + box, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return RY_EHIP;
+  return RY_OK;
+}
+
+ry_status ry_batch_download(ry_ctx* c, int32_t box, double* U) {
+  if (!c || !c->batch || !U || box < 0 || box >= c->nbox) return RY_EINVAL;
+  DevLevel& D = c->lev[0];
+  const int64_t n = c->box_noct[box];
+  for (int v = 0; v < NVAR; ++v)
+    HIPCHK(c, hipMemcpyAsync(U + size_t(v) * 8 * n, D.U[D.cur] + v * D.plane() + c->box_off[box] * 8,
+                             sizeof(double) * 8 * n, hipMemcpyDeviceToHost, c->stream));
+  return sync_and_check(c);
+}
+
+// ---------------------------------------------------------------- tuning
+ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
+  if (!c || !t) return RY_EINVAL;
+  if (t->tiles_per_wg != 1 && t->tiles_per_wg != 2 && t->tiles_per_wg != 4) return RY_EINVAL;
+  // FP64 tiles take 29 KB of LDS each: at most 2 per workgroup (64 KB limit)
+  if (c->cfg.precision == RY_FP64 && t->tiles_per_wg > 2) return RY_EINVAL;
+  if (t->persistent && (t->waves_per_cu < 1 || t->waves_per_cu > 32 || t->batch < 1 || t->batch > 64))
+    return RY_EINVAL;
+  c->tune = *t;
+  drop_graphs(c);
+  if (c->bgraph) {
+    hipGraphExecDestroy(c->bgraph);
+    c->bgraph = nullptr;
+  }
+  return RY_OK;
+}
+
+ry_status ry_get_tuning(const ry_ctx* c, ry_tuning* t) {
+  if (!c || !t) return RY_EINVAL;
+  *t = c->tune;
+  return RY_OK;
+}
+
+// Time the hydro kernels of one coarse step (every level, weighted by its
+// substeps) for a tuning, writing only the scratch buffers.
+static ry_status time_tuning(ry_ctx* c, const ry_tuning& t, double* ms_out) {
+  ry_tuning saved = c->tune;
+  c->tune = t;
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  double best = INFINITY;
+  ry_status s = RY_OK;
+  for (int rep = 0; rep < 4 && !s; ++rep) {
+    hipEventRecord(a, c->stream);
+    for (int k = 0; k < c->nlev && !s; ++k) {
+      const int l = c->cfg.level_min + k;
+      if (!level_nonempty(c, l)) continue;
+      HydroArgs h = hydro_args(c, l, 0);
+      h.lam_dev = c->batch ? c->d_lam : nullptr;
+      h.lam_host = 0.1;
+      h.record_reg = 0;
+      h.reg_own = nullptr;
+      h.smax = nullptr;
+      h.floors = nullptr;
+      h.err = nullptr;
+      h.skip = nullptr;
+      for (int r = 0; r < (1 << k) && !s; ++r) s = enqueue_hydro(c, h);
+    }
+    hipEventRecord(b, c->stream);
+    hipEventSynchronize(b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, a, b);
+    if (rep > 0) best = std::min(best, double(ms));
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  c->tune = saved;
+  *ms_out = best;
+  return s;
+}
+
+ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_cand, int32_t* n_cand) {
+  if (!c || !c->built) return RY_EINVAL;
+  if (c->batch) {
+    // the batched launch reads per-box lambda: make sure it holds values
+    ry_status s0 = enqueue_cfl_all(c);
+    if (s0) return s0;
+  }
+  std::vector<ry_tuning> cand;
+  for (int tpw : {1, 2, 4})
+    if (!(c->cfg.precision == RY_FP64 && tpw > 2)) cand.push_back({tpw, 0, 4, 1});
+  for (int tpw : {1, 2})
+    for (int w : {4, 8})
+      for (int bt : {1, 4}) cand.push_back({tpw, 1, w, bt});
+  double best_ms = INFINITY;
+  ry_tuning bt{};
+  int n = 0;
+  for (auto& t : cand) {
+    double ms = 0;
+    ry_status s = time_tuning(c, t, &ms);
+    if (s) return s;
+    if (times_ms && n < max_cand) times_ms[n] = ms;
+    ++n;
+    if (ms < best_ms) {
+      best_ms = ms;
+      bt = t;
+    }
+  }
+  if (n_cand) *n_cand = n;
+  ry_status s = ry_set_tuning(c, &bt);
+  if (s) return s;
+  if (best) *best = bt;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RY_OK;
+}
+
+// ----------------------------------------------------------- diagnostics
+int64_t ry_floor_count(ry_ctx* c) {
+  if (!c || !c->built) return -1;
+  unsigned long long v = 0;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
+  if (hipMemcpy(&v, c->d_floors, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  return int64_t(v);
+}
+
+ry_status ry_set_timing(ry_ctx* c, int32_t on) {
+  if (!c) return RY_EINVAL;
+  c->timing = on != 0;
+  if (!c->timing) c->ktime.clear();
+  return RY_OK;
+}
+
+ry_status ry_kernel_time(ry_ctx* c, const char* kernel, int64_t* launches, double* total_ms) {
+  if (!c || !kernel) return RY_EINVAL;
+  if (!c->pending.empty()) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return RY_EHIP;
+    time_collect(c);
+  }
+  auto it = c->ktime.find(kernel);
+  if (launches) *launches = it == c->ktime.end() ? 0 : it->second.first;
+  if (total_ms) *total_ms = it == c->ktime.end() ? 0.0 : it->second.second;
+  return RY_OK;
+}
+
+ry_status ry_copy_probe(ry_ctx* c, size_t bytes, int32_t reps, double* ms) {
+  if (!c || !ms || bytes < 1024 || reps < 1) return RY_EINVAL;
+  double *a = nullptr, *b = nullptr;
+  HIPCHK(c, hipMalloc(&a, bytes));
+  if (hipMalloc(&b, bytes) != hipSuccess) {
+    hipFree(a);
+    return fail(c, RY_ENOMEM, "probe allocation");
+  }
+  hipMemsetAsync(a, 0, bytes, c->stream);
+  const int64_t n = int64_t(bytes / sizeof(double));
+  launch_copy(a, b, n, c->stream);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  hipEventRecord(e0, c->stream);
+  for (int i = 0; i < reps; ++i) launch_copy(a, b, n, c->stream);
+  hipEventRecord(e1, c->stream);
+  hipEventSynchronize(e1);
+  float t = 0.f;
+  hipEventElapsedTime(&t, e0, e1);
+  *ms = double(t) / reps;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(a);
+  hipFree(b);
+  return RY_OK;
+}
+
+// ------------------------------------------------------- host-only mesh
+struct ry_mesh {
+  ry_config cfg;
+  std::vector<HostLevel> levels;
+  std::vector<LevelTables> tables;
+};
+
+ry_status ry_mesh_build(const ry_config* cfg, const double* U_base, ry_fill_fn fill, void* user, ry_mesh** out) {
+  if (!out || !U_base) return RY_EINVAL;
+  *out = nullptr;
+  ry_status s = validate(cfg, false);
+  if (s) return s;
+  ry_mesh* m = new (std::nothrow) ry_mesh();
+  if (!m) return RY_ENOMEM;
+  m->cfg = *cfg;
+  DomainSpec d = make_dom(*cfg);
+  std::string e = build_mesh(d, U_base, fill, user, m->levels);
+  if (e.empty()) e = build_tables(d, m->levels, m->tables);
+  if (!e.empty()) {
+    delete m;
+    return RY_EINVAL;
+  }
+  *out = m;
+  return RY_OK;
+}
+
+ry_status ry_mesh_level(const ry_mesh* m, int32_t level, int64_t* n_oct, uint64_t* keys, uint8_t* refined,
+                        int64_t* n_ghost) {
+  if (!m || level < m->cfg.level_min || level > m->cfg.level_max) return RY_EINVAL;
+  const HostLevel& H = m->levels[level - m->cfg.level_min];
+  if (n_oct) *n_oct = H.n;
+  if (keys && H.n) std::memcpy(keys, H.key.data(), sizeof(uint64_t) * H.n);
+  if (refined && H.n) std::memcpy(refined, H.refined.data(), H.n);
+  if (n_ghost) *n_ghost = m->tables[level - m->cfg.level_min].n_ghost;
+  return RY_OK;
+}
+
+void ry_mesh_free(ry_mesh* m) { delete m; }
+
+uint64_t ry_hilbert_key(int32_t bits, uint32_t x, uint32_t y, uint32_t z) { return hilbert3(bits, x, y, z); }
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Internal declarations shared by the host side (mesh.cpp, api.cpp) and the
+// HIP kernels (kernels.hip) of the octree hydro library.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ry.h"
+
+namespace ry {
+
+constexpr int NVAR = 5;
+constexpr int TILE_TAB = 64;       // 4x4x4 oct positions around a 2x2x2-oct tile
+constexpr int REG_PER_OCT = 6 * NVAR * 2;
+
+// Tile flag bits: outflow clamping at the domain faces touched by the tile.
+enum : uint32_t { CL_LOX = 1, CL_HIX = 2, CL_LOY = 4, CL_HIY = 8, CL_LOZ = 16, CL_HIZ = 32 };
+
+// ---------------------------------------------------------------- host mesh
+struct OctIndex {
+  // open addressing: packed coordinates -> oct index
+  std::vector<uint64_t> slot_key;
+  std::vector<int32_t> slot_val;
+  uint64_t mask = 0;
+  void build(const std::vector<int32_t>& x, const std::vector<int32_t>& y, const std::vector<int32_t>& z);
+  int32_t find(int64_t x, int64_t y, int64_t z) const;
+};
+
+struct HostLevel {
+  int64_t n = 0;                     // octs
+  std::vector<uint64_t> key;         // Hilbert keys, ascending
+  std::vector<int32_t> ox, oy, oz;   // oct coordinates
+  std::vector<uint8_t> refined;      // bit c: cell c refined
+  std::vector<double> U;             // 5 planes of 8n
+  OctIndex index;
+};
+
+struct DomainSpec {
+  int32_t lmin = 0, lmax = 0;
+  int32_t nbase[3] = {0, 0, 0};
+  int32_t bc[6] = {0, 0, 0, 0, 0, 0};
+  int32_t refine = 0;
+  double refine_param = 0.0;
+  int hbits0 = 0;                    // Hilbert bits per axis at lmin
+  int64_t ncell(int l, int a) const { return (int64_t)nbase[a] << (l - lmin); }
+  int64_t noct(int l, int a) const { return ncell(l, a) / 2; }
+};
+
+uint64_t hilbert3(int bits, uint32_t x, uint32_t y, uint32_t z);
+
+// Device-side description of one level, produced by the host builder.
+struct LevelTables {
+  int64_t n_oct = 0, n_ghost = 0;
+  int64_t n_leaf = 0;
+  int32_t n_tile = 0;
+  std::vector<int32_t> tab;          // n_tile * 64 ext indices, -1 = unused
+  std::vector<uint32_t> tflag;       // n_tile
+  std::vector<uint8_t> refined_ext;  // n_oct + n_ghost
+  std::vector<int32_t> child;        // 8 * n_oct, child oct at l+1 or -1
+  std::vector<int32_t> parent_cell;  // n_oct: cell index at l-1 (l > lmin)
+  std::vector<int64_t> gsrc;         // n_ghost * 7: (level_up << 48) | cell index
+  std::vector<int32_t> tile_box;     // batch only
+};
+
+// Builds the refined octree (refinement, neighbour rule, Hilbert order,
+// fill, restriction). Returns an error string or empty.
+std::string build_mesh(const DomainSpec& dom, const double* U_base, ry_fill_fn fill, void* user,
+                       std::vector<HostLevel>& levels);
+// Builds tile tables, ghost lists, child/parent maps for every level.
+std::string build_tables(const DomainSpec& dom, const std::vector<HostLevel>& levels,
+                         std::vector<LevelTables>& out);
+
+// ------------------------------------------------------------- kernels
+struct HydroArgs {
+  const double* U;            // current state (ext octs), 5 planes of 8*n_ext
+  double* Un;                 // next state
+  int64_t plane;              // 8 * n_ext
+  int32_t n_oct;              // real octs: ext index < n_oct
+  int32_t n_tile;
+  const int32_t* tab;
+  const uint32_t* tflag;
+  const uint8_t* refined;     // n_ext
+  const int32_t* child;       // 8 n_oct (nullptr when no finer level)
+  const double* reg_fine;     // registers of level l+1
+  double* reg_own;            // registers of level l (written when record_reg)
+  int32_t substep;
+  int32_t record_reg;
+  double gamma, rho_floor, p_floor;
+  const double* lam_dev;      // device lambda (per box when tile_box != nullptr)
+  double lam_host;            // used when lam_dev == nullptr
+  const int32_t* tile_box;
+  unsigned long long* smax;   // CFL epilogue slots (per box / per level), nullptr = off
+  unsigned long long* floors;
+  int32_t* err;
+  const int32_t* skip;        // device flag: skip this launch's work
+  unsigned int* queue;        // persistent mode: 8 per-XCD counters
+};
+
+struct GhostArgs {
+  const double* src[RY_MAX_LEVELS];   // current U of level l-1-k at index k
+  int64_t src_plane[RY_MAX_LEVELS];
+  const int64_t* gsrc;
+  int64_t n_ghost;
+  int64_t n_oct;
+  double* dst0;
+  double* dst1;
+  int64_t plane;
+  const int32_t* skip;
+};
+
+// launchers (kernels.hip)
+int launch_hydro(const HydroArgs& a, int precision, const ry_tuning& t, int num_cu, void* stream);
+int launch_ghost(const GhostArgs& a, void* stream);
+int launch_restrict(const double* Uf, int64_t plane_f, int64_t n_fine, const int32_t* parent_cell,
+                    double* Uc, int64_t plane_c, const int32_t* skip, void* stream);
+int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double gamma,
+               double rho_floor, double p_floor, unsigned long long* slot, int32_t* err, void* stream);
+struct FinalizeArgs {
+  const unsigned long long* smax;   // per level (AMR) or per box (batch)
+  int32_t nslot;
+  double cfl;
+  double dx[RY_MAX_LEVELS];        // AMR: dx of each level; batch: unused
+  const double* dx_box;            // batch: dx per box
+  int32_t lmin_shift_base;         // unused placeholder for alignment
+  double t_end;
+  double* t;                       // AMR: 1 value; batch: per box
+  double* lam;                     // AMR: 1 value; batch: per box
+  int32_t* skip;
+  int32_t* done;
+  int32_t* nstep;
+  unsigned long long* clear;       // slots to clear after reading
+  int32_t batch;
+};
+int launch_finalize(const FinalizeArgs& a, void* stream);
+int launch_zero_u32(unsigned int* p, int64_t n, void* stream);
+int launch_zero_u64(unsigned long long* p, int64_t n, void* stream);
+int launch_totals(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double vol,
+                  double* partial, int nblocks, void* stream);
+int launch_totals_final(const double* partial, int nparts, double* out, void* stream);
+int launch_copy(const double* src, double* dst, int64_t n, void* stream);
+int totals_blocks();
+int hydro_max_tiles_per_wg();
+
+}  // namespace ry

@@ -1,0 +1,109 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function
+include/ry.h declares, validates configurations before any device work, and
+its own host mesh builder / Hilbert curve agree bit-exactly with the
+oracle's (refinement maps and oct order are integer work)."""
+from __future__ import annotations
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.ryo import Oracle, hilbert_key as oracle_key
+from paper_2411_14631_amd import ry
+
+import cases
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ry.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(ry_[a-z_0-9]+)\s*\(", text))
+    return sorted(n for n in names if n not in ("ry_fill_fn",))
+
+
+def test_library_exports_every_header_function():
+    L = ry.lib()
+    declared = header_functions()
+    assert len(declared) >= 20
+    missing = [n for n in declared if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(ry.EXPORTS) == declared
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (dict(nbase=(30, 32, 32)), ry.RY_EINVAL),          # not a multiple of 4
+    (dict(level_min=6, level_max=5), ry.RY_EINVAL),
+    (dict(gamma=1.0), ry.RY_EINVAL),
+    (dict(cfl=0.0), ry.RY_EINVAL),
+    (dict(bc=(0, 1, 0, 0, 0, 0)), ry.RY_EINVAL),       # half-periodic pair
+    (dict(rho_floor=0.0), ry.RY_EINVAL),
+])
+def test_create_rejects_invalid_config(mutate, expect):
+    prob = W.uniform_state(8)
+    for k, v in mutate.items():
+        setattr(prob, k, v)
+    assert ry.create_status(prob) == expect
+
+
+def test_create_rejects_bad_precision():
+    with pytest.raises(KeyError):
+        ry.create_status(W.uniform_state(8), precision="fp16")
+
+
+@pytest.mark.parametrize("bits", [1, 2, 3, 5])
+def test_hilbert_keys_match_oracle(bits):
+    n = 1 << bits
+    rng = np.random.default_rng(bits)
+    pts = rng.integers(0, n, size=(400, 3)) if bits > 3 else np.stack(
+        np.meshgrid(*[np.arange(n)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    for x, y, z in pts:
+        assert ry.hilbert_key(bits, int(x), int(y), int(z)) == oracle_key(bits, int(x), int(y), int(z))
+
+
+def compare_mesh(prob):
+    m = ry.HostMesh(prob)
+    o = Oracle(prob)
+    total = 0
+    for lv in range(prob.level_min, prob.level_max + 1):
+        k, r, _ = m.level(lv)
+        ko, ro = o.mesh(lv)
+        np.testing.assert_array_equal(k, ko)
+        np.testing.assert_array_equal(r, ro)
+        total += len(k)
+    return total
+
+
+def test_mesh_bit_exact_amr_blob_periodic_and_outflow():
+    assert compare_mesh(cases.amr_blob()) > 100
+    assert compare_mesh(cases.amr_blob(bc=(W.BC_OUTFLOW,) * 6, centre=(0.1, 0.5, 0.5))) > 64
+
+
+def test_mesh_bit_exact_twolevel_theta_primary():
+    prob = W.twolevel(64, 0.70)
+    assert compare_mesh(prob) > 4096
+
+
+def test_mesh_bit_exact_gradient_literal_theta():
+    prob = W.twolevel(64, 0.1)
+    m = ry.HostMesh(prob)
+    k, _, _ = m.level(6)
+    assert len(k) > 0.9 * 32 ** 3      # theta = 0.1 refines almost everything
+    compare_mesh(prob)
+
+
+def test_mesh_empty_refinement():
+    prob = W.Problem("unref", 3, 5, (8, 8, 8), 1.4, W.uniform_state(8).U_base, refine=W.REFINE_MASS,
+                     refine_param=1e30, fill=lambda l, ijk: np.zeros((5, len(ijk))))
+    m = ry.HostMesh(prob)
+    assert len(m.level(4)[0]) == 0 and len(m.level(5)[0]) == 0
+
+
+def test_ghost_octs_only_on_refined_levels():
+    m = ry.HostMesh(cases.amr_blob())
+    assert m.level(3)[2] == 0
+    assert m.level(4)[2] > 0 and m.level(5)[2] > 0
