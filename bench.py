@@ -96,10 +96,8 @@ def run_uniform(precision, steps, warmup, tune):
                 tuning=tuning or h.tuning(), floors=h.floors())
 
 
-def run_zoom(precision, steps, tune):
-    import workloads as W
+def run_zoom(prob, precision, steps, tune):
     from paper_2411_14631_amd import Hydro
-    prob = W.zoom()
     t0 = time.perf_counter()
     h = Hydro(prob, precision)
     build_s = time.perf_counter() - t0
@@ -182,10 +180,12 @@ def main():
 
     zoom = None
     if not args.no_zoom:
+        import workloads as W
+        zprob = W.zoom()
         zoom = {}
         for prec in ("fp64", "mixed"):
             log(f"bench: zoom AMR {prec}")
-            z = run_zoom(prec, 3, tune)
+            z = run_zoom(zprob, prec, 3, tune)
             zoom[prec] = {"value": z["cups"] * 3 / z["dt"], "unit": "cell-updates/s",
                           "hbm_frac": round(BYTES_PER_CELL_UPDATE * z["cups"] * 3 / z["dt"] / 1e9 / HBM_PEAK_GBS, 4),
                           "cell_updates_per_coarse_step": z["cups"], "octs": z["noct"],

@@ -123,10 +123,12 @@ ry_status ry_batch_download(ry_ctx* ctx, int32_t box, double* U);
 /* Tuning of the hydro kernel launch (see ry_tuning fields).  Results in FP64
  * do not depend on the tuning. */
 typedef struct {
-  int32_t tiles_per_wg;   /* 1, 2 or 4 tiles (of 2x2x2 octs) per workgroup  */
-  int32_t persistent;     /* 0: one workgroup per tile group; 1: work queue */
-  int32_t waves_per_cu;   /* persistent grid size = CUs * waves_per_cu / tiles_per_wg */
-  int32_t batch;          /* tile groups popped per queue access            */
+  int32_t tiles_per_wg;   /* tiles (aligned 2x2x2 oct blocks) per workgroup: 1, 2 or 4      */
+  int32_t persistent;     /* 0: one workgroup per tile group; 1: work queue                 */
+  int32_t waves_per_cu;   /* persistent grid = CUs * waves_per_cu / waves per workgroup     */
+  int32_t batch;          /* tile groups popped per queue access                            */
+  int32_t waves_per_tile; /* 1, 2 or 4 wavefronts per tile (8, 16, 32 threads per oct);     */
+                          /* tiles_per_wg * waves_per_tile <= 4, FP64: tiles_per_wg <= 2    */
 } ry_tuning;
 ry_status ry_set_tuning(ry_ctx* ctx, const ry_tuning* t);
 ry_status ry_get_tuning(const ry_ctx* ctx, ry_tuning* t);

@@ -54,9 +54,12 @@ struct ry_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int num_cu = 256;
-  ry_tuning tune{1, 0, 4, 1};
+  ry_tuning tune{1, 0, 4, 1, 4};
   // device scalars
-  unsigned long long* d_smax = nullptr;   // per level / per box
+  double* d_smax = nullptr;               // max signal speed per level / per box
+  double* d_part = nullptr;               // per-tile (or per-block) partial maxima
+  int64_t* d_segoff = nullptr;            // tile offsets of levels / boxes in d_part
+  std::vector<int64_t> seg_off;           // host copy
   double* d_lam = nullptr;                // 1 / per box
   double* d_t = nullptr;                  // 1 / per box
   int32_t* d_flags = nullptr;             // [0]=skip [1]=done [2]=nstep [3]=err
@@ -209,7 +212,10 @@ ry_status init_common(ry_ctx* c) {
 }
 
 ry_status alloc_scalars(ry_ctx* c, int nslot) {
-  c->d_smax = static_cast<unsigned long long*>(dalloc(c, sizeof(unsigned long long) * nslot));
+  c->d_smax = static_cast<double*>(dalloc(c, sizeof(double) * nslot));
+  const int64_t npart = std::max<int64_t>(c->seg_off.back(), 1);
+  c->d_part = static_cast<double*>(dalloc(c, sizeof(double) * npart));
+  c->d_segoff = static_cast<int64_t*>(dalloc(c, sizeof(int64_t) * c->seg_off.size()));
   c->d_lam = static_cast<double*>(dalloc(c, sizeof(double) * nslot));
   c->d_t = static_cast<double*>(dalloc(c, sizeof(double) * nslot));
   c->d_flags = static_cast<int32_t*>(dalloc(c, sizeof(int32_t) * 8));
@@ -217,9 +223,12 @@ ry_status alloc_scalars(ry_ctx* c, int nslot) {
   c->d_queue = static_cast<unsigned int*>(dalloc(c, sizeof(unsigned int) * 8));
   c->d_partial = static_cast<double*>(dalloc(c, sizeof(double) * NVAR * totals_blocks()));
   c->d_tot = static_cast<double*>(dalloc(c, sizeof(double) * NVAR));
-  if (!c->d_smax || !c->d_lam || !c->d_t || !c->d_flags || !c->d_floors || !c->d_queue || !c->d_partial || !c->d_tot)
+  if (!c->d_smax || !c->d_lam || !c->d_t || !c->d_flags || !c->d_floors || !c->d_queue || !c->d_partial ||
+      !c->d_tot || !c->d_part || !c->d_segoff)
     return RY_ENOMEM;
-  HIPCHK(c, hipMemsetAsync(c->d_smax, 0, sizeof(unsigned long long) * nslot, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_segoff, c->seg_off.data(), sizeof(int64_t) * c->seg_off.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_smax, 0, sizeof(double) * nslot, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_lam, 0, sizeof(double) * nslot, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_t, 0, sizeof(double) * nslot, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_flags, 0, sizeof(int32_t) * 8, c->stream));
@@ -263,24 +272,33 @@ void time_collect(ry_ctx* c) {
 }
 
 // --- kernel enqueue helpers -------------------------------------------------
+ry_status enqueue_seg_max(ry_ctx* c) {
+  const int nseg = int(c->seg_off.size()) - 1;
+  if (launch_seg_max(c->d_part, c->d_segoff, nseg, c->d_smax, c->stream)) return fail(c, RY_EHIP, "seg_max kernel");
+  return RY_OK;
+}
+
+// Maximum signal speed of every level (box) from the current state.
 ry_status enqueue_cfl_all(ry_ctx* c) {
-  if (launch_zero_u64(c->d_smax, c->batch ? c->nbox : c->nlev, c->stream)) return fail(c, RY_EHIP, "zero kernel");
+  if (launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_part), c->seg_off.back(), c->stream))
+    return fail(c, RY_EHIP, "zero kernel");
   for (int k = 0; k < c->nlev; ++k) {
     DevLevel& L = c->lev[k];
     if (L.n_oct == 0) continue;
     if (c->batch) {
-      // one slot per box: reuse the CFL kernel per box range
       for (int b = 0; b < c->nbox; ++b) {
         const int64_t off = c->box_off[b] * 8;
         if (launch_cfl(L.U[L.cur] + off, L.plane(), c->box_noct[b], L.refined + c->box_off[b], c->cfg.gamma,
-                       c->cfg.rho_floor, c->cfg.p_floor, c->d_smax + b, err_ptr(c), c->stream))
+                       c->cfg.rho_floor, c->cfg.p_floor, c->d_part + c->seg_off[b], err_ptr(c), c->stream))
           return fail(c, RY_EHIP, "cfl kernel");
       }
     } else if (launch_cfl(L.U[L.cur], L.plane(), L.n_oct, L.refined, c->cfg.gamma, c->cfg.rho_floor,
-                          c->cfg.p_floor, c->d_smax + k, err_ptr(c), c->stream)) {
+                          c->cfg.p_floor, c->d_part + c->seg_off[k], err_ptr(c), c->stream)) {
       return fail(c, RY_EHIP, "cfl kernel");
     }
   }
+  ry_status s = enqueue_seg_max(c);
+  if (s) return s;
   c->slots_valid = true;
   return RY_OK;
 }
@@ -366,7 +384,7 @@ ry_status enqueue_level(ry_ctx* c, int l, int substep, bool last) {
   HydroArgs a = hydro_args(c, l, substep);
   a.lam_dev = c->d_lam;
   a.skip = skip_ptr(c);
-  a.smax = last ? c->d_smax + (l - c->cfg.level_min) : nullptr;
+  a.tile_smax = last ? c->d_part + c->seg_off[l - c->cfg.level_min] : nullptr;
   if ((s = enqueue_hydro(c, a))) return s;
   if (fine && (s = enqueue_restrict(c, l, skip_ptr(c)))) return s;
   DevLevel& L = c->lev[l - c->cfg.level_min];
@@ -386,8 +404,9 @@ ry_status enqueue_coarse_step(ry_ctx* c, double t_end) {
   f.skip = skip_ptr(c);
   f.done = done_ptr(c);
   f.nstep = nstep_ptr(c);
-  f.clear = c->d_smax;
   f.batch = 0;
+  ry_status s = enqueue_seg_max(c);
+  if (s) return s;
   if (launch_finalize(f, c->stream)) return fail(c, RY_EHIP, "finalize kernel");
   return enqueue_level(c, c->cfg.level_min, 0, true);
 }
@@ -496,6 +515,8 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
     free_all(c);
     return fail(c, RY_ENOMEM, "device allocation failed");
   }
+  c->seg_off.assign(1, 0);
+  for (int k = 0; k < c->nlev; ++k) c->seg_off.push_back(c->seg_off.back() + c->lev[k].n_tile);
   ry_status s = alloc_scalars(c, std::max(c->nlev, 1));
   if (s) {
     free_all(c);
@@ -529,12 +550,11 @@ ry_status ry_cfl_dt(ry_ctx* c, double* dt) {
   ry_status s = enqueue_cfl_all(c);
   if (s) return s;
   if ((s = sync_and_check(c))) return s;
-  std::vector<unsigned long long> sm(c->nlev);
-  HIPCHK(c, hipMemcpy(sm.data(), c->d_smax, sizeof(unsigned long long) * c->nlev, hipMemcpyDeviceToHost));
+  std::vector<double> sm(c->nlev);
+  HIPCHK(c, hipMemcpy(sm.data(), c->d_smax, sizeof(double) * c->nlev, hipMemcpyDeviceToHost));
   double best = INFINITY;
   for (int k = 0; k < c->nlev; ++k) {
-    double smax;
-    std::memcpy(&smax, &sm[k], sizeof smax);
+    const double smax = sm[k];
     if (!(smax > 0.0)) continue;
     const double dtl = c->cfg.cfl * level_dx(c, c->cfg.level_min + k) / smax;
     const double cand = std::ldexp(dtl, k);
@@ -565,7 +585,7 @@ ry_status ry_hydro_step(ry_ctx* c, int32_t level, double dt) {
   a.lam_dev = nullptr;
   a.lam_host = dt / level_dx(c, level);
   a.skip = nullptr;
-  a.smax = nullptr;
+  a.tile_smax = nullptr;
   if ((s = enqueue_hydro(c, a))) return s;
   if (fine && (s = enqueue_restrict(c, level, nullptr))) return s;
   c->lev[k].cur ^= 1;
@@ -693,6 +713,7 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
   c->nbox = nbox;
   c->tune.persistent = 1;
   c->tune.batch = 4;
+  c->tune.waves_per_cu = 16;
   ry_status s = init_common(c);
   if (s) {
     delete c;
@@ -714,6 +735,8 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
       return RY_EINVAL;
     }
     const LevelTables& t = T[0];
+    if (b == 0) c->seg_off.assign(1, 0);
+    c->seg_off.push_back(c->seg_off.back() + t.n_tile);
     c->box_off.push_back(off);
     c->box_noct.push_back(t.n_oct);
     c->box_dx.push_back(cfgs[b].boxlen / double(cfgs[b].nbase[0]));
@@ -780,8 +803,9 @@ static ry_status enqueue_batch_step(ry_ctx* c) {
   f.t = c->d_t;
   f.lam = c->d_lam;
   f.nstep = nstep_ptr(c);
-  f.clear = c->d_smax;
   f.batch = 1;
+  ry_status s0 = enqueue_seg_max(c);
+  if (s0) return s0;
   if (launch_finalize(f, c->stream)) return fail(c, RY_EHIP, "finalize kernel");
   HydroArgs a = hydro_args(c, c->cfg.level_min, 0);
   a.child = nullptr;
@@ -790,7 +814,7 @@ static ry_status enqueue_batch_step(ry_ctx* c) {
   a.record_reg = 0;
   a.lam_dev = c->d_lam;
   a.tile_box = L.tile_box;
-  a.smax = c->d_smax;
+  a.tile_smax = c->d_part;
   a.skip = nullptr;
   ry_status s = enqueue_hydro(c, a);
   if (s) return s;
@@ -857,6 +881,8 @@ ry_status ry_batch_download(ry_ctx* c, int32_t box, double* U) {
 ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
   if (!c || !t) return RY_EINVAL;
   if (t->tiles_per_wg != 1 && t->tiles_per_wg != 2 && t->tiles_per_wg != 4) return RY_EINVAL;
+  if (t->waves_per_tile != 1 && t->waves_per_tile != 2 && t->waves_per_tile != 4) return RY_EINVAL;
+  if (t->tiles_per_wg * t->waves_per_tile > 4) return RY_EINVAL;
   // FP64 tiles take 29 KB of LDS each: at most 2 per workgroup (64 KB limit)
   if (c->cfg.precision == RY_FP64 && t->tiles_per_wg > 2) return RY_EINVAL;
   if (t->persistent && (t->waves_per_cu < 1 || t->waves_per_cu > 32 || t->batch < 1 || t->batch > 64))
@@ -896,7 +922,7 @@ static ry_status time_tuning(ry_ctx* c, const ry_tuning& t, double* ms_out) {
       h.lam_host = 0.1;
       h.record_reg = 0;
       h.reg_own = nullptr;
-      h.smax = nullptr;
+      h.tile_smax = nullptr;
       h.floors = nullptr;
       h.err = nullptr;
       h.skip = nullptr;
@@ -923,11 +949,13 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
     if (s0) return s0;
   }
   std::vector<ry_tuning> cand;
-  for (int tpw : {1, 2, 4})
-    if (!(c->cfg.precision == RY_FP64 && tpw > 2)) cand.push_back({tpw, 0, 4, 1});
-  for (int tpw : {1, 2})
-    for (int w : {4, 8})
-      for (int bt : {1, 4}) cand.push_back({tpw, 1, w, bt});
+  const int max_tpw = (c->cfg.precision == RY_FP64) ? 2 : 4;
+  for (int wpt : {1, 2, 4})
+    for (int tpw : {1, 2, 4})
+      if (tpw <= max_tpw && tpw * wpt <= 4) cand.push_back({tpw, 0, 4, 1, wpt});
+  for (int wpt : {2, 4})
+    for (int w : {8, 16})
+      for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt});
   double best_ms = INFINITY;
   ry_tuning bt{};
   int n = 0;

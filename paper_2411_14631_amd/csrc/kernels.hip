@@ -25,12 +25,26 @@
 namespace ry {
 
 // ---------------------------------------------------------------------------
-// Stencil position tables (compile-time): positions s in [-2,5]^3 relative to
-// the tile's first cell, stored as (sx+2) + 8 (sy+2) + 64 (sz+2).
+// Tile geometry.  Stencil positions s in [-2,5]^3 relative to the tile's
+// first cell; LDS boxes are padded (strides WSY/WSZ, PSY/PSZ) so that the
+// three face orientations of phase C spread over the LDS banks.
 // ---------------------------------------------------------------------------
+constexpr int WSY = 8, WSZ = 68, WSIZE = 7 + 7 * WSY + 7 * WSZ + 1;   // primitives on [-2,5]^3
+constexpr int PSY = 6, PSZ = 40, PSIZE = 5 + 5 * PSY + 5 * PSZ + 1;   // predictions on [-1,4]^3
+constexpr int NPOS_A = 304;   // positions whose primitives are needed
+constexpr int NPOS_B = 160;   // positions that get a predicted state (core + one layer per face)
+constexpr int NFACE = 240;    // 3 directions x 5 planes x 16
+__host__ __device__ constexpr int widx(int x, int y, int z) { return (x + 2) + WSY * (y + 2) + WSZ * (z + 2); }
+__host__ __device__ constexpr int pidx(int x, int y, int z) { return (x + 1) + PSY * (y + 1) + PSZ * (z + 1); }
+
+// Per-item constants of the three phases, computed at compile time:
+//  a[i]: bits 0-9 LDS index, 10-15 oct-table slot, 16-18 in-oct cell, 19-27 raw (x+2)+8(y+2)+64(z+2)
+//  b[i]: bits 0-9 LDS index of W, 10-17 LDS index of Wt
+//  f[i]: bits 0-9 W index of the face's lower cell, 10-17 its Wt index, 18-19 direction
 struct StencilTables {
-  uint16_t a[304];   // positions whose primitives are needed
-  uint16_t b[160];   // positions that get a predicted state
+  uint32_t a[NPOS_A];
+  uint32_t b[NPOS_B];
+  uint32_t f[NFACE];
 };
 
 constexpr StencilTables make_tables() {
@@ -42,65 +56,100 @@ constexpr StencilTables make_tables() {
         const int ox = (x < 0 || x > 3), oy = (y < 0 || y > 3), oz = (z < 0 || z > 3);
         const int nout = ox + oy + oz;
         const bool ex = (x == -1 || x == 4), ey = (y == -1 || y == 4), ez = (z == -1 || z == 4);
-        bool needA = (nout <= 1);
-        if (nout == 2) needA = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
-        bool needB = (nout == 0) || (nout == 1 && (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true));
-        const uint16_t idx = uint16_t((x + 2) + 8 * (y + 2) + 64 * (z + 2));
-        if (needA) t.a[na++] = idx;
-        if (needB) t.b[nb++] = idx;
+        const bool edges = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
+        const bool needA = (nout <= 1) || (nout == 2 && edges);
+        const bool needB = (nout == 0) || (nout == 1 && edges);
+        const int slot = ((x >> 1) + 1) + 4 * ((y >> 1) + 1) + 16 * ((z >> 1) + 1);
+        const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+        const int raw = (x + 2) + 8 * (y + 2) + 64 * (z + 2);
+        if (needA) t.a[na++] = uint32_t(widx(x, y, z) | (slot << 10) | (cb << 16) | (raw << 19));
+        if (needB) t.b[nb++] = uint32_t(widx(x, y, z) | (pidx(x, y, z) << 10));
       }
+  for (int f = 0; f < NFACE; ++f) {
+    const int d = f / 80, rem = f - 80 * d;
+    const int pl = (rem >> 4) - 1, ta = rem & 3, tb = (rem >> 2) & 3;
+    const int cx = (d == 0) ? pl : ta;
+    const int cy = (d == 0) ? ta : ((d == 1) ? pl : tb);
+    const int cz = (d == 2) ? pl : tb;
+    t.f[f] = uint32_t(widx(cx, cy, cz) | (pidx(cx, cy, cz) << 10) | (d << 18));
+  }
   return t;
 }
 __constant__ StencilTables c_st = make_tables();
-
-static_assert(make_tables().a[303] != 0, "stencil table A must hold 304 positions");
+static_assert(make_tables().a[NPOS_A - 1] != 0 && make_tables().b[NPOS_B - 1] != 0, "stencil tables");
+static_assert(WSIZE <= 1024 && PSIZE <= 256, "LDS indices must fit the table fields");
 
 template <typename Real>
 struct TileLDS {
-  Real W[NVAR][512];      // primitives on the padded 8^3 stencil; reused for fluxes
-  Real Wt[NVAR][216];     // predicted states on the padded 6^3 box [-1,4]^3
+  Real W[NVAR][WSIZE];    // primitives on the padded [-2,5]^3 stencil; reused for fluxes
+  Real Wt[NVAR][PSIZE];   // predicted states on the [-1,4]^3 box
   int32_t tab[TILE_TAB];  // ext oct index of the 4x4x4 oct neighbourhood
   uint8_t ref[TILE_TAB];  // refined-cell bytes of those octs
 };
-static_assert(sizeof(double) * NVAR * 240 <= sizeof(float) * NVAR * 512, "flux alias");
+static_assert(sizeof(double) * NVAR * NFACE <= sizeof(float) * NVAR * WSIZE, "flux alias");
 
 // ---------------------------------------------------------------------------
 // Scalar helpers.
 // ---------------------------------------------------------------------------
-template <typename Real>
-__device__ __forceinline__ Real mmod(Real a, Real b) {
-  // MinMod, sign-test form
-  Real m = (a < b) ? a : b;
-  Real M = (a > b) ? a : b;
-  return (a > Real(0) && b > Real(0)) ? m : ((a < Real(0) && b < Real(0)) ? M : Real(0));
+// MinMod: min(a,b) if both > 0, max(a,b) if both < 0, else 0 -- evaluated
+// without branches as copysign(max(0, min(|a|, sign(a) b)), a).
+__device__ __forceinline__ double mmod(double a, double b) {
+  const long long sa = __double_as_longlong(a) & (long long)0x8000000000000000ull;
+  const double bs = __longlong_as_double(__double_as_longlong(b) ^ sa);
+  return copysign(fmax(fmin(fabs(a), bs), 0.0), a);
+}
+__device__ __forceinline__ float mmod(float a, float b) {
+  const int sa = __float_as_int(a) & int(0x80000000u);
+  const float bs = __int_as_float(__float_as_int(b) ^ sa);
+  return copysignf(fmaxf(fminf(fabsf(a), bs), 0.0f), a);
 }
 
-template <typename Real> __device__ __forceinline__ Real fdiv(Real a, Real b);
-template <> __device__ __forceinline__ double fdiv<double>(double a, double b) { return a / b; }
-template <> __device__ __forceinline__ float fdiv<float>(float a, float b) {
-  return a * __builtin_amdgcn_rcpf(b);
+// Reciprocal and quotient: the hardware reciprocal refined by two Newton
+// steps and a residual correction (operands here are normal numbers).
+__device__ __forceinline__ double rcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  return fma(fma(-b, r, 1.0), r, r);
 }
-template <typename Real> __device__ __forceinline__ Real fsqrt(Real a);
-template <> __device__ __forceinline__ double fsqrt<double>(double a) { return sqrt(a); }
-template <> __device__ __forceinline__ float fsqrt<float>(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ float rcp(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qdiv(double a, double b) {
+  const double r = rcp(b);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// Square root for wave-speed estimates: x * rsq(x) refined by two Newton
+// steps on the root (the raw hardware square root is far from FP64 accurate).
+__device__ __forceinline__ double esqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y;
+  const double hy = 0.5 * y;
+  s = fma(fma(-s, s, x), hy, s);
+  return fma(fma(-s, s, x), hy, s);
+}
+__device__ __forceinline__ float esqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Primitive variables (FP64 in both forms) with floors.
+// Primitive variables (FP64 in both forms) with floors; nfl counts floor
+// activations.
 __device__ __forceinline__ void cons2prim(const double U[NVAR], double W[NVAR], double g, double rf, double pf,
                                           int& nfl) {
-  double rho = U[0];
-  if (rho < rf) { rho = rf; ++nfl; }
-  const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / rho;
-  double p = (g - 1.0) * (U[4] - ke);
-  if (p < pf) { p = pf; ++nfl; }
+  const bool lo_r = U[0] < rf;
+  const double rho = lo_r ? rf : U[0];
+  const double ir = rcp(rho);
+  const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir;
+  const double p0 = (g - 1.0) * (U[4] - ke);
+  const bool lo_p = p0 < pf;
+  nfl += int(lo_r) + int(lo_p);
   W[0] = rho;
-  W[1] = U[1] / rho;
-  W[2] = U[2] / rho;
-  W[3] = U[3] / rho;
-  W[4] = p;
+  W[1] = U[1] * ir;
+  W[2] = U[2] * ir;
+  W[3] = U[3] * ir;
+  W[4] = lo_p ? pf : p0;
 }
 
 // CFL signal speed |u|+|v|+|w|+3c of a conserved state, in the same IEEE
-// operations as the definition (no contraction), so dt is reproducible.
+// operations as the definition (correctly rounded division and square root,
+// no contraction), so dt is reproducible.
 __device__ __forceinline__ double signal_speed(const double U[NVAR], double g, double rf, double pf) {
 #pragma clang fp contract(off)
   double rho = U[0];
@@ -115,39 +164,35 @@ __device__ __forceinline__ double signal_speed(const double U[NVAR], double g, d
 
 // HLLC flux in the face-normal frame: (r, u, a, b, p) = density, normal and
 // two tangential velocities, pressure of the left / right face state.  The
-// star state is formed only for the side the branch selects.  Output Fn in
-// the same frame (mass, normal momentum, tangential momenta, energy).
+// branch picks a side K (L when S_L >= 0 or S* >= 0, else R) and whether the
+// star state of K applies; only that side's star state is formed.
 template <typename Real>
 __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real pl, Real rr, Real ur, Real ar,
-                                       Real br, Real pr, Real g, Real Fn[5]) {
-  const Real cl = fsqrt<Real>(fdiv<Real>(g * pl, rl));
-  const Real cr = fsqrt<Real>(fdiv<Real>(g * pr, rr));
+                                       Real br, Real pr, Real g, Real igm1, Real Fn[5]) {
+  const Real cl = esqrt(g * pl * rcp(rl));
+  const Real cr = esqrt(g * pr * rcp(rr));
   const Real SL = fmin(ul - cl, ur - cr);
   const Real SR = fmax(ul + cl, ur + cr);
   const Real num = pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur);
   const Real den = rl * (SL - ul) - rr * (SR - ur);
-  const Real Ss = fdiv<Real>(num, den);
+  const Real Ss = qdiv(num, den);
   const bool useL = (SL >= Real(0)) || (Ss >= Real(0));
   const Real rK = useL ? rl : rr, uK = useL ? ul : ur, aK = useL ? al : ar, bK = useL ? bl : br;
   const Real pK = useL ? pl : pr, SK = useL ? SL : SR;
   const bool star = useL ? !(SL >= Real(0)) : (SR > Real(0));
-  const Real EK = fdiv<Real>(pK, g - Real(1)) + Real(0.5) * rK * (uK * uK + aK * aK + bK * bK);
+  const Real EK = pK * igm1 + Real(0.5) * rK * (uK * uK + aK * aK + bK * bK);
   const Real mK = rK * uK;
-  Fn[0] = mK;
-  Fn[1] = mK * uK + pK;
-  Fn[2] = mK * aK;
-  Fn[3] = mK * bK;
-  Fn[4] = (EK + pK) * uK;
-  if (star) {
-    const Real r = (SK - uK) / (SK - Ss);   // true division: r == 1 when S* == u_K
-    const Real q = SK - uK;
-    const Real Es = EK + rK * (Ss - uK) * (Ss + fdiv<Real>(pK, rK * q));
-    Fn[0] = Fn[0] + SK * (r * rK - rK);
-    Fn[1] = Fn[1] + SK * (r * (rK * Ss) - mK);
-    Fn[2] = Fn[2] + SK * (r * (rK * aK) - rK * aK);
-    Fn[3] = Fn[3] + SK * (r * (rK * bK) - rK * bK);
-    Fn[4] = Fn[4] + SK * (r * Es - EK);
-  }
+  const Real q = SK - uK;
+  const Real dq = SK - Ss;
+  // r = q / dq, exactly 1 when S* == u_K (stationary contacts stay exact)
+  const Real r = (q == dq) ? Real(1) : qdiv(q, dq);
+  const Real Es = EK + rK * (Ss - uK) * (Ss + qdiv(pK, rK * q));
+  const Real w = star ? SK : Real(0);
+  Fn[0] = mK + w * (r * rK - rK);
+  Fn[1] = (mK * uK + pK) + w * (r * (rK * Ss) - mK);
+  Fn[2] = mK * aK + w * (r * (rK * aK) - rK * aK);
+  Fn[3] = mK * bK + w * (r * (rK * bK) - rK * bK);
+  Fn[4] = (EK + pK) * uK + w * (r * Es - EK);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -171,42 +216,51 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 }
 
 // ---------------------------------------------------------------------------
-// The per-tile hydro update.
+// The per-tile hydro update.  NT = threads cooperating on one tile (64, 128
+// or 256: 8, 16 or 32 threads per oct).  `active` is uniform over the NT
+// threads; an inactive group only keeps the workgroup's barrier count.
 // ---------------------------------------------------------------------------
-template <typename Real>
-__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int lane, bool active) {
-  // `active` is wave-uniform; an inactive wave only keeps the barrier count
+template <typename Real, int NT>
+__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int tid, bool active) {
+  const int lane = tid & 63;
   const double g = A.gamma, rf = A.rho_floor, pf = A.p_floor;
   const int64_t P = A.plane;
   int nfl = 0;
-  const uint32_t fl = A.tflag[tile];
-  const int box = A.tile_box ? A.tile_box[tile] : 0;
+  const uint32_t fl = active ? A.tflag[tile] : 0u;
+  const int box = (active && A.tile_box) ? A.tile_box[tile] : 0;
   const double lam = A.lam_dev ? A.lam_dev[box] : A.lam_host;
   const Real h = Real(0.5 * lam);
+  const Real igm1 = Real(1.0 / (g - 1.0));
 
   // --- phase 0: the tile's oct table and refined bytes
-  if (active) {
-    const int32_t e = A.tab[size_t(tile) * TILE_TAB + lane];
-    S.tab[lane] = e;
-    S.ref[lane] = (e >= 0) ? A.refined[e] : uint8_t(0);
+  if (active && tid < TILE_TAB) {
+    const int32_t e = A.tab[size_t(tile) * TILE_TAB + tid];
+    S.tab[tid] = e;
+    S.ref[tid] = (e >= 0) ? A.refined[e] : uint8_t(0);
   }
   __syncthreads();
 
   // --- phase A: gather + primitives
-  for (int i = lane; active && i < 304; i += 64) {
-    const int iw = c_st.a[i];
-    int sx = (iw & 7) - 2, sy = ((iw >> 3) & 7) - 2, sz = (iw >> 6) - 2;
-    if ((fl & CL_LOX) && sx < 0) sx = 0;
-    if ((fl & CL_HIX) && sx > 3) sx = 3;
-    if ((fl & CL_LOY) && sy < 0) sy = 0;
-    if ((fl & CL_HIY) && sy > 3) sy = 3;
-    if ((fl & CL_LOZ) && sz < 0) sz = 0;
-    if ((fl & CL_HIZ) && sz > 3) sz = 3;
-    const int t = ((sx >> 1) + 1) + 4 * ((sy >> 1) + 1) + 16 * ((sz >> 1) + 1);
-    const int32_t e = S.tab[t];
+  for (int i = tid; active && i < NPOS_A; i += NT) {
+    const uint32_t ent = c_st.a[i];
+    int slot = int((ent >> 10) & 63u), cb = int((ent >> 16) & 7u);
+    if (fl) {
+      // outflow faces: clamp the position into the domain (zero gradient)
+      const int raw = int(ent >> 19);
+      int sx = (raw & 7) - 2, sy = ((raw >> 3) & 7) - 2, sz = (raw >> 6) - 2;
+      if ((fl & CL_LOX) && sx < 0) sx = 0;
+      if ((fl & CL_HIX) && sx > 3) sx = 3;
+      if ((fl & CL_LOY) && sy < 0) sy = 0;
+      if ((fl & CL_HIY) && sy > 3) sy = 3;
+      if ((fl & CL_LOZ) && sz < 0) sz = 0;
+      if ((fl & CL_HIZ) && sz > 3) sz = 3;
+      slot = ((sx >> 1) + 1) + 4 * ((sy >> 1) + 1) + 16 * ((sz >> 1) + 1);
+      cb = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
+    }
+    const int32_t e = S.tab[slot];
     double U[NVAR];
     if (e >= 0) {
-      const int64_t cell = int64_t(e) * 8 + ((sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2));
+      const int64_t cell = int64_t(e) * 8 + cb;
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) U[v] = A.U[v * P + cell];
     } else {
@@ -214,26 +268,26 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int l
     }
     double W[NVAR];
     cons2prim(U, W, g, rf, pf, nfl);
+    const int iw = int(ent & 1023u);
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) S.W[v][iw] = Real(W[v]);
   }
   __syncthreads();
 
   // --- phase B: slopes + predictor
-  for (int i = lane; active && i < 160; i += 64) {
-    const int iw = c_st.b[i];
-    const int sx = (iw & 7) - 2, sy = ((iw >> 3) & 7) - 2, sz = (iw >> 6) - 2;
+  for (int i = tid; active && i < NPOS_B; i += NT) {
+    const uint32_t ent = c_st.b[i];
+    const int iw = int(ent & 1023u), ip = int(ent >> 10);
     Real W0[NVAR], D[3][NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) W0[v] = S.W[v][iw];
-    const int st[3] = {1, 8, 64};
+    constexpr int st[3] = {1, WSY, WSZ};
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v)
-        D[d][v] = mmod<Real>(W0[v] - S.W[v][iw - st[d]], S.W[v][iw + st[d]] - W0[v]);
+      for (int v = 0; v < NVAR; ++v) D[d][v] = mmod(W0[v] - S.W[v][iw - st[d]], S.W[v][iw + st[d]] - W0[v]);
     const Real r = W0[0], u = W0[1], vv = W0[2], w = W0[3], p = W0[4];
-    const Real ir = fdiv<Real>(Real(1), r);
+    const Real ir = rcp(r);
     const Real gg = Real(g);
     Real Wt[NVAR];
     Wt[0] = r - h * (u * D[0][0] + r * D[0][1] + vv * D[1][0] + r * D[1][2] + w * D[2][0] + r * D[2][3]);
@@ -241,50 +295,43 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int l
     Wt[2] = vv - h * (u * D[0][2] + vv * D[1][2] + w * D[2][2] + D[1][4] * ir);
     Wt[3] = w - h * (u * D[0][3] + vv * D[1][3] + w * D[2][3] + D[2][4] * ir);
     Wt[4] = p - h * (u * D[0][4] + vv * D[1][4] + w * D[2][4] + gg * p * (D[0][1] + D[1][2] + D[2][3]));
-    const int ip = (sx + 1) + 6 * (sy + 1) + 36 * (sz + 1);
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) S.Wt[v][ip] = Wt[v];
   }
   __syncthreads();
 
   // --- phase C: face fluxes (kept in registers, then written over W)
-  double Fr[4][NVAR];
+  constexpr int NR = (NFACE + NT - 1) / NT;
+  double Fr[NR][NVAR];
 #pragma unroll
-  for (int rnd = 0; rnd < 4; ++rnd) {
-    const int f = lane + 64 * rnd;
-    if (active && f < 240) {
-      const int d = f / 80;
-      const int rem = f - 80 * d;
-      const int pl_ = (rem >> 4) - 1, ta = rem & 3, tb = (rem >> 2) & 3;
-      // lower cell of the face: coordinate pl_ along d, (ta, tb) along the
-      // tangential axes in increasing order
-      const int cx = (d == 0) ? pl_ : ta;
-      const int cy = (d == 0) ? ta : ((d == 1) ? pl_ : tb);
-      const int cz = (d == 2) ? pl_ : tb;
-      const int stw = (d == 0) ? 1 : ((d == 1) ? 8 : 64);
-      const int stp = (d == 0) ? 1 : ((d == 1) ? 6 : 36);
-      const int iwA = (cx + 2) + 8 * (cy + 2) + 64 * (cz + 2);
-      const int ipA = (cx + 1) + 6 * (cy + 1) + 36 * (cz + 1);
+  for (int rnd = 0; rnd < NR; ++rnd) {
+    const int f = tid + NT * rnd;
+    if (active && f < NFACE) {
+      const uint32_t ent = c_st.f[f];
+      const int iwA = int(ent & 1023u), ipA = int((ent >> 10) & 255u), d = int(ent >> 18);
+      const int stw = (d == 0) ? 1 : ((d == 1) ? WSY : WSZ);
+      const int stp = (d == 0) ? 1 : ((d == 1) ? PSY : PSZ);
       Real WL[NVAR], WR[NVAR];
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
         const Real wam = S.W[v][iwA - stw], wa = S.W[v][iwA], wb = S.W[v][iwA + stw], wbp = S.W[v][iwA + 2 * stw];
-        const Real da = mmod<Real>(wa - wam, wb - wa);
-        const Real db = mmod<Real>(wb - wa, wbp - wb);
+        const Real da = mmod(wa - wam, wb - wa);
+        const Real db = mmod(wb - wa, wbp - wb);
         WL[v] = S.Wt[v][ipA] + Real(0.5) * da;
         WR[v] = S.Wt[v][ipA + stp] - Real(0.5) * db;
       }
       const Real rfr = Real(rf), pfr = Real(pf);
-      if (WL[0] < rfr) { WL[0] = rfr; ++nfl; }
-      if (WR[0] < rfr) { WR[0] = rfr; ++nfl; }
-      if (WL[4] < pfr) { WL[4] = pfr; ++nfl; }
-      if (WR[4] < pfr) { WR[4] = pfr; ++nfl; }
+      nfl += int(WL[0] < rfr) + int(WR[0] < rfr) + int(WL[4] < pfr) + int(WR[4] < pfr);
+      WL[0] = (WL[0] < rfr) ? rfr : WL[0];
+      WR[0] = (WR[0] < rfr) ? rfr : WR[0];
+      WL[4] = (WL[4] < pfr) ? pfr : WL[4];
+      WR[4] = (WR[4] < pfr) ? pfr : WR[4];
       const Real unl = (d == 0) ? WL[1] : ((d == 1) ? WL[2] : WL[3]);
       const Real unr = (d == 0) ? WR[1] : ((d == 1) ? WR[2] : WR[3]);
       const Real t1l = (d == 0) ? WL[2] : WL[1], t1r = (d == 0) ? WR[2] : WR[1];
       const Real t2l = (d == 2) ? WL[2] : WL[3], t2r = (d == 2) ? WR[2] : WR[3];
       Real Fn[5];
-      hllc_n<Real>(WL[0], unl, t1l, t2l, WL[4], WR[0], unr, t1r, t2r, WR[4], Real(g), Fn);
+      hllc_n<Real>(WL[0], unl, t1l, t2l, WL[4], WR[0], unr, t1r, t2r, WR[4], Real(g), igm1, Fn);
       Fr[rnd][0] = double(Fn[0]);
       Fr[rnd][1] = double((d == 0) ? Fn[1] : Fn[2]);
       Fr[rnd][2] = double((d == 1) ? Fn[1] : ((d == 0) ? Fn[2] : Fn[3]));
@@ -293,19 +340,18 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int l
     }
   }
   __syncthreads();
-  double* SF = reinterpret_cast<double*>(&S.W[0][0]);   // [5][240]
+  double* SF = reinterpret_cast<double*>(&S.W[0][0]);   // [5][NFACE]
 #pragma unroll
-  for (int rnd = 0; rnd < 4; ++rnd) {
-    const int f = lane + 64 * rnd;
-    if (active && f < 240) {
+  for (int rnd = 0; rnd < NR; ++rnd) {
+    const int f = tid + NT * rnd;
+    if (active && f < NFACE) {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) SF[v * 240 + f] = Fr[rnd][v];
+      for (int v = 0; v < NVAR; ++v) SF[v * NFACE + f] = Fr[rnd][v];
     }
   }
   __syncthreads();
-
-  // --- phase D: update of the cell owned by this lane
-  {
+  // --- phase D: the first wavefront updates the tile's 64 cells
+  if (tid < 64) {
     const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
     const int ts = ((cx >> 1) + 1) + 4 * ((cy >> 1) + 1) + 16 * ((cz >> 1) + 1);
     const int32_t e = active ? S.tab[ts] : -1;
@@ -323,8 +369,8 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int l
         double Fm[NVAR], Fp[NVAR];
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-          Fm[v] = SF[v * 240 + fm];
-          Fp[v] = SF[v * 240 + fp];
+          Fm[v] = SF[v * NFACE + fm];
+          Fp[v] = SF[v * NFACE + fp];
         }
         if (A.child) {
           // a refined neighbour across a face: use its child oct's register
@@ -360,7 +406,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int l
         Un[v] = A.U[v * P + cell] + lam * acc[v];
         A.Un[v * P + cell] = Un[v];
       }
-      if (A.smax || A.err) {
+      if (A.tile_smax || A.err) {
         s = signal_speed(Un, g, rf, pf);
         const bool bad = !(isfinite(Un[0]) && isfinite(Un[1]) && isfinite(Un[2]) && isfinite(Un[3]) &&
                            isfinite(Un[4])) || !(Un[0] > 0.0) || !(Un[4] > 0.0) || !isfinite(s);
@@ -370,15 +416,18 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int l
         }
       }
     }
-    if (active && A.smax) {
+    if (active && A.tile_smax) {
+      // one partial per tile (no same-address atomics); reduced per level /
+      // box by the segmented max kernel before the next time step
       const double m = wave_max(s);
-      if (lane == 0 && m > 0.0) atomicMax(&A.smax[box], (unsigned long long)__double_as_longlong(m));
+      if (lane == 0) A.tile_smax[tile] = m;
     }
   }
 
   // --- fine-side registers: q_s = (f1 + f2) + (f3 + f4) on coarse-fine faces
-  if (active && A.record_reg && lane < 48) {
-    const int b = lane / 6, face = lane - 6 * (lane / 6);
+  const int rt = (NT > 64) ? tid - 64 : tid;   // a second wavefront, when there is one
+  if (active && A.record_reg && rt >= 0 && rt < 48) {
+    const int b = rt / 6, face = rt - 6 * (rt / 6);
     const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
     const int tb_ = (bx + 1) + 4 * (by + 1) + 16 * (bz + 1);
     const int32_t eb = S.tab[tb_];
@@ -408,7 +457,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int l
 #pragma unroll
         for (int v = 0; v < NVAR; ++v)
           q[2 * v + A.substep] =
-              (SF[v * 240 + fi[0]] + SF[v * 240 + fi[1]]) + (SF[v * 240 + fi[2]] + SF[v * 240 + fi[3]]);
+              (SF[v * NFACE + fi[0]] + SF[v * NFACE + fi[1]]) + (SF[v * NFACE + fi[2]] + SF[v * NFACE + fi[3]]);
       }
     }
   }
@@ -419,28 +468,30 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int l
   __syncthreads();
 }
 
-template <typename Real, int TPW>
-__global__ __launch_bounds__(64 * TPW) void hydro_kernel(HydroArgs A) {
+template <typename Real, int TPW, int WPT>
+__global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel(HydroArgs A) {
+  constexpr int NT = 64 * WPT;
   __shared__ TileLDS<Real> S[TPW];
   if (A.skip && *A.skip) return;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = threadIdx.x / NT, tid = threadIdx.x % NT;
   const int ngroups = (A.n_tile + TPW - 1) / TPW;
   const int grp = xcd_remap(blockIdx.x, gridDim.x);
   if (grp >= ngroups) return;
   const int tile = grp * TPW + w;
-  hydro_tile<Real>(A, tile < A.n_tile ? tile : 0, S[w], lane, tile < A.n_tile);
+  hydro_tile<Real, NT>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
 }
 
 // Persistent variant: workgroups pop groups of tiles from 8 per-XCD queues
 // (one contiguous slice of the Hilbert-ordered tile list per XCD; a
 // workgroup whose own queue is empty takes from the next one).  Every
 // workgroup exits once all 8 queues are exhausted.
-template <typename Real, int TPW>
-__global__ __launch_bounds__(64 * TPW) void hydro_kernel_persistent(HydroArgs A, int batch) {
+template <typename Real, int TPW, int WPT>
+__global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel_persistent(HydroArgs A, int batch) {
+  constexpr int NT = 64 * WPT;
   __shared__ TileLDS<Real> S[TPW];
   __shared__ int s_item;
   if (A.skip && *A.skip) return;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = threadIdx.x / NT, tid = threadIdx.x % NT;
   const int ngroups = (A.n_tile + TPW - 1) / TPW;
   const int nitems = (ngroups + batch - 1) / batch;
   const int q = nitems >> 3, r = nitems & 7;
@@ -469,24 +520,25 @@ __global__ __launch_bounds__(64 * TPW) void hydro_kernel_persistent(HydroArgs A,
       const int grp = item * batch + j;
       if (grp >= ngroups) break;
       const int tile = grp * TPW + w;
-      hydro_tile<Real>(A, tile < A.n_tile ? tile : 0, S[w], lane, tile < A.n_tile);
+      hydro_tile<Real, NT>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
     }
   }
 }
 
-template <typename Real, int TPW>
+template <typename Real, int TPW, int WPT>
 static int launch_hydro_t(const HydroArgs& a, const ry_tuning& t, int num_cu, hipStream_t s) {
   const int ngroups = (a.n_tile + TPW - 1) / TPW;
   if (ngroups == 0) return 0;
   if (!t.persistent) {
-    hipLaunchKernelGGL((hydro_kernel<Real, TPW>), dim3(ngroups), dim3(64 * TPW), 0, s, a);
+    hipLaunchKernelGGL((hydro_kernel<Real, TPW, WPT>), dim3(ngroups), dim3(64 * WPT * TPW), 0, s, a);
   } else {
     const int batch = t.batch > 0 ? t.batch : 1;
     const int nitems = (ngroups + batch - 1) / batch;
-    int grid = num_cu * (t.waves_per_cu > 0 ? t.waves_per_cu : 4) / TPW;
+    int grid = num_cu * (t.waves_per_cu > 0 ? t.waves_per_cu : 4) / (TPW * WPT);
     if (grid < 8) grid = 8;
     if (grid > nitems) grid = ((nitems + 7) / 8) * 8;
-    hipLaunchKernelGGL((hydro_kernel_persistent<Real, TPW>), dim3(grid), dim3(64 * TPW), 0, s, a, batch);
+    hipLaunchKernelGGL((hydro_kernel_persistent<Real, TPW, WPT>), dim3(grid), dim3(64 * WPT * TPW), 0, s, a,
+                       batch);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -495,15 +547,26 @@ int hydro_max_tiles_per_wg() { return 4; }
 
 int launch_hydro(const HydroArgs& a, int precision, const ry_tuning& t, int num_cu, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  const int tpw = t.tiles_per_wg;
+  const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
   if (precision == RY_MIXED) {
-    if (tpw == 1) return launch_hydro_t<float, 1>(a, t, num_cu, s);
-    if (tpw == 2) return launch_hydro_t<float, 2>(a, t, num_cu, s);
-    return launch_hydro_t<float, 4>(a, t, num_cu, s);
+    switch (key) {
+      case 11: return launch_hydro_t<float, 1, 1>(a, t, num_cu, s);
+      case 21: return launch_hydro_t<float, 2, 1>(a, t, num_cu, s);
+      case 41: return launch_hydro_t<float, 4, 1>(a, t, num_cu, s);
+      case 12: return launch_hydro_t<float, 1, 2>(a, t, num_cu, s);
+      case 22: return launch_hydro_t<float, 2, 2>(a, t, num_cu, s);
+      case 14: return launch_hydro_t<float, 1, 4>(a, t, num_cu, s);
+      default: return -1;
+    }
   }
-  if (tpw == 1) return launch_hydro_t<double, 1>(a, t, num_cu, s);
-  if (tpw == 2) return launch_hydro_t<double, 2>(a, t, num_cu, s);
-  return launch_hydro_t<double, 4>(a, t, num_cu, s);
+  switch (key) {
+    case 11: return launch_hydro_t<double, 1, 1>(a, t, num_cu, s);
+    case 21: return launch_hydro_t<double, 2, 1>(a, t, num_cu, s);
+    case 12: return launch_hydro_t<double, 1, 2>(a, t, num_cu, s);
+    case 22: return launch_hydro_t<double, 2, 2>(a, t, num_cu, s);
+    case 14: return launch_hydro_t<double, 1, 4>(a, t, num_cu, s);
+    default: return -1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -531,9 +594,9 @@ __global__ void ghost_kernel(GhostArgs A) {
       val[k] = A.src[up][v * A.src_plane[up] + cell];
     }
     const double q = val[0];
-    const double mx = mmod<double>(q - val[1], val[2] - q);
-    const double my = mmod<double>(q - val[3], val[4] - q);
-    const double mz = mmod<double>(q - val[5], val[6] - q);
+    const double mx = mmod(q - val[1], val[2] - q);
+    const double my = mmod(q - val[3], val[4] - q);
+    const double mz = mmod(q - val[5], val[6] - q);
     const double out = q + (sx * mx + sy * my + sz * mz);
     A.dst0[v * A.plane + dst] = out;
     A.dst1[v * A.plane + dst] = out;
@@ -572,11 +635,13 @@ int launch_restrict(const double* Uf, int64_t pf, int64_t nf, const int32_t* par
 }
 
 // ---------------------------------------------------------------------------
-// CFL: max signal speed over the leaf cells of a level -> atomicMax slot.
+// CFL: max signal speed over the leaf cells of a level, one partial per
+// 256-thread block (wave shuffles, then LDS across the block's 4 waves).
 // ---------------------------------------------------------------------------
-__global__ void cfl_kernel(const double* __restrict__ U, int64_t plane, int64_t n_oct,
-                           const uint8_t* __restrict__ refined, double g, double rf, double pf,
-                           unsigned long long* slot, int32_t* err) {
+__global__ __launch_bounds__(256) void cfl_kernel(const double* __restrict__ U, int64_t plane, int64_t n_oct,
+                                                  const uint8_t* __restrict__ refined, double g, double rf, double pf,
+                                                  double* __restrict__ part, int32_t* err) {
+  __shared__ double red[4];
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   double s = 0.0;
   if (i < n_oct * 8) {
@@ -596,15 +661,35 @@ __global__ void cfl_kernel(const double* __restrict__ U, int64_t plane, int64_t 
     }
   }
   const double m = wave_max(s);
-  if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(slot, (unsigned long long)__double_as_longlong(m));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double g, double rf, double pf,
-               unsigned long long* slot, int32_t* err, void* stream) {
+               double* part, int32_t* err, void* stream) {
   if (n_oct == 0) return 0;
   const int64_t n = n_oct * 8;
   hipLaunchKernelGGL(cfl_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, U, plane, n_oct,
-                     refined, g, rf, pf, slot, err);
+                     refined, g, rf, pf, part, err);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ __launch_bounds__(256) void seg_max_kernel(const double* __restrict__ part,
+                                                      const int64_t* __restrict__ off, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int64_t a = off[blockIdx.x], b = off[blockIdx.x + 1];
+  double m = 0.0;
+  for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) m = fmax(m, part[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+int launch_seg_max(const double* part, const int64_t* off, int nseg, double* out, void* stream) {
+  if (nseg <= 0) return 0;
+  hipLaunchKernelGGL(seg_max_kernel, dim3(nseg), dim3(256), 0, (hipStream_t)stream, part, off, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -623,13 +708,12 @@ __global__ void finalize_kernel(FinalizeArgs A) {
     }
     double best = INFINITY;
     for (int k = 0; k < A.nslot; ++k) {
-      const double smax = __longlong_as_double((long long)A.smax[k]);
+      const double smax = A.smax[k];
       if (!(smax > 0.0)) continue;
       const double dtl = A.cfl * A.dx[k] / smax;
       const double cand = ldexp(dtl, k);
       if (cand < best) best = cand;
     }
-    for (int k = 0; k < A.nslot; ++k) A.clear[k] = 0ull;
     const double t = *A.t;
     double dt = best;
     int last = 0;
@@ -650,8 +734,7 @@ __global__ void finalize_kernel(FinalizeArgs A) {
     if (last) *A.done = 1;
   } else {
     if (i >= A.nslot) return;
-    const double smax = __longlong_as_double((long long)A.smax[i]);
-    A.clear[i] = 0ull;
+    const double smax = A.smax[i];
     const double dx = A.dx_box[i];
     const double dt = A.cfl * dx / smax;
     A.lam[i] = dt / dx;

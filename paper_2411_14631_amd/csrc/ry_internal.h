@@ -90,7 +90,7 @@ struct HydroArgs {
   const double* lam_dev;      // device lambda (per box when tile_box != nullptr)
   double lam_host;            // used when lam_dev == nullptr
   const int32_t* tile_box;
-  unsigned long long* smax;   // CFL epilogue slots (per box / per level), nullptr = off
+  double* tile_smax;          // CFL epilogue: max signal speed per tile, nullptr = off
   unsigned long long* floors;
   int32_t* err;
   const int32_t* skip;        // device flag: skip this launch's work
@@ -114,22 +114,23 @@ int launch_hydro(const HydroArgs& a, int precision, const ry_tuning& t, int num_
 int launch_ghost(const GhostArgs& a, void* stream);
 int launch_restrict(const double* Uf, int64_t plane_f, int64_t n_fine, const int32_t* parent_cell,
                     double* Uc, int64_t plane_c, const int32_t* skip, void* stream);
+// per-block maxima of the signal speed over leaf cells -> part[0 .. ceil(8 n_oct / 256))
 int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double gamma,
-               double rho_floor, double p_floor, unsigned long long* slot, int32_t* err, void* stream);
+               double rho_floor, double p_floor, double* part, int32_t* err, void* stream);
+// out[s] = max of part[off[s] .. off[s+1])
+int launch_seg_max(const double* part, const int64_t* off, int nseg, double* out, void* stream);
 struct FinalizeArgs {
-  const unsigned long long* smax;   // per level (AMR) or per box (batch)
+  const double* smax;              // per level (AMR) or per box (batch)
   int32_t nslot;
   double cfl;
   double dx[RY_MAX_LEVELS];        // AMR: dx of each level; batch: unused
   const double* dx_box;            // batch: dx per box
-  int32_t lmin_shift_base;         // unused placeholder for alignment
   double t_end;
   double* t;                       // AMR: 1 value; batch: per box
   double* lam;                     // AMR: 1 value; batch: per box
   int32_t* skip;
   int32_t* done;
   int32_t* nstep;
-  unsigned long long* clear;       // slots to clear after reading
   int32_t batch;
 };
 int launch_finalize(const FinalizeArgs& a, void* stream);

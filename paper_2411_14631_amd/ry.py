@@ -47,7 +47,7 @@ class RyConfig(C.Structure):
 
 class RyTuning(C.Structure):
     _fields_ = [("tiles_per_wg", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("batch", C.c_int32)]
+                ("batch", C.c_int32), ("waves_per_tile", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -180,8 +180,8 @@ class _Base:
             pass
 
     # tuning / timing / diagnostics
-    def set_tuning(self, tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1):
-        t = RyTuning(tiles_per_wg, persistent, waves_per_cu, batch)
+    def set_tuning(self, tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=4):
+        t = RyTuning(tiles_per_wg, persistent, waves_per_cu, batch, waves_per_tile)
         self._check(lib().ry_set_tuning(self.ctx, C.byref(t)), "ry_set_tuning")
 
     def tuning(self):
