@@ -81,13 +81,15 @@ def cell_updates_per_coarse_step(h):
     return tot
 
 
-def run_uniform(precision, steps, warmup, tune):
+def run_uniform(precision, steps, warmup, tune, fixed=None):
     import workloads as W
     from paper_2411_14631_amd import Hydro
     prob = W.uniform(128)
     h = Hydro(prob, precision)
     tuning = None
-    if tune:
+    if fixed:
+        h.set_tuning(*fixed)
+    elif tune:
         tuning, _ = h.autotune()
     cups = cell_updates_per_coarse_step(h)
     dt_graph, _ = time_advance(h, steps, warmup, timing=False)
@@ -139,6 +141,11 @@ def main():
     ap.add_argument("--no-zoom", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="fixed hydro tuning tiles_per_wg,persistent,waves_per_cu,batch,waves_per_tile")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first launch a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
@@ -147,11 +154,29 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tune = not args.no_tune
+    fixed = [int(x) for x in args.tuning.split(",")] if args.tuning else None
+
+    if args.copy_probe_mb:
+        import workloads as W
+        from paper_2411_14631_amd import Hydro
+        probe = Hydro(W.uniform_state(8), "fp64")
+        ms = probe.copy_probe(args.copy_probe_mb << 20, reps=5)
+        log(f"bench: copy probe {args.copy_probe_mb} MiB: {ms:.4f} ms "
+            f"({2 * (args.copy_probe_mb << 20) / (ms * 1e-3) / 1e9:.1f} GB/s)")
+        probe.close()
+
+    if args.only:
+        log(f"bench: uniform 128^3 {args.only} only")
+        r = run_uniform(args.only, args.steps, args.warmup, tune, fixed)
+        ms = r["kernel_ms"] / max(r["launches"], 1)
+        print(json.dumps({"precision": args.only, "cell_updates_per_s": r["cups"] * args.steps / r["dt_timed"],
+                          "hydro_kernel_avg_ms": ms, "tuning": r["tuning"]}), flush=True)
+        return
 
     log("bench: uniform 128^3 fp64")
-    f = run_uniform("fp64", args.steps, args.warmup, tune)
+    f = run_uniform("fp64", args.steps, args.warmup, tune, fixed)
     log("bench: uniform 128^3 mixed")
-    m = run_uniform("mixed", args.steps, args.warmup, tune)
+    m = run_uniform("mixed", args.steps, args.warmup, tune, fixed)
 
     value = f["cups"] * args.steps / f["dt_timed"]
     ms_per_step = 1e3 * f["dt_timed"] / args.steps
@@ -194,6 +219,28 @@ def main():
             del z
             torch.cuda.empty_cache()
 
+    batch = None
+    if not args.no_zoom:
+        import workloads as W
+        from paper_2411_14631_amd import BatchHydro
+        boxes = W.batch(512)
+        cells = sum(p.nbase[0] ** 3 for p in boxes)
+        batch = {"boxes": 512, "cells": cells, "steps": 20}
+        for prec in ("fp64", "mixed"):
+            log(f"bench: batch 512 boxes {prec}")
+            bh = BatchHydro(boxes, prec)
+            bh.run(2)                                   # warm-up (graph capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bh.run(20)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            batch[prec] = {"value": cells * 20 / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / 20,
+                           "hbm_frac": round(BYTES_PER_CELL_UPDATE * cells * 20 / el / 1e9 / HBM_PEAK_GBS, 4)}
+            bh.close()
+            del bh
+            torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
@@ -210,6 +257,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "zoom_amr": zoom,
+        "batch_boxes": batch,
     }
     print(json.dumps(out), flush=True)
 

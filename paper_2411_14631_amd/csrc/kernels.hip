@@ -8,8 +8,9 @@
 //   A  gather U of the 304 stencil positions through the tile's 4x4x4 table
 //      of neighbouring octs (real or ghost), convert to primitives -> LDS
 //   B  MinMod slopes and the half-step predictor for the 160 cells that
-//      border a flux face (core + one layer per face) -> LDS
-//   C  240 face fluxes (HLLC; normal slopes recomputed from LDS) -> LDS
+//      border a flux face (core + one layer per face); the left / right
+//      face states W~ +- D/2 replace the stencil in LDS
+//   C  240 face fluxes (HLLC) -> LDS
 //   D  per cell: coarse-fine register override, conservative FP64 update,
 //      fused CFL reduction on the new state; fine-side flux registers.
 // The scheme's definitions: ideal-gas primitives with floors; undivided
@@ -26,25 +27,25 @@ namespace ry {
 
 // ---------------------------------------------------------------------------
 // Tile geometry.  Stencil positions s in [-2,5]^3 relative to the tile's
-// first cell; LDS boxes are padded (strides WSY/WSZ, PSY/PSZ) so that the
-// three face orientations of phase C spread over the LDS banks.
+// first cell; the LDS box is padded (strides WSY, WSZ) to spread the
+// stencil reads over the LDS banks.
 // ---------------------------------------------------------------------------
 constexpr int WSY = 8, WSZ = 68, WSIZE = 7 + 7 * WSY + 7 * WSZ + 1;   // primitives on [-2,5]^3
-constexpr int PSY = 6, PSZ = 40, PSIZE = 5 + 5 * PSY + 5 * PSZ + 1;   // predictions on [-1,4]^3
 constexpr int NPOS_A = 304;   // positions whose primitives are needed
 constexpr int NPOS_B = 160;   // positions that get a predicted state (core + one layer per face)
 constexpr int NFACE = 240;    // 3 directions x 5 planes x 16
 __host__ __device__ constexpr int widx(int x, int y, int z) { return (x + 2) + WSY * (y + 2) + WSZ * (z + 2); }
-__host__ __device__ constexpr int pidx(int x, int y, int z) { return (x + 1) + PSY * (y + 1) + PSZ * (z + 1); }
 
 // Per-item constants of the three phases, computed at compile time:
 //  a[i]: bits 0-9 LDS index, 10-15 oct-table slot, 16-18 in-oct cell, 19-27 raw (x+2)+8(y+2)+64(z+2)
-//  b[i]: bits 0-9 LDS index of W, 10-17 LDS index of Wt
-//  f[i]: bits 0-9 W index of the face's lower cell, 10-17 its Wt index, 18-19 direction
+//  b[i]: LDS index of W of predicted position i
+//  bf[i][2d+s]: face (index d*80 + plane*16 + t1 + 4*t2) whose left (s = 1:
+//      upper face of the cell) or right (s = 0: lower face) state position i
+//      provides along axis d, or 255 when there is none
 struct StencilTables {
   uint32_t a[NPOS_A];
   uint32_t b[NPOS_B];
-  uint32_t f[NFACE];
+  uint8_t bf[NPOS_B][6];
 };
 
 constexpr StencilTables make_tables() {
@@ -63,30 +64,35 @@ constexpr StencilTables make_tables() {
         const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
         const int raw = (x + 2) + 8 * (y + 2) + 64 * (z + 2);
         if (needA) t.a[na++] = uint32_t(widx(x, y, z) | (slot << 10) | (cb << 16) | (raw << 19));
-        if (needB) t.b[nb++] = uint32_t(widx(x, y, z) | (pidx(x, y, z) << 10));
+        if (needB) {
+          const int c[3] = {x, y, z};
+          for (int d = 0; d < 3; ++d) {
+            const int t1 = c[d == 0 ? 1 : 0], t2 = c[d == 2 ? 1 : 2];
+            const bool tin = t1 >= 0 && t1 <= 3 && t2 >= 0 && t2 <= 3;
+            const int lo = c[d], hi = c[d] + 1;       // planes of the lower / upper face
+            t.bf[nb][2 * d + 0] = uint8_t((tin && lo >= 0 && lo <= 4) ? d * 80 + lo * 16 + t1 + 4 * t2 : 255);
+            t.bf[nb][2 * d + 1] = uint8_t((tin && hi >= 0 && hi <= 4) ? d * 80 + hi * 16 + t1 + 4 * t2 : 255);
+          }
+          t.b[nb++] = uint32_t(widx(x, y, z));
+        }
       }
-  for (int f = 0; f < NFACE; ++f) {
-    const int d = f / 80, rem = f - 80 * d;
-    const int pl = (rem >> 4) - 1, ta = rem & 3, tb = (rem >> 2) & 3;
-    const int cx = (d == 0) ? pl : ta;
-    const int cy = (d == 0) ? ta : ((d == 1) ? pl : tb);
-    const int cz = (d == 2) ? pl : tb;
-    t.f[f] = uint32_t(widx(cx, cy, cz) | (pidx(cx, cy, cz) << 10) | (d << 18));
-  }
   return t;
 }
 __constant__ StencilTables c_st = make_tables();
 static_assert(make_tables().a[NPOS_A - 1] != 0 && make_tables().b[NPOS_B - 1] != 0, "stencil tables");
-static_assert(WSIZE <= 1024 && PSIZE <= 256, "LDS indices must fit the table fields");
+static_assert(WSIZE <= 1024, "LDS indices must fit the table fields");
 
+// One LDS buffer serves three phases in turn: primitives on the padded
+// [-2,5]^3 stencil (A, B), then the left/right face states [2][NVAR][NFACE]
+// (B -> C), then the FP64 face fluxes [NVAR][NFACE] (C -> D).
 template <typename Real>
 struct TileLDS {
-  Real W[NVAR][WSIZE];    // primitives on the padded [-2,5]^3 stencil; reused for fluxes
-  Real Wt[NVAR][PSIZE];   // predicted states on the [-1,4]^3 box
+  Real W[NVAR][WSIZE];
   int32_t tab[TILE_TAB];  // ext oct index of the 4x4x4 oct neighbourhood
   uint8_t ref[TILE_TAB];  // refined-cell bytes of those octs
 };
 static_assert(sizeof(double) * NVAR * NFACE <= sizeof(float) * NVAR * WSIZE, "flux alias");
+static_assert(2 * NVAR * NFACE <= NVAR * WSIZE, "face-state alias");
 
 // ---------------------------------------------------------------------------
 // Scalar helpers.
@@ -274,58 +280,76 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
   }
   __syncthreads();
 
-  // --- phase B: slopes + predictor
-  for (int i = tid; active && i < NPOS_B; i += NT) {
-    const uint32_t ent = c_st.b[i];
-    const int iw = int(ent & 1023u), ip = int(ent >> 10);
-    Real W0[NVAR], D[3][NVAR];
+  // --- phase B: slopes + predictor, held in registers until every thread has
+  // read its stencil; then the face-extrapolated states W~ -+ D/2 (floored)
+  // replace the stencil in LDS.
+  constexpr int NRB = (NPOS_B + NT - 1) / NT;
+  Real Pw[NRB][NVAR], Pd[NRB][3][NVAR];
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) W0[v] = S.W[v][iw];
-    constexpr int st[3] = {1, WSY, WSZ};
+  for (int rnd = 0; rnd < NRB; ++rnd) {
+    const int i = tid + NT * rnd;
+    if (active && i < NPOS_B) {
+      const int iw = int(c_st.b[i]);
+      Real W0[NVAR];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+      for (int v = 0; v < NVAR; ++v) W0[v] = S.W[v][iw];
+      constexpr int st[3] = {1, WSY, WSZ};
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) D[d][v] = mmod(W0[v] - S.W[v][iw - st[d]], S.W[v][iw + st[d]] - W0[v]);
-    const Real r = W0[0], u = W0[1], vv = W0[2], w = W0[3], p = W0[4];
-    const Real ir = rcp(r);
-    const Real gg = Real(g);
-    Real Wt[NVAR];
-    Wt[0] = r - h * (u * D[0][0] + r * D[0][1] + vv * D[1][0] + r * D[1][2] + w * D[2][0] + r * D[2][3]);
-    Wt[1] = u - h * (u * D[0][1] + vv * D[1][1] + w * D[2][1] + D[0][4] * ir);
-    Wt[2] = vv - h * (u * D[0][2] + vv * D[1][2] + w * D[2][2] + D[1][4] * ir);
-    Wt[3] = w - h * (u * D[0][3] + vv * D[1][3] + w * D[2][3] + D[2][4] * ir);
-    Wt[4] = p - h * (u * D[0][4] + vv * D[1][4] + w * D[2][4] + gg * p * (D[0][1] + D[1][2] + D[2][3]));
+      for (int d = 0; d < 3; ++d)
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) S.Wt[v][ip] = Wt[v];
+        for (int v = 0; v < NVAR; ++v)
+          Pd[rnd][d][v] = mmod(W0[v] - S.W[v][iw - st[d]], S.W[v][iw + st[d]] - W0[v]);
+      const Real(&D)[3][NVAR] = Pd[rnd];
+      const Real r = W0[0], u = W0[1], vv = W0[2], w = W0[3], p = W0[4];
+      const Real ir = rcp(r);
+      const Real gg = Real(g);
+      Pw[rnd][0] = r - h * (u * D[0][0] + r * D[0][1] + vv * D[1][0] + r * D[1][2] + w * D[2][0] + r * D[2][3]);
+      Pw[rnd][1] = u - h * (u * D[0][1] + vv * D[1][1] + w * D[2][1] + D[0][4] * ir);
+      Pw[rnd][2] = vv - h * (u * D[0][2] + vv * D[1][2] + w * D[2][2] + D[1][4] * ir);
+      Pw[rnd][3] = w - h * (u * D[0][3] + vv * D[1][3] + w * D[2][3] + D[2][4] * ir);
+      Pw[rnd][4] = p - h * (u * D[0][4] + vv * D[1][4] + w * D[2][4] + gg * p * (D[0][1] + D[1][2] + D[2][3]));
+    }
+  }
+  __syncthreads();
+  Real* FS = &S.W[0][0];                        // [2][NVAR][NFACE]: 0 = right state, 1 = left state
+  const Real rfr = Real(rf), pfr = Real(pf);
+#pragma unroll
+  for (int rnd = 0; rnd < NRB; ++rnd) {
+    const int i = tid + NT * rnd;
+    if (active && i < NPOS_B) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int f = c_st.bf[i][k];
+        if (f == 255) continue;
+        const int d = k >> 1, side = k & 1;
+        const Real sg = side ? Real(0.5) : Real(-0.5);
+        Real st[NVAR];
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) st[v] = Pw[rnd][v] + sg * Pd[rnd][d][v];
+        nfl += int(st[0] < rfr) + int(st[4] < pfr);
+        st[0] = (st[0] < rfr) ? rfr : st[0];
+        st[4] = (st[4] < pfr) ? pfr : st[4];
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) FS[(side * NVAR + v) * NFACE + f] = st[v];
+      }
+    }
   }
   __syncthreads();
 
-  // --- phase C: face fluxes (kept in registers, then written over W)
+  // --- phase C: face fluxes (kept in registers, then written over the states)
   constexpr int NR = (NFACE + NT - 1) / NT;
   double Fr[NR][NVAR];
 #pragma unroll
   for (int rnd = 0; rnd < NR; ++rnd) {
     const int f = tid + NT * rnd;
     if (active && f < NFACE) {
-      const uint32_t ent = c_st.f[f];
-      const int iwA = int(ent & 1023u), ipA = int((ent >> 10) & 255u), d = int(ent >> 18);
-      const int stw = (d == 0) ? 1 : ((d == 1) ? WSY : WSZ);
-      const int stp = (d == 0) ? 1 : ((d == 1) ? PSY : PSZ);
+      const int d = f / 80;
       Real WL[NVAR], WR[NVAR];
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
-        const Real wam = S.W[v][iwA - stw], wa = S.W[v][iwA], wb = S.W[v][iwA + stw], wbp = S.W[v][iwA + 2 * stw];
-        const Real da = mmod(wa - wam, wb - wa);
-        const Real db = mmod(wb - wa, wbp - wb);
-        WL[v] = S.Wt[v][ipA] + Real(0.5) * da;
-        WR[v] = S.Wt[v][ipA + stp] - Real(0.5) * db;
+        WL[v] = FS[(NVAR + v) * NFACE + f];
+        WR[v] = FS[v * NFACE + f];
       }
-      const Real rfr = Real(rf), pfr = Real(pf);
-      nfl += int(WL[0] < rfr) + int(WR[0] < rfr) + int(WL[4] < pfr) + int(WR[4] < pfr);
-      WL[0] = (WL[0] < rfr) ? rfr : WL[0];
-      WR[0] = (WR[0] < rfr) ? rfr : WR[0];
-      WL[4] = (WL[4] < pfr) ? pfr : WL[4];
-      WR[4] = (WR[4] < pfr) ? pfr : WR[4];
       const Real unl = (d == 0) ? WL[1] : ((d == 1) ? WL[2] : WL[3]);
       const Real unr = (d == 0) ? WR[1] : ((d == 1) ? WR[2] : WR[3]);
       const Real t1l = (d == 0) ? WL[2] : WL[1], t1r = (d == 0) ? WR[2] : WR[1];

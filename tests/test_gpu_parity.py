@@ -297,3 +297,31 @@ def test_twolevel128_full_size_one_coarse_step(ry):
     g.advance(1)
     o.advance(1)
     compare_levels(g, o)
+
+
+def test_zoom_full_size_one_coarse_step(ry):
+    """Zoom-shaped AMR (levels 7-12, about 2M octs): refinement maps and oct
+    order bit-exact, one coarse step (32 level-12 substeps) within 1e-12."""
+    prob = W.zoom()
+    g = ry.Hydro(prob)
+    o = Oracle(prob)
+    assert g.level_info(12)[0] > 0
+    assert sum(g.level_info(lv)[0] for lv in g.levels) > 1_500_000
+    g.advance(1)
+    o.advance(1)
+    compare_levels(g, o)
+    assert g.floors() == 0
+
+
+def test_batch512_full_size_sampled_boxes(ry):
+    """All 512 uneven boxes advanced together 20 steps; 16 boxes spread over
+    the list are recomputed one by one by the oracle."""
+    boxes = W.batch(512)
+    for prec in ("fp64",):
+        bh = ry.BatchHydro(boxes, prec)
+        bh.run(20)
+        for b in range(0, 512, 32):
+            o = Oracle(boxes[b])
+            o.advance(20)
+            assert cases.rel_err(bh.download(b), o.download(1)) <= TOL, b
+            assert abs(bh.box_info(b)[1] - o.t) <= 1e-13 * o.t

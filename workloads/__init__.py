@@ -25,7 +25,8 @@ v_z; box b of the batched workload uses 5000 + 10 b + field):
               refined cells take point values (trilinear background plus
               analytic clumps), mass criterion.
 * batch    -- 512 periodic boxes with sides in {16,24,32,40,48}, per box
-              sigma ~ U(0.5, 1.5), rms Mach ~ U(0.5, 3), gamma 5/3, p = 1.
+              sigma ~ U(0.5, 1.5), rms Mach ~ U(0.5, 3), gamma 5/3, uniform
+              temperature p = rho.
 """
 from __future__ import annotations
 
@@ -270,8 +271,10 @@ BATCH_SIDES = (16, 24, 32, 40, 48)
 
 
 def batch_box(b: int, side: int, sigma_ln: float, mach: float, gamma: float = 5.0 / 3.0) -> Problem:
-    rho, vx, vy, vz, p = lognormal_fields(side, 5000 + 10 * b, sigma_ln, mach, gamma)
-    U = conserved(rho, vx, vy, vz, p, gamma)
+    # uniform temperature (p = rho): the rms Mach number is relative to the
+    # one sound speed sqrt(gamma) everywhere in the box
+    rho, vx, vy, vz, _ = lognormal_fields(side, 5000 + 10 * b, sigma_ln, mach, gamma)
+    U = conserved(rho, vx, vy, vz, rho.copy(), gamma)
     return Problem(f"box{b}", 1, 1, (side, side, side), gamma, U, n_steps=20)
 
 
