@@ -92,10 +92,11 @@ def run_uniform(precision, steps, warmup, tune, fixed=None):
     elif tune:
         tuning, _ = h.autotune()
     cups = cell_updates_per_coarse_step(h)
+    e0 = h.totals()[4]
     dt_graph, _ = time_advance(h, steps, warmup, timing=False)
     dt_ev, (nl, ms) = time_advance(h, steps, 0, timing=True)
     return dict(prob=prob, h=h, cups=cups, dt_graph=dt_graph, dt_timed=dt_ev, launches=nl, kernel_ms=ms,
-                tuning=tuning or h.tuning(), floors=h.floors())
+                tuning=tuning or h.tuning(), floors=h.floors(), e0=e0)
 
 
 def run_zoom(prob, precision, steps, tune):
@@ -107,9 +108,47 @@ def run_zoom(prob, precision, steps, tune):
         h.autotune()
     cups = cell_updates_per_coarse_step(h)
     noct = sum(h.level_info(lv)[0] for lv in h.levels)
+    e0 = h.totals()[4]
     dt_graph, _ = time_advance(h, steps, 1, timing=False)
-    return dict(h=h, cups=cups, noct=noct, dt=dt_graph, build_s=build_s,
+    h.advance(10 - steps - 1)                      # 10 coarse steps in total
+    return dict(h=h, cups=cups, noct=noct, dt=dt_graph, build_s=build_s, e0=e0, floors=h.floors(),
                 levels={lv: h.level_info(lv) for lv in h.levels})
+
+
+def leaf_fields(h):
+    """Leaf-cell density, pressure and cell volume of every level."""
+    import numpy as np
+    g = h.prob.gamma
+    out = []
+    for k, lv in enumerate(h.levels):
+        n, _ = h.level_info(lv)
+        if n == 0:
+            continue
+        U = h.download(lv)
+        _, ref = h.mesh(lv)
+        leaf = ~np.unpackbits(ref[:, None], axis=1, bitorder="little").astype(bool).reshape(-1)
+        rho = U[0][leaf]
+        p = (g - 1.0) * (U[4][leaf] - 0.5 * (U[1][leaf] ** 2 + U[2][leaf] ** 2 + U[3][leaf] ** 2) / rho)
+        vol = (h.prob.boxlen / (h.prob.nbase[0] << k)) ** 3
+        out.append((rho, p, vol))
+    return out
+
+
+def compare_forms(hf, hm, e0f, e0m):
+    """Mixed form against the FP64 form (which is pinned to the oracle):
+    relative L1 and max errors of density and pressure over leaf cells, and
+    each form's total-energy drift."""
+    import numpy as np
+    a, b = leaf_fields(hf), leaf_fields(hm)
+    l1 = sum(np.abs(rm - rf).sum() * v for (rf, _, v), (rm, _, _) in zip(a, b))
+    norm = sum(np.abs(rf).sum() * v for (rf, _, v) in a)
+    mx_r = max(float(np.max(np.abs(rm - rf) / np.abs(rf))) for (rf, _, _), (rm, _, _) in zip(a, b))
+    mx_p = max(float(np.max(np.abs(pm - pf) / np.abs(pf))) for (_, pf, _), (_, pm, _) in zip(a, b))
+    l1p = sum(np.abs(pm - pf).sum() * v for (_, pf, v), (_, pm, _) in zip(a, b)) / \
+        sum(np.abs(pf).sum() * v for (_, pf, v) in a)
+    ef, em = hf.totals()[4], hm.totals()[4]
+    return {"l1_rho_rel": float(l1 / norm), "max_rho_rel": mx_r, "l1_p_rel": float(l1p), "max_p_rel": mx_p,
+            "energy_drift_fp64": float(abs(ef - e0f) / abs(e0f)), "energy_drift_mixed": float(abs(em - e0m) / abs(e0m))}
 
 
 def cpu_baseline(budget_s=15.0):
@@ -195,10 +234,7 @@ def main():
              "hbm_frac": round(BYTES_PER_CELL_UPDATE * m["cups"] / (m_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "graph_value": m["cups"] * args.steps / m["dt_graph"], "tuning": m["tuning"]}
     # mixed vs fp64 after the same number of steps (both ran warmup + 2 x steps)
-    import numpy as np
-    rf = f["h"].download(7)
-    rm = m["h"].download(7)
-    mixed["l1_rho_rel_vs_fp64"] = float(np.abs(rm[0] - rf[0]).sum() / np.abs(rf[0]).sum())
+    mixed["vs_fp64"] = compare_forms(f["h"], m["h"], f["e0"], m["e0"])
     mixed["steps_compared"] = args.warmup + 2 * args.steps
     del f["h"], m["h"]
     torch.cuda.empty_cache()
@@ -208,16 +244,21 @@ def main():
         import workloads as W
         zprob = W.zoom()
         zoom = {}
+        handles = {}
         for prec in ("fp64", "mixed"):
             log(f"bench: zoom AMR {prec}")
             z = run_zoom(zprob, prec, 3, tune)
             zoom[prec] = {"value": z["cups"] * 3 / z["dt"], "unit": "cell-updates/s",
                           "hbm_frac": round(BYTES_PER_CELL_UPDATE * z["cups"] * 3 / z["dt"] / 1e9 / HBM_PEAK_GBS, 4),
                           "cell_updates_per_coarse_step": z["cups"], "octs": z["noct"],
-                          "ms_per_coarse_step": round(1e3 * z["dt"] / 3, 3), "build_s": round(z["build_s"], 1)}
+                          "ms_per_coarse_step": round(1e3 * z["dt"] / 3, 3), "build_s": round(z["build_s"], 1),
+                          "floor_activations": z["floors"]}
             zoom["levels"] = {str(k): v for k, v in z["levels"].items()}
-            del z
-            torch.cuda.empty_cache()
+            handles[prec] = z
+        zoom["mixed_vs_fp64_after_10_coarse_steps"] = compare_forms(
+            handles["fp64"]["h"], handles["mixed"]["h"], handles["fp64"]["e0"], handles["mixed"]["e0"])
+        del handles, z
+        torch.cuda.empty_cache()
 
     batch = None
     if not args.no_zoom:

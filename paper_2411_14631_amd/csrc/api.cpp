@@ -711,9 +711,7 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
   c->batch = true;
   c->nlev = 1;
   c->nbox = nbox;
-  c->tune.persistent = 1;
-  c->tune.batch = 4;
-  c->tune.waves_per_cu = 16;
+  c->tune = ry_tuning{1, 1, 14, 4, 2};
   ry_status s = init_common(c);
   if (s) {
     delete c;
@@ -953,8 +951,8 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
   for (int wpt : {1, 2, 4})
     for (int tpw : {1, 2, 4})
       if (tpw <= max_tpw && tpw * wpt <= 4) cand.push_back({tpw, 0, 4, 1, wpt});
-  for (int wpt : {2, 4})
-    for (int w : {8, 16})
+  for (int wpt : {1, 2, 4})
+    for (int w : {8, 14, 20})
       for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt});
   double best_ms = INFINITY;
   ry_tuning bt{};

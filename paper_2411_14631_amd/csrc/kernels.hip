@@ -35,11 +35,17 @@ constexpr int NPOS_A = 304;   // positions whose primitives are needed
 constexpr int NPOS_B = 160;   // positions that get a predicted state (core + one layer per face)
 constexpr int NFACE = 240;    // 3 directions x 5 planes x 16
 __host__ __device__ constexpr int widx(int x, int y, int z) { return (x + 2) + WSY * (y + 2) + WSZ * (z + 2); }
+// Face index of the face along d whose upper cell is (x, y, z) (the plane
+// coordinate runs 0..4, the transverse ones 0..3); x runs fastest in every
+// direction so that neighbouring lanes touch neighbouring LDS words.
+__host__ __device__ constexpr int fidx(int d, int x, int y, int z) {
+  return d == 0 ? x + 5 * y + 20 * z : (d == 1 ? 80 + x + 4 * y + 20 * z : 160 + x + 4 * y + 16 * z);
+}
 
 // Per-item constants of the three phases, computed at compile time:
 //  a[i]: bits 0-9 LDS index, 10-15 oct-table slot, 16-18 in-oct cell, 19-27 raw (x+2)+8(y+2)+64(z+2)
 //  b[i]: LDS index of W of predicted position i
-//  bf[i][2d+s]: face (index d*80 + plane*16 + t1 + 4*t2) whose left (s = 1:
+//  bf[i][2d+s]: face (index fidx) whose left (s = 1:
 //      upper face of the cell) or right (s = 0: lower face) state position i
 //      provides along axis d, or 255 when there is none
 struct StencilTables {
@@ -50,32 +56,39 @@ struct StencilTables {
 
 constexpr StencilTables make_tables() {
   StencilTables t{};
-  int na = 0, nb = 0;
-  for (int z = -2; z <= 5; ++z)
-    for (int y = -2; y <= 5; ++y)
-      for (int x = -2; x <= 5; ++x) {
-        const int ox = (x < 0 || x > 3), oy = (y < 0 || y > 3), oz = (z < 0 || z > 3);
-        const int nout = ox + oy + oz;
-        const bool ex = (x == -1 || x == 4), ey = (y == -1 || y == 4), ez = (z == -1 || z == 4);
-        const bool edges = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
-        const bool needA = (nout <= 1) || (nout == 2 && edges);
-        const bool needB = (nout == 0) || (nout == 1 && edges);
-        const int slot = ((x >> 1) + 1) + 4 * ((y >> 1) + 1) + 16 * ((z >> 1) + 1);
-        const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-        const int raw = (x + 2) + 8 * (y + 2) + 64 * (z + 2);
-        if (needA) t.a[na++] = uint32_t(widx(x, y, z) | (slot << 10) | (cb << 16) | (raw << 19));
-        if (needB) {
-          const int c[3] = {x, y, z};
-          for (int d = 0; d < 3; ++d) {
-            const int t1 = c[d == 0 ? 1 : 0], t2 = c[d == 2 ? 1 : 2];
-            const bool tin = t1 >= 0 && t1 <= 3 && t2 >= 0 && t2 <= 3;
-            const int lo = c[d], hi = c[d] + 1;       // planes of the lower / upper face
-            t.bf[nb][2 * d + 0] = uint8_t((tin && lo >= 0 && lo <= 4) ? d * 80 + lo * 16 + t1 + 4 * t2 : 255);
-            t.bf[nb][2 * d + 1] = uint8_t((tin && hi >= 0 && hi <= 4) ? d * 80 + hi * 16 + t1 + 4 * t2 : 255);
+  int na = 0;
+  int nb = 0;
+  // predicted positions: the 64 core cells first, then the 96 one-layer face
+  // cells, so that each wavefront of phase B2 takes one uniform path
+  for (int pass = 0; pass < 2; ++pass)
+    for (int z = -2; z <= 5; ++z)
+      for (int y = -2; y <= 5; ++y)
+        for (int x = -2; x <= 5; ++x) {
+          const int ox = (x < 0 || x > 3), oy = (y < 0 || y > 3), oz = (z < 0 || z > 3);
+          const int nout = ox + oy + oz;
+          const bool ex = (x == -1 || x == 4), ey = (y == -1 || y == 4), ez = (z == -1 || z == 4);
+          const bool edges = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
+          const bool needA = (nout <= 1) || (nout == 2 && edges);
+          const bool needB = (pass == 0) ? (nout == 0) : (nout == 1 && edges);
+          if (pass == 0 && needA) {
+            const int slot = ((x >> 1) + 1) + 4 * ((y >> 1) + 1) + 16 * ((z >> 1) + 1);
+            const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+            const int raw = (x + 2) + 8 * (y + 2) + 64 * (z + 2);
+            t.a[na++] = uint32_t(widx(x, y, z) | (slot << 10) | (cb << 16) | (raw << 19));
           }
-          t.b[nb++] = uint32_t(widx(x, y, z));
+          if (needB) {
+            const int c[3] = {x, y, z};
+            for (int d = 0; d < 3; ++d) {
+              const int t1 = c[d == 0 ? 1 : 0], t2 = c[d == 2 ? 1 : 2];
+              const bool tin = t1 >= 0 && t1 <= 3 && t2 >= 0 && t2 <= 3;
+              const int lo = c[d], hi = c[d] + 1;       // planes of the lower / upper face
+              const int ux = x + (d == 0 ? 1 : 0), uy = y + (d == 1 ? 1 : 0), uz = z + (d == 2 ? 1 : 0);
+              t.bf[nb][2 * d + 0] = uint8_t((tin && lo >= 0 && lo <= 4) ? fidx(d, x, y, z) : 255);
+              t.bf[nb][2 * d + 1] = uint8_t((tin && hi >= 0 && hi <= 4) ? fidx(d, ux, uy, uz) : 255);
+            }
+            t.b[nb++] = uint32_t(widx(x, y, z));
+          }
         }
-      }
   return t;
 }
 __constant__ StencilTables c_st = make_tables();
@@ -226,8 +239,17 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // or 256: 8, 16 or 32 threads per oct).  `active` is uniform over the NT
 // threads; an inactive group only keeps the workgroup's barrier count.
 // ---------------------------------------------------------------------------
+// Hides a value from the optimiser so that per-thread table loads are issued
+// per tile instead of being hoisted (and held in registers) across the tile
+// loop of the persistent kernel.
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 template <typename Real, int NT>
-__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int tid, bool active) {
+__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int tid_in, bool active) {
+  const int tid = opaque(tid_in);
   const int lane = tid & 63;
   const double g = A.gamma, rf = A.rho_floor, pf = A.p_floor;
   const int64_t P = A.plane;
@@ -246,37 +268,51 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
   }
   __syncthreads();
 
-  // --- phase A: gather + primitives
-  for (int i = tid; active && i < NPOS_A; i += NT) {
-    const uint32_t ent = c_st.a[i];
-    int slot = int((ent >> 10) & 63u), cb = int((ent >> 16) & 7u);
-    if (fl) {
-      // outflow faces: clamp the position into the domain (zero gradient)
-      const int raw = int(ent >> 19);
-      int sx = (raw & 7) - 2, sy = ((raw >> 3) & 7) - 2, sz = (raw >> 6) - 2;
-      if ((fl & CL_LOX) && sx < 0) sx = 0;
-      if ((fl & CL_HIX) && sx > 3) sx = 3;
-      if ((fl & CL_LOY) && sy < 0) sy = 0;
-      if ((fl & CL_HIY) && sy > 3) sy = 3;
-      if ((fl & CL_LOZ) && sz < 0) sz = 0;
-      if ((fl & CL_HIZ) && sz > 3) sz = 3;
-      slot = ((sx >> 1) + 1) + 4 * ((sy >> 1) + 1) + 16 * ((sz >> 1) + 1);
-      cb = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
-    }
-    const int32_t e = S.tab[slot];
-    double U[NVAR];
-    if (e >= 0) {
-      const int64_t cell = int64_t(e) * 8 + cb;
+  // --- phase A: gather + primitives (all loads of the thread's positions are
+  // issued before any conversion)
+  constexpr int NRA = (NPOS_A + NT - 1) / NT;
+  double Ua[NRA][NVAR];
+  int iwa[NRA];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) U[v] = A.U[v * P + cell];
-    } else {
-      U[0] = 1.0; U[1] = 0.0; U[2] = 0.0; U[3] = 0.0; U[4] = 1.0;   // never read by a leaf update
-    }
-    double W[NVAR];
-    cons2prim(U, W, g, rf, pf, nfl);
-    const int iw = int(ent & 1023u);
+  for (int rnd = 0; rnd < NRA; ++rnd) {
+    const int i = tid + NT * rnd;
+    iwa[rnd] = -1;
+    if (active && i < NPOS_A) {
+      const uint32_t ent = c_st.a[i];
+      int slot = int((ent >> 10) & 63u), cb = int((ent >> 16) & 7u);
+      if (fl) {
+        // outflow faces: clamp the position into the domain (zero gradient)
+        const int raw = int(ent >> 19);
+        int sx = (raw & 7) - 2, sy = ((raw >> 3) & 7) - 2, sz = (raw >> 6) - 2;
+        if ((fl & CL_LOX) && sx < 0) sx = 0;
+        if ((fl & CL_HIX) && sx > 3) sx = 3;
+        if ((fl & CL_LOY) && sy < 0) sy = 0;
+        if ((fl & CL_HIY) && sy > 3) sy = 3;
+        if ((fl & CL_LOZ) && sz < 0) sz = 0;
+        if ((fl & CL_HIZ) && sz > 3) sz = 3;
+        slot = ((sx >> 1) + 1) + 4 * ((sy >> 1) + 1) + 16 * ((sz >> 1) + 1);
+        cb = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
+      }
+      const int32_t e = S.tab[slot];
+      iwa[rnd] = int(ent & 1023u);
+      if (e >= 0) {
+        const int64_t cell = int64_t(e) * 8 + cb;
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) S.W[v][iw] = Real(W[v]);
+        for (int v = 0; v < NVAR; ++v) Ua[rnd][v] = A.U[v * P + cell];
+      } else {
+        // a slot no leaf update reads
+        Ua[rnd][0] = 1.0; Ua[rnd][1] = 0.0; Ua[rnd][2] = 0.0; Ua[rnd][3] = 0.0; Ua[rnd][4] = 1.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int rnd = 0; rnd < NRA; ++rnd) {
+    if (iwa[rnd] >= 0) {
+      double W[NVAR];
+      cons2prim(Ua[rnd], W, g, rf, pf, nfl);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) S.W[v][iwa[rnd]] = Real(W[v]);
+    }
   }
   __syncthreads();
 
@@ -317,15 +353,36 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
     if (active && i < NPOS_B) {
+      if (i < 64) {
+        // core cell: the lower and upper face along every axis
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < 6; ++k) {
+          const int f = c_st.bf[i][k];
+          const int d = k >> 1, side = k & 1;
+          const Real sg = side ? Real(0.5) : Real(-0.5);
+          Real st[NVAR];
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) st[v] = Pw[rnd][v] + sg * Pd[rnd][d][v];
+          nfl += int(st[0] < rfr) + int(st[4] < pfr);
+          st[0] = (st[0] < rfr) ? rfr : st[0];
+          st[4] = (st[4] < pfr) ? pfr : st[4];
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) FS[(side * NVAR + v) * NFACE + f] = st[v];
+        }
+      } else {
+        // one-layer cell: exactly one face, towards the core
+        int k = 0;
+#pragma unroll
+        for (int kk = 1; kk < 6; ++kk) k = (c_st.bf[i][kk] != 255) ? kk : k;
         const int f = c_st.bf[i][k];
-        if (f == 255) continue;
         const int d = k >> 1, side = k & 1;
         const Real sg = side ? Real(0.5) : Real(-0.5);
         Real st[NVAR];
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) st[v] = Pw[rnd][v] + sg * Pd[rnd][d][v];
+        for (int v = 0; v < NVAR; ++v) {
+          const Real dv = (d == 0) ? Pd[rnd][0][v] : ((d == 1) ? Pd[rnd][1][v] : Pd[rnd][2][v]);
+          st[v] = Pw[rnd][v] + sg * dv;
+        }
         nfl += int(st[0] < rfr) + int(st[4] < pfr);
         st[0] = (st[0] < rfr) ? rfr : st[0];
         st[4] = (st[4] < pfr) ? pfr : st[4];
@@ -387,9 +444,8 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
       double acc[NVAR] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const int ta = cc[d == 0 ? 1 : 0], tb = cc[d == 2 ? 1 : 2];
-        const int fm = d * 80 + cc[d] * 16 + ta + 4 * tb;
-        const int fp = fm + 16;
+        const int fm = fidx(d, cx, cy, cz);
+        const int fp = fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
         double Fm[NVAR], Fp[NVAR];
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
@@ -472,10 +528,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
         for (int j = 0; j < 4; ++j) {
           const int c = (j & m) | (up << d) | ((j & ~m) << 1);
           const int ccx = 2 * bx + (c & 1), ccy = 2 * by + ((c >> 1) & 1), ccz = 2 * bz + ((c >> 2) & 1);
-          const int cd = (d == 0) ? ccx : ((d == 1) ? ccy : ccz);
-          const int ta = (d == 0) ? ccy : ccx;
-          const int tbb = (d == 2) ? ccy : ccz;
-          fi[j] = d * 80 + (cd + up) * 16 + ta + 4 * tbb;
+          fi[j] = fidx(d, ccx + (d == 0 ? up : 0), ccy + (d == 1 ? up : 0), ccz + (d == 2 ? up : 0));
         }
         double* q = A.reg_own + (int64_t(eb) * 6 + face) * NVAR * 2;
 #pragma unroll
@@ -699,21 +752,33 @@ int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* ref
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-__global__ __launch_bounds__(256) void seg_max_kernel(const double* __restrict__ part,
-                                                      const int64_t* __restrict__ off, double* __restrict__ out) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(1024) void seg_max_kernel(const double* __restrict__ part,
+                                                       const int64_t* __restrict__ off, double* __restrict__ out) {
+  __shared__ double red[16];
   const int64_t a = off[blockIdx.x], b = off[blockIdx.x + 1];
-  double m = 0.0;
-  for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) m = fmax(m, part[i]);
-  m = wave_max(m);
+  // four independent accumulators per thread keep four loads in flight
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+  int64_t i = a + threadIdx.x;
+  for (; i + 3 * 1024 < b; i += 4 * 1024) {
+    m0 = fmax(m0, part[i]);
+    m1 = fmax(m1, part[i + 1024]);
+    m2 = fmax(m2, part[i + 2 * 1024]);
+    m3 = fmax(m3, part[i + 3 * 1024]);
+  }
+  for (; i < b; i += 1024) m0 = fmax(m0, part[i]);
+  double m = wave_max(fmax(fmax(m0, m1), fmax(m2, m3)));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (threadIdx.x < 64) {
+    m = (threadIdx.x < 16) ? red[threadIdx.x] : 0.0;
+    m = wave_max(m);
+    if (threadIdx.x == 0) out[blockIdx.x] = m;
+  }
 }
 
 int launch_seg_max(const double* part, const int64_t* off, int nseg, double* out, void* stream) {
   if (nseg <= 0) return 0;
-  hipLaunchKernelGGL(seg_max_kernel, dim3(nseg), dim3(256), 0, (hipStream_t)stream, part, off, out);
+  hipLaunchKernelGGL(seg_max_kernel, dim3(nseg), dim3(1024), 0, (hipStream_t)stream, part, off, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

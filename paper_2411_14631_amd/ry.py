@@ -217,13 +217,15 @@ class _Base:
 class Hydro(_Base):
     """One octree (uniform or AMR) on the GPU, built from a workloads.Problem."""
 
-    def __init__(self, prob, precision="fp64", device="cuda", torch_memory=True):
+    def __init__(self, prob, precision="fp64", device="cuda", torch_memory=True, memory=None):
         import torch
         self.torch = torch
         self.prob = prob
         self.ctx = C.c_void_p()
         self.stream = torch.cuda.Stream(device=device)       # default priority
-        self.mem = _TorchMemory(torch, device) if torch_memory else None
+        # device memory: torch's caching allocator (default), a caller-supplied
+        # object with alloc_cb / free_cb, or hipMalloc (torch_memory=False)
+        self.mem = memory if memory is not None else (_TorchMemory(torch, device) if torch_memory else None)
         cfg = _config(prob, precision, self.stream.cuda_stream, self.mem)
         self._cfg = cfg
         self._check(lib().ry_create(C.byref(cfg), C.byref(self.ctx)), "ry_create")

@@ -325,3 +325,67 @@ def test_batch512_full_size_sampled_boxes(ry):
             o.advance(20)
             assert cases.rel_err(bh.download(b), o.download(1)) <= TOL, b
             assert abs(bh.box_info(b)[1] - o.t) <= 1e-13 * o.t
+
+
+# ------------------------------------------------ failure paths, checkpoints
+class _FailingMemory:
+    """dev_alloc hook that succeeds `budget` times, then returns NULL."""
+
+    def __init__(self, ry, budget):
+        import torch
+        self.live = {}
+        self.calls = 0
+
+        def alloc(nbytes, user):
+            self.calls += 1
+            if self.calls > budget:
+                return None
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            self.live[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def free(p, user):
+            self.live.pop(p, None)
+
+        self.alloc_cb = ry.ALLOC_FN(alloc)
+        self.free_cb = ry.FREE_FN(free)
+
+
+def test_allocation_failure_reports_enomem_and_frees(ry):
+    prob = cases.amr_blob()
+    for budget in (0, 3, 12):
+        mem = _FailingMemory(ry, budget)
+        with pytest.raises(ry.RyError) as e:
+            ry.Hydro(prob, memory=mem)
+        assert e.value.code == ry.RY_ENOMEM
+        assert not mem.live          # every successful allocation was released
+    ok = ry.Hydro(prob)              # the library still works afterwards
+    ok.advance(1)
+
+
+def test_checkpoint_resume_bit_exact(ry):
+    prob = cases.amr_blob()
+    full = ry.Hydro(prob)
+    full.advance(4)
+    a = ry.Hydro(prob)
+    a.advance(2)
+    saved = [a.download(lv) for lv in a.levels]
+    t_saved = a.t
+    b = ry.Hydro(prob)
+    for lv, U in zip(b.levels, saved):
+        b.upload(lv, U)
+    b.t = t_saved
+    b.advance(2)
+    for lv in full.levels:
+        np.testing.assert_array_equal(b.download(lv), full.download(lv))
+
+
+def test_amr_with_empty_refinement_equals_single_level(ry):
+    base = W.random_smooth(16, seed=12)
+    amr = W.Problem("unref", 4, 6, (16, 16, 16), base.gamma, base.U_base, refine=W.REFINE_MASS,
+                    refine_param=1e30, fill=lambda l, ijk: np.zeros((5, len(ijk))))
+    g, s = ry.Hydro(amr), ry.Hydro(base)
+    assert g.level_info(5)[0] == 0 and g.level_info(6)[0] == 0
+    g.advance(3)
+    s.advance(3)
+    np.testing.assert_array_equal(g.download(4), s.download(4))
