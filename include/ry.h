@@ -128,7 +128,7 @@ typedef struct {
   int32_t waves_per_cu;   /* persistent grid = CUs * waves_per_cu / waves per workgroup     */
   int32_t batch;          /* tile groups popped per queue access                            */
   int32_t waves_per_tile; /* 1, 2 or 4 wavefronts per tile (8, 16, 32 threads per oct);     */
-                          /* tiles_per_wg * waves_per_tile <= 4, FP64: tiles_per_wg <= 2    */
+                          /* tiles_per_wg * waves_per_tile <= 4                             */
 } ry_tuning;
 ry_status ry_set_tuning(ry_ctx* ctx, const ry_tuning* t);
 ry_status ry_get_tuning(const ry_ctx* ctx, ry_tuning* t);

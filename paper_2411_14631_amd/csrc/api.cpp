@@ -881,8 +881,6 @@ ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
   if (t->tiles_per_wg != 1 && t->tiles_per_wg != 2 && t->tiles_per_wg != 4) return RY_EINVAL;
   if (t->waves_per_tile != 1 && t->waves_per_tile != 2 && t->waves_per_tile != 4) return RY_EINVAL;
   if (t->tiles_per_wg * t->waves_per_tile > 4) return RY_EINVAL;
-  // FP64 tiles take 29 KB of LDS each: at most 2 per workgroup (64 KB limit)
-  if (c->cfg.precision == RY_FP64 && t->tiles_per_wg > 2) return RY_EINVAL;
   if (t->persistent && (t->waves_per_cu < 1 || t->waves_per_cu > 32 || t->batch < 1 || t->batch > 64))
     return RY_EINVAL;
   c->tune = *t;
@@ -947,10 +945,9 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
     if (s0) return s0;
   }
   std::vector<ry_tuning> cand;
-  const int max_tpw = (c->cfg.precision == RY_FP64) ? 2 : 4;
   for (int wpt : {1, 2, 4})
     for (int tpw : {1, 2, 4})
-      if (tpw <= max_tpw && tpw * wpt <= 4) cand.push_back({tpw, 0, 4, 1, wpt});
+      if (tpw * wpt <= 4) cand.push_back({tpw, 0, 4, 1, wpt});
   for (int wpt : {1, 2, 4})
     for (int w : {8, 14, 20})
       for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt});

@@ -1,18 +1,20 @@
 // HIP kernels (gfx950) of the octree MUSCL-Hancock / MinMod / HLLC hydro step.
 //
 // Work unit: a tile = an aligned 2x2x2 block of octs (4x4x4 cells, the octs
-// sharing their Hilbert key except for the lowest 3 bits).  One 64-lane
-// wavefront owns one tile; the tile's primitive-variable stencil (the 8x8x8
-// box around the 4x4x4 core, of which 304 positions are used) is staged in
-// LDS once and shared by the tile's 64 cells.  Phases per tile:
+// sharing their Hilbert key except for the lowest 3 bits), handled by 1, 2
+// or 4 wavefronts of one workgroup; the tile's primitive-variable stencil
+// (304 positions of the 8x8x8 box around the 4x4x4 core) is staged in LDS
+// once and shared by the tile's 64 cells.  Phases per tile:
 //   A  gather U of the 304 stencil positions through the tile's 4x4x4 table
 //      of neighbouring octs (real or ghost), convert to primitives -> LDS
-//   B  MinMod slopes and the half-step predictor for the 160 cells that
-//      border a flux face (core + one layer per face); the left / right
-//      face states W~ +- D/2 replace the stencil in LDS
-//   C  240 face fluxes (HLLC) -> LDS
-//   D  per cell: coarse-fine register override, conservative FP64 update,
-//      fused CFL reduction on the new state; fine-side flux registers.
+//   B1 MinMod slopes and the half-step predictor for the 160 cells that
+//      border a flux face (the 64 core cells + one layer per face), kept in
+//      registers by the thread that owns the cell
+//   B2 the left states W~ + D/2 of the 240 faces replace the stencil in LDS
+//   C  HLLC on each face by the thread owning its upper cell (the right
+//      state W~ - D/2 never leaves registers); fluxes -> LDS
+//   D  per core cell: coarse-fine register override, conservative FP64
+//      update, fused CFL reduction on the new state; fine-side registers.
 // The scheme's definitions: ideal-gas primitives with floors; undivided
 // MinMod slopes; unsplit primitive predictor with h = lambda/2 (van Leer
 // 1979; Toro 2009 ch. 13-14); face states W~ +- D/2; HLLC with Davis wave
@@ -27,14 +29,28 @@ namespace ry {
 
 // ---------------------------------------------------------------------------
 // Tile geometry.  Stencil positions s in [-2,5]^3 relative to the tile's
-// first cell; the LDS box is padded (strides WSY, WSZ) to spread the
-// stencil reads over the LDS banks.
+// first cell.  The primitives that are needed sit in LDS as the 6^3 box
+// [-1,4]^3 (strides 1, WB, WBB) followed by the six 4x4 far planes at -2
+// and 5 (x-, x+, y-, y+, z-, z+); only the one-layer cells next to a far
+// plane read it.
 // ---------------------------------------------------------------------------
-constexpr int WSY = 8, WSZ = 68, WSIZE = 7 + 7 * WSY + 7 * WSZ + 1;   // primitives on [-2,5]^3
+constexpr int WB = 6, WBB = 36, NBOX = 216;
+constexpr int WSIZE = NBOX + 6 * 16;   // primitives per variable
 constexpr int NPOS_A = 304;   // positions whose primitives are needed
 constexpr int NPOS_B = 160;   // positions that get a predicted state (core + one layer per face)
+constexpr int NCORE = 64;     // B positions 0..63: the core cells, x fastest
+constexpr int NUPPER = 48;    // B positions 64..111: the upper one-layer cells
 constexpr int NFACE = 240;    // 3 directions x 5 planes x 16
-__host__ __device__ constexpr int widx(int x, int y, int z) { return (x + 2) + WSY * (y + 2) + WSZ * (z + 2); }
+__host__ __device__ constexpr int widx(int x, int y, int z) {
+  return (x >= -1 && x <= 4 && y >= -1 && y <= 4 && z >= -1 && z <= 4)
+             ? (x + 1) + WB * (y + 1) + WBB * (z + 1)
+             : (x == -2  ? NBOX + y + 4 * z
+                : x == 5  ? NBOX + 16 + y + 4 * z
+                : y == -2 ? NBOX + 32 + x + 4 * z
+                : y == 5  ? NBOX + 48 + x + 4 * z
+                : z == -2 ? NBOX + 64 + x + 4 * y
+                          : NBOX + 80 + x + 4 * y);
+}
 // Face index of the face along d whose upper cell is (x, y, z) (the plane
 // coordinate runs 0..4, the transverse ones 0..3); x runs fastest in every
 // direction so that neighbouring lanes touch neighbouring LDS words.
@@ -42,70 +58,72 @@ __host__ __device__ constexpr int fidx(int d, int x, int y, int z) {
   return d == 0 ? x + 5 * y + 20 * z : (d == 1 ? 80 + x + 4 * y + 20 * z : 160 + x + 4 * y + 16 * z);
 }
 
-// Per-item constants of the three phases, computed at compile time:
-//  a[i]: bits 0-9 LDS index, 10-15 oct-table slot, 16-18 in-oct cell, 19-27 raw (x+2)+8(y+2)+64(z+2)
-//  b[i]: LDS index of W of predicted position i
-//  bf[i][2d+s]: face (index fidx) whose left (s = 1:
-//      upper face of the cell) or right (s = 0: lower face) state position i
-//      provides along axis d, or 255 when there is none
+// Per-item constants, computed at compile time:
+//  a[i]: bits 0-9 LDS index, 10-15 oct-table slot, 16-18 in-oct cell,
+//        19-27 raw (x+2)+8(y+2)+64(z+2) of stencil position i
+//  b[i], i >= NCORE (one-layer cells: 48 upper ones at coordinate 4 along
+//        their normal, then 48 lower ones at -1): bits 0-8 LDS index of the
+//        cell, 9-17 LDS index of its outward neighbour (a far plane), 18-19
+//        normal axis, 20 upper layer, 21-28 the face (fidx) between the cell
+//        and the core.  b[i < NCORE] = LDS index of core cell i.
 struct StencilTables {
   uint32_t a[NPOS_A];
   uint32_t b[NPOS_B];
-  uint8_t bf[NPOS_B][6];
 };
 
 constexpr StencilTables make_tables() {
   StencilTables t{};
   int na = 0;
-  int nb = 0;
-  // predicted positions: the 64 core cells first, then the 96 one-layer face
-  // cells, so that each wavefront of phase B2 takes one uniform path
-  for (int pass = 0; pass < 2; ++pass)
-    for (int z = -2; z <= 5; ++z)
-      for (int y = -2; y <= 5; ++y)
-        for (int x = -2; x <= 5; ++x) {
-          const int ox = (x < 0 || x > 3), oy = (y < 0 || y > 3), oz = (z < 0 || z > 3);
-          const int nout = ox + oy + oz;
-          const bool ex = (x == -1 || x == 4), ey = (y == -1 || y == 4), ez = (z == -1 || z == 4);
-          const bool edges = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
-          const bool needA = (nout <= 1) || (nout == 2 && edges);
-          const bool needB = (pass == 0) ? (nout == 0) : (nout == 1 && edges);
-          if (pass == 0 && needA) {
-            const int slot = ((x >> 1) + 1) + 4 * ((y >> 1) + 1) + 16 * ((z >> 1) + 1);
-            const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-            const int raw = (x + 2) + 8 * (y + 2) + 64 * (z + 2);
-            t.a[na++] = uint32_t(widx(x, y, z) | (slot << 10) | (cb << 16) | (raw << 19));
-          }
-          if (needB) {
-            const int c[3] = {x, y, z};
-            for (int d = 0; d < 3; ++d) {
-              const int t1 = c[d == 0 ? 1 : 0], t2 = c[d == 2 ? 1 : 2];
-              const bool tin = t1 >= 0 && t1 <= 3 && t2 >= 0 && t2 <= 3;
-              const int lo = c[d], hi = c[d] + 1;       // planes of the lower / upper face
-              const int ux = x + (d == 0 ? 1 : 0), uy = y + (d == 1 ? 1 : 0), uz = z + (d == 2 ? 1 : 0);
-              t.bf[nb][2 * d + 0] = uint8_t((tin && lo >= 0 && lo <= 4) ? fidx(d, x, y, z) : 255);
-              t.bf[nb][2 * d + 1] = uint8_t((tin && hi >= 0 && hi <= 4) ? fidx(d, ux, uy, uz) : 255);
-            }
-            t.b[nb++] = uint32_t(widx(x, y, z));
-          }
+  for (int z = -2; z <= 5; ++z)
+    for (int y = -2; y <= 5; ++y)
+      for (int x = -2; x <= 5; ++x) {
+        const int ox = (x < 0 || x > 3), oy = (y < 0 || y > 3), oz = (z < 0 || z > 3);
+        const int nout = ox + oy + oz;
+        const bool ex = (x == -1 || x == 4), ey = (y == -1 || y == 4), ez = (z == -1 || z == 4);
+        const bool edges = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
+        if ((nout <= 1) || (nout == 2 && edges)) {
+          const int slot = ((x >> 1) + 1) + 4 * ((y >> 1) + 1) + 16 * ((z >> 1) + 1);
+          const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+          const int raw = (x + 2) + 8 * (y + 2) + 64 * (z + 2);
+          t.a[na++] = uint32_t(widx(x, y, z) | (slot << 10) | (cb << 16) | (raw << 19));
+        }
+      }
+  for (int i = 0; i < NCORE; ++i) t.b[i] = uint32_t(widx(i & 3, (i >> 2) & 3, i >> 4));
+  int nb = NCORE;
+  for (int up = 1; up >= 0; --up)
+    for (int d = 0; d < 3; ++d)
+      for (int t2 = 0; t2 < 4; ++t2)
+        for (int t1 = 0; t1 < 4; ++t1) {
+          int c[3] = {0, 0, 0};
+          c[d] = up ? 4 : -1;
+          c[d == 0 ? 1 : 0] = t1;
+          c[d == 2 ? 1 : 2] = t2;
+          int o[3] = {c[0], c[1], c[2]};
+          o[d] += up ? 1 : -1;
+          int u[3] = {c[0], c[1], c[2]};
+          if (!up) u[d] += 1;
+          const int face = fidx(d, u[0], u[1], u[2]);
+          t.b[nb++] = uint32_t(widx(c[0], c[1], c[2]) | (widx(o[0], o[1], o[2]) << 9) | (d << 18) | (up << 20) |
+                               (face << 21));
         }
   return t;
 }
 __constant__ StencilTables c_st = make_tables();
 static_assert(make_tables().a[NPOS_A - 1] != 0 && make_tables().b[NPOS_B - 1] != 0, "stencil tables");
-static_assert(WSIZE <= 1024, "LDS indices must fit the table fields");
+static_assert(WSIZE < 512 && NFACE < 256, "LDS indices must fit the table fields");
 
-// One LDS buffer serves three phases in turn: primitives on the padded
-// [-2,5]^3 stencil (A, B), then the left/right face states [2][NVAR][NFACE]
-// (B -> C), then the FP64 face fluxes [NVAR][NFACE] (C -> D).
+// One LDS buffer serves three phases in turn: primitives [NVAR][WSIZE] (A,
+// B1), then the left face states [NVAR][NFACE] and the upper one-layer
+// cells' right states [NVAR][NUPPER] (B2 -> C), then the face fluxes
+// [NVAR][NFACE] (C -> D).  Fluxes are stored in Real: in the mixed
+// form they are FP32 results, so FP32 storage loses nothing.
 template <typename Real>
 struct TileLDS {
-  Real W[NVAR][WSIZE];
+  static constexpr int NW = NVAR * WSIZE, NF = NVAR * (NFACE + NUPPER);
+  Real buf[NW > NF ? NW : NF];
   int32_t tab[TILE_TAB];  // ext oct index of the 4x4x4 oct neighbourhood
   uint8_t ref[TILE_TAB];  // refined-cell bytes of those octs
 };
-static_assert(sizeof(double) * NVAR * NFACE <= sizeof(float) * NVAR * WSIZE, "flux alias");
-static_assert(2 * NVAR * NFACE <= NVAR * WSIZE, "face-state alias");
 
 // ---------------------------------------------------------------------------
 // Scalar helpers.
@@ -214,6 +232,49 @@ __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real 
   Fn[4] = (EK + pK) * uK + w * (r * Es - EK);
 }
 
+// Unsplit half-step predictor of the primitives W0 with undivided slopes
+// D[axis][var] and h = lambda / 2.
+template <typename Real>
+__device__ __forceinline__ void predict(const Real W0[NVAR], const Real D[3][NVAR], Real h, Real g, Real P[NVAR]) {
+  const Real r = W0[0], u = W0[1], vv = W0[2], w = W0[3], p = W0[4];
+  const Real ir = rcp(r);
+  P[0] = r - h * (u * D[0][0] + r * D[0][1] + vv * D[1][0] + r * D[1][2] + w * D[2][0] + r * D[2][3]);
+  P[1] = u - h * (u * D[0][1] + vv * D[1][1] + w * D[2][1] + D[0][4] * ir);
+  P[2] = vv - h * (u * D[0][2] + vv * D[1][2] + w * D[2][2] + D[1][4] * ir);
+  P[3] = w - h * (u * D[0][3] + vv * D[1][3] + w * D[2][3] + D[2][4] * ir);
+  P[4] = p - h * (u * D[0][4] + vv * D[1][4] + w * D[2][4] + g * p * (D[0][1] + D[1][2] + D[2][3]));
+}
+
+// Floors of a face state; nfl counts activations.
+template <typename Real>
+__device__ __forceinline__ void floor_state(Real s[NVAR], Real rf, Real pf, int& nfl) {
+  nfl += int(s[0] < rf) + int(s[4] < pf);
+  s[0] = (s[0] < rf) ? rf : s[0];
+  s[4] = (s[4] < pf) ? pf : s[4];
+}
+
+// Flux through the lower face along axis D of a core cell: the left state
+// comes from LDS (FL[var * NFACE + f]), the right one, W~ - D/2, from the
+// cell's predicted state Pw and slope Pdd along D.  The HLLC runs in the
+// face-normal frame; F is returned in the global frame.
+template <typename Real, int D>
+__device__ __forceinline__ void core_face_flux(const Real* FL, int f, const Real Pw[NVAR], const Real Pdd[NVAR],
+                                               Real rf, Real pf, Real g, Real igm1, int& nfl, Real F[NVAR]) {
+  constexpr int iu = 1 + D, i1 = (D == 0) ? 2 : 1, i2 = (D == 2) ? 2 : 3;
+  Real wr[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) wr[v] = Pw[v] - Real(0.5) * Pdd[v];
+  floor_state<Real>(wr, rf, pf, nfl);
+  Real Fn[5];
+  hllc_n<Real>(FL[f], FL[iu * NFACE + f], FL[i1 * NFACE + f], FL[i2 * NFACE + f], FL[4 * NFACE + f], wr[0], wr[iu],
+               wr[i1], wr[i2], wr[4], g, igm1, Fn);
+  F[0] = Fn[0];
+  F[iu] = Fn[1];
+  F[i1] = Fn[2];
+  F[i2] = Fn[3];
+  F[4] = Fn[4];
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -270,6 +331,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
 
   // --- phase A: gather + primitives (all loads of the thread's positions are
   // issued before any conversion)
+  Real* W = S.buf;                              // [NVAR][WSIZE]
   constexpr int NRA = (NPOS_A + NT - 1) / NT;
   double Ua[NRA][NVAR];
   int iwa[NRA];
@@ -308,149 +370,166 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     if (iwa[rnd] >= 0) {
-      double W[NVAR];
-      cons2prim(Ua[rnd], W, g, rf, pf, nfl);
+      double Wc[NVAR];
+      cons2prim(Ua[rnd], Wc, g, rf, pf, nfl);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) S.W[v][iwa[rnd]] = Real(W[v]);
+      for (int v = 0; v < NVAR; ++v) W[v * WSIZE + iwa[rnd]] = Real(Wc[v]);
     }
   }
   __syncthreads();
 
-  // --- phase B: slopes + predictor, held in registers until every thread has
-  // read its stencil; then the face-extrapolated states W~ -+ D/2 (floored)
-  // replace the stencil in LDS.
+  // --- phase B1: slopes + predictor.  The core cell of a thread (round 0,
+  // tid < 64) keeps W~ and its slopes in registers for its six faces; a
+  // one-layer cell keeps only its state on the face toward the core.
   constexpr int NRB = (NPOS_B + NT - 1) / NT;
-  Real Pw[NRB][NVAR], Pd[NRB][3][NVAR];
+  constexpr int st[3] = {1, WB, WBB};
+  const bool core = (NT == 64) || tid < NCORE;
+  const int cx = tid & 3, cy = (tid >> 2) & 3, cz = (tid >> 4) & 3;
+  const Real rfr = Real(rf), pfr = Real(pf), gr = Real(g);
+  Real Pw[NVAR], Pd[3][NVAR];
+  Real Ls[NRB][NVAR];
+  uint32_t Lb[NRB];
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
-    if (active && i < NPOS_B) {
-      const int iw = int(c_st.b[i]);
+    Lb[rnd] = 0u;
+    if (!active || i >= NPOS_B) continue;
+    if (rnd == 0 && core) {
+      const int iw = (cx + 1) + WB * (cy + 1) + WBB * (cz + 1);
       Real W0[NVAR];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) W0[v] = S.W[v][iw];
-      constexpr int st[3] = {1, WSY, WSZ};
+      for (int v = 0; v < NVAR; ++v) W0[v] = W[v * WSIZE + iw];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int v = 0; v < NVAR; ++v)
-          Pd[rnd][d][v] = mmod(W0[v] - S.W[v][iw - st[d]], S.W[v][iw + st[d]] - W0[v]);
-      const Real(&D)[3][NVAR] = Pd[rnd];
-      const Real r = W0[0], u = W0[1], vv = W0[2], w = W0[3], p = W0[4];
-      const Real ir = rcp(r);
-      const Real gg = Real(g);
-      Pw[rnd][0] = r - h * (u * D[0][0] + r * D[0][1] + vv * D[1][0] + r * D[1][2] + w * D[2][0] + r * D[2][3]);
-      Pw[rnd][1] = u - h * (u * D[0][1] + vv * D[1][1] + w * D[2][1] + D[0][4] * ir);
-      Pw[rnd][2] = vv - h * (u * D[0][2] + vv * D[1][2] + w * D[2][2] + D[1][4] * ir);
-      Pw[rnd][3] = w - h * (u * D[0][3] + vv * D[1][3] + w * D[2][3] + D[2][4] * ir);
-      Pw[rnd][4] = p - h * (u * D[0][4] + vv * D[1][4] + w * D[2][4] + gg * p * (D[0][1] + D[1][2] + D[2][3]));
-    }
-  }
-  __syncthreads();
-  Real* FS = &S.W[0][0];                        // [2][NVAR][NFACE]: 0 = right state, 1 = left state
-  const Real rfr = Real(rf), pfr = Real(pf);
+          Pd[d][v] = mmod(W0[v] - W[v * WSIZE + iw - st[d]], W[v * WSIZE + iw + st[d]] - W0[v]);
+      predict<Real>(W0, Pd, h, gr, Pw);
+    } else {
+      const uint32_t e = c_st.b[i];
+      Lb[rnd] = e;
+      const int iw = int(e & 511u), far = int((e >> 9) & 511u), dn = int((e >> 18) & 3u);
+      const bool up = (e >> 20) & 1u;
+      Real W0[NVAR], D[3][NVAR], Q[NVAR];
 #pragma unroll
-  for (int rnd = 0; rnd < NRB; ++rnd) {
-    const int i = tid + NT * rnd;
-    if (active && i < NPOS_B) {
-      if (i < 64) {
-        // core cell: the lower and upper face along every axis
+      for (int v = 0; v < NVAR; ++v) W0[v] = W[v * WSIZE + iw];
+      Real Dn[NVAR];                            // the slope along the normal
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const int f = c_st.bf[i][k];
-          const int d = k >> 1, side = k & 1;
-          const Real sg = side ? Real(0.5) : Real(-0.5);
-          Real st[NVAR];
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) st[v] = Pw[rnd][v] + sg * Pd[rnd][d][v];
-          nfl += int(st[0] < rfr) + int(st[4] < pfr);
-          st[0] = (st[0] < rfr) ? rfr : st[0];
-          st[4] = (st[4] < pfr) ? pfr : st[4];
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) FS[(side * NVAR + v) * NFACE + f] = st[v];
-        }
-      } else {
-        // one-layer cell: exactly one face, towards the core
-        int k = 0;
-#pragma unroll
-        for (int kk = 1; kk < 6; ++kk) k = (c_st.bf[i][kk] != 255) ? kk : k;
-        const int f = c_st.bf[i][k];
-        const int d = k >> 1, side = k & 1;
-        const Real sg = side ? Real(0.5) : Real(-0.5);
-        Real st[NVAR];
+      for (int d = 0; d < 3; ++d) {
+        const int lo = (d == dn && !up) ? far : iw - st[d];
+        const int hi = (d == dn && up) ? far : iw + st[d];
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-          const Real dv = (d == 0) ? Pd[rnd][0][v] : ((d == 1) ? Pd[rnd][1][v] : Pd[rnd][2][v]);
-          st[v] = Pw[rnd][v] + sg * dv;
+          const Real sl = mmod(W0[v] - W[v * WSIZE + lo], W[v * WSIZE + hi] - W0[v]);
+          D[d][v] = sl;
+          Dn[v] = (d == 0 || d == dn) ? sl : Dn[v];
         }
-        nfl += int(st[0] < rfr) + int(st[4] < pfr);
-        st[0] = (st[0] < rfr) ? rfr : st[0];
-        st[4] = (st[4] < pfr) ? pfr : st[4];
-#pragma unroll
-        for (int v = 0; v < NVAR; ++v) FS[(side * NVAR + v) * NFACE + f] = st[v];
       }
+      predict<Real>(W0, D, h, gr, Q);
+      const Real sg = up ? Real(-0.5) : Real(0.5);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) Ls[rnd][v] = Q[v] + sg * Dn[v];
+      floor_state<Real>(Ls[rnd], rfr, pfr, nfl);
     }
   }
   __syncthreads();
 
-  // --- phase C: face fluxes (kept in registers, then written over the states)
-  constexpr int NR = (NFACE + NT - 1) / NT;
-  double Fr[NR][NVAR];
+  // --- phase B2: the left states (W~ + D/2 of the lower cell) of the 240
+  // faces replace the primitives in LDS
+  Real* FL = S.buf;                             // [NVAR][NFACE]
+  Real* FR = S.buf + NVAR * NFACE;              // [NVAR][NUPPER]: right states of the upper layer
 #pragma unroll
-  for (int rnd = 0; rnd < NR; ++rnd) {
-    const int f = tid + NT * rnd;
-    if (active && f < NFACE) {
-      const int d = f / 80;
-      Real WL[NVAR], WR[NVAR];
+  for (int rnd = 0; rnd < NRB; ++rnd) {
+    const int i = tid + NT * rnd;
+    if (!active || i >= NPOS_B) continue;
+    if (rnd == 0 && core) {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        WL[v] = FS[(NVAR + v) * NFACE + f];
-        WR[v] = FS[v * NFACE + f];
+      for (int d = 0; d < 3; ++d) {
+        Real s[NVAR];
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) s[v] = Pw[v] + Real(0.5) * Pd[d][v];
+        floor_state<Real>(s, rfr, pfr, nfl);
+        const int f = fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) FL[v * NFACE + f] = s[v];
       }
-      const Real unl = (d == 0) ? WL[1] : ((d == 1) ? WL[2] : WL[3]);
-      const Real unr = (d == 0) ? WR[1] : ((d == 1) ? WR[2] : WR[3]);
-      const Real t1l = (d == 0) ? WL[2] : WL[1], t1r = (d == 0) ? WR[2] : WR[1];
-      const Real t2l = (d == 2) ? WL[2] : WL[3], t2r = (d == 2) ? WR[2] : WR[3];
-      Real Fn[5];
-      hllc_n<Real>(WL[0], unl, t1l, t2l, WL[4], WR[0], unr, t1r, t2r, WR[4], Real(g), igm1, Fn);
-      Fr[rnd][0] = double(Fn[0]);
-      Fr[rnd][1] = double((d == 0) ? Fn[1] : Fn[2]);
-      Fr[rnd][2] = double((d == 1) ? Fn[1] : ((d == 0) ? Fn[2] : Fn[3]));
-      Fr[rnd][3] = double((d == 2) ? Fn[1] : Fn[3]);
-      Fr[rnd][4] = double(Fn[4]);
+    } else if (!((Lb[rnd] >> 20) & 1u)) {
+      const int f = int(Lb[rnd] >> 21);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) FL[v * NFACE + f] = Ls[rnd][v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) FR[v * NUPPER + (i - NCORE)] = Ls[rnd][v];
     }
   }
   __syncthreads();
-  double* SF = reinterpret_cast<double*>(&S.W[0][0]);   // [5][NFACE]
+
+  // --- phase C: HLLC on the faces whose upper cell the thread holds (a core
+  // cell: its three lower faces; an upper one-layer cell: its face, read in
+  // the face-normal frame straight from LDS)
+  Real Fc[3][NVAR];
+  Real Fl[NRB][NVAR];
 #pragma unroll
-  for (int rnd = 0; rnd < NR; ++rnd) {
-    const int f = tid + NT * rnd;
-    if (active && f < NFACE) {
-#pragma unroll
-      for (int v = 0; v < NVAR; ++v) SF[v * NFACE + f] = Fr[rnd][v];
+  for (int rnd = 0; rnd < NRB; ++rnd) {
+    const int i = tid + NT * rnd;
+    if (!active || i >= NPOS_B) continue;
+    if (rnd == 0 && core) {
+      core_face_flux<Real, 0>(FL, fidx(0, cx, cy, cz), Pw, Pd[0], rfr, pfr, gr, igm1, nfl, Fc[0]);
+      core_face_flux<Real, 1>(FL, fidx(1, cx, cy, cz), Pw, Pd[1], rfr, pfr, gr, igm1, nfl, Fc[1]);
+      core_face_flux<Real, 2>(FL, fidx(2, cx, cy, cz), Pw, Pd[2], rfr, pfr, gr, igm1, nfl, Fc[2]);
+    } else if ((Lb[rnd] >> 20) & 1u) {
+      const int f = int(Lb[rnd] >> 21), dn = int((Lb[rnd] >> 18) & 3u), k = i - NCORE;
+      const int iu = 1 + dn, i1 = (dn == 0) ? 2 : 1, i2 = (dn == 2) ? 2 : 3;
+      hllc_n<Real>(FL[f], FL[iu * NFACE + f], FL[i1 * NFACE + f], FL[i2 * NFACE + f], FL[4 * NFACE + f], FR[k],
+                   FR[iu * NUPPER + k], FR[i1 * NUPPER + k], FR[i2 * NUPPER + k], FR[4 * NUPPER + k], gr, igm1,
+                   Fl[rnd]);
     }
   }
   __syncthreads();
+  Real* SF = S.buf;                             // [NVAR][NFACE]
+#pragma unroll
+  for (int rnd = 0; rnd < NRB; ++rnd) {
+    const int i = tid + NT * rnd;
+    if (!active || i >= NPOS_B) continue;
+    if (rnd == 0 && core) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int f = fidx(d, cx, cy, cz);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) SF[v * NFACE + f] = Fc[d][v];
+      }
+    } else if ((Lb[rnd] >> 20) & 1u) {
+      // Fl is in the face-normal frame: rotate back on the way out
+      const int f = int(Lb[rnd] >> 21), dn = int((Lb[rnd] >> 18) & 3u);
+      const int iu = 1 + dn, i1 = (dn == 0) ? 2 : 1, i2 = (dn == 2) ? 2 : 3;
+      SF[f] = Fl[rnd][0];
+      SF[iu * NFACE + f] = Fl[rnd][1];
+      SF[i1 * NFACE + f] = Fl[rnd][2];
+      SF[i2 * NFACE + f] = Fl[rnd][3];
+      SF[4 * NFACE + f] = Fl[rnd][4];
+    }
+  }
+  __syncthreads();
+
   // --- phase D: the first wavefront updates the tile's 64 cells
   if (tid < 64) {
-    const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
     const int ts = ((cx >> 1) + 1) + 4 * ((cy >> 1) + 1) + 16 * ((cz >> 1) + 1);
     const int32_t e = active ? S.tab[ts] : -1;
     const int ci = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
     const bool leaf = (e >= 0) && (e < A.n_oct) && !((S.ref[ts] >> ci) & 1);
     double s = 0.0;
     if (leaf) {
-      const int cc[3] = {cx, cy, cz};
       double acc[NVAR] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const int fm = fidx(d, cx, cy, cz);
+        // the lower face's flux is the thread's own (phase C), the upper
+        // one comes from the neighbouring cell's thread through LDS
         const int fp = fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
         double Fm[NVAR], Fp[NVAR];
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-          Fm[v] = SF[v * NFACE + fm];
-          Fp[v] = SF[v * NFACE + fp];
+          Fm[v] = double(Fc[d][v]);
+          Fp[v] = double(SF[v * NFACE + fp]);
         }
         if (A.child) {
           // a refined neighbour across a face: use its child oct's register
@@ -533,8 +612,8 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
         double* q = A.reg_own + (int64_t(eb) * 6 + face) * NVAR * 2;
 #pragma unroll
         for (int v = 0; v < NVAR; ++v)
-          q[2 * v + A.substep] =
-              (SF[v * NFACE + fi[0]] + SF[v * NFACE + fi[1]]) + (SF[v * NFACE + fi[2]] + SF[v * NFACE + fi[3]]);
+          q[2 * v + A.substep] = (double(SF[v * NFACE + fi[0]]) + double(SF[v * NFACE + fi[1]])) +
+                                 (double(SF[v * NFACE + fi[2]]) + double(SF[v * NFACE + fi[3]]));
       }
     }
   }
@@ -639,6 +718,7 @@ int launch_hydro(const HydroArgs& a, int precision, const ry_tuning& t, int num_
   switch (key) {
     case 11: return launch_hydro_t<double, 1, 1>(a, t, num_cu, s);
     case 21: return launch_hydro_t<double, 2, 1>(a, t, num_cu, s);
+    case 41: return launch_hydro_t<double, 4, 1>(a, t, num_cu, s);
     case 12: return launch_hydro_t<double, 1, 2>(a, t, num_cu, s);
     case 22: return launch_hydro_t<double, 2, 2>(a, t, num_cu, s);
     case 14: return launch_hydro_t<double, 1, 4>(a, t, num_cu, s);

@@ -190,7 +190,7 @@ def test_tuning_invariance_bit_exact(ry):
     prob = cases.amr_blob()
     ref = None
     for t in ([1, 0, 4, 1, 4], [1, 0, 4, 1, 1], [2, 0, 4, 1, 1], [2, 0, 4, 1, 2], [1, 0, 4, 1, 2],
-              [1, 1, 16, 1, 4], [2, 1, 8, 4, 1], [1, 1, 2, 2, 2]):
+              [4, 0, 4, 1, 1], [1, 1, 16, 1, 4], [2, 1, 8, 4, 1], [4, 1, 8, 2, 1], [1, 1, 2, 2, 2]):
         g = ry.Hydro(prob)
         g.set_tuning(*t)
         g.advance(2)
