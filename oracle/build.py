@@ -8,12 +8,14 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libryo.so")
+SOURCES = ["ryo.c", "poisson.c"]
+HEADERS = ["ryo.h", "poisson.h"]
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
            "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", LIB + ".tmp", os.path.join(HERE, "ryo.c"), "-lm"]
+           "-o", LIB + ".tmp"] + [os.path.join(HERE, f) for f in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -22,10 +24,8 @@ def build(verbose: bool = False) -> str:
 
 
 def ensure_built() -> str:
-    src = os.path.join(HERE, "ryo.c")
-    hdr = os.path.join(HERE, "ryo.h")
-    if (not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(src)
-            or os.path.getmtime(LIB) < os.path.getmtime(hdr)):
+    if not os.path.exists(LIB) or any(os.path.getmtime(LIB) < os.path.getmtime(os.path.join(HERE, f))
+                                      for f in SOURCES + HEADERS):
         build()
     return LIB
 
