@@ -30,6 +30,15 @@ EXPORTS = [
     "ry_kernel_time", "ry_copy_probe", "ry_last_error", "ry_mesh_build", "ry_mesh_level",
     "ry_mesh_free", "ry_hilbert_key",
 ]
+# Every function declared in include/ry_poisson.h.
+POISSON_EXPORTS = [
+    "ry_poisson_create", "ry_poisson_destroy", "ry_poisson_set_rhs", "ry_poisson_solve", "ry_poisson_iterate",
+    "ry_poisson_eps_history", "ry_poisson_download", "ry_poisson_scalars", "ry_poisson_set_timing",
+    "ry_poisson_kernel_time", "ry_poisson_last_error",
+]
+RY_PBC_PERIODIC, RY_PBC_DIRICHLET = 0, 1
+RY_PC_NONE, RY_PC_STENCIL7 = 0, 1
+POISSON_VECTORS = ("x", "r", "u", "w", "z", "q", "s", "p")
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -43,6 +52,11 @@ class RyConfig(C.Structure):
                 ("refine_param", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_user", C.c_void_p)]
+
+
+class RyPoissonConfig(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("bc", C.c_int32), ("precond", C.c_int32), ("stream", C.c_void_p),
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", C.c_void_p)]
 
 
 class RyTuning(C.Structure):
@@ -100,6 +114,17 @@ def lib():
         "ry_mesh_level": ([P, I32, C.POINTER(I64), P, P, C.POINTER(I64)], I32),
         "ry_mesh_free": ([P], None),
         "ry_hilbert_key": ([I32, C.c_uint32, C.c_uint32, C.c_uint32], C.c_uint64),
+        "ry_poisson_create": ([C.POINTER(RyPoissonConfig), C.POINTER(P)], I32),
+        "ry_poisson_destroy": ([P], None),
+        "ry_poisson_set_rhs": ([P, P, P], I32),
+        "ry_poisson_solve": ([P, D, I32, C.POINTER(I32)], I32),
+        "ry_poisson_iterate": ([P, I32], I32),
+        "ry_poisson_eps_history": ([P, P, I32, C.POINTER(I32)], I32),
+        "ry_poisson_download": ([P, I32, P], I32),
+        "ry_poisson_scalars": ([P, C.POINTER(D), C.POINTER(D), C.POINTER(I32)], I32),
+        "ry_poisson_set_timing": ([P, I32], I32),
+        "ry_poisson_kernel_time": ([P, C.POINTER(I32), C.POINTER(D)], I32),
+        "ry_poisson_last_error": ([P], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -362,4 +387,107 @@ def create_status(prob, precision="fp64"):
     rc = lib().ry_create(C.byref(cfg), C.byref(ctx))
     if rc == RY_OK:
         lib().ry_destroy(ctx)
+    return rc
+
+
+def _poisson_config(shape, bc, precond, stream_handle, mem):
+    """shape = (n2, n1, n0) of a numpy grid array (x fastest)."""
+    cfg = RyPoissonConfig()
+    cfg.n[0], cfg.n[1], cfg.n[2] = int(shape[2]), int(shape[1]), int(shape[0])
+    cfg.bc, cfg.precond = bc, precond
+    cfg.stream = stream_handle
+    if mem is not None:
+        cfg.dev_alloc = mem.alloc_cb
+        cfg.dev_free = mem.free_cb
+    return cfg
+
+
+class Poisson:
+    """PPCG Poisson solver on one uniform grid (include/ry_poisson.h).
+
+    Grid arrays are numpy arrays of shape (n2, n1, n0), x fastest."""
+
+    def __init__(self, shape, bc=RY_PBC_PERIODIC, precond=RY_PC_STENCIL7, device="cuda", torch_memory=True):
+        import torch
+        self.torch = torch
+        self.shape = tuple(int(v) for v in shape)
+        self.ctx = C.c_void_p()
+        self.stream = torch.cuda.Stream(device=device)       # default priority
+        self.mem = _TorchMemory(torch, device) if torch_memory else None
+        cfg = _poisson_config(self.shape, bc, precond, self.stream.cuda_stream, self.mem)
+        self._cfg = cfg
+        self._check(lib().ry_poisson_create(C.byref(cfg), C.byref(self.ctx)), "ry_poisson_create")
+
+    def _check(self, rc, what):
+        if rc != RY_OK:
+            msg = lib().ry_poisson_last_error(self.ctx).decode() if self.ctx else ""
+            raise RyError(what, rc, msg)
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            lib().ry_poisson_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _grid(self, a):
+        a = np.ascontiguousarray(a, np.float64)
+        if a.shape != self.shape:
+            raise ValueError(f"grid array of shape {a.shape}, solver shape {self.shape}")
+        return a
+
+    def set_rhs(self, b, x0=None):
+        self._b = self._grid(b)
+        self._x0 = None if x0 is None else self._grid(x0)
+        self._check(lib().ry_poisson_set_rhs(self.ctx, self._b.ctypes.data,
+                                             None if self._x0 is None else self._x0.ctypes.data),
+                    "ry_poisson_set_rhs")
+
+    def solve(self, eps=1e-4, max_iter=1000):
+        n = C.c_int32()
+        self._check(lib().ry_poisson_solve(self.ctx, eps, max_iter, C.byref(n)), "ry_poisson_solve")
+        return n.value
+
+    def iterate(self, n):
+        self._check(lib().ry_poisson_iterate(self.ctx, n), "ry_poisson_iterate")
+
+    def eps_history(self):
+        buf = np.zeros(65536)
+        n = C.c_int32()
+        self._check(lib().ry_poisson_eps_history(self.ctx, buf.ctypes.data, len(buf), C.byref(n)),
+                    "ry_poisson_eps_history")
+        return buf[: n.value].copy()
+
+    def download(self, which="x"):
+        out = np.zeros(self.shape)
+        self._check(lib().ry_poisson_download(self.ctx, POISSON_VECTORS.index(which), out.ctypes.data),
+                    "ry_poisson_download")
+        return out
+
+    def state(self):
+        """All eight recurrence vectors plus (alpha_prev, gamma_prev, i)."""
+        a, g, i = C.c_double(), C.c_double(), C.c_int32()
+        self._check(lib().ry_poisson_scalars(self.ctx, C.byref(a), C.byref(g), C.byref(i)), "ry_poisson_scalars")
+        return {k: self.download(k) for k in POISSON_VECTORS}, a.value, g.value, i.value
+
+    def set_timing(self, on=True):
+        self._check(lib().ry_poisson_set_timing(self.ctx, 1 if on else 0), "ry_poisson_set_timing")
+
+    def kernel_time(self):
+        n, ms = C.c_int32(), C.c_double()
+        self._check(lib().ry_poisson_kernel_time(self.ctx, C.byref(n), C.byref(ms)), "ry_poisson_kernel_time")
+        return n.value, ms.value
+
+
+def poisson_create_status(shape, bc=RY_PBC_PERIODIC, precond=RY_PC_STENCIL7):
+    """ry_poisson_create's status (validation runs before any device call)."""
+    cfg = _poisson_config(shape, bc, precond, None, None)
+    ctx = C.c_void_p()
+    rc = lib().ry_poisson_create(C.byref(cfg), C.byref(ctx))
+    if rc == RY_OK:
+        lib().ry_poisson_destroy(ctx)
     return rc

@@ -19,20 +19,35 @@ import cases
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    text = open(os.path.join(ROOT, "include", "ry.h")).read()
+def header_functions(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = set(re.findall(r"\b(ry_[a-z_0-9]+)\s*\(", text))
     return sorted(n for n in names if n not in ("ry_fill_fn",))
 
 
-def test_library_exports_every_header_function():
+def test_every_header_is_covered():
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["ry.h", "ry_poisson.h"]
+
+
+@pytest.mark.parametrize("header,exports", [("ry.h", ry.EXPORTS), ("ry_poisson.h", ry.POISSON_EXPORTS)])
+def test_library_exports_every_header_function(header, exports):
     L = ry.lib()
-    declared = header_functions()
-    assert len(declared) >= 20
+    declared = header_functions(header)
+    assert len(declared) >= 10
     missing = [n for n in declared if not hasattr(L, n)]
     assert not missing, missing
-    assert sorted(ry.EXPORTS) == declared
+    assert sorted(exports) == declared
+
+
+@pytest.mark.parametrize("shape,bc,pc", [
+    ((4, 4, 0), ry.RY_PBC_PERIODIC, ry.RY_PC_STENCIL7),     # empty axis
+    ((4, 4, 4), 2, ry.RY_PC_STENCIL7),                      # unknown boundary
+    ((4, 4, 4), ry.RY_PBC_DIRICHLET, 3),                    # unknown preconditioner
+    ((2048, 1024, 1024), ry.RY_PBC_PERIODIC, ry.RY_PC_NONE),  # 2^31 cells
+])
+def test_poisson_create_rejects_invalid_config(shape, bc, pc):
+    assert ry.poisson_create_status(shape, bc, pc) == ry.RY_EINVAL
 
 
 @pytest.mark.parametrize("mutate,expect", [

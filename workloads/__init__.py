@@ -27,6 +27,10 @@ v_z; box b of the batched workload uses 5000 + 10 b + field):
 * batch    -- 512 periodic boxes with sides in {16,24,32,40,48}, per box
               sigma ~ U(0.5, 1.5), rms Mach ~ U(0.5, 3), gamma 5/3, uniform
               temperature p = rho.
+* poisson  -- source of the cell-level Poisson equation on one uniform
+              periodic level: the uniform generator's lognormal density
+              (sigma_ln 1, smoothing 4 cells per 128 cells of box, seed
+              6000), b = (mean rho - rho) dx^2 in units 4 pi G = 1, box 1.
 """
 from __future__ import annotations
 
@@ -303,3 +307,14 @@ def random_smooth(n=16, seed=7, sigma_ln=0.5, mach=0.8, gamma=1.4, smooth=2.0) -
     U = conserved(rho, vx, vy, vz, p, gamma)
     lvl = int(round(math.log2(n)))
     return Problem(f"random{n}", lvl, lvl, (n, n, n), gamma, U)
+
+
+# ---------------------------------------------------------------------------
+# Poisson solver workload: gravity source of a lognormal density on one
+# uniform periodic level
+# ---------------------------------------------------------------------------
+def poisson_source(n: int = 256, seed: int = 6000, sigma_ln: float = 1.0) -> np.ndarray:
+    """b[z, y, x] = (mean(rho) - rho) / n^2 (zero sum, as a periodic problem needs)."""
+    rho = np.exp(sigma_ln * smooth_gaussian_field(n, seed, 4.0 * n / 128.0))
+    b = (rho.mean() - rho) / float(n * n)
+    return b - b.mean()
