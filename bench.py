@@ -10,6 +10,12 @@ its launch stream, and the CPU oracle timed on the host as a baseline.
 
 A cell-update is one leaf cell advanced by one step of its own level;
 algorithmic HBM bytes are 80 per cell-update (5 FP64 read + 5 written).
+
+The line also carries the uniform-level Poisson solver (PPCG with the
+seven-point preconditioner) on a 256^3 periodic gravity source: iterations
+to eps = 1e-4 against pipelined plain CG, time to solution, and the
+iteration kernel's rate against HBM (128 algorithmic bytes per cell and
+iteration: the eight recurrence vectors read and written once).
 """
 from __future__ import annotations
 
@@ -95,8 +101,25 @@ def run_uniform(precision, steps, warmup, tune, fixed=None):
     e0 = h.totals()[4]
     dt_graph, _ = time_advance(h, steps, warmup, timing=False)
     dt_ev, (nl, ms) = time_advance(h, steps, 0, timing=True)
+    pcie = pcie_inclusive(h, steps)
     return dict(prob=prob, h=h, cups=cups, dt_graph=dt_graph, dt_timed=dt_ev, launches=nl, kernel_ms=ms,
-                tuning=tuning or h.tuning(), floors=h.floors(), e0=e0)
+                tuning=tuning or h.tuning(), floors=h.floors(), e0=e0, pcie=pcie)
+
+
+def pcie_inclusive(h, steps):
+    """Cell-updates/s when the state crosses PCIe both ways: upload the
+    current state from the host, advance `steps` coarse steps, download."""
+    import torch
+    lv = h.prob.level_min
+    U = h.download(lv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.upload(lv, U)
+    h.advance(steps)
+    h.download(lv)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return cell_updates_per_coarse_step(h) * steps / el
 
 
 def run_zoom(prob, precision, steps, tune):
@@ -151,7 +174,7 @@ def compare_forms(hf, hm, e0f, e0m):
             "energy_drift_fp64": float(abs(ef - e0f) / abs(e0f)), "energy_drift_mixed": float(abs(em - e0m) / abs(e0m))}
 
 
-def cpu_baseline(budget_s=15.0):
+def cpu_baseline(budget_s=12.0):
     """The oracle, as it is, on the host: 128^3 uniform box, whole steps
     until about budget_s of wall time."""
     import workloads as W
@@ -165,11 +188,56 @@ def cpu_baseline(budget_s=15.0):
         o.advance(1)
         n += 1
         el = time.perf_counter() - t0
-        if el > budget_s or n >= 10:
+        if el > budget_s or n >= 100:
             break
     cups = 128 ** 3 * n / el
     return {"value": cups, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"uniform 128^3 periodic box, {n} whole coarse steps ({el:.1f} s wall)"}
+
+
+POISSON_BYTES_PER_CELL = 128
+
+
+def run_poisson(n=256, eps=1e-4, timed_iters=20):
+    """PPCG vs pipelined plain CG on the n^3 periodic gravity source."""
+    import torch
+    import workloads as W
+    from paper_2411_14631_amd import ry
+    b = W.poisson_source(n)
+    N = n ** 3
+    res = {"workload": f"{n}^3 periodic lognormal gravity source, FP64, eps target {eps:g}", "cells": N,
+           "alg_bytes_per_iteration": POISSON_BYTES_PER_CELL * N}
+    for name, pc in (("ppcg", ry.RY_PC_STENCIL7), ("cg", ry.RY_PC_NONE)):
+        g = ry.Poisson(b.shape, ry.RY_PBC_PERIODIC, pc)
+        g.set_rhs(b)
+        g.solve(eps, 5000)                      # warm-up (graph capture, clocks)
+        g.set_rhs(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = g.solve(eps, 5000)
+        torch.cuda.synchronize()
+        solve_s = time.perf_counter() - t0
+        eps_reached = float(g.eps_history()[-1])
+        g.set_rhs(b)
+        g.set_timing(True)
+        g.iterate(timed_iters)
+        nl, ms = g.kernel_time()
+        g.set_timing(False)
+        kern_ms = ms / max(nl, 1)
+        achieved = POISSON_BYTES_PER_CELL * N / (kern_ms * 1e-3) / 1e9
+        res[name] = {"iterations": k, "eps_reached": eps_reached, "solve_ms": round(1e3 * solve_s, 3),
+                     "ms_per_iteration": round(1e3 * solve_s / max(k, 1), 4),
+                     "kernel_avg_ms": round(kern_ms, 5), "achieved_GBps": round(achieved, 1),
+                     "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    res["iteration_ratio_cg_over_ppcg"] = round(res["cg"]["iterations"] / max(res["ppcg"]["iterations"], 1), 3)
+    res["paper_iteration_ratio"] = 1.86
+    res["roofline"] = {"bound": "hbm", "kernel": "ppcg_iterate_kernel<stencil7>",
+                       "achieved": res["ppcg"]["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": res["ppcg"]["hbm_frac"]}
+    return res
 
 
 def main():
@@ -179,6 +247,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-zoom", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-poisson", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tuning", type=str, default="",
                     help="fixed hydro tuning tiles_per_wg,persistent,waves_per_cu,batch,waves_per_tile")
@@ -282,6 +351,11 @@ def main():
             del bh
             torch.cuda.empty_cache()
 
+    poisson = None
+    if not args.no_poisson:
+        log("bench: poisson 256^3 ppcg vs cg")
+        poisson = run_poisson()
+
     cpu = None
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
@@ -293,12 +367,14 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "uniform 128^3 periodic lognormal box (262144 octs), FP64, gamma 5/3, CFL 0.8",
                    "cells": 128 ** 3, "cell_updates_per_step": f["cups"], "tuning": f["tuning"],
-                   "graph_value": f["cups"] * args.steps / f["dt_graph"], "floor_activations": f["floors"]},
+                   "graph_value": f["cups"] * args.steps / f["dt_graph"], "floor_activations": f["floors"],
+                   "pcie_inclusive_value": f["pcie"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": mixed,
         "zoom_amr": zoom,
         "batch_boxes": batch,
+        "poisson": poisson,
     }
     print(json.dumps(out), flush=True)
 

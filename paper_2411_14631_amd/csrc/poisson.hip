@@ -32,6 +32,7 @@
 
 namespace ryp {
 
+
 constexpr int TX = 32, TY = 8, NTH = TX * TY;
 constexpr int WX = TX + 4, WY = TY + 4, WPL = WX * WY;   // w plane, 2-cell halo
 constexpr int MX = TX + 2, MY = TY + 2, MPL = MX * MY;   // m plane, 1-cell halo
@@ -185,12 +186,36 @@ __global__ __launch_bounds__(NTH) void ppcg_iterate_kernel(IterArgs A) {
   double acc_g = 0.0, acc_d = 0.0;
   const int X = x0 + tx, Y = y0 + ty;
   const bool own = X < g.n0 && Y < g.n1;
+  const int64_t plane = int64_t(g.n0) * g.n1;
+  const int64_t col = int64_t(X) + int64_t(g.n0) * Y;
+  // The eight recurrence vectors are touched once per iteration: stream
+  // them with non-temporal loads and stores so that L2 keeps the w planes
+  // the neighbouring workgroups read as halo.
+  constexpr int NW = (WPL + NTH - 1) / NTH;
   for (int z = z0; z < z1; ++z) {
-    load_w(z + 2);
+    double wr[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int k = tid + j * NTH;
+      if (k < WPL) wr[j] = grid_val(win, g, x0 - 2 + k % WX, y0 - 2 + k / WX, z + 2);
+    }
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int k = tid + j * NTH;
+      if (k < WPL) Wp[wslot(z + 2)][k] = wr[j];
+    }
     __syncthreads();
     comp_m(z + 1);
     __syncthreads();
     if (own) {
+      const int64_t i = col + plane * z;
+      const double z_old = __builtin_nontemporal_load(A.z + i);
+      const double q_old = __builtin_nontemporal_load(A.q + i);
+      const double s_old = __builtin_nontemporal_load(A.s + i);
+      const double p_old = __builtin_nontemporal_load(A.p + i);
+      const double u_old = __builtin_nontemporal_load(A.u + i);
+      const double x_old = __builtin_nontemporal_load(A.x + i);
+      const double r_old = __builtin_nontemporal_load(A.r + i);
       const double* mm = Mp[mslot(z - 1)];
       const double* m0 = Mp[mslot(z)];
       const double* mp = Mp[mslot(z + 1)];
@@ -204,23 +229,22 @@ __global__ __launch_bounds__(NTH) void ppcg_iterate_kernel(IterArgs A) {
       const double mv = m0[c];
       const double nv = 6.0 * mv - s;                         // n_i = A m_i
       const double wv = Wp[wslot(z)][(tx + 2) + WX * (ty + 2)];
-      const int64_t i = int64_t(X) + int64_t(g.n0) * (int64_t(Y) + int64_t(g.n1) * z);
-      const double zz = nv + beta * A.z[i];
-      const double qq = mv + beta * A.q[i];
-      const double ss = wv + beta * A.s[i];
-      const double pp = A.u[i] + beta * A.p[i];
-      const double xx = A.x[i] + alpha * pp;
-      const double rr = A.r[i] - alpha * ss;
-      const double uu = A.u[i] - alpha * qq;
+      const double zz = nv + beta * z_old;
+      const double qq = mv + beta * q_old;
+      const double ss = wv + beta * s_old;
+      const double pp = u_old + beta * p_old;
+      const double xx = x_old + alpha * pp;
+      const double rr = r_old - alpha * ss;
+      const double uu = u_old - alpha * qq;
       const double ww = wv - alpha * zz;
-      A.z[i] = zz;
-      A.q[i] = qq;
-      A.s[i] = ss;
-      A.p[i] = pp;
-      A.x[i] = xx;
-      A.r[i] = rr;
-      A.u[i] = uu;
-      wout[i] = ww;
+      __builtin_nontemporal_store(zz, A.z + i);
+      __builtin_nontemporal_store(qq, A.q + i);
+      __builtin_nontemporal_store(ss, A.s + i);
+      __builtin_nontemporal_store(pp, A.p + i);
+      __builtin_nontemporal_store(xx, A.x + i);
+      __builtin_nontemporal_store(rr, A.r + i);
+      __builtin_nontemporal_store(uu, A.u + i);
+      __builtin_nontemporal_store(ww, wout + i);
       acc_g += rr * uu;
       acc_d += ww * uu;
     }
