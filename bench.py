@@ -251,7 +251,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tuning", type=str, default="",
                     help="fixed hydro tuning tiles_per_wg,persistent,waves_per_cu,batch,waves_per_tile")
-    ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--only", choices=["fp64", "mixed", "poisson"], default=None)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first launch a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -273,6 +273,10 @@ def main():
             f"({2 * (args.copy_probe_mb << 20) / (ms * 1e-3) / 1e9:.1f} GB/s)")
         probe.close()
 
+    if args.only == "poisson":
+        log("bench: poisson 256^3 only")
+        print(json.dumps(run_poisson()), flush=True)
+        return
     if args.only:
         log(f"bench: uniform 128^3 {args.only} only")
         r = run_uniform(args.only, args.steps, args.warmup, tune, fixed)
