@@ -31,16 +31,18 @@
 #include <omp.h>
 #endif
 
-#define NV 5
+/* NV: array bound (5 hydro variables + the most passive scalars); c->nv:
+ * the variables of this context (5 + nscalar). */
+#define NV (5 + RYO_MAX_SCALARS)
 
 typedef struct {
   int64_t n;          /* number of octs                                   */
   uint64_t* key;      /* Hilbert keys, ascending                          */
   int32_t* oc;        /* oct coordinates, 3 per oct                       */
   uint8_t* refined;   /* bit c set when cell c has a child oct            */
-  double* U;          /* state, 5 planes of 8n                            */
+  double* U;          /* state, nv planes of 8n                           */
   double* Un;         /* next state                                       */
-  double* reg;        /* flux registers: [oct][face 6][var 5][substep 2]  */
+  double* reg;        /* flux registers: [oct][face 6][var nv][substep 2] */
   uint64_t* hkey;     /* hash table: packed coords + 1 (0 = empty)        */
   int64_t* hval;
   uint64_t hmask;
@@ -48,6 +50,7 @@ typedef struct {
 
 struct ryo_ctx {
   ryo_config cfg;
+  int nv;                    /* 5 + passive scalars                       */
   int nlev;
   int bits0;                 /* Hilbert bits per axis at level_min        */
   level_t lev[RYO_MAX_LEVELS];
@@ -185,7 +188,7 @@ static void cover_value(const ryo_ctx* c, int l, const int64_t q_in[3], double U
     int64_t o = find_oct(L, q[0] >> 1, q[1] >> 1, q[2] >> 1);
     if (o >= 0) {
       int64_t cell = 8 * o + cell_of(q);
-      for (int v = 0; v < NV; v++) U[v] = L->U[(int64_t)v * 8 * L->n + cell];
+      for (int v = 0; v < c->nv; v++) U[v] = L->U[(int64_t)v * 8 * L->n + cell];
       return;
     }
     /* not at this level: go to the parent cell one level up */
@@ -206,7 +209,7 @@ static void value_at(const ryo_ctx* c, int l, int64_t x, int64_t y, int64_t z, d
   int64_t o = find_oct(L, p[0] >> 1, p[1] >> 1, p[2] >> 1);
   if (o >= 0) {
     int64_t cell = 8 * o + cell_of(p);
-    for (int v = 0; v < NV; v++) U[v] = L->U[(int64_t)v * 8 * L->n + cell];
+    for (int v = 0; v < c->nv; v++) U[v] = L->U[(int64_t)v * 8 * L->n + cell];
     return;
   }
   int64_t q[3] = {p[0] >> 1, p[1] >> 1, p[2] >> 1};
@@ -218,11 +221,11 @@ static void value_at(const ryo_ctx* c, int l, int64_t x, int64_t y, int64_t z, d
     qp[d] += 1;
     cover_value(c, l - 1, qm, Um);
     cover_value(c, l - 1, qp, Up);
-    for (int v = 0; v < NV; v++) s[d][v] = ryo_minmod(UQ[v] - Um[v], Up[v] - UQ[v]);
+    for (int v = 0; v < c->nv; v++) s[d][v] = ryo_minmod(UQ[v] - Um[v], Up[v] - UQ[v]);
   }
   double sg[3];
   for (int d = 0; d < 3; d++) sg[d] = (p[d] & 1) ? 1.0 : -1.0;
-  for (int v = 0; v < NV; v++)
+  for (int v = 0; v < c->nv; v++)
     U[v] = UQ[v] + (sg[0] * 0.25 * s[0][v] + sg[1] * 0.25 * s[1][v] + sg[2] * 0.25 * s[2][v]);
 }
 
@@ -241,6 +244,8 @@ static void cons_to_prim(const ryo_ctx* c, const double U[NV], double W[NV], int
   W[2] = U[2] / rho;
   W[3] = U[3] / rho;
   W[4] = p;
+  /* passive scalars: conserved rho*s, primitive s */
+  for (int v = 5; v < c->nv; v++) W[v] = U[v] / rho;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -265,7 +270,7 @@ static void predict(const ryo_ctx* c, int l, int64_t x, int64_t y, int64_t z, do
     cons_to_prim(c, U, Wm, fl);
     value_at(c, l, pp[0], pp[1], pp[2], U);
     cons_to_prim(c, U, Wp, fl);
-    for (int v = 0; v < NV; v++) P->D[d][v] = ryo_minmod(W0[v] - Wm[v], Wp[v] - W0[v]);
+    for (int v = 0; v < c->nv; v++) P->D[d][v] = ryo_minmod(W0[v] - Wm[v], Wp[v] - W0[v]);
   }
   double g = c->cfg.gamma;
   double r = W0[0], u = W0[1], v = W0[2], w = W0[3], p = W0[4];
@@ -277,12 +282,16 @@ static void predict(const ryo_ctx* c, int l, int64_t x, int64_t y, int64_t z, do
   P->Wt[2] = v - h * (u * Dx[2] + v * Dy[2] + w * Dz[2] + Dy[4] / r);
   P->Wt[3] = w - h * (u * Dx[3] + v * Dy[3] + w * Dz[3] + Dz[4] / r);
   P->Wt[4] = p - h * (u * Dx[4] + v * Dy[4] + w * Dz[4] + g * p * (Dx[1] + Dy[2] + Dz[3]));
+  /* a passive scalar is advected: s~ = s - h (u Dx s + v Dy s + w Dz s) */
+  for (int k = 5; k < c->nv; k++) P->Wt[k] = W0[k] - h * (u * Dx[k] + v * Dy[k] + w * Dz[k]);
 }
 
 /* ------------------------------------------------------------------------ */
 /* HLLC flux (Toro, Spruce & Speares 1994; Davis 1988 wave speeds).          */
 /* ------------------------------------------------------------------------ */
-void ryo_hllc(const double WL[5], const double WR[5], int32_t d, double g, double F[5]) {
+/* nv = 5 + passive scalars; a passive scalar s is carried like a transverse
+ * velocity: flux rho u s, star state r (rho_K s_K) (Toro 2009, Sec. 10.6). */
+static void hllc_nv(const double* WL, const double* WR, int nv, int32_t d, double g, double* F) {
   int t1 = (d == 0) ? 1 : 0;   /* tangential axes in increasing order */
   int t2 = (d == 2) ? 1 : 2;
   double rl = WL[0], ul = WL[1 + d], al = WL[1 + t1], bl = WL[1 + t2], pl = WL[4];
@@ -296,25 +305,37 @@ void ryo_hllc(const double WL[5], const double WR[5], int32_t d, double g, doubl
   double num = pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur);
   double den = rl * (SL - ul) - rr * (SR - ur);
   double Ss = num / den;
-  double FL[5] = {rl * ul, rl * ul * ul + pl, rl * ul * al, rl * ul * bl, (El + pl) * ul};
-  double FR[5] = {rr * ur, rr * ur * ur + pr, rr * ur * ar, rr * ur * br, (Er + pr) * ur};
-  double Fn[5];
+  double FL[NV] = {rl * ul, rl * ul * ul + pl, rl * ul * al, rl * ul * bl, (El + pl) * ul};
+  double FR[NV] = {rr * ur, rr * ur * ur + pr, rr * ur * ar, rr * ur * br, (Er + pr) * ur};
+  for (int k = 5; k < nv; k++) {
+    FL[k] = rl * ul * WL[k];
+    FR[k] = rr * ur * WR[k];
+  }
+  double Fn[NV] = {0.0};
   if (SL >= 0.0) {
-    for (int i = 0; i < 5; i++) Fn[i] = FL[i];
+    for (int i = 0; i < nv; i++) Fn[i] = FL[i];
   } else if (Ss >= 0.0) {
     double r = (SL - ul) / (SL - Ss);
-    double Us[5] = {r * rl, r * (rl * Ss), r * (rl * al), r * (rl * bl),
-                    r * (El + rl * (Ss - ul) * (Ss + pl / (rl * (SL - ul))))};
-    double Uk[5] = {rl, rl * ul, rl * al, rl * bl, El};
-    for (int i = 0; i < 5; i++) Fn[i] = FL[i] + SL * (Us[i] - Uk[i]);
+    double Us[NV] = {r * rl, r * (rl * Ss), r * (rl * al), r * (rl * bl),
+                     r * (El + rl * (Ss - ul) * (Ss + pl / (rl * (SL - ul))))};
+    double Uk[NV] = {rl, rl * ul, rl * al, rl * bl, El};
+    for (int k = 5; k < nv; k++) {
+      Us[k] = r * (rl * WL[k]);
+      Uk[k] = rl * WL[k];
+    }
+    for (int i = 0; i < nv; i++) Fn[i] = FL[i] + SL * (Us[i] - Uk[i]);
   } else if (SR > 0.0) {
     double r = (SR - ur) / (SR - Ss);
-    double Us[5] = {r * rr, r * (rr * Ss), r * (rr * ar), r * (rr * br),
-                    r * (Er + rr * (Ss - ur) * (Ss + pr / (rr * (SR - ur))))};
-    double Uk[5] = {rr, rr * ur, rr * ar, rr * br, Er};
-    for (int i = 0; i < 5; i++) Fn[i] = FR[i] + SR * (Us[i] - Uk[i]);
+    double Us[NV] = {r * rr, r * (rr * Ss), r * (rr * ar), r * (rr * br),
+                     r * (Er + rr * (Ss - ur) * (Ss + pr / (rr * (SR - ur))))};
+    double Uk[NV] = {rr, rr * ur, rr * ar, rr * br, Er};
+    for (int k = 5; k < nv; k++) {
+      Us[k] = r * (rr * WR[k]);
+      Uk[k] = rr * WR[k];
+    }
+    for (int i = 0; i < nv; i++) Fn[i] = FR[i] + SR * (Us[i] - Uk[i]);
   } else {
-    for (int i = 0; i < 5; i++) Fn[i] = FR[i];
+    for (int i = 0; i < nv; i++) Fn[i] = FR[i];
   }
   /* rotate back: normal momentum to axis d, tangential to t1, t2 */
   F[0] = Fn[0];
@@ -322,6 +343,15 @@ void ryo_hllc(const double WL[5], const double WR[5], int32_t d, double g, doubl
   F[1 + t1] = Fn[2];
   F[1 + t2] = Fn[3];
   F[4] = Fn[4];
+  for (int k = 5; k < nv; k++) F[k] = Fn[k];
+}
+
+void ryo_hllc(const double WL[5], const double WR[5], int32_t d, double g, double F[5]) {
+  hllc_nv(WL, WR, 5, d, g, F);
+}
+
+void ryo_hllc_scalars(const double* WL, const double* WR, int32_t nscalar, int32_t d, double g, double* F) {
+  hllc_nv(WL, WR, 5 + nscalar, d, g, F);
 }
 
 /* Flux through the face between cells A (lower) and B (upper) along d, from
@@ -329,7 +359,7 @@ void ryo_hllc(const double WL[5], const double WR[5], int32_t d, double g, doubl
 static void face_flux(const ryo_ctx* c, const pred_t* A, const pred_t* B, int d, double F[NV],
                       int64_t* fl) {
   double WL[NV], WR[NV];
-  for (int v = 0; v < NV; v++) {
+  for (int v = 0; v < c->nv; v++) {
     WL[v] = A->Wt[v] + 0.5 * A->D[d][v];
     WR[v] = B->Wt[v] - 0.5 * B->D[d][v];
   }
@@ -337,7 +367,7 @@ static void face_flux(const ryo_ctx* c, const pred_t* A, const pred_t* B, int d,
   if (WR[0] < c->cfg.rho_floor) { WR[0] = c->cfg.rho_floor; (*fl)++; }
   if (WL[4] < c->cfg.p_floor) { WL[4] = c->cfg.p_floor; (*fl)++; }
   if (WR[4] < c->cfg.p_floor) { WR[4] = c->cfg.p_floor; (*fl)++; }
-  ryo_hllc(WL, WR, d, c->cfg.gamma, F);
+  hllc_nv(WL, WR, c->nv, d, c->cfg.gamma, F);
 }
 
 /* Is position p (level l, after boundary conditions) a refined cell of l?
@@ -357,8 +387,8 @@ static int64_t refined_child(const ryo_ctx* c, int l, const int64_t p_in[3]) {
  * the fine oct: Fbar = (q_1 + q_2) / 8 (Berger & Colella 1989). */
 static void register_flux(const ryo_ctx* c, int lf, int64_t child, int face, double F[NV]) {
   const level_t* Lf = LVc(c, lf);
-  for (int v = 0; v < NV; v++) {
-    const double* q = &Lf->reg[((child * 6 + face) * NV + v) * 2];
+  for (int v = 0; v < c->nv; v++) {
+    const double* q = &Lf->reg[((child * 6 + face) * c->nv + v) * 2];
     F[v] = 0.125 * (q[0] + q[1]);
   }
 }
@@ -401,7 +431,7 @@ static void update_level(ryo_ctx* c, int l, double lam, int substep) {
         }
       }
       int64_t cell = 8 * o + ci;
-      for (int v = 0; v < NV; v++) {
+      for (int v = 0; v < c->nv; v++) {
         double acc = (Fm[0][v] - Fp[0][v]) + (Fm[1][v] - Fp[1][v]) + (Fm[2][v] - Fp[2][v]);
         L->Un[v * 8 * n + cell] = L->U[v * 8 * n + cell] + lam * acc;
       }
@@ -431,8 +461,8 @@ static void update_level(ryo_ctx* c, int l, double lam, int substep) {
           else face_flux(c, &Pb, &Pa, d, f[k], &fl);
           k++;
         }
-        for (int v = 0; v < NV; v++)
-          L->reg[((o * 6 + face) * NV + v) * 2 + substep] = (f[0][v] + f[1][v]) + (f[2][v] + f[3][v]);
+        for (int v = 0; v < c->nv; v++)
+          L->reg[((o * 6 + face) * c->nv + v) * 2 + substep] = (f[0][v] + f[1][v]) + (f[2][v] + f[3][v]);
       }
     }
     floors += fl;
@@ -450,7 +480,7 @@ static void restrict_level(ryo_ctx* c, int l, double* dst) {
     int64_t p[3] = {F->oc[3 * k], F->oc[3 * k + 1], F->oc[3 * k + 2]};
     int64_t o = find_oct(L, p[0] >> 1, p[1] >> 1, p[2] >> 1);
     int64_t cell = 8 * o + cell_of(p);
-    for (int v = 0; v < NV; v++) {
+    for (int v = 0; v < c->nv; v++) {
       const double* s = &F->U[v * 8 * F->n + 8 * k];
       dst[v * 8 * L->n + cell] = 0.125 * (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
     }
@@ -482,14 +512,14 @@ static int cmp_okey(const void* a, const void* b) {
   return ka < kb ? -1 : (ka > kb ? 1 : 0);
 }
 
-static int alloc_level(level_t* L, int64_t n) {
+static int alloc_level(level_t* L, int64_t n, int nv) {
   L->n = n;
   L->key = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
   L->oc = (int32_t*)malloc((n ? n : 1) * 3 * sizeof(int32_t));
   L->refined = (uint8_t*)calloc(n ? n : 1, 1);
-  L->U = (double*)calloc((n ? n : 1) * 40, sizeof(double));
-  L->Un = (double*)calloc((n ? n : 1) * 40, sizeof(double));
-  L->reg = (double*)calloc((n ? n : 1) * 60, sizeof(double));
+  L->U = (double*)calloc((n ? n : 1) * 8 * nv, sizeof(double));
+  L->Un = (double*)calloc((n ? n : 1) * 8 * nv, sizeof(double));
+  L->reg = (double*)calloc((n ? n : 1) * 12 * nv, sizeof(double));
   if (!L->key || !L->oc || !L->refined || !L->U || !L->Un || !L->reg) return -1;
   return 0;
 }
@@ -507,7 +537,7 @@ static int set_octs(ryo_ctx* c, int l, okey_t* list, int64_t n) {
   qsort(list, (size_t)n, sizeof(okey_t), cmp_okey);
   level_t* L = LV(c, l);
   free_level(L);
-  if (alloc_level(L, n)) return -1;
+  if (alloc_level(L, n, c->nv)) return -1;
   for (int64_t i = 0; i < n; i++) {
     L->key[i] = list[i].key;
     L->oc[3 * i] = list[i].x;
@@ -593,7 +623,7 @@ int ryo_amr_build(ryo_ctx* c, const double* U_base, ryo_fill_fn fill, void* user
       int64_t x = 2 * (int64_t)L->oc[3 * o] + (ci & 1);
       int64_t y = 2 * (int64_t)L->oc[3 * o + 1] + ((ci >> 1) & 1);
       int64_t z = 2 * (int64_t)L->oc[3 * o + 2] + ((ci >> 2) & 1);
-      for (int v = 0; v < NV; v++)
+      for (int v = 0; v < c->nv; v++)
         L->U[v * 8 * L->n + 8 * o + ci] = U_base[v * ncell0 + x + nb0 * (y + nb1 * z)];
     }
   for (int l = l0; l < c->cfg.level_max; l++) {
@@ -631,7 +661,7 @@ int ryo_amr_build(ryo_ctx* c, const double* U_base, ryo_fill_fn fill, void* user
     free(nl);
     level_t* Lf = LV(c, l + 1);
     int32_t* ijk = (int32_t*)malloc(Lf->n * 8 * 3 * sizeof(int32_t));
-    double* Uf = (double*)malloc(Lf->n * 8 * NV * sizeof(double));
+    double* Uf = (double*)malloc(Lf->n * 8 * c->nv * sizeof(double));
     if (!ijk || !Uf) { free(ijk); free(Uf); return RYO_ENOMEM; }
     for (int64_t o = 0; o < Lf->n; o++)
       for (int ci = 0; ci < 8; ci++) {
@@ -641,7 +671,7 @@ int ryo_amr_build(ryo_ctx* c, const double* U_base, ryo_fill_fn fill, void* user
         ijk[3 * i + 2] = 2 * Lf->oc[3 * o + 2] + ((ci >> 2) & 1);
       }
     fill(user, l + 1, Lf->n * 8, ijk, Uf);
-    memcpy(Lf->U, Uf, Lf->n * 8 * NV * sizeof(double));
+    memcpy(Lf->U, Uf, Lf->n * 8 * c->nv * sizeof(double));
     free(ijk);
     free(Uf);
   }
@@ -665,7 +695,7 @@ static int check_state(ryo_ctx* c) {
         int64_t cell = 8 * o + ci;
         double r = L->U[cell], E = L->U[4 * 8 * L->n + cell];
         int fin = 1;
-        for (int v = 0; v < NV; v++) fin &= isfinite(L->U[v * 8 * L->n + cell]);
+        for (int v = 0; v < c->nv; v++) fin &= isfinite(L->U[v * 8 * L->n + cell]);
         if (!fin || !(r > 0.0) || !(E > 0.0)) bad = 1;
       }
   }
@@ -688,7 +718,7 @@ int ryo_cfl_dt(ryo_ctx* c, double* dt_coarse) {
       for (int ci = 0; ci < 8; ci++) {
         if (L->refined[o] & (1u << ci)) continue;
         double U[NV], W[NV];
-        for (int v = 0; v < NV; v++) U[v] = L->U[v * 8 * L->n + 8 * o + ci];
+        for (int v = 0; v < c->nv; v++) U[v] = L->U[v * 8 * L->n + 8 * o + ci];
         cons_to_prim(c, U, W, &fl);
         double cs = sqrt(g * W[4] / W[0]);
         double s = fabs(W[1]) + fabs(W[2]) + fabs(W[3]) + 3.0 * cs;
@@ -732,9 +762,9 @@ int ryo_advance(ryo_ctx* c, int32_t n_coarse, double t_end, double* t_io, int32_
 
 /* Sum over leaf cells of U * dx^3 (Neumaier compensated summation, levels
  * ascending, octs in Hilbert order, cells in in-oct order). */
-int ryo_conserved_totals(const ryo_ctx* c, double tot[5]) {
+int ryo_conserved_totals(const ryo_ctx* c, double* tot) {
   if (!c || !tot || !c->built) return RYO_EINVAL;
-  for (int v = 0; v < NV; v++) {
+  for (int v = 0; v < c->nv; v++) {
     double s = 0.0, comp = 0.0;
     for (int l = c->cfg.level_min; l <= c->cfg.level_max; l++) {
       const level_t* L = LVc(c, l);
@@ -775,9 +805,11 @@ int ryo_create(const ryo_config* cfg, ryo_ctx** out) {
   if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0) || !(cfg->boxlen > 0.0)) return RYO_EINVAL;
   if (!(cfg->rho_floor > 0.0) || !(cfg->p_floor > 0.0)) return RYO_EINVAL;
   if (cfg->refine < RYO_REFINE_NONE || cfg->refine > RYO_REFINE_MASS) return RYO_EINVAL;
+  if (cfg->nscalar < 0 || cfg->nscalar > RYO_MAX_SCALARS) return RYO_EINVAL;
   ryo_ctx* c = (ryo_ctx*)calloc(1, sizeof(ryo_ctx));
   if (!c) return RYO_ENOMEM;
   c->cfg = *cfg;
+  c->nv = 5 + cfg->nscalar;
   c->nlev = cfg->level_max - cfg->level_min + 1;
   int m = cfg->nbase[0];
   if (cfg->nbase[1] > m) m = cfg->nbase[1];
@@ -828,14 +860,14 @@ int ryo_get_coords(const ryo_ctx* c, int32_t l, int32_t* xyz) {
 int ryo_download(const ryo_ctx* c, int32_t l, double* U) {
   if (!level_ok(c, l) || !U) return RYO_EINVAL;
   const level_t* L = LVc(c, l);
-  memcpy(U, L->U, L->n * 40 * sizeof(double));
+  memcpy(U, L->U, L->n * 8 * c->nv * sizeof(double));
   return RYO_OK;
 }
 
 int ryo_upload(ryo_ctx* c, int32_t l, const double* U) {
   if (!level_ok(c, l) || !U) return RYO_EINVAL;
   level_t* L = LV(c, l);
-  memcpy(L->U, U, L->n * 40 * sizeof(double));
+  memcpy(L->U, U, L->n * 8 * c->nv * sizeof(double));
   c->numeric_error = 0;
   return RYO_OK;
 }

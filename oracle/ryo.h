@@ -29,6 +29,7 @@ enum { RYO_OK = 0, RYO_EINVAL = -1, RYO_ENOMEM = -2, RYO_ESTATE = -4, RYO_ENUMER
 enum { RYO_BC_PERIODIC = 0, RYO_BC_OUTFLOW = 1 };
 enum { RYO_REFINE_NONE = 0, RYO_REFINE_GRAD = 1, RYO_REFINE_MASS = 2 };
 #define RYO_MAX_LEVELS 16
+#define RYO_MAX_SCALARS 4
 
 typedef struct {
   int32_t level_min, level_max;  /* levels are numbered like the paper's l  */
@@ -38,9 +39,13 @@ typedef struct {
   int32_t refine;                /* RYO_REFINE_*                              */
   double refine_param;           /* theta (GRAD) or rho_thr (MASS)            */
   double rho_floor, p_floor;
+  int32_t nscalar;               /* passive scalars advected with the mass
+                                  * flux (0..RYO_MAX_SCALARS); the state then
+                                  * has 5 + nscalar planes, the scalars
+                                  * conserved as rho*s                       */
 } ryo_config;
 
-/* Fill callback: values U (5 planes of ncell, SoA) of new cells at `level`,
+/* Fill callback: values U (5 + nscalar planes of ncell, SoA) of new cells at `level`,
  * given their integer cell coordinates ijk (3*ncell, x,y,z interleaved). */
 typedef void (*ryo_fill_fn)(void* user, int32_t level, int64_t ncell,
                             const int32_t* ijk, double* U);
@@ -49,18 +54,19 @@ typedef struct ryo_ctx ryo_ctx;
 
 int  ryo_create(const ryo_config* cfg, ryo_ctx** out);
 void ryo_destroy(ryo_ctx* c);
-/* U_base: host, 5 planes of nbase[0]*nbase[1]*nbase[2] values, x fastest. */
+/* U_base: host, 5 + nscalar planes of nbase[0]*nbase[1]*nbase[2] values, x fastest. */
 int  ryo_amr_build(ryo_ctx* c, const double* U_base, ryo_fill_fn fill, void* user);
 int  ryo_level_info(const ryo_ctx* c, int32_t level, int64_t* n_oct, int64_t* n_leaf_cells);
 int  ryo_get_mesh(const ryo_ctx* c, int32_t level, uint64_t* keys, uint8_t* refined);
 int  ryo_get_coords(const ryo_ctx* c, int32_t level, int32_t* oct_xyz);
-/* U: 5 planes of 8*n_oct values; cell index = 8*oct + (ix + 2 iy + 4 iz). */
+/* U: 5 + nscalar planes of 8*n_oct values; cell index = 8*oct + (ix + 2 iy + 4 iz). */
 int  ryo_download(const ryo_ctx* c, int32_t level, double* U);
 int  ryo_upload(ryo_ctx* c, int32_t level, const double* U);
 int  ryo_cfl_dt(ryo_ctx* c, double* dt_coarse);
 int  ryo_coarse_step(ryo_ctx* c, double dt_coarse);
 int  ryo_advance(ryo_ctx* c, int32_t n_coarse, double t_end, double* t_io, int32_t* n_done);
-int  ryo_conserved_totals(const ryo_ctx* c, double tot[5]);
+/* tot: 5 + nscalar sums over leaf cells of U dx^3. */
+int  ryo_conserved_totals(const ryo_ctx* c, double* tot);
 int64_t ryo_floor_count(const ryo_ctx* c);
 void ryo_reset_floor_count(ryo_ctx* c);
 const char* ryo_last_error(const ryo_ctx* c);
@@ -72,6 +78,8 @@ uint64_t ryo_hilbert_key(int32_t bits, uint32_t x, uint32_t y, uint32_t z);
 /* Single-face HLLC flux in direction d (0,1,2) for primitive states
  * W = (rho, u, v, w, p); exposed for unit pins. */
 void ryo_hllc(const double WL[5], const double WR[5], int32_t d, double gamma, double F[5]);
+/* The same with nscalar passive scalars appended to W and F. */
+void ryo_hllc_scalars(const double* WL, const double* WR, int32_t nscalar, int32_t d, double gamma, double* F);
 double ryo_minmod(double a, double b);
 
 #ifdef __cplusplus

@@ -17,7 +17,7 @@ class RyoConfig(C.Structure):
     _fields_ = [("level_min", C.c_int32), ("level_max", C.c_int32), ("nbase", C.c_int32 * 3),
                 ("boxlen", C.c_double), ("gamma", C.c_double), ("cfl", C.c_double),
                 ("bc", C.c_int32 * 6), ("refine", C.c_int32), ("refine_param", C.c_double),
-                ("rho_floor", C.c_double), ("p_floor", C.c_double)]
+                ("rho_floor", C.c_double), ("p_floor", C.c_double), ("nscalar", C.c_int32)]
 
 
 FILL_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
@@ -52,6 +52,8 @@ def lib():
         L.ryo_hilbert_key.restype = C.c_uint64
         L.ryo_hllc.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.c_double,
                                C.POINTER(C.c_double)]
+        L.ryo_hllc_scalars.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.c_int32,
+                                       C.c_double, C.POINTER(C.c_double)]
         L.ryo_minmod.argtypes = [C.c_double, C.c_double]
         L.ryo_minmod.restype = C.c_double
         L.ryo_set_num_threads.argtypes = [C.c_int]
@@ -64,11 +66,11 @@ class OracleError(RuntimeError):
     pass
 
 
-def make_fill(fill):
-    """Wrap a Python fill(level, ijk[n,3]) -> U[5,n] as a C callback."""
+def make_fill(fill, nv=5):
+    """Wrap a Python fill(level, ijk[n,3]) -> U[nv,n] as a C callback."""
     def cb(user, level, ncell, ijk, U):
         a = np.ctypeslib.as_array(ijk, shape=(ncell, 3))
-        out = np.ctypeslib.as_array(U, shape=(5, ncell))
+        out = np.ctypeslib.as_array(U, shape=(nv, ncell))
         out[...] = fill(int(level), a.copy())
     return FILL_FN(cb)
 
@@ -89,11 +91,14 @@ class Oracle:
             cfg.bc[i] = prob.bc[i]
         cfg.refine, cfg.refine_param = prob.refine, prob.refine_param
         cfg.rho_floor, cfg.p_floor = prob.rho_floor, prob.p_floor
+        cfg.nscalar = prob.nscalar
+        self.nv = 5 + prob.nscalar
         self.prob = prob
         self.ctx = C.c_void_p()
         self._check(L.ryo_create(C.byref(cfg), C.byref(self.ctx)), "create")
         base = prob.base_flat()
-        self._fill = make_fill(prob.fill if prob.fill else (lambda l, ijk: np.zeros((5, len(ijk)))))
+        nv = self.nv
+        self._fill = make_fill(prob.fill if prob.fill else (lambda l, ijk: np.zeros((nv, len(ijk)))), nv)
         self._check(L.ryo_amr_build(self.ctx, base.ctypes.data_as(C.POINTER(C.c_double)), self._fill, None),
                     "amr_build")
         self.t = 0.0
@@ -132,7 +137,7 @@ class Oracle:
 
     def download(self, level):
         n, _ = self.level_info(level)
-        U = np.zeros((5, 8 * n), np.float64)
+        U = np.zeros((self.nv, 8 * n), np.float64)
         self._check(lib().ryo_download(self.ctx, level, U.ctypes.data), "download")
         return U
 
@@ -156,7 +161,7 @@ class Oracle:
         return nd.value
 
     def totals(self):
-        tot = (C.c_double * 5)()
+        tot = (C.c_double * self.nv)()
         self._check(lib().ryo_conserved_totals(self.ctx, tot), "conserved_totals")
         return np.array(tot[:])
 
@@ -173,6 +178,16 @@ def hllc(WL, WR, d, gamma):
     b = (C.c_double * 5)(*WR)
     F = (C.c_double * 5)()
     lib().ryo_hllc(a, b, d, gamma, F)
+    return np.array(F[:])
+
+
+def hllc_scalars(WL, WR, d, gamma):
+    """HLLC flux of (rho, u, v, w, p, s_1..s_k) states; len(WL) = 5 + k."""
+    n = len(WL)
+    a = (C.c_double * n)(*WL)
+    b = (C.c_double * n)(*WR)
+    F = (C.c_double * n)()
+    lib().ryo_hllc_scalars(a, b, n - 5, d, gamma, F)
     return np.array(F[:])
 
 

@@ -77,3 +77,39 @@ def rel_err(a, b, floor_frac=1e-3):
     scale = np.maximum(np.abs(b), floor_frac * np.abs(b).max(axis=-1, keepdims=True))
     scale = np.where(scale == 0, 1.0, scale)
     return float((np.abs(a - b) / scale).max())
+
+
+def scalar_profiles(pos):
+    """Three passive-scalar profiles: smooth, a step (exercises the limiter)
+    and a constant."""
+    tp = 2 * math.pi
+    return [0.5 + 0.4 * np.sin(tp * pos[:, 0]) * np.cos(tp * pos[:, 1]),
+            np.where(pos[:, 0] + 0.3 * pos[:, 2] > 0.55, 0.9, 0.1),
+            np.full(len(pos), 0.3)]
+
+
+def with_scalars(prob, nscalar, profiles=scalar_profiles):
+    """A copy of a cubic-box problem with `nscalar` passive scalars appended
+    (conserved rho*s, s from `profiles` at cell centres on every level)."""
+    import dataclasses
+    n0 = prob.nbase[0]
+
+    def scal(level_cells, ijk, rho):
+        pos = cell_centres(0, ijk, level_cells)
+        s = profiles(pos)[:nscalar]
+        return [rho * sk for sk in s]
+
+    idx = np.indices(prob.U_base.shape[1:])
+    ijk = np.stack([idx[2].ravel(), idx[1].ravel(), idx[0].ravel()], axis=1).astype(np.int32)
+    rho0 = prob.U_base[0].ravel()
+    extra = np.array(scal(n0, ijk, rho0)).reshape((nscalar,) + prob.U_base.shape[1:])
+    Ub = np.concatenate([prob.U_base[:5], extra], axis=0)
+    fill = None
+    if prob.fill is not None:
+        base_fill = prob.fill
+
+        def fill(level, ijk):
+            U = base_fill(level, ijk)
+            cells = n0 << (level - prob.level_min)
+            return np.concatenate([U[:5], np.array(scal(cells, ijk, U[0]))], axis=0)
+    return dataclasses.replace(prob, name=prob.name + f"_s{nscalar}", U_base=Ub, fill=fill, nscalar=nscalar)

@@ -55,7 +55,7 @@ class Problem:
     level_max: int
     nbase: tuple
     gamma: float
-    U_base: np.ndarray            # (5, nz, ny, nx) float64, conserved variables
+    U_base: np.ndarray            # (5 + nscalar, nz, ny, nx) float64, conserved variables
     boxlen: float = 1.0
     cfl: float = 0.8
     bc: tuple = (BC_PERIODIC,) * 6
@@ -63,13 +63,14 @@ class Problem:
     refine_param: float = 0.0
     rho_floor: float = 1e-10
     p_floor: float = 1e-10
-    fill: Optional[FillFn] = None  # (level, ijk[n,3] int32) -> U[5, n] float64
+    fill: Optional[FillFn] = None  # (level, ijk[n,3] int32) -> U[5 + nscalar, n] float64
     t_end: float = math.inf
     n_steps: int = 10
+    nscalar: int = 0              # passive scalars, conserved as rho*s after the 5 hydro planes
 
     def base_flat(self) -> np.ndarray:
-        """U_base as 5 contiguous planes, x fastest."""
-        return np.ascontiguousarray(self.U_base.reshape(5, -1), dtype=np.float64)
+        """U_base as 5 + nscalar contiguous planes, x fastest."""
+        return np.ascontiguousarray(self.U_base.reshape(5 + self.nscalar, -1), dtype=np.float64)
 
 
 def conserved(rho, vx, vy, vz, p, gamma):
