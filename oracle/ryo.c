@@ -202,6 +202,8 @@ static void cover_value(const ryo_ctx* c, int l, const int64_t q_in[3], double U
  * interpolation of the conserved variables of the covering level l-1 cell Q:
  *   U = U_Q + sum_d sigma_d * 0.25 * minmod(U_Q - U_{Q-e_d}, U_{Q+e_d} - U_Q),
  * sigma_d = +1 / -1 for the upper / lower child of Q along d. */
+static void coarse_interp(const ryo_ctx* c, int l, const int64_t p[3], double U[NV]);
+
 static void value_at(const ryo_ctx* c, int l, int64_t x, int64_t y, int64_t z, double U[NV]) {
   int64_t p[3] = {x, y, z};
   bc_cell(c, l, p);
@@ -212,6 +214,12 @@ static void value_at(const ryo_ctx* c, int l, int64_t x, int64_t y, int64_t z, d
     for (int v = 0; v < c->nv; v++) U[v] = L->U[(int64_t)v * 8 * L->n + cell];
     return;
   }
+  coarse_interp(c, l, p, U);
+}
+
+/* The MinMod-linear interpolation of cell p of level l (inside the domain)
+ * from its covering level l-1 cell and that cell's six neighbours. */
+static void coarse_interp(const ryo_ctx* c, int l, const int64_t p[3], double U[NV]) {
   int64_t q[3] = {p[0] >> 1, p[1] >> 1, p[2] >> 1};
   double UQ[NV], Um[NV], Up[NV], s[3][NV];
   cover_value(c, l - 1, q, UQ);
@@ -683,6 +691,85 @@ int ryo_amr_build(ryo_ctx* c, const double* U_base, ryo_fill_fn fill, void* user
 }
 
 /* ------------------------------------------------------------------------ */
+/* Regrid between coarse steps (dynamic refinement).                          */
+/*                                                                            */
+/* Top-down over l = level_min .. level_max-1, with level l already final:    */
+/*   1. every cell of level l (leaf or refined) is flagged by the build's     */
+/*      criterion on its current value, and refined only when its 26          */
+/*      neighbours exist at level l (the build's neighbour rule);              */
+/*   2. level l+1 becomes the children of the refined cells, in Hilbert       */
+/*      order: a child oct that existed keeps its values, a new one is         */
+/*      filled by the MinMod-linear interpolation of its parent cell (the     */
+/*      coarse-fine ghost formula); octs whose parent cell is no longer       */
+/*      refined disappear with their descendants (the parent cell keeps its   */
+/*      restricted value).                                                     */
+/* Finally every refined cell is restricted bottom-up from its children.      */
+/* ------------------------------------------------------------------------ */
+int ryo_regrid(ryo_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
+  if (!c || !c->built) return RYO_EINVAL;
+  int64_t created = 0, destroyed = 0;
+  for (int l = c->cfg.level_min; l < c->cfg.level_max; l++) {
+    level_t* Lc = LV(c, l);
+    uint8_t* flag = (uint8_t*)calloc(Lc->n ? Lc->n : 1, 1);
+    if (!flag) return RYO_ENOMEM;
+    int64_t nref = 0;
+    for (int64_t o = 0; o < Lc->n; o++)
+      for (int ci = 0; ci < 8; ci++) {
+        int64_t p[3] = {2 * (int64_t)Lc->oc[3 * o] + (ci & 1), 2 * (int64_t)Lc->oc[3 * o + 1] + ((ci >> 1) & 1),
+                        2 * (int64_t)Lc->oc[3 * o + 2] + ((ci >> 2) & 1)};
+        double rho_c = Lc->U[8 * o + ci];
+        if (flag_cell(c, l, p, rho_c) && neighbours_exist(c, l, p)) {
+          flag[o] |= (uint8_t)(1u << ci);
+          nref++;
+        }
+      }
+    okey_t* nl = (okey_t*)malloc((nref ? nref : 1) * sizeof(okey_t));
+    if (!nl) { free(flag); return RYO_ENOMEM; }
+    int64_t m = 0;
+    for (int64_t o = 0; o < Lc->n; o++) {
+      Lc->refined[o] = flag[o];
+      for (int ci = 0; ci < 8; ci++)
+        if (flag[o] & (1u << ci)) {
+          nl[m].x = 2 * Lc->oc[3 * o] + (ci & 1);
+          nl[m].y = 2 * Lc->oc[3 * o + 1] + ((ci >> 1) & 1);
+          nl[m].z = 2 * Lc->oc[3 * o + 2] + ((ci >> 2) & 1);
+          m++;
+        }
+    }
+    free(flag);
+    /* detach the old level l+1; build the new one */
+    level_t old = *LV(c, l + 1);
+    memset(LV(c, l + 1), 0, sizeof(level_t));
+    if (set_octs(c, l + 1, nl, nref)) { free(nl); free_level(&old); return RYO_ENOMEM; }
+    free(nl);
+    level_t* Lf = LV(c, l + 1);
+    for (int64_t o = 0; o < Lf->n; o++) {
+      int64_t ko = find_oct(&old, Lf->oc[3 * o], Lf->oc[3 * o + 1], Lf->oc[3 * o + 2]);
+      for (int ci = 0; ci < 8; ci++) {
+        double U[NV];
+        if (ko >= 0) {
+          for (int v = 0; v < c->nv; v++) U[v] = old.U[(int64_t)v * 8 * old.n + 8 * ko + ci];
+        } else {
+          int64_t p[3] = {2 * (int64_t)Lf->oc[3 * o] + (ci & 1), 2 * (int64_t)Lf->oc[3 * o + 1] + ((ci >> 1) & 1),
+                          2 * (int64_t)Lf->oc[3 * o + 2] + ((ci >> 2) & 1)};
+          coarse_interp(c, l + 1, p, U);
+        }
+        for (int v = 0; v < c->nv; v++) Lf->U[(int64_t)v * 8 * Lf->n + 8 * o + ci] = U[v];
+      }
+      if (ko < 0) created++;
+    }
+    for (int64_t o = 0; o < old.n; o++)
+      if (find_oct(Lf, old.oc[3 * o], old.oc[3 * o + 1], old.oc[3 * o + 2]) < 0) destroyed++;
+    free_level(&old);
+  }
+  for (int l = c->cfg.level_max - 1; l >= c->cfg.level_min; l--)
+    if (LV(c, l + 1)->n > 0) restrict_level(c, l, LV(c, l)->U);
+  if (n_created) *n_created = created;
+  if (n_destroyed) *n_destroyed = destroyed;
+  return RYO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Time step, totals, driver.                                                 */
 /* ------------------------------------------------------------------------ */
 static int check_state(ryo_ctx* c) {
@@ -869,6 +956,12 @@ int ryo_upload(ryo_ctx* c, int32_t l, const double* U) {
   level_t* L = LV(c, l);
   memcpy(L->U, U, L->n * 8 * c->nv * sizeof(double));
   c->numeric_error = 0;
+  return RYO_OK;
+}
+
+int ryo_set_refine_param(ryo_ctx* c, double value) {
+  if (!c || !(value == value)) return RYO_EINVAL;
+  c->cfg.refine_param = value;
   return RYO_OK;
 }
 

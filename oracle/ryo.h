@@ -62,6 +62,15 @@ int  ryo_get_coords(const ryo_ctx* c, int32_t level, int32_t* oct_xyz);
 /* U: 5 + nscalar planes of 8*n_oct values; cell index = 8*oct + (ix + 2 iy + 4 iz). */
 int  ryo_download(const ryo_ctx* c, int32_t level, double* U);
 int  ryo_upload(ryo_ctx* c, int32_t level, const double* U);
+/* Regrid between coarse steps: re-flag every cell of levels level_min ..
+ * level_max-1 top-down with the build's criterion and neighbour rule; kept
+ * child octs keep their values, new ones take the MinMod-linear
+ * interpolation of their parent cell, orphaned octs disappear; then
+ * restriction bottom-up.  Counts of created / destroyed octs. */
+int  ryo_regrid(ryo_ctx* c, int64_t* n_created, int64_t* n_destroyed);
+/* Change the refinement criterion's parameter (theta or rho_thr) for later
+ * regrids. */
+int  ryo_set_refine_param(ryo_ctx* c, double value);
 int  ryo_cfl_dt(ryo_ctx* c, double* dt_coarse);
 int  ryo_coarse_step(ryo_ctx* c, double dt_coarse);
 int  ryo_advance(ryo_ctx* c, int32_t n_coarse, double t_end, double* t_io, int32_t* n_done);

@@ -43,6 +43,8 @@ def lib():
         L.ryo_coarse_step.argtypes = [P, C.c_double]
         L.ryo_advance.argtypes = [P, C.c_int32, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.ryo_conserved_totals.argtypes = [P, C.POINTER(C.c_double)]
+        L.ryo_regrid.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.ryo_set_refine_param.argtypes = [P, C.c_double]
         L.ryo_floor_count.argtypes = [P]
         L.ryo_floor_count.restype = C.c_int64
         L.ryo_reset_floor_count.argtypes = [P]
@@ -167,6 +169,15 @@ class Oracle:
 
     def floors(self):
         return lib().ryo_floor_count(self.ctx)
+
+    def set_refine_param(self, value):
+        self._check(lib().ryo_set_refine_param(self.ctx, value), "set_refine_param")
+
+    def regrid(self):
+        """Dynamic refinement between coarse steps: (octs created, destroyed)."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().ryo_regrid(self.ctx, C.byref(a), C.byref(b)), "regrid")
+        return a.value, b.value
 
 
 def hilbert_key(bits, x, y, z):
