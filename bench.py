@@ -195,6 +195,31 @@ def cpu_baseline(budget_s=12.0):
             "sample": f"uniform 128^3 periodic box, {n} whole coarse steps ({el:.1f} s wall)"}
 
 
+def run_scalars(nscalar=2, steps=10, warmup=2):
+    """Uniform 128^3 box carrying passive scalars: both precision forms, HIP
+    events on the hydro kernel; algorithmic bytes 16 per variable and
+    cell-update (5 + nscalar variables read and written)."""
+    import torch
+    import workloads as W
+    from paper_2411_14631_amd import Hydro
+    prob = W.uniform(128, nscalar=nscalar)
+    res = {"workload": f"uniform 128^3 periodic lognormal box with {nscalar} passive scalars",
+           "nscalar": nscalar, "alg_bytes_per_cell_update": 16 * (5 + nscalar)}
+    for prec in ("fp64", "mixed"):
+        h = Hydro(prob, prec)
+        tuning, _ = h.autotune()
+        cups = cell_updates_per_coarse_step(h)
+        dt, (nl, ms) = time_advance(h, steps, warmup, timing=True)
+        k = ms / max(nl, 1)
+        gbs = 16 * (5 + nscalar) * cups / (k * 1e-3) / 1e9
+        res[prec] = {"value": cups * steps / dt, "unit": "cell-updates/s", "kernel_avg_ms": round(k, 5),
+                     "achieved_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tuning": tuning}
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+    return res
+
+
 POISSON_BYTES_PER_CELL = 128
 
 
@@ -330,7 +355,19 @@ def main():
             handles[prec] = z
         zoom["mixed_vs_fp64_after_10_coarse_steps"] = compare_forms(
             handles["fp64"]["h"], handles["mixed"]["h"], handles["fp64"]["e0"], handles["mixed"]["e0"])
-        del handles, z
+        # one regrid of the evolved FP64 mesh, then one coarse step on it
+        h = handles["fp64"]["h"]
+        before = sum(h.level_info(lv)[0] for lv in h.levels)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        created, destroyed = h.regrid()
+        rg = time.perf_counter() - t0
+        after = sum(h.level_info(lv)[0] for lv in h.levels)
+        h.advance(1)
+        zoom["regrid_fp64"] = {"ms": round(1e3 * rg, 1), "octs_before": before, "octs_after": after,
+                               "created": created, "destroyed": destroyed,
+                               "note": "flags on the host from downloaded densities, state remap on the device"}
+        del handles, z, h
         torch.cuda.empty_cache()
 
     batch = None
@@ -355,6 +392,11 @@ def main():
             del bh
             torch.cuda.empty_cache()
 
+    scalars = None
+    if not args.no_zoom:
+        log("bench: uniform 128^3 with 2 passive scalars")
+        scalars = run_scalars()
+
     poisson = None
     if not args.no_poisson:
         log("bench: poisson 256^3 ppcg vs cg")
@@ -378,6 +420,7 @@ def main():
         "mixed": mixed,
         "zoom_amr": zoom,
         "batch_boxes": batch,
+        "passive_scalars": scalars,
         "poisson": poisson,
     }
     print(json.dumps(out), flush=True)

@@ -25,8 +25,9 @@
  *     own stream).  Calls marked "syncs" wait for that stream.
  *
  * State layout (also the ry_download / ry_upload layout): per level, octs in
- * ascending Hilbert key order; 5 planes (rho, rho u, rho v, rho w, E) of
- * 8*n_oct FP64 values; cell index = 8*oct + (ix + 2*iy + 4*iz).
+ * ascending Hilbert key order; nv = 5 + nscalar planes (rho, rho u, rho v,
+ * rho w, E, then rho s_k for each passive scalar s_k) of 8*n_oct FP64
+ * values; cell index = 8*oct + (ix + 2*iy + 4*iz).
  */
 #ifndef RY_H
 #define RY_H
@@ -51,6 +52,7 @@ enum { RY_FP64 = 0, RY_MIXED = 1 };               /* precision form           */
 enum { RY_BC_PERIODIC = 0, RY_BC_OUTFLOW = 1 };
 enum { RY_REFINE_NONE = 0, RY_REFINE_GRAD = 1, RY_REFINE_MASS = 2 };
 #define RY_MAX_LEVELS 16
+#define RY_MAX_SCALARS 4
 
 typedef struct {
   int32_t level_min, level_max; /* level numbers; dx(l) = boxlen / (nbase[0] 2^(l-level_min)) */
@@ -65,10 +67,12 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* user);  /* NULL = hipMalloc                      */
   void (*dev_free)(void* p, void* user);
   void* alloc_user;
+  int32_t nscalar;              /* passive scalars (metals, chemistry, dust) advected with    */
+                                /* the mass flux, 0..RY_MAX_SCALARS; not in batched boxes     */
 } ry_config;
 
 /* Host callback filling newly created cells of `level`: ijk holds 3*ncell
- * integer cell coordinates (x,y,z interleaved), U receives 5 planes of
+ * integer cell coordinates (x,y,z interleaved), U receives nv planes of
  * ncell conserved values.  Called during ry_amr_build only. */
 typedef void (*ry_fill_fn)(void* user, int32_t level, int64_t ncell, const int32_t* ijk, double* U);
 
@@ -76,7 +80,7 @@ typedef void (*ry_fill_fn)(void* user, int32_t level, int64_t ncell, const int32
 ry_status ry_create(const ry_config* cfg, ry_ctx** out);
 void ry_destroy(ry_ctx* ctx);
 
-/* Build the octree from the level_min field U_base (host, 5 planes of
+/* Build the octree from the level_min field U_base (host, nv planes of
  * nbase[0]*nbase[1]*nbase[2] values, x fastest): refinement flags by the
  * configured criterion on leaf cells, the neighbour rule (a cell is refined
  * only when its 26 neighbours exist at its level), Hilbert ordering, values
@@ -102,8 +106,26 @@ ry_status ry_hydro_step(ry_ctx* ctx, int32_t level, double dt);
  * steps are replayed from a captured hipGraph.  *t_io: time in/out.  Syncs. */
 ry_status ry_advance(ry_ctx* ctx, int32_t n_coarse, double t_end, double* t_io);
 
-/* Sum over leaf cells of U * dx^3, deterministic reduction order.  Syncs. */
-ry_status ry_conserved_totals(ry_ctx* ctx, double tot[5]);
+/* Regrid between coarse steps (dynamic refinement, the refine_fine step of
+ * the paper's Table 1).  Top-down over l = level_min .. level_max-1: every
+ * cell of level l is re-flagged on its current density by the configured
+ * criterion, under the build's neighbour rule (26 neighbours at level l);
+ * level l+1 becomes the children of the refined cells in Hilbert order --
+ * surviving octs keep their state, new octs take the MinMod-linear
+ * interpolation of their parent cell and its six face neighbours (the
+ * coarse-fine ghost formula), octs whose parent is no longer refined
+ * disappear with their descendants.  Then refined cells are restricted
+ * bottom-up.  The flags are evaluated on the host from each level's
+ * densities (8 B per cell crosses PCIe), the state is remapped on the
+ * device, the tables are rebuilt.  RY_ESTATE inside a coarse step.  Counts
+ * of created / destroyed octs (either may be NULL).  Syncs. */
+ry_status ry_regrid(ry_ctx* ctx, int64_t* n_created, int64_t* n_destroyed);
+/* Change the refinement parameter (theta or rho_thr) used by later regrids. */
+ry_status ry_set_refine_param(ry_ctx* ctx, double value);
+
+/* Sum over leaf cells of U * dx^3 (nv values: mass, momentum, energy, then
+ * the scalar masses), deterministic reduction order.  Syncs. */
+ry_status ry_conserved_totals(ry_ctx* ctx, double* tot);
 
 /* Copy one level's state (all cells of all octs) to / from the host.
  * ry_download syncs; ry_upload syncs and recomputes the stored CFL data. */
@@ -128,7 +150,8 @@ typedef struct {
   int32_t waves_per_cu;   /* persistent grid = CUs * waves_per_cu / waves per workgroup     */
   int32_t batch;          /* tile groups popped per queue access                            */
   int32_t waves_per_tile; /* 1, 2 or 4 wavefronts per tile (8, 16, 32 threads per oct);     */
-                          /* tiles_per_wg * waves_per_tile <= 4                             */
+                          /* tiles_per_wg * waves_per_tile <= 4; with passive scalars only  */
+                          /* {1,0,*,*,1}, {1,0,*,*,2} and {2,0,*,*,1} (else RY_EINVAL)      */
 } ry_tuning;
 ry_status ry_set_tuning(ry_ctx* ctx, const ry_tuning* t);
 ry_status ry_get_tuning(const ry_ctx* ctx, ry_tuning* t);

@@ -51,10 +51,11 @@ struct ry_ctx {
   bool built = false;
   bool batch = false;
   std::vector<DevLevel> lev;
+  std::vector<HostLevel> host;            // topology of the current mesh (no state)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int num_cu = 256;
-  ry_tuning tune{1, 0, 4, 1, 4};
+  ry_tuning tune{1, 0, 4, 1, 1};
   // device scalars
   double* d_smax = nullptr;               // max signal speed per level / per box
   double* d_part = nullptr;               // per-tile (or per-block) partial maxima
@@ -123,6 +124,16 @@ void* dalloc(ry_ctx* c, size_t bytes) {
   return p;
 }
 
+// Release one allocation made by dalloc (the stream must be idle).
+void dfree(ry_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it == c->allocs.end()) return;
+  c->allocs.erase(it);
+  if (c->cfg.dev_free) c->cfg.dev_free(p, c->cfg.alloc_user);
+  else if (!c->cfg.dev_alloc) (void)hipFree(p);
+}
+
 void free_all(ry_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   for (void* p : c->allocs) {
@@ -173,6 +184,7 @@ ry_status validate(const ry_config* cfg, bool single_level) {
   if (cfg->precision != RY_FP64 && cfg->precision != RY_MIXED) return RY_EINVAL;
   if (cfg->refine < RY_REFINE_NONE || cfg->refine > RY_REFINE_MASS) return RY_EINVAL;
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return RY_EINVAL;
+  if (cfg->nscalar < 0 || cfg->nscalar > RY_MAX_SCALARS) return RY_EINVAL;
   for (int a = 0; a < 3; ++a)
     if ((int64_t(cfg->nbase[a] / 2) << (cfg->level_max - cfg->level_min)) >= (int64_t(1) << 21)) return RY_EINVAL;
   return RY_OK;
@@ -186,6 +198,7 @@ DomainSpec make_dom(const ry_config& cfg) {
   for (int i = 0; i < 6; ++i) d.bc[i] = cfg.bc[i];
   d.refine = cfg.refine;
   d.refine_param = cfg.refine_param;
+  d.nv = NVAR + cfg.nscalar;
   int m = std::max(cfg.nbase[0], std::max(cfg.nbase[1], cfg.nbase[2])) / 2, bits = 0;
   while ((1 << bits) < m) ++bits;
   d.hbits0 = bits;
@@ -221,8 +234,8 @@ ry_status alloc_scalars(ry_ctx* c, int nslot) {
   c->d_flags = static_cast<int32_t*>(dalloc(c, sizeof(int32_t) * 8));
   c->d_floors = static_cast<unsigned long long*>(dalloc(c, sizeof(unsigned long long)));
   c->d_queue = static_cast<unsigned int*>(dalloc(c, sizeof(unsigned int) * 8));
-  c->d_partial = static_cast<double*>(dalloc(c, sizeof(double) * NVAR * totals_blocks()));
-  c->d_tot = static_cast<double*>(dalloc(c, sizeof(double) * NVAR));
+  c->d_partial = static_cast<double*>(dalloc(c, sizeof(double) * NVMAX * totals_blocks()));
+  c->d_tot = static_cast<double*>(dalloc(c, sizeof(double) * NVMAX));
   if (!c->d_smax || !c->d_lam || !c->d_t || !c->d_flags || !c->d_floors || !c->d_queue || !c->d_partial ||
       !c->d_tot || !c->d_part || !c->d_segoff)
     return RY_ENOMEM;
@@ -320,6 +333,7 @@ ry_status enqueue_ghost(ry_ctx* c, int l, const int32_t* skip) {
   g.dst0 = L.U[0];
   g.dst1 = L.U[1];
   g.plane = L.plane();
+  g.nv = c->dom.nv;
   g.skip = skip;
   TimedLaunch tl;
   if (c->timing) time_begin(c, "ghost", tl);
@@ -359,7 +373,8 @@ ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a) {
   if (c->tune.persistent && launch_zero_u32(c->d_queue, 8, c->stream)) return fail(c, RY_EHIP, "zero kernel");
   TimedLaunch tl;
   if (c->timing) time_begin(c, "hydro", tl);
-  if (launch_hydro(a, c->cfg.precision, c->tune, c->num_cu, c->stream)) return fail(c, RY_EHIP, "hydro kernel");
+  if (launch_hydro(a, c->cfg.precision, c->cfg.nscalar, c->tune, c->num_cu, c->stream))
+    return fail(c, RY_EHIP, "hydro kernel");
   if (c->timing) time_end(c, tl);
   return RY_OK;
 }
@@ -367,7 +382,8 @@ ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a) {
 ry_status enqueue_restrict(ry_ctx* c, int l, const int32_t* skip) {
   DevLevel& L = c->lev[l - c->cfg.level_min];
   DevLevel& F = c->lev[l + 1 - c->cfg.level_min];
-  if (launch_restrict(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur ^ 1], L.plane(), skip, c->stream))
+  if (launch_restrict(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur ^ 1], L.plane(), c->dom.nv, skip,
+                      c->stream))
     return fail(c, RY_EHIP, "restrict kernel");
   return RY_OK;
 }
@@ -420,9 +436,22 @@ ry_status sync_and_check(ry_ctx* c) {
   return RY_OK;
 }
 
+// Device tables of one level (tiles, flags, refined bytes, child / parent
+// maps, ghost sources, zeroed flux registers on refined levels).
+void upload_level_tables(ry_ctx* c, DevLevel& D, const LevelTables& t, int k, bool& ok) {
+  D.tab = upload_vec(c, t.tab, ok);
+  D.tflag = upload_vec(c, t.tflag, ok);
+  D.refined = upload_vec(c, t.refined_ext, ok);
+  D.child = t.child.empty() ? nullptr : upload_vec(c, t.child, ok);
+  D.parent_cell = t.parent_cell.empty() ? nullptr : upload_vec(c, t.parent_cell, ok);
+  D.gsrc = t.gsrc.empty() ? nullptr : upload_vec(c, t.gsrc, ok);
+  std::vector<double> zeros(size_t(D.n_oct) * reg_per_oct(c->dom.nv), 0.0);
+  D.reg = (k > 0) ? upload_vec(c, zeros, ok) : nullptr;
+}
+
 ry_status upload_level_state(ry_ctx* c, DevLevel& D, const double* U_host) {
   for (int b = 0; b < 2; ++b)
-    for (int v = 0; v < NVAR; ++v)
+    for (int v = 0; v < c->dom.nv; ++v)
       HIPCHK(c, hipMemcpyAsync(D.U[b] + v * D.plane(), U_host + size_t(v) * 8 * D.n_oct,
                                sizeof(double) * 8 * D.n_oct, hipMemcpyHostToDevice, c->stream));
   return RY_OK;
@@ -497,19 +526,12 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
     D.refined_host = H[k].refined;
     if (D.n_oct == 0) continue;
     for (int b = 0; b < 2; ++b) {
-      D.U[b] = static_cast<double*>(dalloc(c, sizeof(double) * NVAR * 8 * D.n_ext));
+      D.U[b] = static_cast<double*>(dalloc(c, sizeof(double) * c->dom.nv * 8 * D.n_ext));
       if (!D.U[b]) ok = false;
     }
     if (!ok) break;
     if (upload_level_state(c, D, H[k].U.data())) return c->err.empty() ? RY_EHIP : RY_EHIP;
-    D.tab = upload_vec(c, t.tab, ok);
-    D.tflag = upload_vec(c, t.tflag, ok);
-    D.refined = upload_vec(c, t.refined_ext, ok);
-    if (!t.child.empty()) D.child = upload_vec(c, t.child, ok);
-    if (!t.parent_cell.empty()) D.parent_cell = upload_vec(c, t.parent_cell, ok);
-    if (!t.gsrc.empty()) D.gsrc = upload_vec(c, t.gsrc, ok);
-    std::vector<double> zeros(size_t(D.n_oct) * REG_PER_OCT, 0.0);
-    if (k > 0) D.reg = upload_vec(c, zeros, ok);
+    upload_level_tables(c, D, t, k, ok);
   }
   if (!ok) {
     free_all(c);
@@ -525,7 +547,143 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
   std::fill(std::begin(c->count), std::end(c->count), 0);
   if ((s = enqueue_cfl_all(c))) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& h : H) std::vector<double>().swap(h.U);
+  c->host = std::move(H);
   c->built = true;
+  return RY_OK;
+}
+
+ry_status ry_set_refine_param(ry_ctx* c, double value) {
+  if (!c || c->batch || std::isnan(value)) return RY_EINVAL;
+  c->cfg.refine_param = value;
+  c->dom.refine_param = value;
+  return RY_OK;
+}
+
+ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
+  if (!c || c->batch) return RY_EINVAL;
+  if (!c->built) return fail(c, RY_ESTATE, "not built");
+  for (int k = 0; k < c->nlev; ++k)
+    if (c->count[k]) return fail(c, RY_ESTATE, "regrid inside a coarse step");
+  ry_status s = sync_and_check(c);
+  if (s) return s;
+  const int nl = c->nlev, nv = c->dom.nv;
+  std::vector<HostLevel>& H = c->host;
+  // new state of levels 1.. (level 0 keeps its octs and its buffers)
+  std::vector<double*> tmp(nl, nullptr);
+  int64_t created = 0, destroyed = 0;
+  for (int k = 0; k + 1 < nl; ++k) {
+    const int l = c->cfg.level_min + k;
+    DevLevel& Lk = c->lev[k];
+    const double* Uk = (k == 0) ? Lk.U[Lk.cur] : tmp[k];
+    const int64_t pk = (k == 0) ? Lk.plane() : 8 * H[k].n;
+    std::vector<double> rho(size_t(8 * H[k].n));
+    if (H[k].n) HIPCHK(c, hipMemcpy(rho.data(), Uk, sizeof(double) * rho.size(), hipMemcpyDeviceToHost));
+    HostLevel Fnew;
+    std::vector<int32_t> src_old, src7;
+    std::string e = regrid_level(c->dom, l, H[k], rho, H[k + 1], Fnew, src_old, src7, created, destroyed);
+    if (!e.empty()) return fail(c, RY_EINVAL, "%s", e.c_str());
+    if (Fnew.n > 0) {
+      bool ok = true;
+      tmp[k + 1] = static_cast<double*>(dalloc(c, sizeof(double) * nv * 8 * Fnew.n));
+      int32_t* d_old = upload_vec(c, src_old, ok);
+      int32_t* d_src = upload_vec(c, src7, ok);
+      if (!tmp[k + 1] || !ok) {
+        for (double* p : tmp) dfree(c, p);
+        dfree(c, d_old);
+        dfree(c, d_src);
+        return fail(c, RY_ENOMEM, "regrid allocation failed (mesh unchanged on the device, host topology stale)");
+      }
+      const DevLevel& Fo = c->lev[k + 1];
+      if (launch_regrid_remap(d_old, d_src, Fnew.n, Fo.n_oct ? Fo.U[Fo.cur] : nullptr, Fo.plane(), Uk, pk,
+                              tmp[k + 1], 8 * Fnew.n, nv, c->stream))
+        return fail(c, RY_EHIP, "regrid remap kernel");
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      dfree(c, d_old);
+      dfree(c, d_src);
+    }
+    H[k + 1] = std::move(Fnew);
+  }
+  // tables of the new mesh
+  std::vector<LevelTables> T;
+  std::string e = build_tables(c->dom, H, T);
+  if (!e.empty()) return fail(c, RY_EINVAL, "%s", e.c_str());
+  // release the old per-level arrays (level 0 keeps its state buffers)
+  for (int k = 0; k < nl; ++k) {
+    DevLevel& D = c->lev[k];
+    for (void* p : {(void*)D.tab, (void*)D.tflag, (void*)D.refined, (void*)D.child, (void*)D.parent_cell,
+                    (void*)D.gsrc, (void*)D.reg})
+      dfree(c, p);
+    if (k > 0) {
+      dfree(c, D.U[0]);
+      dfree(c, D.U[1]);
+      D.U[0] = D.U[1] = nullptr;
+    }
+    D.tab = nullptr;
+    D.tflag = nullptr;
+    D.refined = nullptr;
+    D.child = nullptr;
+    D.parent_cell = nullptr;
+    D.gsrc = nullptr;
+    D.reg = nullptr;
+  }
+  bool ok = true;
+  for (int k = 0; k < nl && ok; ++k) {
+    DevLevel& D = c->lev[k];
+    const LevelTables& t = T[k];
+    D.n_oct = t.n_oct;
+    D.n_ghost = t.n_ghost;
+    D.n_ext = t.n_oct + t.n_ghost;
+    D.n_leaf = t.n_leaf;
+    D.n_tile = t.n_tile;
+    D.keys = H[k].key;
+    D.refined_host = H[k].refined;
+    if (D.n_oct == 0) continue;
+    if (k > 0) {
+      D.cur = 0;
+      for (int b = 0; b < 2 && ok; ++b) {
+        D.U[b] = static_cast<double*>(dalloc(c, sizeof(double) * nv * 8 * D.n_ext));
+        if (!D.U[b]) ok = false;
+      }
+      if (!ok) break;
+      for (int v = 0; v < nv; ++v)
+        HIPCHK(c, hipMemcpyAsync(D.U[0] + v * D.plane(), tmp[k] + v * 8 * D.n_oct, sizeof(double) * 8 * D.n_oct,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    }
+    upload_level_tables(c, D, t, k, ok);
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (double* p : tmp) dfree(c, p);
+  // tile-indexed CFL partials
+  dfree(c, c->d_part);
+  dfree(c, c->d_segoff);
+  c->seg_off.assign(1, 0);
+  for (int k = 0; k < nl; ++k) c->seg_off.push_back(c->seg_off.back() + c->lev[k].n_tile);
+  c->d_part = static_cast<double*>(dalloc(c, sizeof(double) * std::max<int64_t>(c->seg_off.back(), 1)));
+  c->d_segoff = static_cast<int64_t*>(dalloc(c, sizeof(int64_t) * c->seg_off.size()));
+  if (!ok || !c->d_part || !c->d_segoff) {
+    free_all(c);
+    c->built = false;
+    return fail(c, RY_ENOMEM, "regrid allocation failed; the context must be rebuilt");
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_segoff, c->seg_off.data(), sizeof(int64_t) * c->seg_off.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  // refined cells = ordered 8-child means, bottom-up
+  for (int k = nl - 2; k >= 0; --k) {
+    DevLevel& L = c->lev[k];
+    DevLevel& F = c->lev[k + 1];
+    if (F.n_oct == 0) continue;
+    if (launch_restrict(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur], L.plane(), nv, nullptr,
+                        c->stream))
+      return fail(c, RY_EHIP, "restrict kernel");
+  }
+  drop_graphs(c);
+  std::fill(std::begin(c->count), std::end(c->count), 0);
+  c->slots_valid = false;
+  if ((s = enqueue_cfl_all(c))) return s;
+  if ((s = sync_and_check(c))) return s;
+  if (n_created) *n_created = created;
+  if (n_destroyed) *n_destroyed = destroyed;
   return RY_OK;
 }
 
@@ -653,29 +811,30 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
   return RY_OK;
 }
 
-ry_status ry_conserved_totals(ry_ctx* c, double tot[5]) {
+ry_status ry_conserved_totals(ry_ctx* c, double* tot) {
   if (!c || !tot || !c->built || c->batch) return RY_EINVAL;
   const int nb = totals_blocks();
-  if (launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_partial), int64_t(NVAR) * nb, c->stream))
+  const int nv = c->dom.nv;
+  if (launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_partial), int64_t(nv) * nb, c->stream))
     return fail(c, RY_EHIP, "zero kernel");
   for (int k = 0; k < c->nlev; ++k) {
     DevLevel& L = c->lev[k];
     if (!L.n_oct) continue;
     const double dx = level_dx(c, c->cfg.level_min + k);
-    if (launch_totals(L.U[L.cur], L.plane(), L.n_oct, L.refined, dx * dx * dx, c->d_partial, nb, c->stream))
+    if (launch_totals(L.U[L.cur], L.plane(), L.n_oct, L.refined, dx * dx * dx, nv, c->d_partial, nb, c->stream))
       return fail(c, RY_EHIP, "totals kernel");
   }
-  if (launch_totals_final(c->d_partial, nb, c->d_tot, c->stream)) return fail(c, RY_EHIP, "totals kernel");
+  if (launch_totals_final(c->d_partial, nb, nv, c->d_tot, c->stream)) return fail(c, RY_EHIP, "totals kernel");
   ry_status s = sync_and_check(c);
   if (s) return s;
-  HIPCHK(c, hipMemcpy(tot, c->d_tot, sizeof(double) * NVAR, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(tot, c->d_tot, sizeof(double) * nv, hipMemcpyDeviceToHost));
   return RY_OK;
 }
 
 ry_status ry_download(ry_ctx* c, int32_t level, double* U) {
   if (!c || !U || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
   DevLevel& D = c->lev[level - c->cfg.level_min];
-  for (int v = 0; v < NVAR && D.n_oct; ++v)
+  for (int v = 0; v < c->dom.nv && D.n_oct; ++v)
     HIPCHK(c, hipMemcpyAsync(U + size_t(v) * 8 * D.n_oct, D.U[D.cur] + v * D.plane(), sizeof(double) * 8 * D.n_oct,
                              hipMemcpyDeviceToHost, c->stream));
   return sync_and_check(c);
@@ -702,7 +861,7 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
     if (s) return s;
     if (!U0[b]) return RY_EINVAL;
     if (cfgs[b].gamma != cfgs[0].gamma || cfgs[b].cfl != cfgs[0].cfl || cfgs[b].rho_floor != cfgs[0].rho_floor ||
-        cfgs[b].p_floor != cfgs[0].p_floor || cfgs[b].precision != cfgs[0].precision)
+        cfgs[b].p_floor != cfgs[0].p_floor || cfgs[b].precision != cfgs[0].precision || cfgs[b].nscalar != 0)
       return RY_EINVAL;
   }
   ry_ctx* c = new (std::nothrow) ry_ctx();
@@ -881,6 +1040,7 @@ ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
   if (t->tiles_per_wg != 1 && t->tiles_per_wg != 2 && t->tiles_per_wg != 4) return RY_EINVAL;
   if (t->waves_per_tile != 1 && t->waves_per_tile != 2 && t->waves_per_tile != 4) return RY_EINVAL;
   if (t->tiles_per_wg * t->waves_per_tile > 4) return RY_EINVAL;
+  if (!hydro_tuning_supported(c->cfg.precision, c->cfg.nscalar, *t)) return RY_EINVAL;
   if (t->persistent && (t->waves_per_cu < 1 || t->waves_per_cu > 32 || t->batch < 1 || t->batch > 64))
     return RY_EINVAL;
   c->tune = *t;
@@ -951,6 +1111,11 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
   for (int wpt : {1, 2, 4})
     for (int w : {8, 14, 20})
       for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt});
+  cand.erase(std::remove_if(cand.begin(), cand.end(),
+                            [&](const ry_tuning& t) {
+                              return !hydro_tuning_supported(c->cfg.precision, c->cfg.nscalar, t);
+                            }),
+             cand.end());
   double best_ms = INFINITY;
   ry_tuning bt{};
   int n = 0;

@@ -117,9 +117,9 @@ static_assert(WSIZE < 512 && NFACE < 256, "LDS indices must fit the table fields
 // cells' right states [NVAR][NUPPER] (B2 -> C), then the face fluxes
 // [NVAR][NFACE] (C -> D).  Fluxes are stored in Real: in the mixed
 // form they are FP32 results, so FP32 storage loses nothing.
-template <typename Real>
+template <typename Real, int NV>
 struct TileLDS {
-  static constexpr int NW = NVAR * WSIZE, NF = NVAR * (NFACE + NUPPER);
+  static constexpr int NW = NV * WSIZE, NF = NV * (NFACE + NUPPER);
   Real buf[NW > NF ? NW : NF];
   int32_t tab[TILE_TAB];  // ext oct index of the 4x4x4 oct neighbourhood
   uint8_t ref[TILE_TAB];  // refined-cell bytes of those octs
@@ -167,9 +167,10 @@ __device__ __forceinline__ double esqrt(double x) {
 __device__ __forceinline__ float esqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Primitive variables (FP64 in both forms) with floors; nfl counts floor
-// activations.
-__device__ __forceinline__ void cons2prim(const double U[NVAR], double W[NVAR], double g, double rf, double pf,
-                                          int& nfl) {
+// activations.  Passive scalars: s = (rho s) / rho.
+template <int NS>
+__device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NVAR + NS], double g, double rf,
+                                          double pf, int& nfl) {
   const bool lo_r = U[0] < rf;
   const double rho = lo_r ? rf : U[0];
   const double ir = rcp(rho);
@@ -182,6 +183,8 @@ __device__ __forceinline__ void cons2prim(const double U[NVAR], double W[NVAR], 
   W[2] = U[2] * ir;
   W[3] = U[3] * ir;
   W[4] = lo_p ? pf : p0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) W[NVAR + k] = U[NVAR + k] * ir;
 }
 
 // CFL signal speed |u|+|v|+|w|+3c of a conserved state, in the same IEEE
@@ -199,13 +202,27 @@ __device__ __forceinline__ double signal_speed(const double U[NVAR], double g, d
   return fabs(u) + fabs(v) + fabs(w) + 3.0 * c;
 }
 
+// What a passive scalar's HLLC flux needs from the hydro solve: the side K,
+// its density and mass flux, the star weight w (S_K on star faces, else 0)
+// and r = (S_K - u_K) / (S_K - S*).  A scalar is carried like a transverse
+// velocity (Toro 2009, Sec. 10.6): F_s = m_K s_K + w (r (rho_K s_K) - rho_K s_K).
+template <typename Real>
+struct HllcSide {
+  bool useL;
+  Real rK, mK, w, r;
+  __device__ __forceinline__ Real scalar_flux(Real sl, Real sr) const {
+    const Real sK = useL ? sl : sr;
+    return mK * sK + w * (r * (rK * sK) - rK * sK);
+  }
+};
+
 // HLLC flux in the face-normal frame: (r, u, a, b, p) = density, normal and
 // two tangential velocities, pressure of the left / right face state.  The
 // branch picks a side K (L when S_L >= 0 or S* >= 0, else R) and whether the
 // star state of K applies; only that side's star state is formed.
 template <typename Real>
 __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real pl, Real rr, Real ur, Real ar,
-                                       Real br, Real pr, Real g, Real igm1, Real Fn[5]) {
+                                       Real br, Real pr, Real g, Real igm1, Real Fn[5], HllcSide<Real>& side) {
   const Real cl = esqrt(g * pl * rcp(rl));
   const Real cr = esqrt(g * pr * rcp(rr));
   const Real SL = fmin(ul - cl, ur - cr);
@@ -230,12 +247,18 @@ __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real 
   Fn[2] = mK * aK + w * (r * (rK * aK) - rK * aK);
   Fn[3] = mK * bK + w * (r * (rK * bK) - rK * bK);
   Fn[4] = (EK + pK) * uK + w * (r * Es - EK);
+  side.useL = useL;
+  side.rK = rK;
+  side.mK = mK;
+  side.w = w;
+  side.r = r;
 }
 
 // Unsplit half-step predictor of the primitives W0 with undivided slopes
 // D[axis][var] and h = lambda / 2.
-template <typename Real>
-__device__ __forceinline__ void predict(const Real W0[NVAR], const Real D[3][NVAR], Real h, Real g, Real P[NVAR]) {
+template <typename Real, int NS>
+__device__ __forceinline__ void predict(const Real W0[NVAR + NS], const Real D[3][NVAR + NS], Real h, Real g,
+                                        Real P[NVAR + NS]) {
   const Real r = W0[0], u = W0[1], vv = W0[2], w = W0[3], p = W0[4];
   const Real ir = rcp(r);
   P[0] = r - h * (u * D[0][0] + r * D[0][1] + vv * D[1][0] + r * D[1][2] + w * D[2][0] + r * D[2][3]);
@@ -243,11 +266,14 @@ __device__ __forceinline__ void predict(const Real W0[NVAR], const Real D[3][NVA
   P[2] = vv - h * (u * D[0][2] + vv * D[1][2] + w * D[2][2] + D[1][4] * ir);
   P[3] = w - h * (u * D[0][3] + vv * D[1][3] + w * D[2][3] + D[2][4] * ir);
   P[4] = p - h * (u * D[0][4] + vv * D[1][4] + w * D[2][4] + g * p * (D[0][1] + D[1][2] + D[2][3]));
+  // a passive scalar is advected: s~ = s - h (u Dx s + v Dy s + w Dz s)
+#pragma unroll
+  for (int k = NVAR; k < NVAR + NS; ++k) P[k] = W0[k] - h * (u * D[0][k] + vv * D[1][k] + w * D[2][k]);
 }
 
 // Floors of a face state; nfl counts activations.
 template <typename Real>
-__device__ __forceinline__ void floor_state(Real s[NVAR], Real rf, Real pf, int& nfl) {
+__device__ __forceinline__ void floor_state(Real* s, Real rf, Real pf, int& nfl) {
   nfl += int(s[0] < rf) + int(s[4] < pf);
   s[0] = (s[0] < rf) ? rf : s[0];
   s[4] = (s[4] < pf) ? pf : s[4];
@@ -257,22 +283,26 @@ __device__ __forceinline__ void floor_state(Real s[NVAR], Real rf, Real pf, int&
 // comes from LDS (FL[var * NFACE + f]), the right one, W~ - D/2, from the
 // cell's predicted state Pw and slope Pdd along D.  The HLLC runs in the
 // face-normal frame; F is returned in the global frame.
-template <typename Real, int D>
-__device__ __forceinline__ void core_face_flux(const Real* FL, int f, const Real Pw[NVAR], const Real Pdd[NVAR],
-                                               Real rf, Real pf, Real g, Real igm1, int& nfl, Real F[NVAR]) {
+template <typename Real, int D, int NS>
+__device__ __forceinline__ void core_face_flux(const Real* FL, int f, const Real Pw[NVAR + NS],
+                                               const Real Pdd[NVAR + NS], Real rf, Real pf, Real g, Real igm1,
+                                               int& nfl, Real F[NVAR + NS]) {
   constexpr int iu = 1 + D, i1 = (D == 0) ? 2 : 1, i2 = (D == 2) ? 2 : 3;
-  Real wr[NVAR];
+  Real wr[NVAR + NS];
 #pragma unroll
-  for (int v = 0; v < NVAR; ++v) wr[v] = Pw[v] - Real(0.5) * Pdd[v];
+  for (int v = 0; v < NVAR + NS; ++v) wr[v] = Pw[v] - Real(0.5) * Pdd[v];
   floor_state<Real>(wr, rf, pf, nfl);
   Real Fn[5];
+  HllcSide<Real> side;
   hllc_n<Real>(FL[f], FL[iu * NFACE + f], FL[i1 * NFACE + f], FL[i2 * NFACE + f], FL[4 * NFACE + f], wr[0], wr[iu],
-               wr[i1], wr[i2], wr[4], g, igm1, Fn);
+               wr[i1], wr[i2], wr[4], g, igm1, Fn, side);
   F[0] = Fn[0];
   F[iu] = Fn[1];
   F[i1] = Fn[2];
   F[i2] = Fn[3];
   F[4] = Fn[4];
+#pragma unroll
+  for (int k = NVAR; k < NVAR + NS; ++k) F[k] = side.scalar_flux(FL[k * NFACE + f], wr[k]);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -308,8 +338,10 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
-template <typename Real, int NT>
-__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int tid_in, bool active) {
+template <typename Real, int NT, int NS>
+__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS>& S, int tid_in,
+                           bool active) {
+  constexpr int NV = NVAR + NS;
   const int tid = opaque(tid_in);
   const int lane = tid & 63;
   const double g = A.gamma, rf = A.rho_floor, pf = A.p_floor;
@@ -331,9 +363,9 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
 
   // --- phase A: gather + primitives (all loads of the thread's positions are
   // issued before any conversion)
-  Real* W = S.buf;                              // [NVAR][WSIZE]
+  Real* W = S.buf;                              // [NV][WSIZE]
   constexpr int NRA = (NPOS_A + NT - 1) / NT;
-  double Ua[NRA][NVAR];
+  double Ua[NRA][NV];
   int iwa[NRA];
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
@@ -360,7 +392,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
       if (e >= 0) {
         const int64_t cell = int64_t(e) * 8 + cb;
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) Ua[rnd][v] = A.U[v * P + cell];
+        for (int v = 0; v < NV; ++v) Ua[rnd][v] = A.U[v * P + cell];
       } else {
         // a slot no leaf update reads
         Ua[rnd][0] = 1.0; Ua[rnd][1] = 0.0; Ua[rnd][2] = 0.0; Ua[rnd][3] = 0.0; Ua[rnd][4] = 1.0;
@@ -370,15 +402,15 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     if (iwa[rnd] >= 0) {
-      double Wc[NVAR];
-      cons2prim(Ua[rnd], Wc, g, rf, pf, nfl);
+      double Wc[NV];
+      cons2prim<NS>(Ua[rnd], Wc, g, rf, pf, nfl);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) W[v * WSIZE + iwa[rnd]] = Real(Wc[v]);
+      for (int v = 0; v < NV; ++v) W[v * WSIZE + iwa[rnd]] = Real(Wc[v]);
     }
   }
   __syncthreads();
 
-  // --- phase B1: slopes + predictor.  The core cell of a thread (round 0,
+  // --- phase B1: slopes + predictor.  The core cell of a thread (first pass,
   // tid < 64) keeps W~ and its slopes in registers for its six faces; a
   // one-layer cell keeps only its state on the face toward the core.
   constexpr int NRB = (NPOS_B + NT - 1) / NT;
@@ -386,8 +418,8 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
   const bool core = (NT == 64) || tid < NCORE;
   const int cx = tid & 3, cy = (tid >> 2) & 3, cz = (tid >> 4) & 3;
   const Real rfr = Real(rf), pfr = Real(pf), gr = Real(g);
-  Real Pw[NVAR], Pd[3][NVAR];
-  Real Ls[NRB][NVAR];
+  Real Pw[NV], Pd[3][NV];
+  Real Ls[NRB][NV];
   uint32_t Lb[NRB];
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
@@ -396,39 +428,39 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
     if (!active || i >= NPOS_B) continue;
     if (rnd == 0 && core) {
       const int iw = (cx + 1) + WB * (cy + 1) + WBB * (cz + 1);
-      Real W0[NVAR];
+      Real W0[NV];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) W0[v] = W[v * WSIZE + iw];
+      for (int v = 0; v < NV; ++v) W0[v] = W[v * WSIZE + iw];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v)
+        for (int v = 0; v < NV; ++v)
           Pd[d][v] = mmod(W0[v] - W[v * WSIZE + iw - st[d]], W[v * WSIZE + iw + st[d]] - W0[v]);
-      predict<Real>(W0, Pd, h, gr, Pw);
+      predict<Real, NS>(W0, Pd, h, gr, Pw);
     } else {
       const uint32_t e = c_st.b[i];
       Lb[rnd] = e;
       const int iw = int(e & 511u), far = int((e >> 9) & 511u), dn = int((e >> 18) & 3u);
       const bool up = (e >> 20) & 1u;
-      Real W0[NVAR], D[3][NVAR], Q[NVAR];
+      Real W0[NV], D[3][NV], Q[NV];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) W0[v] = W[v * WSIZE + iw];
-      Real Dn[NVAR];                            // the slope along the normal
+      for (int v = 0; v < NV; ++v) W0[v] = W[v * WSIZE + iw];
+      Real Dn[NV];                            // the slope along the normal
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int lo = (d == dn && !up) ? far : iw - st[d];
         const int hi = (d == dn && up) ? far : iw + st[d];
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
           const Real sl = mmod(W0[v] - W[v * WSIZE + lo], W[v * WSIZE + hi] - W0[v]);
           D[d][v] = sl;
           Dn[v] = (d == 0 || d == dn) ? sl : Dn[v];
         }
       }
-      predict<Real>(W0, D, h, gr, Q);
+      predict<Real, NS>(W0, D, h, gr, Q);
       const Real sg = up ? Real(-0.5) : Real(0.5);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) Ls[rnd][v] = Q[v] + sg * Dn[v];
+      for (int v = 0; v < NV; ++v) Ls[rnd][v] = Q[v] + sg * Dn[v];
       floor_state<Real>(Ls[rnd], rfr, pfr, nfl);
     }
   }
@@ -436,8 +468,8 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
 
   // --- phase B2: the left states (W~ + D/2 of the lower cell) of the 240
   // faces replace the primitives in LDS
-  Real* FL = S.buf;                             // [NVAR][NFACE]
-  Real* FR = S.buf + NVAR * NFACE;              // [NVAR][NUPPER]: right states of the upper layer
+  Real* FL = S.buf;                             // [NV][NFACE]
+  Real* FR = S.buf + NV * NFACE;              // [NV][NUPPER]: right states of the upper layer
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
@@ -445,21 +477,21 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
     if (rnd == 0 && core) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        Real s[NVAR];
+        Real s[NV];
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) s[v] = Pw[v] + Real(0.5) * Pd[d][v];
+        for (int v = 0; v < NV; ++v) s[v] = Pw[v] + Real(0.5) * Pd[d][v];
         floor_state<Real>(s, rfr, pfr, nfl);
         const int f = fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) FL[v * NFACE + f] = s[v];
+        for (int v = 0; v < NV; ++v) FL[v * NFACE + f] = s[v];
       }
     } else if (!((Lb[rnd] >> 20) & 1u)) {
       const int f = int(Lb[rnd] >> 21);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) FL[v * NFACE + f] = Ls[rnd][v];
+      for (int v = 0; v < NV; ++v) FL[v * NFACE + f] = Ls[rnd][v];
     } else {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) FR[v * NUPPER + (i - NCORE)] = Ls[rnd][v];
+      for (int v = 0; v < NV; ++v) FR[v * NUPPER + (i - NCORE)] = Ls[rnd][v];
     }
   }
   __syncthreads();
@@ -467,26 +499,29 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
   // --- phase C: HLLC on the faces whose upper cell the thread holds (a core
   // cell: its three lower faces; an upper one-layer cell: its face, read in
   // the face-normal frame straight from LDS)
-  Real Fc[3][NVAR];
-  Real Fl[NRB][NVAR];
+  Real Fc[3][NV];
+  Real Fl[NRB][NV];
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
     if (!active || i >= NPOS_B) continue;
     if (rnd == 0 && core) {
-      core_face_flux<Real, 0>(FL, fidx(0, cx, cy, cz), Pw, Pd[0], rfr, pfr, gr, igm1, nfl, Fc[0]);
-      core_face_flux<Real, 1>(FL, fidx(1, cx, cy, cz), Pw, Pd[1], rfr, pfr, gr, igm1, nfl, Fc[1]);
-      core_face_flux<Real, 2>(FL, fidx(2, cx, cy, cz), Pw, Pd[2], rfr, pfr, gr, igm1, nfl, Fc[2]);
+      core_face_flux<Real, 0, NS>(FL, fidx(0, cx, cy, cz), Pw, Pd[0], rfr, pfr, gr, igm1, nfl, Fc[0]);
+      core_face_flux<Real, 1, NS>(FL, fidx(1, cx, cy, cz), Pw, Pd[1], rfr, pfr, gr, igm1, nfl, Fc[1]);
+      core_face_flux<Real, 2, NS>(FL, fidx(2, cx, cy, cz), Pw, Pd[2], rfr, pfr, gr, igm1, nfl, Fc[2]);
     } else if ((Lb[rnd] >> 20) & 1u) {
       const int f = int(Lb[rnd] >> 21), dn = int((Lb[rnd] >> 18) & 3u), k = i - NCORE;
       const int iu = 1 + dn, i1 = (dn == 0) ? 2 : 1, i2 = (dn == 2) ? 2 : 3;
+      HllcSide<Real> side;
       hllc_n<Real>(FL[f], FL[iu * NFACE + f], FL[i1 * NFACE + f], FL[i2 * NFACE + f], FL[4 * NFACE + f], FR[k],
                    FR[iu * NUPPER + k], FR[i1 * NUPPER + k], FR[i2 * NUPPER + k], FR[4 * NUPPER + k], gr, igm1,
-                   Fl[rnd]);
+                   Fl[rnd], side);
+#pragma unroll
+      for (int v = NVAR; v < NV; ++v) Fl[rnd][v] = side.scalar_flux(FL[v * NFACE + f], FR[v * NUPPER + k]);
     }
   }
   __syncthreads();
-  Real* SF = S.buf;                             // [NVAR][NFACE]
+  Real* SF = S.buf;                             // [NV][NFACE]
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
@@ -496,7 +531,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
       for (int d = 0; d < 3; ++d) {
         const int f = fidx(d, cx, cy, cz);
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) SF[v * NFACE + f] = Fc[d][v];
+        for (int v = 0; v < NV; ++v) SF[v * NFACE + f] = Fc[d][v];
       }
     } else if ((Lb[rnd] >> 20) & 1u) {
       // Fl is in the face-normal frame: rotate back on the way out
@@ -507,6 +542,8 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
       SF[i1 * NFACE + f] = Fl[rnd][2];
       SF[i2 * NFACE + f] = Fl[rnd][3];
       SF[4 * NFACE + f] = Fl[rnd][4];
+#pragma unroll
+      for (int v = NVAR; v < NV; ++v) SF[v * NFACE + f] = Fl[rnd][v];
     }
   }
   __syncthreads();
@@ -519,15 +556,15 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
     const bool leaf = (e >= 0) && (e < A.n_oct) && !((S.ref[ts] >> ci) & 1);
     double s = 0.0;
     if (leaf) {
-      double acc[NVAR] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      double acc[NV] = {};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         // the lower face's flux is the thread's own (phase C), the upper
         // one comes from the neighbouring cell's thread through LDS
         const int fp = fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
-        double Fm[NVAR], Fp[NVAR];
+        double Fm[NV], Fp[NV];
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
           Fm[v] = double(Fc[d][v]);
           Fp[v] = double(SF[v * NFACE + fp]);
         }
@@ -546,9 +583,9 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
             if (en >= 0 && en < A.n_oct && ((S.ref[tn] >> cn) & 1)) {
               const int32_t ch = A.child[int64_t(en) * 8 + cn];
               const int face = 2 * d + (side ? 0 : 1);   // child's face toward this cell
-              const double* q = A.reg_fine + (int64_t(ch) * 6 + face) * NVAR * 2;
+              const double* q = A.reg_fine + (int64_t(ch) * 6 + face) * NV * 2;
 #pragma unroll
-              for (int v = 0; v < NVAR; ++v) {
+              for (int v = 0; v < NV; ++v) {
                 const double fb = 0.125 * (q[2 * v] + q[2 * v + 1]);
                 if (side) Fp[v] = fb; else Fm[v] = fb;
               }
@@ -556,12 +593,12 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
           }
         }
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) acc[v] += (Fm[v] - Fp[v]);
+        for (int v = 0; v < NV; ++v) acc[v] += (Fm[v] - Fp[v]);
       }
       const int64_t cell = int64_t(e) * 8 + ci;
-      double Un[NVAR];
+      double Un[NV];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
+      for (int v = 0; v < NV; ++v) {
         Un[v] = A.U[v * P + cell] + lam * acc[v];
         A.Un[v * P + cell] = Un[v];
       }
@@ -609,9 +646,9 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
           const int ccx = 2 * bx + (c & 1), ccy = 2 * by + ((c >> 1) & 1), ccz = 2 * bz + ((c >> 2) & 1);
           fi[j] = fidx(d, ccx + (d == 0 ? up : 0), ccy + (d == 1 ? up : 0), ccz + (d == 2 ? up : 0));
         }
-        double* q = A.reg_own + (int64_t(eb) * 6 + face) * NVAR * 2;
+        double* q = A.reg_own + (int64_t(eb) * 6 + face) * NV * 2;
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v)
+        for (int v = 0; v < NV; ++v)
           q[2 * v + A.substep] = (double(SF[v * NFACE + fi[0]]) + double(SF[v * NFACE + fi[1]])) +
                                  (double(SF[v * NFACE + fi[2]]) + double(SF[v * NFACE + fi[3]]));
       }
@@ -624,17 +661,17 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real>& S, int t
   __syncthreads();
 }
 
-template <typename Real, int TPW, int WPT>
+template <typename Real, int TPW, int WPT, int NS>
 __global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel(HydroArgs A) {
   constexpr int NT = 64 * WPT;
-  __shared__ TileLDS<Real> S[TPW];
+  __shared__ TileLDS<Real, NVAR + NS> S[TPW];
   if (A.skip && *A.skip) return;
   const int w = threadIdx.x / NT, tid = threadIdx.x % NT;
   const int ngroups = (A.n_tile + TPW - 1) / TPW;
   const int grp = xcd_remap(blockIdx.x, gridDim.x);
   if (grp >= ngroups) return;
   const int tile = grp * TPW + w;
-  hydro_tile<Real, NT>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
+  hydro_tile<Real, NT, NS>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
 }
 
 // Persistent variant: workgroups pop groups of tiles from 8 per-XCD queues
@@ -644,7 +681,7 @@ __global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel(HydroArgs A) {
 template <typename Real, int TPW, int WPT>
 __global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel_persistent(HydroArgs A, int batch) {
   constexpr int NT = 64 * WPT;
-  __shared__ TileLDS<Real> S[TPW];
+  __shared__ TileLDS<Real, NVAR> S[TPW];
   __shared__ int s_item;
   if (A.skip && *A.skip) return;
   const int w = threadIdx.x / NT, tid = threadIdx.x % NT;
@@ -676,17 +713,18 @@ __global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel_persistent(HydroA
       const int grp = item * batch + j;
       if (grp >= ngroups) break;
       const int tile = grp * TPW + w;
-      hydro_tile<Real, NT>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
+      hydro_tile<Real, NT, 0>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
     }
   }
 }
 
-template <typename Real, int TPW, int WPT>
+// The persistent kernel exists for the hydro variables alone (NS = 0).
+template <typename Real, int TPW, int WPT, int NS>
 static int launch_hydro_t(const HydroArgs& a, const ry_tuning& t, int num_cu, hipStream_t s) {
   const int ngroups = (a.n_tile + TPW - 1) / TPW;
   if (ngroups == 0) return 0;
-  if (!t.persistent) {
-    hipLaunchKernelGGL((hydro_kernel<Real, TPW, WPT>), dim3(ngroups), dim3(64 * WPT * TPW), 0, s, a);
+  if (NS > 0 || !t.persistent) {
+    hipLaunchKernelGGL((hydro_kernel<Real, TPW, WPT, NS>), dim3(ngroups), dim3(64 * WPT * TPW), 0, s, a);
   } else {
     const int batch = t.batch > 0 ? t.batch : 1;
     const int nitems = (ngroups + batch - 1) / batch;
@@ -701,27 +739,61 @@ static int launch_hydro_t(const HydroArgs& a, const ry_tuning& t, int num_cu, hi
 
 int hydro_max_tiles_per_wg() { return 4; }
 
-int launch_hydro(const HydroArgs& a, int precision, const ry_tuning& t, int num_cu, void* stream) {
+bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t) {
+  const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
+  if (nscalar == 0) {
+    if (precision == RY_MIXED) return key == 11 || key == 21 || key == 41 || key == 12 || key == 22 || key == 14;
+    return key == 11 || key == 21 || key == 41 || key == 12 || key == 22 || key == 14;
+  }
+  return nscalar <= RY_MAX_SCALARS && !t.persistent && (key == 11 || key == 12 || key == 21);
+}
+
+template <typename Real, int NS>
+static int launch_hydro_ns(const HydroArgs& a, const ry_tuning& t, int num_cu, hipStream_t s) {
+  switch (t.tiles_per_wg * 10 + t.waves_per_tile) {
+    case 11: return launch_hydro_t<Real, 1, 1, NS>(a, t, num_cu, s);
+    case 12: return launch_hydro_t<Real, 1, 2, NS>(a, t, num_cu, s);
+    case 21: return launch_hydro_t<Real, 2, 1, NS>(a, t, num_cu, s);
+    default: return -1;
+  }
+}
+
+template <typename Real>
+static int launch_hydro_scalars(const HydroArgs& a, int nscalar, const ry_tuning& t, int num_cu, hipStream_t s) {
+  switch (nscalar) {
+    case 1: return launch_hydro_ns<Real, 1>(a, t, num_cu, s);
+    case 2: return launch_hydro_ns<Real, 2>(a, t, num_cu, s);
+    case 3: return launch_hydro_ns<Real, 3>(a, t, num_cu, s);
+    case 4: return launch_hydro_ns<Real, 4>(a, t, num_cu, s);
+    default: return -1;
+  }
+}
+
+int launch_hydro(const HydroArgs& a, int precision, int nscalar, const ry_tuning& t, int num_cu, void* stream) {
   hipStream_t s = (hipStream_t)stream;
+  if (!hydro_tuning_supported(precision, nscalar, t)) return -1;
+  if (nscalar > 0)
+    return precision == RY_MIXED ? launch_hydro_scalars<float>(a, nscalar, t, num_cu, s)
+                                 : launch_hydro_scalars<double>(a, nscalar, t, num_cu, s);
   const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
   if (precision == RY_MIXED) {
     switch (key) {
-      case 11: return launch_hydro_t<float, 1, 1>(a, t, num_cu, s);
-      case 21: return launch_hydro_t<float, 2, 1>(a, t, num_cu, s);
-      case 41: return launch_hydro_t<float, 4, 1>(a, t, num_cu, s);
-      case 12: return launch_hydro_t<float, 1, 2>(a, t, num_cu, s);
-      case 22: return launch_hydro_t<float, 2, 2>(a, t, num_cu, s);
-      case 14: return launch_hydro_t<float, 1, 4>(a, t, num_cu, s);
+      case 11: return launch_hydro_t<float, 1, 1, 0>(a, t, num_cu, s);
+      case 21: return launch_hydro_t<float, 2, 1, 0>(a, t, num_cu, s);
+      case 41: return launch_hydro_t<float, 4, 1, 0>(a, t, num_cu, s);
+      case 12: return launch_hydro_t<float, 1, 2, 0>(a, t, num_cu, s);
+      case 22: return launch_hydro_t<float, 2, 2, 0>(a, t, num_cu, s);
+      case 14: return launch_hydro_t<float, 1, 4, 0>(a, t, num_cu, s);
       default: return -1;
     }
   }
   switch (key) {
-    case 11: return launch_hydro_t<double, 1, 1>(a, t, num_cu, s);
-    case 21: return launch_hydro_t<double, 2, 1>(a, t, num_cu, s);
-    case 41: return launch_hydro_t<double, 4, 1>(a, t, num_cu, s);
-    case 12: return launch_hydro_t<double, 1, 2>(a, t, num_cu, s);
-    case 22: return launch_hydro_t<double, 2, 2>(a, t, num_cu, s);
-    case 14: return launch_hydro_t<double, 1, 4>(a, t, num_cu, s);
+    case 11: return launch_hydro_t<double, 1, 1, 0>(a, t, num_cu, s);
+    case 21: return launch_hydro_t<double, 2, 1, 0>(a, t, num_cu, s);
+    case 41: return launch_hydro_t<double, 4, 1, 0>(a, t, num_cu, s);
+    case 12: return launch_hydro_t<double, 1, 2, 0>(a, t, num_cu, s);
+    case 22: return launch_hydro_t<double, 2, 2, 0>(a, t, num_cu, s);
+    case 14: return launch_hydro_t<double, 1, 4, 0>(a, t, num_cu, s);
     default: return -1;
   }
 }
@@ -741,8 +813,7 @@ __global__ void ghost_kernel(GhostArgs A) {
 #pragma unroll
   for (int k = 0; k < 7; ++k) src[k] = A.gsrc[gi * 7 + k];
   const int64_t dst = (A.n_oct + gi) * 8 + c;
-#pragma unroll
-  for (int v = 0; v < NVAR; ++v) {
+  for (int v = 0; v < A.nv; ++v) {
     double val[7];
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
@@ -771,23 +842,23 @@ int launch_ghost(const GhostArgs& a, void* stream) {
 // Restriction: refined cell of level l = mean of its 8 children.
 // ---------------------------------------------------------------------------
 __global__ void restrict_kernel(const double* __restrict__ Uf, int64_t pf, int64_t nf,
-                                const int32_t* __restrict__ parent, double* __restrict__ Uc, int64_t pc,
+                                const int32_t* __restrict__ parent, double* __restrict__ Uc, int64_t pc, int nv,
                                 const int32_t* skip) {
   if (skip && *skip) return;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nf * NVAR) return;
-  const int64_t k = i / NVAR;
-  const int v = int(i - k * NVAR);
+  if (i >= nf * nv) return;
+  const int64_t k = i / nv;
+  const int v = int(i - k * nv);
   const double* s = Uf + v * pf + 8 * k;
   Uc[v * pc + parent[k]] = 0.125 * (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
 }
 
 int launch_restrict(const double* Uf, int64_t pf, int64_t nf, const int32_t* parent, double* Uc, int64_t pc,
-                    const int32_t* skip, void* stream) {
+                    int nv, const int32_t* skip, void* stream) {
   if (nf == 0) return 0;
-  const int64_t n = nf * NVAR;
+  const int64_t n = nf * nv;
   hipLaunchKernelGGL(restrict_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, Uf, pf,
-                     nf, parent, Uc, pc, skip);
+                     nf, parent, Uc, pc, nv, skip);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -944,35 +1015,32 @@ constexpr int TOT_BLOCKS = 1024;
 int totals_blocks() { return TOT_BLOCKS; }
 
 __global__ void totals_kernel(const double* __restrict__ U, int64_t plane, int64_t n_oct,
-                              const uint8_t* __restrict__ refined, double vol, double* __restrict__ partial) {
-  __shared__ double red[NVAR][256];
+                              const uint8_t* __restrict__ refined, double vol, int nv, double* __restrict__ partial) {
+  __shared__ double red[256];
   const int64_t ncell = n_oct * 8;
   const int64_t per = (ncell + gridDim.x - 1) / gridDim.x;
   const int64_t i0 = int64_t(blockIdx.x) * per;
   const int64_t i1 = (i0 + per < ncell) ? i0 + per : ncell;
-  double acc[NVAR] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    if ((refined[i >> 3] >> (i & 7)) & 1) continue;
-#pragma unroll
-    for (int v = 0; v < NVAR; ++v) acc[v] += U[v * plane + i] * vol;
-  }
-#pragma unroll
-  for (int v = 0; v < NVAR; ++v) red[v][threadIdx.x] = acc[v];
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s)
-#pragma unroll
-      for (int v = 0; v < NVAR; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + s];
+  for (int v = 0; v < nv; ++v) {
+    double acc = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      if ((refined[i >> 3] >> (i & 7)) & 1) continue;
+      acc += U[v * plane + i] * vol;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[v * TOT_BLOCKS + blockIdx.x] += red[0];
     __syncthreads();
   }
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int v = 0; v < NVAR; ++v) partial[v * TOT_BLOCKS + blockIdx.x] += red[v][0];
 }
 
-__global__ void totals_final_kernel(const double* __restrict__ partial, int nparts, double* out) {
+__global__ void totals_final_kernel(const double* __restrict__ partial, int nparts, int nv, double* out) {
   __shared__ double red[256];
-  for (int v = 0; v < NVAR; ++v) {
+  for (int v = 0; v < nv; ++v) {
     double a = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) a += partial[v * nparts + i];
     red[threadIdx.x] = a;
@@ -986,15 +1054,57 @@ __global__ void totals_final_kernel(const double* __restrict__ partial, int npar
   }
 }
 
-int launch_totals(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double vol, double* partial,
-                  int nblocks, void* stream) {
+int launch_totals(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double vol, int nv,
+                  double* partial, int nblocks, void* stream) {
   if (n_oct == 0) return 0;
   hipLaunchKernelGGL(totals_kernel, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, U, plane, n_oct, refined, vol,
-                     partial);
+                     nv, partial);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-int launch_totals_final(const double* partial, int nparts, double* out, void* stream) {
-  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, partial, nparts, out);
+int launch_totals_final(const double* partial, int nparts, int nv, double* out, void* stream) {
+  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, partial, nparts, nv, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Regrid remap: kept octs copy their state, new octs take the MinMod-linear
+// interpolation of their parent cell (the ghost formula).
+// ---------------------------------------------------------------------------
+__global__ void regrid_remap_kernel(const int32_t* __restrict__ src_old, const int32_t* __restrict__ src7,
+                                    int64_t n_new, const double* __restrict__ Uold, int64_t pold,
+                                    const double* __restrict__ Uc, int64_t pc, double* __restrict__ Unew,
+                                    int64_t pnew, int nv) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_new * 8) return;
+  const int64_t k = i >> 3;
+  const int c = int(i & 7);
+  const int32_t so = src_old[k];
+  if (so >= 0) {
+    for (int v = 0; v < nv; ++v) Unew[v * pnew + i] = Uold[v * pold + int64_t(so) * 8 + c];
+    return;
+  }
+  const double sx = (c & 1) ? 0.25 : -0.25, sy = (c & 2) ? 0.25 : -0.25, sz = (c & 4) ? 0.25 : -0.25;
+  int32_t src[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) src[j] = src7[7 * k + j];
+  for (int v = 0; v < nv; ++v) {
+    double val[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) val[j] = Uc[v * pc + src[j]];
+    const double q = val[0];
+    const double mx = mmod(q - val[1], val[2] - q);
+    const double my = mmod(q - val[3], val[4] - q);
+    const double mz = mmod(q - val[5], val[6] - q);
+    Unew[v * pnew + i] = q + (sx * mx + sy * my + sz * mz);
+  }
+}
+
+int launch_regrid_remap(const int32_t* src_old, const int32_t* src7, int64_t n_new, const double* Uold, int64_t pold,
+                        const double* Uc, int64_t pc, double* Unew, int64_t pnew, int nv, void* stream) {
+  if (n_new == 0) return 0;
+  const int64_t n = n_new * 8;
+  hipLaunchKernelGGL(regrid_remap_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     src_old, src7, n_new, Uold, pold, Uc, pc, Unew, pnew, nv);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -137,7 +137,7 @@ static CellRef covering(const DomainSpec& d, const std::vector<HostLevel>& L, in
   }
 }
 
-static void sort_level(const DomainSpec& d, int l, HostLevel& H) {
+static void sort_level(const DomainSpec& d, int l, HostLevel& H, bool with_state = true) {
   const int bits = d.hbits0 + (l - d.lmin);
   std::vector<uint64_t> k(H.n);
   for (int64_t i = 0; i < H.n; ++i) k[i] = hilbert3(bits, uint32_t(H.ox[i]), uint32_t(H.oy[i]), uint32_t(H.oz[i]));
@@ -157,20 +157,94 @@ static void sort_level(const DomainSpec& d, int l, HostLevel& H) {
   H.oz.swap(z);
   H.index.build(H.ox, H.oy, H.oz);
   H.refined.assign(H.n, 0);
-  H.U.assign(size_t(H.n) * 8 * NVAR, 0.0);
+  if (with_state) H.U.assign(size_t(H.n) * 8 * d.nv, 0.0);
 }
 
-static void restrict_into(const HostLevel& F, HostLevel& C) {
+static void restrict_into(const HostLevel& F, HostLevel& C, int nv) {
   for (int64_t k = 0; k < F.n; ++k) {
     const int64_t px = F.ox[k], py = F.oy[k], pz = F.oz[k];
     int32_t o = C.index.find(px >> 1, py >> 1, pz >> 1);
     const int64_t cell = int64_t(o) * 8 + cidx(px, py, pz);
-    for (int v = 0; v < NVAR; ++v) {
+    for (int v = 0; v < nv; ++v) {
       const double* s = &F.U[size_t(v) * 8 * F.n + 8 * k];
       C.U[size_t(v) * 8 * C.n + cell] =
           0.125 * (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
     }
   }
+}
+
+// Refinement flags of level l (bit c of flag[o] for cell c of oct o): a cell
+// is refined when its 26 neighbour cells exist at level l (outside an
+// outflow face counts as existing) and the criterion holds on its density
+// rho(o, c) -- GRAD with the central differences of its face neighbours
+// (which exist at level l once the neighbour rule holds), MASS against
+// rho_thr 8^(l - lmin).  Returns the number of refined cells.
+template <typename RhoFn>
+static int64_t flag_level(const DomainSpec& d, const HostLevel& H, int l, RhoFn rho, std::vector<uint8_t>& flag) {
+  Geo g(d);
+  flag.assign(H.n, 0);
+  int64_t nnew = 0;
+  const double mass_thr = d.refine_param * std::ldexp(1.0, 3 * (l - d.lmin));
+  auto rho_at = [&](int64_t x, int64_t y, int64_t z) {
+    g.apply(l, x, y, z);
+    return rho(H.index.find(x >> 1, y >> 1, z >> 1), cidx(x, y, z));
+  };
+  for (int64_t o = 0; o < H.n; ++o) {
+    // which of the 27 octs around o exist at this level (outside an outflow
+    // face counts as existing); bit (dx+1) + 3 (dy+1) + 9 (dz+1)
+    uint32_t have = 0;
+    bool known = false;
+    auto neighbour_octs = [&]() {
+      if (known) return;
+      known = true;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            // a representative cell of the neighbouring oct
+            int64_t qx = 2 * int64_t(H.ox[o]) + 2 * dx, qy = 2 * int64_t(H.oy[o]) + 2 * dy,
+                    qz = 2 * int64_t(H.oz[o]) + 2 * dz;
+            bool ex;
+            if (g.outside_outflow(l, qx, qy, qz)) {
+              ex = true;
+            } else {
+              g.apply(l, qx, qy, qz);
+              ex = H.index.find(qx >> 1, qy >> 1, qz >> 1) >= 0;
+            }
+            if (ex) have |= 1u << ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+          }
+    };
+    for (int c = 0; c < 8; ++c) {
+      const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+      const int64_t x = 2 * int64_t(H.ox[o]) + bx, y = 2 * int64_t(H.oy[o]) + by, z = 2 * int64_t(H.oz[o]) + bz;
+      const double rc = rho(o, c);
+      // the mass criterion needs nothing else: test it before the rule
+      if (d.refine == RY_REFINE_MASS && !(rc > mass_thr)) continue;
+      if (d.refine != RY_REFINE_MASS && d.refine != RY_REFINE_GRAD) continue;
+      // neighbour rule: the 26 neighbour cells lie in the 7 octs of the
+      // cell's corner of the 3x3x3 oct block (and in o itself)
+      neighbour_octs();
+      const int sx = bx ? 1 : -1, sy = by ? 1 : -1, sz = bz ? 1 : -1;
+      bool ok = true;
+      for (int k = 1; k < 8 && ok; ++k) {
+        const int dx = (k & 1) ? sx : 0, dy = (k & 2) ? sy : 0, dz = (k & 4) ? sz : 0;
+        if (!((have >> ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1))) & 1u)) ok = false;
+      }
+      if (!ok) continue;
+      bool want = true;
+      if (d.refine == RY_REFINE_GRAD) {
+        const double gx = 0.5 * (rho_at(x + 1, y, z) - rho_at(x - 1, y, z));
+        const double gy = 0.5 * (rho_at(x, y + 1, z) - rho_at(x, y - 1, z));
+        const double gz = 0.5 * (rho_at(x, y, z + 1) - rho_at(x, y, z - 1));
+        const double th = d.refine_param;
+        want = gx * gx + gy * gy + gz * gz > (th * rc) * (th * rc);
+      }
+      if (want) {
+        flag[o] |= uint8_t(1u << c);
+        ++nnew;
+      }
+    }
+  }
+  return nnew;
 }
 
 std::string build_mesh(const DomainSpec& d, const double* U_base, ry_fill_fn fill, void* user,
@@ -198,7 +272,7 @@ std::string build_mesh(const DomainSpec& d, const double* U_base, ry_fill_fn fil
       for (int c = 0; c < 8; ++c) {
         const int64_t x = 2 * int64_t(H.ox[o]) + (c & 1), y = 2 * int64_t(H.oy[o]) + ((c >> 1) & 1),
                       z = 2 * int64_t(H.oz[o]) + ((c >> 2) & 1);
-        for (int v = 0; v < NVAR; ++v)
+        for (int v = 0; v < d.nv; ++v)
           H.U[size_t(v) * 8 * H.n + 8 * o + c] = U_base[size_t(v) * ncell + x + cx * (y + cy * z)];
       }
   }
@@ -206,51 +280,8 @@ std::string build_mesh(const DomainSpec& d, const double* U_base, ry_fill_fn fil
   for (int l = d.lmin; l < d.lmax; ++l) {
     HostLevel& H = L[l - d.lmin];
     if (H.n == 0 || d.refine == RY_REFINE_NONE) break;
-    std::vector<uint8_t> flag(H.n, 0);
-    int64_t nnew = 0;
-    const double mass_thr = d.refine_param * std::ldexp(1.0, 3 * (l - d.lmin));
-    for (int64_t o = 0; o < H.n; ++o) {
-      for (int c = 0; c < 8; ++c) {
-        const int64_t x = 2 * int64_t(H.ox[o]) + (c & 1), y = 2 * int64_t(H.oy[o]) + ((c >> 1) & 1),
-                      z = 2 * int64_t(H.oz[o]) + ((c >> 2) & 1);
-        const double rc = H.U[8 * o + c];
-        bool want = false;
-        if (d.refine == RY_REFINE_GRAD) {
-          double gr[3];
-          const int64_t pos[3] = {x, y, z};
-          for (int a = 0; a < 3; ++a) {
-            int64_t lo[3] = {pos[0], pos[1], pos[2]}, hi[3] = {pos[0], pos[1], pos[2]};
-            lo[a] -= 1;
-            hi[a] += 1;
-            CellRef rl = covering(d, L, l, lo[0], lo[1], lo[2]);
-            CellRef rh = covering(d, L, l, hi[0], hi[1], hi[2]);
-            const double rho_lo = L[rl.level - d.lmin].U[rl.cell];
-            const double rho_hi = L[rh.level - d.lmin].U[rh.cell];
-            gr[a] = 0.5 * (rho_hi - rho_lo);
-          }
-          const double th = d.refine_param;
-          want = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] > (th * rc) * (th * rc);
-        } else if (d.refine == RY_REFINE_MASS) {
-          want = rc > mass_thr;
-        }
-        if (!want) continue;
-        // neighbour rule: all 26 neighbours exist at this level
-        bool ok = true;
-        for (int dz = -1; dz <= 1 && ok; ++dz)
-          for (int dy = -1; dy <= 1 && ok; ++dy)
-            for (int dx = -1; dx <= 1 && ok; ++dx) {
-              if (!dx && !dy && !dz) continue;
-              int64_t qx = x + dx, qy = y + dy, qz = z + dz;
-              if (g.outside_outflow(l, qx, qy, qz)) continue;
-              g.apply(l, qx, qy, qz);
-              if (H.index.find(qx >> 1, qy >> 1, qz >> 1) < 0) ok = false;
-            }
-        if (ok) {
-          flag[o] |= uint8_t(1u << c);
-          ++nnew;
-        }
-      }
-    }
+    std::vector<uint8_t> flag;
+    const int64_t nnew = flag_level(d, H, l, [&](int64_t o, int c) { return H.U[8 * o + c]; }, flag);
     if (nnew == 0) break;
     HostLevel& F = L[l + 1 - d.lmin];
     F.n = nnew;
@@ -275,7 +306,56 @@ std::string build_mesh(const DomainSpec& d, const double* U_base, ry_fill_fn fil
     fill(user, l + 1, F.n * 8, ijk.data(), F.U.data());
   }
   for (int l = d.lmax - 1; l >= d.lmin; --l)
-    if (L[l + 1 - d.lmin].n > 0) restrict_into(L[l + 1 - d.lmin], L[l - d.lmin]);
+    if (L[l + 1 - d.lmin].n > 0) restrict_into(L[l + 1 - d.lmin], L[l - d.lmin], d.nv);
+  return "";
+}
+
+// ---------------------------------------------------------------------------
+// One level of a regrid between coarse steps.
+// ---------------------------------------------------------------------------
+std::string regrid_level(const DomainSpec& d, int l, HostLevel& C, const std::vector<double>& rho,
+                         const HostLevel& F_old, HostLevel& F_new, std::vector<int32_t>& src_old,
+                         std::vector<int32_t>& src7, int64_t& created, int64_t& destroyed) {
+  if (int64_t(rho.size()) < 8 * C.n) return "regrid: density array too short";
+  std::vector<uint8_t> flag;
+  const int64_t nnew = (C.n == 0 || d.refine == RY_REFINE_NONE)
+                           ? (flag.assign(C.n, 0), 0)
+                           : flag_level(d, C, l, [&](int64_t o, int c) { return rho[8 * o + c]; }, flag);
+  C.refined = flag;
+  F_new = HostLevel();
+  F_new.n = nnew;
+  for (int64_t o = 0; o < C.n; ++o)
+    for (int c = 0; c < 8; ++c)
+      if (flag[o] & (1u << c)) {
+        F_new.ox.push_back(2 * C.ox[o] + (c & 1));
+        F_new.oy.push_back(2 * C.oy[o] + ((c >> 1) & 1));
+        F_new.oz.push_back(2 * C.oz[o] + ((c >> 2) & 1));
+      }
+  sort_level(d, l + 1, F_new, false);
+  src_old.assign(F_new.n, -1);
+  src7.assign(size_t(F_new.n) * 7, -1);
+  Geo g(d);
+  for (int64_t k = 0; k < F_new.n; ++k) {
+    const int32_t o = F_old.index.find(F_new.ox[k], F_new.oy[k], F_new.oz[k]);
+    if (o >= 0) {
+      src_old[k] = o;
+      continue;
+    }
+    ++created;
+    // the parent cell Q (level l) and its six face neighbours, which exist
+    // at level l by the neighbour rule (or are clamped to Q at an outflow face)
+    const int64_t q[3] = {F_new.ox[k], F_new.oy[k], F_new.oz[k]};
+    for (int j = 0; j < 7; ++j) {
+      int64_t p[3] = {q[0], q[1], q[2]};
+      if (j > 0) p[(j - 1) >> 1] += ((j - 1) & 1) ? 1 : -1;
+      g.apply(l, p[0], p[1], p[2]);
+      const int32_t po = C.index.find(p[0] >> 1, p[1] >> 1, p[2] >> 1);
+      if (po < 0) return "regrid: interpolation source missing";
+      src7[7 * k + j] = po * 8 + cidx(p[0], p[1], p[2]);
+    }
+  }
+  for (int64_t o = 0; o < F_old.n; ++o)
+    if (F_new.index.find(F_old.ox[o], F_old.oy[o], F_old.oz[o]) < 0) ++destroyed;
   return "";
 }
 

@@ -10,9 +10,11 @@
 
 namespace ry {
 
-constexpr int NVAR = 5;
+constexpr int NVAR = 5;            // hydro variables; passive scalars follow them
+constexpr int NVMAX = NVAR + RY_MAX_SCALARS;
 constexpr int TILE_TAB = 64;       // 4x4x4 oct positions around a 2x2x2-oct tile
-constexpr int REG_PER_OCT = 6 * NVAR * 2;
+// flux registers per oct: [face 6][variable nv][substep 2]
+constexpr int reg_per_oct(int nv) { return 6 * nv * 2; }
 
 // Tile flag bits: outflow clamping at the domain faces touched by the tile.
 enum : uint32_t { CL_LOX = 1, CL_HIX = 2, CL_LOY = 4, CL_HIY = 8, CL_LOZ = 16, CL_HIZ = 32 };
@@ -32,7 +34,7 @@ struct HostLevel {
   std::vector<uint64_t> key;         // Hilbert keys, ascending
   std::vector<int32_t> ox, oy, oz;   // oct coordinates
   std::vector<uint8_t> refined;      // bit c: cell c refined
-  std::vector<double> U;             // 5 planes of 8n
+  std::vector<double> U;             // nv planes of 8n
   OctIndex index;
 };
 
@@ -42,6 +44,7 @@ struct DomainSpec {
   int32_t bc[6] = {0, 0, 0, 0, 0, 0};
   int32_t refine = 0;
   double refine_param = 0.0;
+  int nv = NVAR;                     // 5 + passive scalars
   int hbits0 = 0;                    // Hilbert bits per axis at lmin
   int64_t ncell(int l, int a) const { return (int64_t)nbase[a] << (l - lmin); }
   int64_t noct(int l, int a) const { return ncell(l, a) / 2; }
@@ -67,13 +70,21 @@ struct LevelTables {
 // fill, restriction). Returns an error string or empty.
 std::string build_mesh(const DomainSpec& dom, const double* U_base, ry_fill_fn fill, void* user,
                        std::vector<HostLevel>& levels);
+// One level of a regrid: flags of level l (densities rho, 8 per oct) by the
+// build's criterion and neighbour rule replace C.refined; F_new gets the
+// children of the refined cells in Hilbert order; per F_new oct, src_old is
+// its index in F_old (kept) or -1 (new), and for new octs src7 holds the 7
+// level-l cells (Q, -x, +x, -y, +y, -z, +z) its values are interpolated from.
+std::string regrid_level(const DomainSpec& d, int l, HostLevel& C, const std::vector<double>& rho,
+                         const HostLevel& F_old, HostLevel& F_new, std::vector<int32_t>& src_old,
+                         std::vector<int32_t>& src7, int64_t& created, int64_t& destroyed);
 // Builds tile tables, ghost lists, child/parent maps for every level.
 std::string build_tables(const DomainSpec& dom, const std::vector<HostLevel>& levels,
                          std::vector<LevelTables>& out);
 
 // ------------------------------------------------------------- kernels
 struct HydroArgs {
-  const double* U;            // current state (ext octs), 5 planes of 8*n_ext
+  const double* U;            // current state (ext octs), nv planes of 8*n_ext
   double* Un;                 // next state
   int64_t plane;              // 8 * n_ext
   int32_t n_oct;              // real octs: ext index < n_oct
@@ -106,14 +117,17 @@ struct GhostArgs {
   double* dst0;
   double* dst1;
   int64_t plane;
+  int32_t nv;
   const int32_t* skip;
 };
 
 // launchers (kernels.hip)
-int launch_hydro(const HydroArgs& a, int precision, const ry_tuning& t, int num_cu, void* stream);
+int launch_hydro(const HydroArgs& a, int precision, int nscalar, const ry_tuning& t, int num_cu, void* stream);
+// whether a hydro kernel exists for this precision / scalar count / tuning
+bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t);
 int launch_ghost(const GhostArgs& a, void* stream);
 int launch_restrict(const double* Uf, int64_t plane_f, int64_t n_fine, const int32_t* parent_cell,
-                    double* Uc, int64_t plane_c, const int32_t* skip, void* stream);
+                    double* Uc, int64_t plane_c, int nv, const int32_t* skip, void* stream);
 // per-block maxima of the signal speed over leaf cells -> part[0 .. ceil(8 n_oct / 256))
 int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double gamma,
                double rho_floor, double p_floor, double* part, int32_t* err, void* stream);
@@ -136,10 +150,15 @@ struct FinalizeArgs {
 int launch_finalize(const FinalizeArgs& a, void* stream);
 int launch_zero_u32(unsigned int* p, int64_t n, void* stream);
 int launch_zero_u64(unsigned long long* p, int64_t n, void* stream);
-int launch_totals(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double vol,
+int launch_totals(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double vol, int nv,
                   double* partial, int nblocks, void* stream);
-int launch_totals_final(const double* partial, int nparts, double* out, void* stream);
+int launch_totals_final(const double* partial, int nparts, int nv, double* out, void* stream);
 int launch_copy(const double* src, double* dst, int64_t n, void* stream);
+// Regrid state remap of one level: for new oct k, cell c, variable v: a kept
+// oct copies Uold[v*pold + 8*src_old[k] + c]; a new one takes the MinMod-
+// linear interpolation of the level-l cells src7[7k..7k+6] of Uc (plane pc).
+int launch_regrid_remap(const int32_t* src_old, const int32_t* src7, int64_t n_new, const double* Uold, int64_t pold,
+                        const double* Uc, int64_t pc, double* Unew, int64_t pnew, int nv, void* stream);
 int totals_blocks();
 int hydro_max_tiles_per_wg();
 

@@ -28,7 +28,7 @@ EXPORTS = [
     "ry_batch_create", "ry_batch_run", "ry_batch_box_info", "ry_batch_download",
     "ry_set_tuning", "ry_get_tuning", "ry_autotune", "ry_floor_count", "ry_set_timing",
     "ry_kernel_time", "ry_copy_probe", "ry_last_error", "ry_mesh_build", "ry_mesh_level",
-    "ry_mesh_free", "ry_hilbert_key",
+    "ry_mesh_free", "ry_hilbert_key", "ry_regrid", "ry_set_refine_param",
 ]
 # Every function declared in include/ry_poisson.h.
 POISSON_EXPORTS = [
@@ -51,7 +51,7 @@ class RyConfig(C.Structure):
                 ("bc", C.c_int32 * 6), ("precision", C.c_int32), ("refine", C.c_int32),
                 ("refine_param", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_user", C.c_void_p)]
+                ("alloc_user", C.c_void_p), ("nscalar", C.c_int32)]
 
 
 class RyPoissonConfig(C.Structure):
@@ -114,6 +114,8 @@ def lib():
         "ry_mesh_level": ([P, I32, C.POINTER(I64), P, P, C.POINTER(I64)], I32),
         "ry_mesh_free": ([P], None),
         "ry_hilbert_key": ([I32, C.c_uint32, C.c_uint32, C.c_uint32], C.c_uint64),
+        "ry_regrid": ([P, C.POINTER(I64), C.POINTER(I64)], I32),
+        "ry_set_refine_param": ([P, D], I32),
         "ry_poisson_create": ([C.POINTER(RyPoissonConfig), C.POINTER(P)], I32),
         "ry_poisson_destroy": ([P], None),
         "ry_poisson_set_rhs": ([P, P, P], I32),
@@ -161,10 +163,10 @@ class _TorchMemory:
         return sum(t.numel() for t in self.live.values())
 
 
-def _make_fill(fill):
+def _make_fill(fill, nv=5):
     def cb(user, level, ncell, ijk, U):
         a = np.ctypeslib.as_array(ijk, shape=(ncell, 3)).copy()
-        out = np.ctypeslib.as_array(U, shape=(5, ncell))
+        out = np.ctypeslib.as_array(U, shape=(nv, ncell))
         out[...] = fill(int(level), a)
     return FILL_FN(cb)
 
@@ -180,6 +182,7 @@ def _config(prob, precision, stream_handle, mem):
     cfg.precision = PRECISION[precision]
     cfg.refine, cfg.refine_param = prob.refine, prob.refine_param
     cfg.rho_floor, cfg.p_floor = prob.rho_floor, prob.p_floor
+    cfg.nscalar = getattr(prob, "nscalar", 0)
     cfg.stream = stream_handle
     if mem is not None:
         cfg.dev_alloc = mem.alloc_cb
@@ -205,7 +208,7 @@ class _Base:
             pass
 
     # tuning / timing / diagnostics
-    def set_tuning(self, tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=4):
+    def set_tuning(self, tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=1):
         t = RyTuning(tiles_per_wg, persistent, waves_per_cu, batch, waves_per_tile)
         self._check(lib().ry_set_tuning(self.ctx, C.byref(t)), "ry_set_tuning")
 
@@ -255,7 +258,8 @@ class Hydro(_Base):
         self._cfg = cfg
         self._check(lib().ry_create(C.byref(cfg), C.byref(self.ctx)), "ry_create")
         base = prob.base_flat()
-        self._fill = _make_fill(prob.fill if prob.fill else (lambda l, ijk: np.zeros((5, len(ijk)))))
+        nv = self.nv = 5 + prob.nscalar
+        self._fill = _make_fill(prob.fill if prob.fill else (lambda l, ijk: np.zeros((nv, len(ijk)))), nv)
         self._check(lib().ry_amr_build(self.ctx, base.ctypes.data_as(C.POINTER(C.c_double)), self._fill, None),
                     "ry_amr_build")
         self.t = 0.0
@@ -278,7 +282,7 @@ class Hydro(_Base):
 
     def download(self, level):
         n, _ = self.level_info(level)
-        U = np.zeros((5, 8 * n), np.float64)
+        U = np.zeros((self.nv, 8 * n), np.float64)
         self._check(lib().ry_download(self.ctx, level, U.ctypes.data), "ry_download")
         return U
 
@@ -308,8 +312,17 @@ class Hydro(_Base):
         self._check(lib().ry_advance(self.ctx, n_coarse, t_end, C.byref(t)), "ry_advance")
         self.t = t.value
 
+    def regrid(self):
+        """Dynamic refinement between coarse steps: (octs created, destroyed)."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().ry_regrid(self.ctx, C.byref(a), C.byref(b)), "ry_regrid")
+        return a.value, b.value
+
+    def set_refine_param(self, value):
+        self._check(lib().ry_set_refine_param(self.ctx, value), "ry_set_refine_param")
+
     def totals(self):
-        tot = (C.c_double * 5)()
+        tot = (C.c_double * self.nv)()
         self._check(lib().ry_conserved_totals(self.ctx, tot), "ry_conserved_totals")
         return np.array(tot[:])
 
@@ -354,7 +367,8 @@ class HostMesh:
         self.m = C.c_void_p()
         cfg = _config(prob, "fp64", None, None)
         base = prob.base_flat()
-        self._fill = _make_fill(prob.fill if prob.fill else (lambda l, ijk: np.zeros((5, len(ijk)))))
+        nv = 5 + prob.nscalar
+        self._fill = _make_fill(prob.fill if prob.fill else (lambda l, ijk: np.zeros((nv, len(ijk)))), nv)
         rc = lib().ry_mesh_build(C.byref(cfg), base.ctypes.data_as(C.POINTER(C.c_double)), self._fill, None,
                                  C.byref(self.m))
         if rc != RY_OK:

@@ -80,12 +80,13 @@ def rel_err(a, b, floor_frac=1e-3):
 
 
 def scalar_profiles(pos):
-    """Three passive-scalar profiles: smooth, a step (exercises the limiter)
-    and a constant."""
+    """Four passive-scalar profiles: smooth, a step (exercises the limiter),
+    a constant and a smooth one varying along z."""
     tp = 2 * math.pi
     return [0.5 + 0.4 * np.sin(tp * pos[:, 0]) * np.cos(tp * pos[:, 1]),
             np.where(pos[:, 0] + 0.3 * pos[:, 2] > 0.55, 0.9, 0.1),
-            np.full(len(pos), 0.3)]
+            np.full(len(pos), 0.3),
+            0.2 + 0.1 * np.cos(tp * pos[:, 2] + 0.4)]
 
 
 def with_scalars(prob, nscalar, profiles=scalar_profiles):

@@ -57,6 +57,8 @@ def test_poisson_create_rejects_invalid_config(shape, bc, pc):
     (dict(cfl=0.0), ry.RY_EINVAL),
     (dict(bc=(0, 1, 0, 0, 0, 0)), ry.RY_EINVAL),       # half-periodic pair
     (dict(rho_floor=0.0), ry.RY_EINVAL),
+    (dict(nscalar=5), ry.RY_EINVAL),                    # more passive scalars than supported
+    (dict(nscalar=-1), ry.RY_EINVAL),
 ])
 def test_create_rejects_invalid_config(mutate, expect):
     prob = W.uniform_state(8)

@@ -27,6 +27,9 @@ v_z; box b of the batched workload uses 5000 + 10 b + field):
 * batch    -- 512 periodic boxes with sides in {16,24,32,40,48}, per box
               sigma ~ U(0.5, 1.5), rms Mach ~ U(0.5, 3), gamma 5/3, uniform
               temperature p = rho.
+* uniform with scalars -- the uniform box plus passive scalars s_k =
+              0.5 (1 + tanh g_k), g_k smoothed like ln rho (seed 1000 *
+              config + 4 + k), stored as rho s_k.
 * poisson  -- source of the cell-level Poisson equation on one uniform
               periodic level: the uniform generator's lognormal density
               (sigma_ln 1, smoothing 4 cells per 128 cells of box, seed
@@ -124,11 +127,20 @@ def sod(n: int = 32, gamma: float = 1.4, t_end: float = 0.1) -> Problem:
 # config 2: uniform periodic lognormal box
 # ---------------------------------------------------------------------------
 def uniform(n: int = 128, seed_cfg: int = 2, sigma_ln: float = 1.0, mach_rms: float = 1.0,
-            gamma: float = 5.0 / 3.0, n_steps: int = 10) -> Problem:
+            gamma: float = 5.0 / 3.0, n_steps: int = 10, nscalar: int = 0) -> Problem:
     rho, vx, vy, vz, p = lognormal_fields(n, 1000 * seed_cfg, sigma_ln, mach_rms, gamma)
     U = conserved(rho, vx, vy, vz, p, gamma)
+    if nscalar:
+        U = np.concatenate([U, rho[None] * scalar_fields(n, 1000 * seed_cfg, nscalar)], axis=0)
     lvl = int(round(math.log2(n)))
-    return Problem(f"uniform{n}", lvl, lvl, (n, n, n), gamma, U, n_steps=n_steps)
+    return Problem(f"uniform{n}" + (f"_s{nscalar}" if nscalar else ""), lvl, lvl, (n, n, n), gamma, U,
+                   n_steps=n_steps, nscalar=nscalar)
+
+
+def scalar_fields(n: int, seed0: int, nscalar: int) -> np.ndarray:
+    """Passive scalars s_k in (0, 1): smoothed Gaussian fields (seeds seed0 +
+    4 + k, sigma 4 cells) through 0.5 (1 + tanh); metallicity-like tracers."""
+    return np.array([0.5 * (1.0 + np.tanh(smooth_gaussian_field(n, seed0 + 4 + k, 4.0))) for k in range(nscalar)])
 
 
 # ---------------------------------------------------------------------------
