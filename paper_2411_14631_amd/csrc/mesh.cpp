@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 
 #include "ry_internal.h"
@@ -362,17 +363,15 @@ std::string regrid_level(const DomainSpec& d, int l, HostLevel& C, const std::ve
 // ---------------------------------------------------------------------------
 // Device tables.
 // ---------------------------------------------------------------------------
-std::string build_tables(const DomainSpec& d, const std::vector<HostLevel>& L,
-                         std::vector<LevelTables>& out) {
+// Tables of level k (reads the host levels only; levels are independent).
+static std::string build_level_tables(const DomainSpec& d, const std::vector<HostLevel>& L, int k,
+                                      LevelTables& T) {
   const int nl = int(L.size());
-  out.assign(nl, LevelTables());
-  Geo g(d);
-  for (int k = 0; k < nl; ++k) {
+  {
     const int l = d.lmin + k;
     const HostLevel& H = L[k];
-    LevelTables& T = out[k];
     T.n_oct = H.n;
-    if (H.n == 0) continue;
+    if (H.n == 0) return "";
     for (int64_t o = 0; o < H.n; ++o) T.n_leaf += 8 - __builtin_popcount(H.refined[o]);
     // tiles: groups of octs sharing key >> 3 (an aligned 2x2x2 block of octs)
     std::vector<int64_t> tile_start;
@@ -486,7 +485,20 @@ std::string build_tables(const DomainSpec& d, const std::vector<HostLevel>& L,
       }
     }
   }
-  (void)g;
+  return "";
+}
+
+std::string build_tables(const DomainSpec& d, const std::vector<HostLevel>& L,
+                         std::vector<LevelTables>& out) {
+  const int nl = int(L.size());
+  out.assign(nl, LevelTables());
+  std::vector<std::string> err(nl);
+  std::vector<std::thread> pool;
+  for (int k = 0; k < nl; ++k)
+    pool.emplace_back([&, k]() { err[k] = build_level_tables(d, L, k, out[k]); });
+  for (auto& t : pool) t.join();
+  for (auto& e : err)
+    if (!e.empty()) return e;
   return "";
 }
 
