@@ -355,18 +355,22 @@ def main():
             handles[prec] = z
         zoom["mixed_vs_fp64_after_10_coarse_steps"] = compare_forms(
             handles["fp64"]["h"], handles["mixed"]["h"], handles["fp64"]["e0"], handles["mixed"]["e0"])
-        # one regrid of the evolved FP64 mesh, then one coarse step on it
-        h = handles["fp64"]["h"]
-        before = sum(h.level_info(lv)[0] for lv in h.levels)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        created, destroyed = h.regrid()
-        rg = time.perf_counter() - t0
-        after = sum(h.level_info(lv)[0] for lv in h.levels)
-        h.advance(1)
-        zoom["regrid_fp64"] = {"ms": round(1e3 * rg, 1), "octs_before": before, "octs_after": after,
-                               "created": created, "destroyed": destroyed,
-                               "note": "flags on the host from downloaded densities, state remap on the device"}
+        # one regrid of each evolved mesh (FP64: all on the device; mixed: the
+        # host-flag path, for comparison), then one coarse step on it
+        for prec, on_device in (("fp64", True), ("mixed", False)):
+            h = handles[prec]["h"]
+            h.set_regrid_device(on_device)
+            before = sum(h.level_info(lv)[0] for lv in h.levels)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            created, destroyed = h.regrid()
+            rg = time.perf_counter() - t0
+            after = sum(h.level_info(lv)[0] for lv in h.levels)
+            h.advance(1)
+            zoom[f"regrid_{prec}"] = {
+                "ms": round(1e3 * rg, 2), "octs_before": before, "octs_after": after, "created": created,
+                "destroyed": destroyed,
+                "path": "device" if on_device else "host flags and tables, device state remap"}
         del handles, z, h
         torch.cuda.empty_cache()
 

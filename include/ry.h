@@ -88,7 +88,8 @@ void ry_destroy(ry_ctx* ctx);
 ry_status ry_amr_build(ry_ctx* ctx, const double* U_base, ry_fill_fn fill, void* user);
 
 ry_status ry_level_info(const ry_ctx* ctx, int32_t level, int64_t* n_oct, int64_t* n_leaf_cells);
-/* Hilbert keys (n_oct) and refined-cell masks (n_oct bytes, bit c = cell c). */
+/* Hilbert keys (n_oct) and refined-cell masks (n_oct bytes, bit c = cell c)
+ * copied from the device (syncs; RY_EHIP on a copy failure). */
 ry_status ry_get_mesh(const ry_ctx* ctx, int32_t level, uint64_t* keys, uint8_t* refined);
 
 /* dt of the next coarse step: min over levels of 2^(l-level_min) * cfl *
@@ -115,11 +116,17 @@ ry_status ry_advance(ry_ctx* ctx, int32_t n_coarse, double t_end, double* t_io);
  * interpolation of their parent cell and its six face neighbours (the
  * coarse-fine ghost formula), octs whose parent is no longer refined
  * disappear with their descendants.  Then refined cells are restricted
- * bottom-up.  The flags are evaluated on the host from each level's
- * densities (8 B per cell crosses PCIe), the state is remapped on the
- * device, the tables are rebuilt.  RY_ESTATE inside a coarse step.  Counts
- * of created / destroyed octs (either may be NULL).  Syncs. */
+ * bottom-up.  By default every step runs on the device (flags, child
+ * levels, state remap, tile tables, ghost octs); only counts cross PCIe.
+ * RY_ESTATE inside a coarse step; RY_EINVAL (mesh unchanged) if a source
+ * the neighbour rule guarantees is missing.  Counts of created / destroyed
+ * octs (either may be NULL).  Syncs. */
 ry_status ry_regrid(ry_ctx* ctx, int64_t* n_created, int64_t* n_destroyed);
+/* on = 0: later regrids evaluate flags and build tables on the host from
+ * the densities (8 B per cell crosses PCIe) and keep only the state remap on
+ * the device; on != 0 (the default): all on the device.  Both give the same
+ * mesh and state bit for bit. */
+ry_status ry_set_regrid_device(ry_ctx* ctx, int32_t on);
 /* Change the refinement parameter (theta or rho_thr) used by later regrids. */
 ry_status ry_set_refine_param(ry_ctx* ctx, double value);
 

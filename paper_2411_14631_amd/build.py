@@ -11,7 +11,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libry.so")
-SOURCES = ["mesh.cpp", "api.cpp", "kernels.hip", "poisson.hip"]
+SOURCES = ["mesh.cpp", "api.cpp", "kernels.hip", "poisson.hip", "regrid.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -32,8 +32,8 @@ struct DevLevel {
   int32_t* parent_cell = nullptr;
   int32_t* tile_box = nullptr;
   int32_t* oct_box = nullptr;
-  std::vector<uint64_t> keys;
-  std::vector<uint8_t> refined_host;
+  uint64_t* dkey = nullptr;          // sorted Hilbert keys (device regrid lookups)
+  int32_t* doc = nullptr;            // oct coordinates, x y z interleaved
   int64_t plane() const { return 8 * n_ext; }
 };
 
@@ -52,6 +52,8 @@ struct ry_ctx {
   bool batch = false;
   std::vector<DevLevel> lev;
   std::vector<HostLevel> host;            // topology of the current mesh (no state)
+  bool host_valid = true;                 // false after a device-side regrid
+  bool regrid_device = true;              // build regrid flags / tables on the device
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int num_cu = 256;
@@ -449,6 +451,18 @@ void upload_level_tables(ry_ctx* c, DevLevel& D, const LevelTables& t, int k, bo
   D.reg = (k > 0) ? upload_vec(c, zeros, ok) : nullptr;
 }
 
+// Sorted keys and interleaved oct coordinates of one level (device copies).
+void upload_level_topology(ry_ctx* c, DevLevel& D, const HostLevel& H, bool& ok) {
+  std::vector<int32_t> oc(size_t(3 * H.n));
+  for (int64_t o = 0; o < H.n; ++o) {
+    oc[3 * o] = H.ox[o];
+    oc[3 * o + 1] = H.oy[o];
+    oc[3 * o + 2] = H.oz[o];
+  }
+  D.dkey = upload_vec(c, H.key, ok);
+  D.doc = upload_vec(c, oc, ok);
+}
+
 ry_status upload_level_state(ry_ctx* c, DevLevel& D, const double* U_host) {
   for (int b = 0; b < 2; ++b)
     for (int v = 0; v < c->dom.nv; ++v)
@@ -522,8 +536,6 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
     D.n_ext = t.n_oct + t.n_ghost;
     D.n_leaf = t.n_leaf;
     D.n_tile = t.n_tile;
-    D.keys = H[k].key;
-    D.refined_host = H[k].refined;
     if (D.n_oct == 0) continue;
     for (int b = 0; b < 2; ++b) {
       D.U[b] = static_cast<double*>(dalloc(c, sizeof(double) * c->dom.nv * 8 * D.n_ext));
@@ -532,6 +544,7 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
     if (!ok) break;
     if (upload_level_state(c, D, H[k].U.data())) return c->err.empty() ? RY_EHIP : RY_EHIP;
     upload_level_tables(c, D, t, k, ok);
+    upload_level_topology(c, D, H[k], ok);
   }
   if (!ok) {
     free_all(c);
@@ -549,6 +562,7 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (auto& h : H) std::vector<double>().swap(h.U);
   c->host = std::move(H);
+  c->host_valid = true;
   c->built = true;
   return RY_OK;
 }
@@ -560,12 +574,47 @@ ry_status ry_set_refine_param(ry_ctx* c, double value) {
   return RY_OK;
 }
 
-ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
-  if (!c || c->batch) return RY_EINVAL;
-  if (!c->built) return fail(c, RY_ESTATE, "not built");
-  for (int k = 0; k < c->nlev; ++k)
-    if (c->count[k]) return fail(c, RY_ESTATE, "regrid inside a coarse step");
-  ry_status s = sync_and_check(c);
+}  // extern "C"
+
+namespace {
+
+// Host copy of the mesh topology from the device mirrors (after a device
+// regrid the host copy is stale).
+ry_status refresh_host_topology(ry_ctx* c) {
+  if (c->host_valid) return RY_OK;
+  c->host.assign(c->nlev, HostLevel());
+  for (int k = 0; k < c->nlev; ++k) {
+    DevLevel& D = c->lev[k];
+    HostLevel& H = c->host[k];
+    H.n = D.n_oct;
+    H.key.resize(H.n);
+    H.refined.resize(H.n);
+    std::vector<int32_t> oc(size_t(3 * H.n));
+    if (H.n) {
+      HIPCHK(c, hipMemcpy(H.key.data(), D.dkey, sizeof(uint64_t) * H.n, hipMemcpyDeviceToHost));
+      HIPCHK(c, hipMemcpy(H.refined.data(), D.refined, H.n, hipMemcpyDeviceToHost));
+      HIPCHK(c, hipMemcpy(oc.data(), D.doc, sizeof(int32_t) * oc.size(), hipMemcpyDeviceToHost));
+    }
+    H.ox.resize(H.n);
+    H.oy.resize(H.n);
+    H.oz.resize(H.n);
+    for (int64_t o = 0; o < H.n; ++o) {
+      H.ox[o] = oc[3 * o];
+      H.oy[o] = oc[3 * o + 1];
+      H.oz[o] = oc[3 * o + 2];
+    }
+    H.index.build(H.ox, H.oy, H.oz);
+  }
+  c->host_valid = true;
+  return RY_OK;
+}
+
+ry_status finish_regrid(ry_ctx* c);
+
+// Regrid with flags and tables built on the host (the state stays on the
+// device).
+ry_status regrid_host(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
+  ry_status s = refresh_host_topology(c);
   if (s) return s;
   const int nl = c->nlev, nv = c->dom.nv;
   std::vector<HostLevel>& H = c->host;
@@ -612,8 +661,10 @@ ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
   for (int k = 0; k < nl; ++k) {
     DevLevel& D = c->lev[k];
     for (void* p : {(void*)D.tab, (void*)D.tflag, (void*)D.refined, (void*)D.child, (void*)D.parent_cell,
-                    (void*)D.gsrc, (void*)D.reg})
+                    (void*)D.gsrc, (void*)D.reg, (void*)D.dkey, (void*)D.doc})
       dfree(c, p);
+    D.dkey = nullptr;
+    D.doc = nullptr;
     if (k > 0) {
       dfree(c, D.U[0]);
       dfree(c, D.U[1]);
@@ -636,8 +687,6 @@ ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     D.n_ext = t.n_oct + t.n_ghost;
     D.n_leaf = t.n_leaf;
     D.n_tile = t.n_tile;
-    D.keys = H[k].key;
-    D.refined_host = H[k].refined;
     if (D.n_oct == 0) continue;
     if (k > 0) {
       D.cur = 0;
@@ -651,17 +700,33 @@ ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
                                  hipMemcpyDeviceToDevice, c->stream));
     }
     upload_level_tables(c, D, t, k, ok);
+    upload_level_topology(c, D, H[k], ok);
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (double* p : tmp) dfree(c, p);
-  // tile-indexed CFL partials
+  if (!ok) {
+    free_all(c);
+    c->built = false;
+    return fail(c, RY_ENOMEM, "regrid allocation failed; the context must be rebuilt");
+  }
+  if ((s = finish_regrid(c))) return s;
+  if (n_created) *n_created = created;
+  if (n_destroyed) *n_destroyed = destroyed;
+  return RY_OK;
+}
+
+// Common tail of both regrid paths: CFL partial slots for the new tile
+// counts, restriction bottom-up, CFL data; graphs and subcycle counters reset.
+ry_status finish_regrid(ry_ctx* c) {
+  const int nl = c->nlev, nv = c->dom.nv;
+  ry_status s;
   dfree(c, c->d_part);
   dfree(c, c->d_segoff);
   c->seg_off.assign(1, 0);
   for (int k = 0; k < nl; ++k) c->seg_off.push_back(c->seg_off.back() + c->lev[k].n_tile);
   c->d_part = static_cast<double*>(dalloc(c, sizeof(double) * std::max<int64_t>(c->seg_off.back(), 1)));
   c->d_segoff = static_cast<int64_t*>(dalloc(c, sizeof(int64_t) * c->seg_off.size()));
-  if (!ok || !c->d_part || !c->d_segoff) {
+  if (!c->d_part || !c->d_segoff) {
     free_all(c);
     c->built = false;
     return fail(c, RY_ENOMEM, "regrid allocation failed; the context must be rebuilt");
@@ -681,10 +746,299 @@ ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
   std::fill(std::begin(c->count), std::end(c->count), 0);
   c->slots_valid = false;
   if ((s = enqueue_cfl_all(c))) return s;
-  if ((s = sync_and_check(c))) return s;
+  return sync_and_check(c);
+}
+
+// Regrid with the mesh work on the device: per level, refinement flags from
+// the new state, the child level in Hilbert order (kept octs copied, new octs
+// interpolated), then its tiles, 4x4x4 tables, ghost octs and their sources.
+// The host only reads back counts.  Level lmin keeps its octs, state and
+// tile tables.
+ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
+  const int nl = c->nlev, nv = c->dom.nv, lmin = c->cfg.level_min;
+  hipStream_t st = c->stream;
+  RegridDom RD{};
+  for (int i = 0; i < 6; ++i) RD.bc[i] = c->dom.bc[i];
+  RD.lmin = lmin;
+  RD.refine = c->dom.refine;
+  RD.refine_param = c->dom.refine_param;
+
+  struct NewLevel {
+    int64_t n = 0, n_ghost = 0, n_leaf = 0;
+    int32_t n_tile = 0;
+    uint64_t* key = nullptr;
+    int32_t* oc = nullptr;
+    int32_t* parent = nullptr;
+    uint8_t* flag = nullptr;
+    int32_t* child = nullptr;
+    int32_t* tab = nullptr;
+    uint32_t* tflag = nullptr;
+    uint8_t* refined = nullptr;
+    int64_t* gsrc = nullptr;
+    double* reg = nullptr;
+    double* U[2] = {nullptr, nullptr};
+  };
+  std::vector<NewLevel> N(nl);
+  std::vector<void*> fresh, temps;   // new level arrays / scratch of this call
+  bool ok = true;
+  auto A = [&](size_t bytes, bool temp) -> void* {
+    void* p = dalloc(c, bytes);
+    if (!p) ok = false;
+    else (temp ? temps : fresh).push_back(p);
+    return p;
+  };
+  auto release = [&](std::vector<void*>& v) {
+    for (void* p : v) dfree(c, p);
+    v.clear();
+  };
+  // failure before the new mesh is installed: the old mesh stays as it was
+  auto abandon = [&](ry_status s, const char* what) {
+    (void)hipStreamSynchronize(st);
+    release(temps);
+    release(fresh);
+    return fail(c, s, "regrid: %s (mesh unchanged)", what);
+  };
+#define RG_TRY(cond, status, what) \
+  do {                              \
+    if (!(cond)) return abandon(status, what); \
+  } while (0)
+  auto view = [&](int k) {
+    LevelView v{};
+    v.key = N[k].key;
+    v.oc = N[k].oc;
+    v.n = N[k].n;
+    v.bits = c->dom.hbits0 + k;
+    for (int a = 0; a < 3; ++a) v.noct[a] = int32_t(c->dom.noct(lmin + k, a));
+    return v;
+  };
+  auto old_view = [&](int k) {
+    LevelView v{};
+    v.key = c->lev[k].dkey;
+    v.oc = c->lev[k].doc;
+    v.n = c->lev[k].n_oct;
+    v.bits = c->dom.hbits0 + k;
+    for (int a = 0; a < 3; ++a) v.noct[a] = int32_t(c->dom.noct(lmin + k, a));
+    return v;
+  };
+  // exclusive scan of n counts; returns the total (stream synchronised)
+  auto scan_total = [&](const int32_t* in, int32_t* out, int64_t n, int64_t& total) -> bool {
+    const int nt = scan_tmp_ints(n);
+    int32_t* tmp = static_cast<int32_t*>(A(sizeof(int32_t) * nt, true));
+    if (!tmp || launch_scan(in, out, n, tmp, st)) return false;
+    int32_t h = 0;
+    if (hipMemcpyAsync(&h, tmp + nt - 1, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return false;
+    total = h;
+    return true;
+  };
+  int32_t* d_err = static_cast<int32_t*>(A(sizeof(int32_t), true));
+  RG_TRY(ok && hipMemsetAsync(d_err, 0, sizeof(int32_t), st) == hipSuccess, RY_ENOMEM, "allocation failed");
+
+  {  // level lmin keeps its octs and tile tables
+    const DevLevel& D = c->lev[0];
+    N[0].n = D.n_oct;
+    N[0].key = D.dkey;
+    N[0].oc = D.doc;
+    N[0].n_tile = D.n_tile;
+    N[0].tab = D.tab;
+    N[0].tflag = D.tflag;
+    N[0].U[0] = D.U[D.cur];
+  }
+  int64_t created = 0, destroyed = 0;
+  int32_t* src_old = nullptr;   // remap sources of the level built last
+  int32_t* src7 = nullptr;
+  for (int k = 0; k < nl; ++k) {
+    NewLevel& L = N[k];
+    const int l = lmin + k;
+    if (L.n == 0) {
+      if (k + 1 < nl) destroyed += c->lev[k + 1].n_oct;
+      continue;
+    }
+    const LevelView V = view(k);
+    if (k > 0) {
+      // tiles: octs sharing key >> 3
+      int32_t* start = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
+      int32_t* tid = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
+      RG_TRY(ok, RY_ENOMEM, "allocation failed");
+      int64_t nt = 0;
+      RG_TRY(!launch_tile_starts(L.key, L.n, start, st) && scan_total(start, tid, L.n, nt), RY_EHIP,
+             "tile kernels");
+      L.n_tile = int32_t(nt);
+      int32_t* first = static_cast<int32_t*>(A(sizeof(int32_t) * (nt + 1), true));
+      const int64_t nslot = nt * TILE_TAB;
+      L.tab = static_cast<int32_t*>(A(sizeof(int32_t) * nslot, false));
+      L.tflag = static_cast<uint32_t*>(A(sizeof(uint32_t) * nt, false));
+      int32_t* miss = static_cast<int32_t*>(A(sizeof(int32_t) * nslot, true));
+      int32_t* midx = static_cast<int32_t*>(A(sizeof(int32_t) * nslot, true));
+      RG_TRY(ok, RY_ENOMEM, "allocation failed");
+      int64_t nm = 0;
+      RG_TRY(!launch_tile_first(start, tid, L.n, L.n_tile, first, st) &&
+                 !launch_tile_table(V, RD, first, L.n_tile, L.tab, L.tflag, miss, st) &&
+                 scan_total(miss, midx, nslot, nm),
+             RY_EHIP, "tile table kernels");
+      // ghost octs: numbered by first use over (tile, slot)
+      int32_t* gpos = nullptr;
+      if (nm > 0) {
+        uint64_t hsize = 64;
+        while (hsize < 2 * uint64_t(nm)) hsize <<= 1;
+        uint64_t* mpos = static_cast<uint64_t*>(A(sizeof(uint64_t) * nm, true));
+        int32_t* mentry = static_cast<int32_t*>(A(sizeof(int32_t) * nm, true));
+        auto* hkey = static_cast<unsigned long long*>(A(sizeof(unsigned long long) * hsize, true));
+        int32_t* hval = static_cast<int32_t*>(A(sizeof(int32_t) * hsize, true));
+        int32_t* owner = static_cast<int32_t*>(A(sizeof(int32_t) * nm, true));
+        int32_t* gidx = static_cast<int32_t*>(A(sizeof(int32_t) * nm, true));
+        const int ntmp = scan_tmp_ints(nm);
+        int32_t* gtmp = static_cast<int32_t*>(A(sizeof(int32_t) * ntmp, true));
+        gpos = static_cast<int32_t*>(A(sizeof(int32_t) * 3 * nm, true));
+        RG_TRY(ok, RY_ENOMEM, "allocation failed");
+        RG_TRY(!launch_missing_list(V, first, L.n_tile, miss, midx, mpos, mentry, st) &&
+                   !launch_ghost_numbering(mpos, mentry, nm, hkey, hval, hsize, owner, gidx, gtmp, L.n, L.tab, gpos,
+                                           st),
+               RY_EHIP, "ghost numbering kernels");
+        int32_t h = 0;
+        RG_TRY(hipMemcpyAsync(&h, gtmp + ntmp - 1, sizeof h, hipMemcpyDeviceToHost, st) == hipSuccess &&
+                   hipStreamSynchronize(st) == hipSuccess,
+               RY_EHIP, "ghost count");
+        L.n_ghost = h;
+      }
+      if (L.n_ghost > 0) {
+        std::vector<LevelView> cv(k);
+        for (int j = 0; j < k; ++j) cv[j] = view(k - 1 - j);
+        LevelView* d_cv = static_cast<LevelView*>(A(sizeof(LevelView) * k, true));
+        L.gsrc = static_cast<int64_t*>(A(sizeof(int64_t) * 7 * L.n_ghost, false));
+        RG_TRY(ok, RY_ENOMEM, "allocation failed");
+        RG_TRY(hipMemcpyAsync(d_cv, cv.data(), sizeof(LevelView) * k, hipMemcpyHostToDevice, st) == hipSuccess &&
+                   !launch_ghost_sources(d_cv, k, RD, gpos, L.n_ghost, L.gsrc, d_err, st) &&
+                   hipStreamSynchronize(st) == hipSuccess,
+               RY_EHIP, "ghost source kernel");
+      }
+      // state: kept octs copied, new octs interpolated from level l-1
+      const int64_t n_ext = L.n + L.n_ghost;
+      for (int b = 0; b < 2; ++b) L.U[b] = static_cast<double*>(A(sizeof(double) * nv * 8 * n_ext, false));
+      L.reg = static_cast<double*>(A(sizeof(double) * L.n * reg_per_oct(nv), false));
+      RG_TRY(ok, RY_ENOMEM, "allocation failed");
+      const DevLevel& Fo = c->lev[k];
+      const double* Uc = N[k - 1].U[0];
+      const int64_t pc = (k == 1) ? c->lev[0].plane() : 8 * (N[k - 1].n + N[k - 1].n_ghost);
+      RG_TRY(!launch_regrid_remap(src_old, src7, L.n, Fo.n_oct ? Fo.U[Fo.cur] : nullptr, Fo.plane(), Uc, pc, L.U[0],
+                                  8 * n_ext, nv, st) &&
+                 !launch_zero_u64(reinterpret_cast<unsigned long long*>(L.reg), L.n * reg_per_oct(nv), st),
+             RY_EHIP, "regrid remap kernel");
+    }
+    // flags of level l from its new state, the child level, its remap sources
+    int64_t n_fine = 0;
+    L.flag = static_cast<uint8_t*>(A(L.n, true));
+    RG_TRY(ok, RY_ENOMEM, "allocation failed");
+    if (k + 1 < nl) {
+      int32_t* cnt = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
+      int32_t* off = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
+      RG_TRY(ok, RY_ENOMEM, "allocation failed");
+      RG_TRY(!launch_regrid_flags(V, RD, l, L.U[0], L.flag, cnt, st) && scan_total(cnt, off, L.n, n_fine), RY_EHIP,
+             "regrid flag kernel");
+      NewLevel& F = N[k + 1];
+      F.n = n_fine;
+      const int64_t n_old = c->lev[k + 1].n_oct;
+      if (n_fine > 0) {
+        F.key = static_cast<uint64_t*>(A(sizeof(uint64_t) * n_fine, false));
+        F.oc = static_cast<int32_t*>(A(sizeof(int32_t) * 3 * n_fine, false));
+        F.parent = static_cast<int32_t*>(A(sizeof(int32_t) * n_fine, false));
+        L.child = static_cast<int32_t*>(A(sizeof(int32_t) * 8 * L.n, false));
+        src_old = static_cast<int32_t*>(A(sizeof(int32_t) * n_fine, true));
+        src7 = static_cast<int32_t*>(A(sizeof(int32_t) * 7 * n_fine, true));
+        RG_TRY(ok, RY_ENOMEM, "allocation failed");
+        RG_TRY(!launch_regrid_children(V, old_view(k + 1), RD, c->dom.hbits0 + k + 1, L.flag, off, F.key, F.oc,
+                                       F.parent, L.child, src_old, src7, d_err, st),
+               RY_EHIP, "regrid children kernel");
+        std::vector<int32_t> so(n_fine);
+        RG_TRY(hipMemcpyAsync(so.data(), src_old, sizeof(int32_t) * n_fine, hipMemcpyDeviceToHost, st) ==
+                       hipSuccess &&
+                   hipStreamSynchronize(st) == hipSuccess,
+               RY_EHIP, "regrid children kernel");
+        int64_t kept = 0;
+        for (int32_t v : so) kept += v >= 0;
+        created += n_fine - kept;
+        destroyed += n_old - kept;
+      } else {
+        destroyed += n_old;
+      }
+    } else {
+      RG_TRY(hipMemsetAsync(L.flag, 0, L.n, st) == hipSuccess, RY_EHIP, "flag clear");
+    }
+    L.n_leaf = 8 * L.n - n_fine;
+    L.refined = static_cast<uint8_t*>(A(L.n + L.n_ghost, false));
+    RG_TRY(ok, RY_ENOMEM, "allocation failed");
+    RG_TRY(!launch_refined_ext(L.flag, L.n, L.n + L.n_ghost, L.refined, st), RY_EHIP, "refined kernel");
+  }
+  int32_t herr = 0;
+  RG_TRY(hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, st) == hipSuccess &&
+             hipStreamSynchronize(st) == hipSuccess,
+         RY_EHIP, "regrid kernels");
+  RG_TRY(herr == 0, RY_EINVAL, herr & 1 ? "interpolation source missing" : "ghost source missing");
+#undef RG_TRY
+  // install: release the old arrays (level lmin keeps state, keys, tables)
+  for (int k = 0; k < nl; ++k) {
+    DevLevel& D = c->lev[k];
+    for (void* p : {(void*)D.refined, (void*)D.child, (void*)D.parent_cell, (void*)D.gsrc, (void*)D.reg})
+      dfree(c, p);
+    if (k > 0) {
+      for (void* p : {(void*)D.tab, (void*)D.tflag, (void*)D.dkey, (void*)D.doc, (void*)D.U[0], (void*)D.U[1]})
+        dfree(c, p);
+      D.tab = nullptr;
+      D.tflag = nullptr;
+      D.dkey = nullptr;
+      D.doc = nullptr;
+      D.U[0] = D.U[1] = nullptr;
+      D.cur = 0;
+    }
+    const NewLevel& L = N[k];
+    D.n_oct = L.n;
+    D.n_ghost = L.n_ghost;
+    D.n_ext = L.n + L.n_ghost;
+    D.n_leaf = L.n_leaf;
+    D.refined = L.n ? L.refined : nullptr;
+    D.child = (k + 1 < nl && N[k + 1].n > 0) ? L.child : nullptr;
+    D.parent_cell = L.parent;
+    D.gsrc = L.gsrc;
+    D.reg = L.reg;
+    if (k > 0) {
+      D.n_tile = L.n_tile;
+      D.tab = L.tab;
+      D.tflag = L.tflag;
+      D.dkey = L.key;
+      D.doc = L.oc;
+      D.U[0] = L.U[0];
+      D.U[1] = L.U[1];
+    }
+  }
+  fresh.clear();
+  release(temps);
+  c->host_valid = false;
+  ry_status s = finish_regrid(c);
+  if (s) return s;
   if (n_created) *n_created = created;
   if (n_destroyed) *n_destroyed = destroyed;
   return RY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ry_status ry_set_regrid_device(ry_ctx* c, int32_t on) {
+  if (!c || c->batch) return RY_EINVAL;
+  c->regrid_device = on != 0;
+  return RY_OK;
+}
+
+ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
+  if (!c || c->batch) return RY_EINVAL;
+  if (!c->built) return fail(c, RY_ESTATE, "not built");
+  for (int k = 0; k < c->nlev; ++k)
+    if (c->count[k]) return fail(c, RY_ESTATE, "regrid inside a coarse step");
+  ry_status s = sync_and_check(c);
+  if (s) return s;
+  return c->regrid_device ? regrid_device(c, n_created, n_destroyed) : regrid_host(c, n_created, n_destroyed);
 }
 
 ry_status ry_level_info(const ry_ctx* c, int32_t level, int64_t* n_oct, int64_t* n_leaf) {
@@ -698,8 +1052,10 @@ ry_status ry_level_info(const ry_ctx* c, int32_t level, int64_t* n_oct, int64_t*
 ry_status ry_get_mesh(const ry_ctx* c, int32_t level, uint64_t* keys, uint8_t* refined) {
   if (!c || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
   const DevLevel& D = c->lev[level - c->cfg.level_min];
-  if (keys && D.n_oct) std::memcpy(keys, D.keys.data(), sizeof(uint64_t) * D.n_oct);
-  if (refined && D.n_oct) std::memcpy(refined, D.refined_host.data(), D.n_oct);
+  if (!D.n_oct) return RY_OK;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return RY_EHIP;
+  if (keys && hipMemcpy(keys, D.dkey, sizeof(uint64_t) * D.n_oct, hipMemcpyDeviceToHost) != hipSuccess) return RY_EHIP;
+  if (refined && hipMemcpy(refined, D.refined, D.n_oct, hipMemcpyDeviceToHost) != hipSuccess) return RY_EHIP;
   return RY_OK;
 }
 

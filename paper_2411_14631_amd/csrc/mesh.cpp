@@ -24,36 +24,6 @@ namespace ry {
 // excess rotations/reflections from the top bit down and Gray-coding, then
 // the transposed form is read out bit-plane by bit-plane, x first.
 // ---------------------------------------------------------------------------
-uint64_t hilbert3(int bits, uint32_t x, uint32_t y, uint32_t z) {
-  std::array<uint32_t, 3> a{x, y, z};
-  if (bits <= 0) return 0;
-  const uint32_t top = 1u << (bits - 1);
-  for (uint32_t q = top; q > 1; q >>= 1) {
-    const uint32_t low = q - 1;
-    for (int i = 0; i < 3; ++i) {
-      if (a[i] & q) {
-        a[0] ^= low;
-      } else {
-        const uint32_t swap = (a[0] ^ a[i]) & low;
-        a[0] ^= swap;
-        a[i] ^= swap;
-      }
-    }
-  }
-  a[1] ^= a[0];
-  a[2] ^= a[1];
-  uint32_t flip = 0;
-  for (uint32_t q = top; q > 1; q >>= 1)
-    if (a[2] & q) flip ^= (q - 1);
-  for (auto& v : a) v ^= flip;
-  uint64_t key = 0;
-  for (int b = bits - 1; b >= 0; --b) {
-    key = (key << 3) | (uint64_t((a[0] >> b) & 1u) << 2) | (uint64_t((a[1] >> b) & 1u) << 1) |
-          uint64_t((a[2] >> b) & 1u);
-  }
-  return key;
-}
-
 // ---------------------------------------------------------------------------
 static inline uint64_t packc(int64_t x, int64_t y, int64_t z) {
   return uint64_t(x) | (uint64_t(y) << 22) | (uint64_t(z) << 44);

@@ -1,0 +1,528 @@
+// Device-side mesh work of the regrid between coarse steps: refinement
+// flags, the child level in Hilbert order with its kept / new mapping and
+// interpolation sources, and the per-level device tables (tiles, the 4x4x4
+// oct neighbourhood of each tile, ghost octs and their sources).
+//
+// Octs of a level are looked up by binary search of their Hilbert key in
+// the level's sorted key array.  Children of a level-l oct occupy a
+// contiguous, ordered run of level-l+1 keys (key_{l+1} >> 3 == key_l), so the
+// child level comes out sorted from a scan over the parent octs: no global
+// sort.  Ghost octs are numbered in the order the host builder numbers them
+// (first use over tiles and slots), found with a device hash of positions.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ry_internal.h"
+
+namespace ry {
+
+namespace {
+
+__device__ __forceinline__ int64_t find_key(const uint64_t* __restrict__ key, int64_t n, uint64_t k) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (key[mid] < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n && key[lo] == k) ? lo : -1;
+}
+
+// Oct at integer oct position q of a level after the boundary rule: returns
+// its index, -1 when it does not exist, or -2 when q lies outside an
+// outflow face (such positions count as existing; the caller clamps).
+__device__ __forceinline__ int64_t oct_at(const LevelView& L, const int32_t* bc, int64_t qx, int64_t qy, int64_t qz) {
+  int64_t q[3] = {qx, qy, qz};
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = L.noct[a];
+    if (q[a] < 0) {
+      if (bc[2 * a] != RY_BC_PERIODIC) return -2;
+      q[a] = ((q[a] % n) + n) % n;
+    } else if (q[a] >= n) {
+      if (bc[2 * a + 1] != RY_BC_PERIODIC) return -2;
+      q[a] = q[a] % n;
+    }
+  }
+  return find_key(L.key, L.n, hilbert3(L.bits, uint32_t(q[0]), uint32_t(q[1]), uint32_t(q[2])));
+}
+
+__device__ __forceinline__ int cell_bits(int64_t x, int64_t y, int64_t z) {
+  return int((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+}
+
+// Level-l cell index (8*oct + cell) of cell position p after the boundary
+// rule (periodic wrap, outflow clamp); -1 when its oct does not exist.
+__device__ __forceinline__ int64_t cell_at(const LevelView& L, const int32_t* bc, int64_t x, int64_t y, int64_t z) {
+  int64_t p[3] = {x, y, z};
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = 2 * int64_t(L.noct[a]);
+    if (p[a] < 0) p[a] = (bc[2 * a] == RY_BC_PERIODIC) ? ((p[a] % n) + n) % n : 0;
+    else if (p[a] >= n) p[a] = (bc[2 * a + 1] == RY_BC_PERIODIC) ? p[a] % n : n - 1;
+  }
+  const int64_t o = find_key(L.key, L.n, hilbert3(L.bits, uint32_t(p[0] >> 1), uint32_t(p[1] >> 1),
+                                                   uint32_t(p[2] >> 1)));
+  return o < 0 ? -1 : o * 8 + cell_bits(p[0], p[1], p[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Flags: the build's criterion under the 26-neighbour rule.
+// ---------------------------------------------------------------------------
+__global__ void regrid_flag_kernel(LevelView L, RegridDom D, int l, const double* __restrict__ rho,
+                                   uint8_t* __restrict__ flag, int32_t* __restrict__ cnt) {
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o >= L.n) return;
+  const int64_t ox = L.oc[3 * o], oy = L.oc[3 * o + 1], oz = L.oc[3 * o + 2];
+  const double mass_thr = D.refine_param * ldexp(1.0, 3 * (l - D.lmin));
+  uint32_t have = 0;
+  bool known = false;
+  uint8_t f = 0;
+  for (int c = 0; c < 8; ++c) {
+    const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+    const double rc = rho[8 * o + c];
+    if (D.refine == RY_REFINE_MASS && !(rc > mass_thr)) continue;
+    if (D.refine != RY_REFINE_MASS && D.refine != RY_REFINE_GRAD) continue;
+    if (!known) {
+      known = true;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int64_t e = (dx | dy | dz) ? oct_at(L, D.bc, ox + dx, oy + dy, oz + dz) : o;
+            if (e != -1) have |= 1u << ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+          }
+    }
+    const int sx = bx ? 1 : -1, sy = by ? 1 : -1, sz = bz ? 1 : -1;
+    bool ok = true;
+    for (int k = 1; k < 8 && ok; ++k) {
+      const int dx = (k & 1) ? sx : 0, dy = (k & 2) ? sy : 0, dz = (k & 4) ? sz : 0;
+      if (!((have >> ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1))) & 1u)) ok = false;
+    }
+    if (!ok) continue;
+    bool want = true;
+    if (D.refine == RY_REFINE_GRAD) {
+#pragma clang fp contract(off)
+      const int64_t x = 2 * ox + bx, y = 2 * oy + by, z = 2 * oz + bz;
+      // the six cells lie in octs the rule just found; checked anyway
+      const int64_t xp = cell_at(L, D.bc, x + 1, y, z), xm = cell_at(L, D.bc, x - 1, y, z);
+      const int64_t yp = cell_at(L, D.bc, x, y + 1, z), ym = cell_at(L, D.bc, x, y - 1, z);
+      const int64_t zp = cell_at(L, D.bc, x, y, z + 1), zm = cell_at(L, D.bc, x, y, z - 1);
+      if ((xp | xm | yp | ym | zp | zm) < 0) continue;
+      const double gx = 0.5 * (rho[xp] - rho[xm]);
+      const double gy = 0.5 * (rho[yp] - rho[ym]);
+      const double gz = 0.5 * (rho[zp] - rho[zm]);
+      const double th = D.refine_param;
+      want = gx * gx + gy * gy + gz * gz > (th * rc) * (th * rc);
+    }
+    if (want) f |= uint8_t(1u << c);
+  }
+  flag[o] = f;
+  cnt[o] = __popc(uint32_t(f));
+}
+
+// ---------------------------------------------------------------------------
+// Children of the refined cells (level l+1) in Hilbert order, their
+// mapping to the old level l+1 and the interpolation sources of new octs.
+// ---------------------------------------------------------------------------
+__global__ void regrid_children_kernel(LevelView C, LevelView Fold, RegridDom D, int fbits,
+                                       const uint8_t* __restrict__ flag, const int32_t* __restrict__ off,
+                                       uint64_t* __restrict__ nkey, int32_t* __restrict__ noc,
+                                       int32_t* __restrict__ parent, int32_t* __restrict__ child,
+                                       int32_t* __restrict__ src_old, int32_t* __restrict__ src7,
+                                       int32_t* __restrict__ err) {
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o >= C.n) return;
+  const uint8_t f = flag[o];
+  for (int c = 0; c < 8; ++c) child[8 * o + c] = -1;
+  if (!f) return;
+  const int64_t ox = C.oc[3 * o], oy = C.oc[3 * o + 1], oz = C.oc[3 * o + 2];
+  uint64_t k8[8];
+  int c8[8];
+  int m = 0;
+  for (int c = 0; c < 8; ++c) {
+    if (!((f >> c) & 1)) continue;
+    const uint32_t x = uint32_t(2 * ox + (c & 1)), y = uint32_t(2 * oy + ((c >> 1) & 1)),
+                   z = uint32_t(2 * oz + ((c >> 2) & 1));
+    const uint64_t k = hilbert3(fbits, x, y, z);
+    int j = m++;
+    while (j > 0 && k8[j - 1] > k) {   // insertion sort by key
+      k8[j] = k8[j - 1];
+      c8[j] = c8[j - 1];
+      --j;
+    }
+    k8[j] = k;
+    c8[j] = c;
+  }
+  const int64_t base = off[o];
+  for (int j = 0; j < m; ++j) {
+    const int c = c8[j];
+    const int64_t k = base + j;
+    const int64_t x = 2 * ox + (c & 1), y = 2 * oy + ((c >> 1) & 1), z = 2 * oz + ((c >> 2) & 1);
+    nkey[k] = k8[j];
+    noc[3 * k] = int32_t(x);
+    noc[3 * k + 1] = int32_t(y);
+    noc[3 * k + 2] = int32_t(z);
+    parent[k] = int32_t(o * 8 + c);
+    child[8 * o + c] = int32_t(k);
+    const int64_t so = find_key(Fold.key, Fold.n, k8[j]);
+    src_old[k] = int32_t(so);
+    if (so >= 0) continue;
+    // parent cell Q = (x, y, z) of level l and its six face neighbours
+    src7[7 * k] = int32_t(o * 8 + c);
+    for (int a = 0; a < 3; ++a)
+      for (int s = 0; s < 2; ++s) {
+        int64_t p[3] = {x, y, z};
+        p[a] += s ? 1 : -1;
+        int64_t r = cell_at(C, D.bc, p[0], p[1], p[2]);
+        if (r < 0) {             // excluded by the neighbour rule; reported, read kept in bounds
+          atomicOr(err, 1);
+          r = o * 8 + c;
+        }
+        src7[7 * k + 1 + 2 * a + s] = int32_t(r);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int32 counts (three passes: block scans, a scan of the
+// block sums, block offsets).  tmp holds nblocks + 1 ints; *total gets the
+// sum.
+// ---------------------------------------------------------------------------
+constexpr int SCAN_BLOCK = 1024;
+
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* total) {
+  __shared__ int32_t ws[SCAN_BLOCK / 64];
+  const int32_t incl = wave_incl_scan(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) ws[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const int32_t s = (lane < SCAN_BLOCK / 64) ? ws[lane] : 0;
+    const int32_t si = wave_incl_scan(s);
+    if (lane < SCAN_BLOCK / 64) ws[lane] = si - s;
+    if (lane == SCAN_BLOCK / 64 - 1) *total = si;
+  }
+  __syncthreads();
+  return incl - v + ws[w];
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void scan_blocks_kernel(const int32_t* __restrict__ in,
+                                                                 int32_t* __restrict__ out, int64_t n,
+                                                                 int32_t* __restrict__ bsum) {
+  __shared__ int32_t tot;
+  const int64_t i = int64_t(blockIdx.x) * SCAN_BLOCK + threadIdx.x;
+  const int32_t v = (i < n) ? in[i] : 0;
+  const int32_t e = block_excl_scan(v, &tot);
+  if (i < n) out[i] = e;
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void scan_sums_kernel(int32_t* __restrict__ bsum, int nb,
+                                                               int32_t* __restrict__ total) {
+  __shared__ int32_t tot;
+  int32_t carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += SCAN_BLOCK) {
+    const int i = b0 + threadIdx.x;
+    const int32_t v = (i < nb) ? bsum[i] : 0;
+    const int32_t e = block_excl_scan(v, &tot);
+    __syncthreads();
+    if (i < nb) bsum[i] = e + carry;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void scan_add_kernel(int32_t* __restrict__ out, int64_t n,
+                                                              const int32_t* __restrict__ bsum) {
+  const int64_t i = int64_t(blockIdx.x) * SCAN_BLOCK + threadIdx.x;
+  if (i < n) out[i] += bsum[blockIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Tiles: octs sharing key >> 3.
+// ---------------------------------------------------------------------------
+__global__ void tile_start_kernel(const uint64_t* __restrict__ key, int64_t n, int32_t* __restrict__ start) {
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o < n) start[o] = (o == 0 || (key[o] >> 3) != (key[o - 1] >> 3)) ? 1 : 0;
+}
+
+__global__ void tile_first_kernel(const int32_t* __restrict__ start, const int32_t* __restrict__ tid, int64_t n,
+                                  int32_t n_tile, int32_t* __restrict__ first) {
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o < n && start[o]) first[tid[o]] = int32_t(o);
+  if (o == 0) first[n_tile] = int32_t(n);
+}
+
+// One thread per (tile, slot): the tile's 4x4x4 oct neighbourhood.  tab
+// gets the oct index, -1 (not needed, or outside an outflow face) or -2
+// (missing: a ghost oct, numbered later); miss = 1 for missing entries.
+__global__ void tile_table_kernel(LevelView L, RegridDom D, const int32_t* __restrict__ first, int32_t n_tile,
+                                  int32_t* __restrict__ tab, uint32_t* __restrict__ tflag,
+                                  int32_t* __restrict__ miss) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(n_tile) * TILE_TAB) return;
+  const int t = int(i / TILE_TAB), slot = int(i % TILE_TAB);
+  const int rx = slot % 4 - 1, ry_ = (slot / 4) % 4 - 1, rz = slot / 16 - 1;
+  const int64_t o0 = first[t], o1 = first[t + 1];
+  const int64_t bx = L.oc[3 * o0] & ~1, by = L.oc[3 * o0 + 1] & ~1, bz = L.oc[3 * o0 + 2] & ~1;
+  bool needed = false;
+  for (int64_t o = o0; o < o1 && !needed; ++o) {
+    const int px = int(L.oc[3 * o] - bx), py = int(L.oc[3 * o + 1] - by), pz = int(L.oc[3 * o + 2] - bz);
+    needed = abs(rx - px) <= 1 && abs(ry_ - py) <= 1 && abs(rz - pz) <= 1;
+  }
+  if (slot == 0) {
+    uint32_t fl = 0;
+    if (bx == 0 && D.bc[0] == RY_BC_OUTFLOW) fl |= CL_LOX;
+    if (bx + 2 == L.noct[0] && D.bc[1] == RY_BC_OUTFLOW) fl |= CL_HIX;
+    if (by == 0 && D.bc[2] == RY_BC_OUTFLOW) fl |= CL_LOY;
+    if (by + 2 == L.noct[1] && D.bc[3] == RY_BC_OUTFLOW) fl |= CL_HIY;
+    if (bz == 0 && D.bc[4] == RY_BC_OUTFLOW) fl |= CL_LOZ;
+    if (bz + 2 == L.noct[2] && D.bc[5] == RY_BC_OUTFLOW) fl |= CL_HIZ;
+    tflag[t] = fl;
+  }
+  int32_t v = -1, m = 0;
+  if (needed) {
+    const int64_t e = oct_at(L, D.bc, bx + rx, by + ry_, bz + rz);
+    if (e >= 0) v = int32_t(e);
+    else if (e == -1) {
+      v = -2;
+      m = 1;
+    }
+  }
+  tab[i] = v;
+  miss[i] = m;
+}
+
+// Missing entries in (tile, slot) order: their wrapped oct positions.
+__device__ __forceinline__ uint64_t pack_pos(int64_t x, int64_t y, int64_t z) {
+  return uint64_t(x) | (uint64_t(y) << 21) | (uint64_t(z) << 42);
+}
+
+__global__ void missing_list_kernel(LevelView L, const int32_t* __restrict__ first, int32_t n_tile,
+                                    const int32_t* __restrict__ miss, const int32_t* __restrict__ midx,
+                                    uint64_t* __restrict__ mpos, int32_t* __restrict__ mentry) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(n_tile) * TILE_TAB || !miss[i]) return;
+  const int t = int(i / TILE_TAB), slot = int(i % TILE_TAB);
+  const int64_t o0 = first[t];
+  int64_t q[3] = {(L.oc[3 * o0] & ~1) + slot % 4 - 1, (L.oc[3 * o0 + 1] & ~1) + (slot / 4) % 4 - 1,
+                  (L.oc[3 * o0 + 2] & ~1) + slot / 16 - 1};
+  for (int a = 0; a < 3; ++a) q[a] = ((q[a] % L.noct[a]) + L.noct[a]) % L.noct[a];
+  mpos[midx[i]] = pack_pos(q[0], q[1], q[2]);
+  mentry[midx[i]] = int32_t(i);
+}
+
+// Open-addressing hash of positions -> the first (smallest) list index.
+__device__ __forceinline__ uint64_t mix_pos(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  return k;
+}
+
+__global__ void hash_insert_kernel(const uint64_t* __restrict__ mpos, int64_t nm, unsigned long long* hkey,
+                                   int32_t* hval, uint64_t mask) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nm) return;
+  const unsigned long long k = mpos[i];
+  uint64_t s = mix_pos(k) & mask;
+  while (true) {
+    const unsigned long long prev = atomicCAS(&hkey[s], ~0ull, k);
+    if (prev == ~0ull || prev == k) {
+      atomicMin(&hval[s], int32_t(i));
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ int64_t hash_find(const unsigned long long* hkey, uint64_t mask, uint64_t k) {
+  uint64_t s = mix_pos(k) & mask;
+  while (hkey[s] != k) s = (s + 1) & mask;
+  return int64_t(s);
+}
+
+__global__ void owner_kernel(const uint64_t* __restrict__ mpos, int64_t nm, const unsigned long long* hkey,
+                             const int32_t* hval, uint64_t mask, int32_t* __restrict__ owner) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nm) return;
+  owner[i] = (hval[hash_find(hkey, mask, mpos[i])] == int32_t(i)) ? 1 : 0;
+}
+
+__global__ void ghost_assign_kernel(const uint64_t* __restrict__ mpos, const int32_t* __restrict__ mentry,
+                                    int64_t nm, const unsigned long long* hkey, const int32_t* hval, uint64_t mask,
+                                    const int32_t* __restrict__ owner, const int32_t* __restrict__ gidx,
+                                    int64_t n_oct, int32_t* __restrict__ tab, int32_t* __restrict__ gpos) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nm) return;
+  const int32_t first = hval[hash_find(hkey, mask, mpos[i])];
+  const int32_t g = gidx[first];
+  tab[mentry[i]] = int32_t(n_oct + g);
+  if (owner[i]) {
+    const uint64_t p = mpos[i];
+    gpos[3 * g] = int32_t(p & 0x1FFFFF);
+    gpos[3 * g + 1] = int32_t((p >> 21) & 0x1FFFFF);
+    gpos[3 * g + 2] = int32_t((p >> 42) & 0x1FFFFF);
+  }
+}
+
+// Ghost sources: the covering level l-1 cell Q and, per face, the cell of the
+// finest level <= l-1 covering Q's neighbour: (levels up << 48) | cell.
+// Sources that cannot exist under the neighbour rule are reported in err and
+// replaced by cell 0 of level l-1, so that later reads stay in bounds.
+__global__ void ghost_source_kernel(const LevelView* __restrict__ coarse, int ncoarse, RegridDom D,
+                                    const int32_t* __restrict__ gpos, int64_t n_ghost, int64_t* __restrict__ gsrc,
+                                    int32_t* __restrict__ err) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= n_ghost) return;
+  const int64_t qx = gpos[3 * g], qy = gpos[3 * g + 1], qz = gpos[3 * g + 2];   // a cell of level l-1
+  const int64_t q = cell_at(coarse[0], D.bc, qx, qy, qz);
+  if (q < 0) atomicOr(err, 2);
+  gsrc[7 * g] = q < 0 ? 0 : q;
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) {
+      int64_t p[3] = {qx, qy, qz};
+      p[a] += s ? 1 : -1;
+      int64_t r = -1;
+      int up = 0;
+      for (; up < ncoarse; ++up) {
+        r = cell_at(coarse[up], D.bc, p[0], p[1], p[2]);
+        if (r >= 0) break;
+        p[0] >>= 1;
+        p[1] >>= 1;
+        p[2] >>= 1;
+      }
+      if (r < 0) {
+        atomicOr(err, 2);
+        r = 0;
+        up = 0;
+      }
+      gsrc[7 * g + 1 + 2 * a + s] = (int64_t(up) << 48) | r;
+    }
+}
+
+__global__ void refined_ext_kernel(const uint8_t* __restrict__ flag, int64_t n, int64_t n_ext,
+                                   uint8_t* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n_ext) out[i] = (i < n) ? flag[i] : uint8_t(0);
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned blocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const double* rho, uint8_t* flag, int32_t* cnt,
+                        void* stream) {
+  if (L.n == 0) return 0;
+  hipLaunchKernelGGL(regrid_flag_kernel, dim3(blocks(L.n)), dim3(256), 0, (hipStream_t)stream, L, D, l, rho, flag,
+                     cnt);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int scan_tmp_ints(int64_t n) { return int((n + SCAN_BLOCK - 1) / SCAN_BLOCK) + 2; }
+
+int launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = int((n + SCAN_BLOCK - 1) / SCAN_BLOCK);
+  int32_t* total = tmp + nb + 1;
+  if (n == 0) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(1), 0, s, total, int64_t(1), int32_t(0));
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(SCAN_BLOCK), 0, s, in, out, n, tmp);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nb, total);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(SCAN_BLOCK), 0, s, out, n, tmp);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_regrid_children(const LevelView& C, const LevelView& Fold, const RegridDom& D, int fbits,
+                           const uint8_t* flag, const int32_t* off, uint64_t* nkey, int32_t* noc, int32_t* parent,
+                           int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err, void* stream) {
+  if (C.n == 0) return 0;
+  hipLaunchKernelGGL(regrid_children_kernel, dim3(blocks(C.n)), dim3(256), 0, (hipStream_t)stream, C, Fold, D, fbits,
+                     flag, off, nkey, noc, parent, child, src_old, src7, err);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_tile_starts(const uint64_t* key, int64_t n, int32_t* start, void* stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(tile_start_kernel, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, key, n, start);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_tile_first(const int32_t* start, const int32_t* tid, int64_t n, int32_t n_tile, int32_t* first,
+                      void* stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(tile_first_kernel, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, start, tid, n, n_tile,
+                     first);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_tile_table(const LevelView& L, const RegridDom& D, const int32_t* first, int32_t n_tile, int32_t* tab,
+                      uint32_t* tflag, int32_t* miss, void* stream) {
+  if (n_tile == 0) return 0;
+  hipLaunchKernelGGL(tile_table_kernel, dim3(blocks(int64_t(n_tile) * TILE_TAB)), dim3(256), 0, (hipStream_t)stream,
+                     L, D, first, n_tile, tab, tflag, miss);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_missing_list(const LevelView& L, const int32_t* first, int32_t n_tile, const int32_t* miss,
+                        const int32_t* midx, uint64_t* mpos, int32_t* mentry, void* stream) {
+  if (n_tile == 0) return 0;
+  hipLaunchKernelGGL(missing_list_kernel, dim3(blocks(int64_t(n_tile) * TILE_TAB)), dim3(256), 0,
+                     (hipStream_t)stream, L, first, n_tile, miss, midx, mpos, mentry);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_ghost_numbering(const uint64_t* mpos, const int32_t* mentry, int64_t nm, unsigned long long* hkey,
+                           int32_t* hval, uint64_t hsize, int32_t* owner, int32_t* gidx, int32_t* scan_tmp,
+                           int64_t n_oct, int32_t* tab, int32_t* gpos, void* stream) {
+  if (nm == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t mask = hsize - 1;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks(int64_t(hsize))), dim3(256), 0, s, hkey, int64_t(hsize), ~0ull);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks(int64_t(hsize))), dim3(256), 0, s, hval, int64_t(hsize),
+                     int32_t(0x7fffffff));
+  hipLaunchKernelGGL(hash_insert_kernel, dim3(blocks(nm)), dim3(256), 0, s, mpos, nm, hkey, hval, mask);
+  hipLaunchKernelGGL(owner_kernel, dim3(blocks(nm)), dim3(256), 0, s, mpos, nm, hkey, hval, mask, owner);
+  if (launch_scan(owner, gidx, nm, scan_tmp, stream)) return -1;
+  hipLaunchKernelGGL(ghost_assign_kernel, dim3(blocks(nm)), dim3(256), 0, s, mpos, mentry, nm, hkey, hval, mask,
+                     owner, gidx, n_oct, tab, gpos);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_ghost_sources(const LevelView* coarse_dev, int ncoarse, const RegridDom& D, const int32_t* gpos,
+                         int64_t n_ghost, int64_t* gsrc, int32_t* err, void* stream) {
+  if (n_ghost == 0) return 0;
+  hipLaunchKernelGGL(ghost_source_kernel, dim3(blocks(n_ghost)), dim3(256), 0, (hipStream_t)stream, coarse_dev,
+                     ncoarse, D, gpos, n_ghost, gsrc, err);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_refined_ext(const uint8_t* flag, int64_t n, int64_t n_ext, uint8_t* out, void* stream) {
+  if (n_ext == 0) return 0;
+  hipLaunchKernelGGL(refined_ext_kernel, dim3(blocks(n_ext)), dim3(256), 0, (hipStream_t)stream, flag, n, n_ext, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ry

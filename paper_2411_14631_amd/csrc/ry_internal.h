@@ -1,6 +1,8 @@
 // Internal declarations shared by the host side (mesh.cpp, api.cpp) and the
 // HIP kernels (kernels.hip) of the octree hydro library.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -50,7 +52,37 @@ struct DomainSpec {
   int64_t noct(int l, int a) const { return ncell(l, a) / 2; }
 };
 
-uint64_t hilbert3(int bits, uint32_t x, uint32_t y, uint32_t z);
+// Hilbert key of oct coordinates with `bits` bits per axis (Skilling 2004,
+// transpose form; x is the most significant axis of each 3-bit group).
+__host__ __device__ inline uint64_t hilbert3(int bits, uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t a[3] = {x, y, z};
+  if (bits <= 0) return 0;
+  const uint32_t top = 1u << (bits - 1);
+  for (uint32_t q = top; q > 1; q >>= 1) {
+    const uint32_t low = q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (a[i] & q) {
+        a[0] ^= low;
+      } else {
+        const uint32_t swap = (a[0] ^ a[i]) & low;
+        a[0] ^= swap;
+        a[i] ^= swap;
+      }
+    }
+  }
+  a[1] ^= a[0];
+  a[2] ^= a[1];
+  uint32_t flip = 0;
+  for (uint32_t q = top; q > 1; q >>= 1)
+    if (a[2] & q) flip ^= (q - 1);
+  for (int i = 0; i < 3; ++i) a[i] ^= flip;
+  uint64_t key = 0;
+  for (int b = bits - 1; b >= 0; --b) {
+    key = (key << 3) | (uint64_t((a[0] >> b) & 1u) << 2) | (uint64_t((a[1] >> b) & 1u) << 1) |
+          uint64_t((a[2] >> b) & 1u);
+  }
+  return key;
+}
 
 // Device-side description of one level, produced by the host builder.
 struct LevelTables {
@@ -154,6 +186,45 @@ int launch_totals(const double* U, int64_t plane, int64_t n_oct, const uint8_t* 
                   double* partial, int nblocks, void* stream);
 int launch_totals_final(const double* partial, int nparts, int nv, double* out, void* stream);
 int launch_copy(const double* src, double* dst, int64_t n, void* stream);
+// ---- device regrid (regrid.hip) ----
+// What the device regrid reads of one level: sorted Hilbert keys, oct
+// coordinates (x, y, z interleaved), counts.
+struct LevelView {
+  const uint64_t* key;
+  const int32_t* oc;
+  int64_t n;
+  int32_t bits;                      // Hilbert bits per axis at this level
+  int32_t noct[3];                   // octs per axis at this level
+};
+struct RegridDom {
+  int32_t bc[6];
+  int32_t lmin;
+  int32_t refine;
+  double refine_param;
+};
+int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const double* rho, uint8_t* flag, int32_t* cnt,
+                        void* stream);
+// exclusive scan of n int32 (tmp: scan_tmp_ints(n) ints; the total lands in
+// tmp[scan_tmp_ints(n) - 1])
+int scan_tmp_ints(int64_t n);
+int launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, void* stream);
+int launch_regrid_children(const LevelView& C, const LevelView& Fold, const RegridDom& D, int fbits,
+                           const uint8_t* flag, const int32_t* off, uint64_t* nkey, int32_t* noc, int32_t* parent,
+                           int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err, void* stream);
+int launch_tile_starts(const uint64_t* key, int64_t n, int32_t* start, void* stream);
+int launch_tile_first(const int32_t* start, const int32_t* tid, int64_t n, int32_t n_tile, int32_t* first,
+                      void* stream);
+int launch_tile_table(const LevelView& L, const RegridDom& D, const int32_t* first, int32_t n_tile, int32_t* tab,
+                      uint32_t* tflag, int32_t* miss, void* stream);
+int launch_missing_list(const LevelView& L, const int32_t* first, int32_t n_tile, const int32_t* miss,
+                        const int32_t* midx, uint64_t* mpos, int32_t* mentry, void* stream);
+int launch_ghost_numbering(const uint64_t* mpos, const int32_t* mentry, int64_t nm, unsigned long long* hkey,
+                           int32_t* hval, uint64_t hsize, int32_t* owner, int32_t* gidx, int32_t* scan_tmp,
+                           int64_t n_oct, int32_t* tab, int32_t* gpos, void* stream);
+int launch_ghost_sources(const LevelView* coarse_dev, int ncoarse, const RegridDom& D, const int32_t* gpos,
+                         int64_t n_ghost, int64_t* gsrc, int32_t* err, void* stream);
+int launch_refined_ext(const uint8_t* flag, int64_t n, int64_t n_ext, uint8_t* out, void* stream);
+
 // Regrid state remap of one level: for new oct k, cell c, variable v: a kept
 // oct copies Uold[v*pold + 8*src_old[k] + c]; a new one takes the MinMod-
 // linear interpolation of the level-l cells src7[7k..7k+6] of Uc (plane pc).

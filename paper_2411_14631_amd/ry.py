@@ -28,7 +28,7 @@ EXPORTS = [
     "ry_batch_create", "ry_batch_run", "ry_batch_box_info", "ry_batch_download",
     "ry_set_tuning", "ry_get_tuning", "ry_autotune", "ry_floor_count", "ry_set_timing",
     "ry_kernel_time", "ry_copy_probe", "ry_last_error", "ry_mesh_build", "ry_mesh_level",
-    "ry_mesh_free", "ry_hilbert_key", "ry_regrid", "ry_set_refine_param",
+    "ry_mesh_free", "ry_hilbert_key", "ry_regrid", "ry_set_refine_param", "ry_set_regrid_device",
 ]
 # Every function declared in include/ry_poisson.h.
 POISSON_EXPORTS = [
@@ -116,6 +116,7 @@ def lib():
         "ry_hilbert_key": ([I32, C.c_uint32, C.c_uint32, C.c_uint32], C.c_uint64),
         "ry_regrid": ([P, C.POINTER(I64), C.POINTER(I64)], I32),
         "ry_set_refine_param": ([P, D], I32),
+        "ry_set_regrid_device": ([P, I32], I32),
         "ry_poisson_create": ([C.POINTER(RyPoissonConfig), C.POINTER(P)], I32),
         "ry_poisson_destroy": ([P], None),
         "ry_poisson_set_rhs": ([P, P, P], I32),
@@ -320,6 +321,11 @@ class Hydro(_Base):
 
     def set_refine_param(self, value):
         self._check(lib().ry_set_refine_param(self.ctx, value), "ry_set_refine_param")
+
+    def set_regrid_device(self, on):
+        """True (default): regrid entirely on the device; False: flags and
+        tables on the host, state remap on the device."""
+        self._check(lib().ry_set_regrid_device(self.ctx, 1 if on else 0), "ry_set_regrid_device")
 
     def totals(self):
         tot = (C.c_double * self.nv)()

@@ -115,3 +115,63 @@ def test_regrid_inside_a_coarse_step_is_refused(ry):
     g.hydro_step(prob.level_max, 0.25 * dt)
     with pytest.raises(ry.RyError):
         g.regrid()
+
+
+def same_mesh_and_state(a, b):
+    for lv in a.levels:
+        assert a.level_info(lv) == b.level_info(lv), lv
+        if a.level_info(lv)[0] == 0:
+            continue
+        ka, ra = a.mesh(lv)
+        kb, rb = b.mesh(lv)
+        np.testing.assert_array_equal(ka, kb)
+        np.testing.assert_array_equal(ra, rb)
+        np.testing.assert_array_equal(a.download(lv), b.download(lv))
+
+
+@pytest.mark.parametrize("bc", [(W.BC_PERIODIC,) * 6, (W.BC_OUTFLOW,) * 6])
+def test_device_and_host_regrid_paths_bit_identical(ry, bc):
+    """The all-device regrid and the host-flag path give the same mesh and
+    state bit for bit, and the solver continues identically on both (the
+    tile tables, ghost numbering and ghost sources agree)."""
+    prob = cases.with_scalars(cases.amr_blob(bc=bc), 2)
+    a, b = ry.Hydro(prob), ry.Hydro(prob)
+    b.set_regrid_device(False)
+    for _ in range(3):
+        a.advance(1)
+        b.advance(1)
+        assert a.regrid() == b.regrid()
+        same_mesh_and_state(a, b)
+    a.advance(2)
+    b.advance(2)
+    same_mesh_and_state(a, b)
+
+
+def test_device_regrid_empties_and_regrows_levels(ry):
+    """Thresholds that remove every refined level, then restore them: counts,
+    meshes and states against the oracle on the way down and back up."""
+    prob = ramp_problem(5.4)
+    g, o = ry.Hydro(prob), Oracle(prob)
+    for thr in (1e9, 5.4, 4.6):
+        g.set_refine_param(thr)
+        o.set_refine_param(thr)
+        assert g.regrid() == o.regrid()
+        compare(g, o, 0.0)
+    g.advance(1)
+    o.advance(1)
+    compare(g, o)
+
+
+def test_zoom_full_size_device_regrid_matches_host_path(ry):
+    """The zoom-in hierarchy (levels 7-12) after two coarse steps: one regrid
+    on each path, bit-identical meshes and states, then one more step."""
+    prob = W.zoom()
+    a, b = ry.Hydro(prob), ry.Hydro(prob)
+    b.set_regrid_device(False)
+    a.advance(2)
+    b.advance(2)
+    assert a.regrid() == b.regrid()
+    same_mesh_and_state(a, b)
+    a.advance(1)
+    b.advance(1)
+    same_mesh_and_state(a, b)
