@@ -353,18 +353,42 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   const Real h = Real(0.5 * lam);
   const Real igm1 = Real(1.0 / (g - 1.0));
 
-  // --- phase 0: the tile's oct table and refined bytes
+  // The thread's stencil-table entries for phases A and B, loaded together up
+  // front: a load issued inside a round would make that round wait for every
+  // state load issued before it.
+  constexpr int NRA = (NPOS_A + NT - 1) / NT;
+  constexpr int NRB = (NPOS_B + NT - 1) / NT;
+  uint32_t entA[NRA], entB[NRB];
+#pragma unroll
+  for (int rnd = 0; rnd < NRA; ++rnd) {
+    const int i = tid + NT * rnd;
+    entA[rnd] = c_st.a[i < NPOS_A ? i : 0];
+  }
+#pragma unroll
+  for (int rnd = 0; rnd < NRB; ++rnd) {
+    const int i = tid + NT * rnd;
+    entB[rnd] = c_st.b[i < NPOS_B ? i : 0];
+  }
+
+  // --- phase 0: the tile's oct table (the refined bytes of its octs are
+  // loaded in phase A behind the state loads; phase D is their first reader)
+  int32_t e_tab = -1;
   if (active && tid < TILE_TAB) {
-    const int32_t e = A.tab[size_t(tile) * TILE_TAB + tid];
-    S.tab[tid] = e;
-    S.ref[tid] = (e >= 0) ? A.refined[e] : uint8_t(0);
+    e_tab = A.tab[size_t(tile) * TILE_TAB + tid];
+    S.tab[tid] = e_tab;
   }
   __syncthreads();
+  // Wait for the table entries here on every path: otherwise the gather's
+  // conditional state loads leave the compiler's load counting unsure of them,
+  // and each round would wait for the state loads of the rounds before it.
+#pragma unroll
+  for (int rnd = 0; rnd < NRA; ++rnd) asm volatile("" ::"v"(entA[rnd]));
+#pragma unroll
+  for (int rnd = 0; rnd < NRB; ++rnd) asm volatile("" ::"v"(entB[rnd]));
 
   // --- phase A: gather + primitives (all loads of the thread's positions are
   // issued before any conversion)
   Real* W = S.buf;                              // [NV][WSIZE]
-  constexpr int NRA = (NPOS_A + NT - 1) / NT;
   double Ua[NRA][NV];
   int iwa[NRA];
 #pragma unroll
@@ -372,7 +396,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     const int i = tid + NT * rnd;
     iwa[rnd] = -1;
     if (active && i < NPOS_A) {
-      const uint32_t ent = c_st.a[i];
+      const uint32_t ent = entA[rnd];
       int slot = int((ent >> 10) & 63u), cb = int((ent >> 16) & 7u);
       if (fl) {
         // outflow faces: clamp the position into the domain (zero gradient)
@@ -399,6 +423,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       }
     }
   }
+  const uint8_t rb = (e_tab >= 0) ? A.refined[e_tab] : uint8_t(0);
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     if (iwa[rnd] >= 0) {
@@ -408,12 +433,12 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       for (int v = 0; v < NV; ++v) W[v * WSIZE + iwa[rnd]] = Real(Wc[v]);
     }
   }
+  if (active && tid < TILE_TAB) S.ref[tid] = rb;
   __syncthreads();
 
   // --- phase B1: slopes + predictor.  The core cell of a thread (first pass,
   // tid < 64) keeps W~ and its slopes in registers for its six faces; a
   // one-layer cell keeps only its state on the face toward the core.
-  constexpr int NRB = (NPOS_B + NT - 1) / NT;
   constexpr int st[3] = {1, WB, WBB};
   const bool core = (NT == 64) || tid < NCORE;
   const int cx = tid & 3, cy = (tid >> 2) & 3, cz = (tid >> 4) & 3;
@@ -438,7 +463,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
           Pd[d][v] = mmod(W0[v] - W[v * WSIZE + iw - st[d]], W[v * WSIZE + iw + st[d]] - W0[v]);
       predict<Real, NS>(W0, Pd, h, gr, Pw);
     } else {
-      const uint32_t e = c_st.b[i];
+      const uint32_t e = entB[rnd];
       Lb[rnd] = e;
       const int iw = int(e & 511u), far = int((e >> 9) & 511u), dn = int((e >> 18) & 3u);
       const bool up = (e >> 20) & 1u;
