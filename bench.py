@@ -41,7 +41,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "ry_internal.h"):
+    for f in ("hydro_tile.h", "hydro.hip", "ry_internal.h"):
         with open(os.path.join(ROOT, "paper_2411_14631_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -11,7 +11,10 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libry.so")
-SOURCES = ["mesh.cpp", "api.cpp", "kernels.hip", "poisson.hip", "regrid.hip"]
+SOURCES = ["mesh.cpp", "api.cpp", "kernels.hip", "hydro.hip", "poisson.hip", "regrid.hip"]
+# per-source options: the hydro-only tile kernels schedule for instruction-
+# level parallelism (their occupancy is bounded by LDS, not registers)
+SOURCE_FLAGS = {"hydro.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -39,7 +42,7 @@ def build(verbose: bool = False, extra=None) -> str:
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(bdir, s + ".o")
-        cmd = [HIPCC] + flags() + (extra or []) + ["-c", src, "-o", obj]
+        cmd = [HIPCC] + flags() + SOURCE_FLAGS.get(s, []) + (extra or []) + ["-c", src, "-o", obj]
         if s.endswith(".cpp"):
             cmd = [HIPCC, "-x", "hip"] + cmd[1:]
         if verbose:

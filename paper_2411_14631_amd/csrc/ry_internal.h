@@ -155,6 +155,8 @@ struct GhostArgs {
 
 // launchers (kernels.hip)
 int launch_hydro(const HydroArgs& a, int precision, int nscalar, const ry_tuning& t, int num_cu, void* stream);
+// the hydro-only (nscalar = 0) part of launch_hydro (hydro.hip)
+int launch_hydro_plain(const HydroArgs& a, int precision, const ry_tuning& t, int num_cu, void* stream);
 // whether a hydro kernel exists for this precision / scalar count / tuning
 bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t);
 int launch_ghost(const GhostArgs& a, void* stream);
