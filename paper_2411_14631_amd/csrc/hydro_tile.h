@@ -157,16 +157,16 @@ __device__ __forceinline__ double qdiv(double a, double b) {
   return fma(fma(-b, q, a), r, q);
 }
 __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-// Square root for wave-speed estimates: x * rsq(x) refined by two Newton
-// steps on the root (the raw hardware square root is far from FP64 accurate).
-__device__ __forceinline__ double esqrt(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  double s = x * y;
-  const double hy = 0.5 * y;
-  s = fma(fma(-s, s, x), hy, s);
-  return fma(fma(-s, s, x), hy, s);
+// Sound speed sqrt(gp / rho) for gp = gamma p, written as gp / sqrt(gp rho):
+// one reciprocal square root, refined by two Newton steps in FP64.
+__device__ __forceinline__ double sound_speed(double gp, double rho) {
+  const double a = gp * rho;
+  double y = __builtin_amdgcn_rsq(a);
+  y = fma(fma(-(a * y), y, 1.0), 0.5 * y, y);
+  y = fma(fma(-(a * y), y, 1.0), 0.5 * y, y);
+  return gp * y;
 }
-__device__ __forceinline__ float esqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float sound_speed(float gp, float rho) { return gp * __builtin_amdgcn_rsqf(gp * rho); }
 
 // Primitive variables (FP64 in both forms) with floors; nfl counts floor
 // activations.  Passive scalars: s = (rho s) / rho.
@@ -189,19 +189,16 @@ __device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NV
   for (int k = 0; k < NS; ++k) W[NVAR + k] = U[NVAR + k] * ir;
 }
 
-// CFL signal speed |u|+|v|+|w|+3c of a conserved state, in the same IEEE
-// operations as the definition (correctly rounded division and square root,
-// no contraction), so dt is reproducible.
+// CFL signal speed |u|+|v|+|w|+3c of a conserved state (floors as for the
+// primitives), with one refined reciprocal and one refined reciprocal
+// square root: within a few ulp of the definition.
 __device__ __forceinline__ double signal_speed(const double U[NVAR], double g, double rf, double pf) {
-#pragma clang fp contract(off)
-  double rho = U[0];
-  if (rho < rf) rho = rf;
-  const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / rho;
+  const double rho = U[0] < rf ? rf : U[0];
+  const double ir = rcp(rho);
+  const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir;
   double p = (g - 1.0) * (U[4] - ke);
   if (p < pf) p = pf;
-  const double u = U[1] / rho, v = U[2] / rho, w = U[3] / rho;
-  const double c = sqrt(g * p / rho);
-  return fabs(u) + fabs(v) + fabs(w) + 3.0 * c;
+  return (fabs(U[1]) + fabs(U[2]) + fabs(U[3])) * ir + 3.0 * sound_speed(g * p, rho);
 }
 
 // What a passive scalar's HLLC flux needs from the hydro solve: the side K,
@@ -225,8 +222,8 @@ struct HllcSide {
 template <typename Real>
 __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real pl, Real rr, Real ur, Real ar,
                                        Real br, Real pr, Real g, Real igm1, Real Fn[5], HllcSide<Real>& side) {
-  const Real cl = esqrt(g * pl * rcp(rl));
-  const Real cr = esqrt(g * pr * rcp(rr));
+  const Real cl = sound_speed(g * pl, rl);
+  const Real cr = sound_speed(g * pr, rr);
   const Real SL = fmin(ul - cl, ur - cr);
   const Real SR = fmax(ul + cl, ur + cr);
   const Real num = pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur);
@@ -240,9 +237,12 @@ __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real 
   const Real mK = rK * uK;
   const Real q = SK - uK;
   const Real dq = SK - Ss;
-  // r = q / dq, exactly 1 when S* == u_K (stationary contacts stay exact)
-  const Real r = (q == dq) ? Real(1) : qdiv(q, dq);
-  const Real Es = EK + rK * (Ss - uK) * (Ss + qdiv(pK, rK * q));
+  // r = q / dq (exactly 1 when S* == u_K: stationary contacts stay exact)
+  // and p_K / (rho_K q) from one reciprocal of their denominators' product
+  const Real rq = rK * q;
+  const Real inv = rcp(dq * rq);
+  const Real r = (q == dq) ? Real(1) : q * (rq * inv);
+  const Real Es = EK + rK * (Ss - uK) * (Ss + pK * (dq * inv));
   const Real w = star ? SK : Real(0);
   Fn[0] = mK + w * (r * rK - rK);
   Fn[1] = (mK * uK + pK) + w * (r * (rK * Ss) - mK);
