@@ -688,8 +688,12 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   __syncthreads();
 }
 
+// Hydro variables alone: at least 3 wavefronts per SIMD (the FP64 tile's LDS
+// allows no more, so the register budget of an instruction-level-parallel
+// schedule stops there).  With passive scalars the LDS tile sets the limit.
 template <typename Real, int TPW, int WPT, int NS>
-__global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel(HydroArgs A) {
+__global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(NS == 0 ? 3 : 1))) void hydro_kernel(
+    HydroArgs A) {
   constexpr int NT = 64 * WPT;
   __shared__ TileLDS<Real, NVAR + NS> S[TPW];
   if (A.skip && *A.skip) return;
@@ -706,7 +710,8 @@ __global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel(HydroArgs A) {
 // workgroup whose own queue is empty takes from the next one).  Every
 // workgroup exits once all 8 queues are exhausted.
 template <typename Real, int TPW, int WPT>
-__global__ __launch_bounds__(64 * WPT * TPW) void hydro_kernel_persistent(HydroArgs A, int batch) {
+__global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(3))) void hydro_kernel_persistent(HydroArgs A,
+                                                                                                      int batch) {
   constexpr int NT = 64 * WPT;
   __shared__ TileLDS<Real, NVAR> S[TPW];
   __shared__ int s_item;
