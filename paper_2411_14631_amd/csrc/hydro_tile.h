@@ -130,18 +130,11 @@ struct TileLDS {
 // ---------------------------------------------------------------------------
 // Scalar helpers.
 // ---------------------------------------------------------------------------
-// MinMod: min(a,b) if both > 0, max(a,b) if both < 0, else 0 -- evaluated
-// without branches as copysign(max(0, min(|a|, sign(a) b)), a).
-__device__ __forceinline__ double mmod(double a, double b) {
-  const long long sa = __double_as_longlong(a) & (long long)0x8000000000000000ull;
-  const double bs = __longlong_as_double(__double_as_longlong(b) ^ sa);
-  return copysign(fmax(fmin(fabs(a), bs), 0.0), a);
-}
-__device__ __forceinline__ float mmod(float a, float b) {
-  const int sa = __float_as_int(a) & int(0x80000000u);
-  const float bs = __int_as_float(__float_as_int(b) ^ sa);
-  return copysignf(fmaxf(fminf(fabsf(a), bs), 0.0f), a);
-}
+// MinMod: min(a,b) if both > 0, max(a,b) if both < 0, else 0 -- which is
+// the median of (a, b, 0): max(min(a,b), min(max(a,b), 0)) in FP64 (four
+// min/max), one v_med3 in FP32.
+__device__ __forceinline__ double mmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
+__device__ __forceinline__ float mmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 
 // Reciprocal and quotient: the hardware reciprocal refined by two Newton
 // steps and a residual correction (operands here are normal numbers).
@@ -472,22 +465,20 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       Real W0[NV], D[3][NV], Q[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) W0[v] = W[v * WSIZE + iw];
-      Real Dn[NV];                            // the slope along the normal
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int lo = (d == dn && !up) ? far : iw - st[d];
         const int hi = (d == dn && up) ? far : iw + st[d];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const Real sl = mmod(W0[v] - W[v * WSIZE + lo], W[v * WSIZE + hi] - W0[v]);
-          D[d][v] = sl;
-          Dn[v] = (d == 0 || d == dn) ? sl : Dn[v];
-        }
+        for (int v = 0; v < NV; ++v) D[d][v] = mmod(W0[v] - W[v * WSIZE + lo], W[v * WSIZE + hi] - W0[v]);
       }
       predict<Real, NS>(W0, D, h, gr, Q);
+      // the face state Q +- D/2 along the normal: the weights of the two other
+      // axes are zero, so their fused terms add exact zeros
       const Real sg = up ? Real(-0.5) : Real(0.5);
+      const Real t0 = (dn == 0) ? sg : Real(0), t1 = (dn == 1) ? sg : Real(0), t2 = (dn == 2) ? sg : Real(0);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Ls[rnd][v] = Q[v] + sg * Dn[v];
+      for (int v = 0; v < NV; ++v) Ls[rnd][v] = fma(t2, D[2][v], fma(t1, D[1][v], fma(t0, D[0][v], Q[v])));
       floor_state<Real>(Ls[rnd], rfr, pfr, nfl);
     }
   }
