@@ -29,6 +29,13 @@
 
 namespace ry {
 
+// Multiply-adds written in one expression are fused (FMA) in the per-tile
+// update: the same source expression compiles to the same fused operations
+// wherever it is inlined, so a face flux computed by two tiles stays
+// identical.  The code after this header (in the files that include it) is
+// compiled without contraction again.
+#pragma clang fp contract(on)
+
 // ---------------------------------------------------------------------------
 // Tile geometry.  Stencil positions s in [-2,5]^3 relative to the tile's
 // first cell.  The primitives that are needed sit in LDS as the 6^3 box
@@ -759,5 +766,7 @@ static int launch_hydro_t(const HydroArgs& a, const ry_tuning& t, int num_cu, hi
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
+#pragma clang fp contract(off)
 
 }  // namespace ry
