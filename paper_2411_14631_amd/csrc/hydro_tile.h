@@ -173,8 +173,10 @@ __device__ __forceinline__ float sound_speed(float gp, float rho) { return gp * 
 template <int NS>
 __device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NVAR + NS], double g, double rf,
                                           double pf, int& nfl) {
+  // floors as max(): a non-finite state never gets here unnoticed (the CFL
+  // pass flags it on upload, the update flags it where it is produced)
   const bool lo_r = U[0] < rf;
-  const double rho = lo_r ? rf : U[0];
+  const double rho = fmax(U[0], rf);
   const double ir = rcp(rho);
   const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir;
   const double p0 = (g - 1.0) * (U[4] - ke);
@@ -184,7 +186,7 @@ __device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NV
   W[1] = U[1] * ir;
   W[2] = U[2] * ir;
   W[3] = U[3] * ir;
-  W[4] = lo_p ? pf : p0;
+  W[4] = fmax(p0, pf);
 #pragma unroll
   for (int k = 0; k < NS; ++k) W[NVAR + k] = U[NVAR + k] * ir;
 }
@@ -193,11 +195,11 @@ __device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NV
 // primitives), with one refined reciprocal and one refined reciprocal
 // square root: within a few ulp of the definition.
 __device__ __forceinline__ double signal_speed(const double U[NVAR], double g, double rf, double pf) {
-  const double rho = U[0] < rf ? rf : U[0];
+  const double rho = fmax(U[0], rf);
   const double ir = rcp(rho);
   const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir;
   double p = (g - 1.0) * (U[4] - ke);
-  if (p < pf) p = pf;
+  p = fmax(p, pf);
   return (fabs(U[1]) + fabs(U[2]) + fabs(U[3])) * ir + 3.0 * sound_speed(g * p, rho);
 }
 
@@ -277,8 +279,8 @@ __device__ __forceinline__ void predict(const Real W0[NVAR + NS], const Real D[3
 template <typename Real>
 __device__ __forceinline__ void floor_state(Real* s, Real rf, Real pf, int& nfl) {
   nfl += int(s[0] < rf) + int(s[4] < pf);
-  s[0] = (s[0] < rf) ? rf : s[0];
-  s[4] = (s[4] < pf) ? pf : s[4];
+  s[0] = fmax(s[0], rf);
+  s[4] = fmax(s[4], pf);
 }
 
 // Flux through the lower face along axis D of a core cell: the left state
