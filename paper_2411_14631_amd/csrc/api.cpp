@@ -362,6 +362,7 @@ HydroArgs hydro_args(ry_ctx* c, int l, int substep) {
   a.substep = substep;
   a.record_reg = (l > c->cfg.level_min) ? 1 : 0;
   a.gamma = c->cfg.gamma;
+  a.igm1 = 1.0 / (c->cfg.gamma - 1.0);
   a.rho_floor = c->cfg.rho_floor;
   a.p_floor = c->cfg.p_floor;
   a.floors = c->d_floors;

@@ -203,24 +203,28 @@ __device__ __forceinline__ double signal_speed(const double U[NVAR], double g, d
   return (fabs(U[1]) + fabs(U[2]) + fabs(U[3])) * ir + 3.0 * sound_speed(g * p, rho);
 }
 
-// What a passive scalar's HLLC flux needs from the hydro solve: the side K,
-// its density and mass flux, the star weight w (S_K on star faces, else 0)
-// and r = (S_K - u_K) / (S_K - S*).  A scalar is carried like a transverse
-// velocity (Toro 2009, Sec. 10.6): F_s = m_K s_K + w (r (rho_K s_K) - rho_K s_K).
+// What a passive scalar's HLLC flux needs from the hydro solve: the side K
+// and the mass flux.  A scalar is carried like a transverse velocity (Toro
+// 2009, Sec. 10.6), so its flux is s_K times the mass flux.
 template <typename Real>
 struct HllcSide {
   bool useL;
-  Real rK, mK, w, r;
-  __device__ __forceinline__ Real scalar_flux(Real sl, Real sr) const {
-    const Real sK = useL ? sl : sr;
-    return mK * sK + w * (r * (rK * sK) - rK * sK);
-  }
+  Real F0;
+  __device__ __forceinline__ Real scalar_flux(Real sl, Real sr) const { return (useL ? sl : sr) * F0; }
 };
 
 // HLLC flux in the face-normal frame: (r, u, a, b, p) = density, normal and
 // two tangential velocities, pressure of the left / right face state.  The
 // branch picks a side K (L when S_L >= 0 or S* >= 0, else R) and whether the
-// star state of K applies; only that side's star state is formed.
+// star state of K applies; only that side's star state is formed.  With
+// x = (S* - u_K) / (S_K - S*) (so that rho*_K = rho_K (1 + x), and x is
+// exactly 0 when S* = u_K: stationary contacts stay exact), the star flux
+// F_K + S_K (U*_K - U_K) reads
+//   mass      m_K + S_K rho_K x
+//   normal    m_K u_K + p_K + S_K rho_K (S* - u_K + x S*)
+//   tangent   a_K (mass flux), b_K (mass flux)
+//   energy    (E_K + p_K) u_K + S_K (E' + x (E_K + E')),
+//             E' = rho_K (S* - u_K) (S* + p_K / (rho_K (S_K - u_K))).
 template <typename Real>
 __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real pl, Real rr, Real ur, Real ar,
                                        Real br, Real pr, Real g, Real igm1, Real Fn[5], HllcSide<Real>& side) {
@@ -237,25 +241,24 @@ __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real 
   const bool star = useL ? !(SL >= Real(0)) : (SR > Real(0));
   const Real EK = pK * igm1 + Real(0.5) * rK * (uK * uK + aK * aK + bK * bK);
   const Real mK = rK * uK;
-  const Real q = SK - uK;
+  const Real dSu = Ss - uK;
+  // rho_K (S_K - u_K) and S_K - S* (never 0 on a star face) share one
+  // reciprocal; off star faces the weights below are 0 and the reciprocal
+  // is of 1, so nothing non-finite enters
+  const Real rq = rK * (SK - uK);
   const Real dq = SK - Ss;
-  // r = q / dq (exactly 1 when S* == u_K: stationary contacts stay exact)
-  // and p_K / (rho_K q) from one reciprocal of their denominators' product
-  const Real rq = rK * q;
-  const Real inv = rcp(dq * rq);
-  const Real r = (q == dq) ? Real(1) : q * (rq * inv);
-  const Real Es = EK + rK * (Ss - uK) * (Ss + pK * (dq * inv));
+  const Real inv = rcp(star ? dq * rq : Real(1));
+  const Real x = dSu * (rq * inv);
+  const Real Ep = rK * dSu * (Ss + pK * (dq * inv));
   const Real w = star ? SK : Real(0);
-  Fn[0] = mK + w * (r * rK - rK);
-  Fn[1] = (mK * uK + pK) + w * (r * (rK * Ss) - mK);
-  Fn[2] = mK * aK + w * (r * (rK * aK) - rK * aK);
-  Fn[3] = mK * bK + w * (r * (rK * bK) - rK * bK);
-  Fn[4] = (EK + pK) * uK + w * (r * Es - EK);
+  const Real wr = w * rK;
+  Fn[0] = mK + wr * x;
+  Fn[1] = (mK * uK + pK) + wr * (dSu + x * Ss);
+  Fn[2] = aK * Fn[0];
+  Fn[3] = bK * Fn[0];
+  Fn[4] = (EK + pK) * uK + w * (Ep + x * (EK + Ep));
   side.useL = useL;
-  side.rK = rK;
-  side.mK = mK;
-  side.w = w;
-  side.r = r;
+  side.F0 = Fn[0];
 }
 
 // Unsplit half-step predictor of the primitives W0 with undivided slopes
@@ -355,7 +358,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   const int box = (active && A.tile_box) ? A.tile_box[tile] : 0;
   const double lam = A.lam_dev ? A.lam_dev[box] : A.lam_host;
   const Real h = Real(0.5 * lam);
-  const Real igm1 = Real(1.0 / (g - 1.0));
+  const Real igm1 = Real(A.igm1);
 
   // The thread's stencil-table entries for phases A and B, loaded together up
   // front: a load issued inside a round would make that round wait for every
@@ -366,12 +369,12 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     const int i = tid + NT * rnd;
-    entA[rnd] = c_st.a[i < NPOS_A ? i : 0];
+    entA[rnd] = c_st.a[uint32_t(i < NPOS_A ? i : 0)];
   }
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
-    entB[rnd] = c_st.b[i < NPOS_B ? i : 0];
+    entB[rnd] = c_st.b[uint32_t(i < NPOS_B ? i : 0)];
   }
 
   // --- phase 0: the tile's oct table (the refined bytes of its octs are
@@ -393,6 +396,16 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   // --- phase A: gather + primitives (all loads of the thread's positions are
   // issued before any conversion)
   Real* W = S.buf;                              // [NV][WSIZE]
+  // the planes' base addresses, formed in scalar registers (an empty asm on
+  // the plane offset keeps the compiler from folding it back into every
+  // per-lane address)
+  const double* Up[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    int64_t off = v * P;
+    asm volatile("" : "+s"(off));
+    Up[v] = A.U + off;
+  }
   double Ua[NRA][NV];
   int iwa[NRA];
 #pragma unroll
@@ -418,9 +431,11 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       const int32_t e = S.tab[slot];
       iwa[rnd] = int(ent & 1023u);
       if (e >= 0) {
-        const int64_t cell = int64_t(e) * 8 + cb;
+        // 32-bit cell index (octs of a level stay below 2^29): one 64-bit
+        // address per variable from the plane's base
+        const uint32_t cell = uint32_t(e) * 8u + uint32_t(cb);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Ua[rnd][v] = A.U[v * P + cell];
+        for (int v = 0; v < NV; ++v) Ua[rnd][v] = Up[v][cell];
       } else {
         // a slot no leaf update reads
         Ua[rnd][0] = 1.0; Ua[rnd][1] = 0.0; Ua[rnd][2] = 0.0; Ua[rnd][3] = 0.0; Ua[rnd][4] = 1.0;
@@ -622,12 +637,12 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] += (Fm[v] - Fp[v]);
       }
-      const int64_t cell = int64_t(e) * 8 + ci;
+      const uint32_t cell = uint32_t(e) * 8u + uint32_t(ci);
       double Un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Un[v] = A.U[v * P + cell] + lam * acc[v];
-        A.Un[v * P + cell] = Un[v];
+        Un[v] = (A.U + v * P)[cell] + lam * acc[v];
+        (A.Un + v * P)[cell] = Un[v];
       }
       if (A.tile_smax || A.err) {
         s = signal_speed(Un, g, rf, pf);

@@ -130,6 +130,7 @@ struct HydroArgs {
   int32_t substep;
   int32_t record_reg;
   double gamma, rho_floor, p_floor;
+  double igm1;                // 1 / (gamma - 1)
   const double* lam_dev;      // device lambda (per box when tile_box != nullptr)
   double lam_host;            // used when lam_dev == nullptr
   const int32_t* tile_box;
