@@ -306,7 +306,8 @@ def main():
         log(f"bench: uniform 128^3 {args.only} only")
         r = run_uniform(args.only, args.steps, args.warmup, tune, fixed)
         ms = r["kernel_ms"] / max(r["launches"], 1)
-        print(json.dumps({"precision": args.only, "cell_updates_per_s": r["cups"] * args.steps / r["dt_timed"],
+        print(json.dumps({"precision": args.only, "cell_updates_per_s": r["cups"] * args.steps / r["dt_graph"],
+                          "timed_cell_updates_per_s": r["cups"] * args.steps / r["dt_timed"],
                           "hydro_kernel_avg_ms": ms, "tuning": r["tuning"]}), flush=True)
         return
 
@@ -315,8 +316,11 @@ def main():
     log("bench: uniform 128^3 mixed")
     m = run_uniform("mixed", args.steps, args.warmup, tune, fixed)
 
-    value = f["cups"] * args.steps / f["dt_timed"]
-    ms_per_step = 1e3 * f["dt_timed"] / args.steps
+    # value: the production path (one coarse step per captured graph, no
+    # per-kernel events); the kernel average comes from the second timed run
+    # of the same steps with HIP events around every launch
+    value = f["cups"] * args.steps / f["dt_graph"]
+    ms_per_step = 1e3 * f["dt_graph"] / args.steps
     kernel_avg_ms = f["kernel_ms"] / max(f["launches"], 1)
     alg_bytes = BYTES_PER_CELL_UPDATE * f["cups"]          # one launch per coarse step
     achieved = alg_bytes / (kernel_avg_ms * 1e-3) / 1e9
@@ -327,10 +331,10 @@ def main():
                 "alg_bytes_per_launch": alg_bytes}
 
     m_kernel_ms = m["kernel_ms"] / max(m["launches"], 1)
-    mixed = {"value": m["cups"] * args.steps / m["dt_timed"], "unit": "cell-updates/s",
+    mixed = {"value": m["cups"] * args.steps / m["dt_graph"], "unit": "cell-updates/s",
              "kernel_avg_ms": round(m_kernel_ms, 5),
              "hbm_frac": round(BYTES_PER_CELL_UPDATE * m["cups"] / (m_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-             "graph_value": m["cups"] * args.steps / m["dt_graph"], "tuning": m["tuning"]}
+             "timed_value": m["cups"] * args.steps / m["dt_timed"], "tuning": m["tuning"]}
     # mixed vs fp64 after the same number of steps (both ran warmup + 2 x steps)
     mixed["vs_fp64"] = compare_forms(f["h"], m["h"], f["e0"], m["e0"])
     mixed["steps_compared"] = args.warmup + 2 * args.steps
@@ -417,7 +421,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "uniform 128^3 periodic lognormal box (262144 octs), FP64, gamma 5/3, CFL 0.8",
                    "cells": 128 ** 3, "cell_updates_per_step": f["cups"], "tuning": f["tuning"],
-                   "graph_value": f["cups"] * args.steps / f["dt_graph"], "floor_activations": f["floors"],
+                   "timed_value": f["cups"] * args.steps / f["dt_timed"], "floor_activations": f["floors"],
                    "pcie_inclusive_value": f["pcie"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -60,6 +60,7 @@ struct ry_ctx {
   ry_tuning tune{1, 0, 4, 1, 1};
   // device scalars
   double* d_smax = nullptr;               // max signal speed per level / per box
+  unsigned long long* d_slots = nullptr;  // per level: SMAX_SLOTS partial maxima of the fused CFL
   double* d_part = nullptr;               // per-tile (or per-block) partial maxima
   int64_t* d_segoff = nullptr;            // tile offsets of levels / boxes in d_part
   std::vector<int64_t> seg_off;           // host copy
@@ -75,10 +76,11 @@ struct ry_ctx {
   // subcycling order state for ry_hydro_step
   int count[RY_MAX_LEVELS] = {0};
   double dt_of[RY_MAX_LEVELS] = {0};
-  // graphs: key = parity of the base level buffer
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  std::vector<int> graph_par[2];
-  double graph_tend[2] = {0, 0};
+  // graphs of 1 and of kGraphSteps coarse steps: [steps == kGraphSteps][parity
+  // of the base level buffer]
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  std::vector<int> graph_par[2][2];
+  double graph_tend[2][2] = {{0, 0}, {0, 0}};
   // batch
   int nbox = 0;
   std::vector<int64_t> box_off, box_noct;
@@ -143,11 +145,12 @@ void free_all(ry_ctx* c) {
     else if (!c->cfg.dev_alloc) hipFree(p);
   }
   c->allocs.clear();
-  for (auto& g : c->graph)
-    if (g) {
-      hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto& gs : c->graph)
+    for (auto& g : gs)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
   if (c->bgraph) {
     hipGraphExecDestroy(c->bgraph);
     c->bgraph = nullptr;
@@ -228,6 +231,7 @@ ry_status init_common(ry_ctx* c) {
 
 ry_status alloc_scalars(ry_ctx* c, int nslot) {
   c->d_smax = static_cast<double*>(dalloc(c, sizeof(double) * nslot));
+  c->d_slots = static_cast<unsigned long long*>(dalloc(c, sizeof(unsigned long long) * nslot * SMAX_SLOTS));
   const int64_t npart = std::max<int64_t>(c->seg_off.back(), 1);
   c->d_part = static_cast<double*>(dalloc(c, sizeof(double) * npart));
   c->d_segoff = static_cast<int64_t*>(dalloc(c, sizeof(int64_t) * c->seg_off.size()));
@@ -238,12 +242,13 @@ ry_status alloc_scalars(ry_ctx* c, int nslot) {
   c->d_queue = static_cast<unsigned int*>(dalloc(c, sizeof(unsigned int) * 8));
   c->d_partial = static_cast<double*>(dalloc(c, sizeof(double) * NVMAX * totals_blocks()));
   c->d_tot = static_cast<double*>(dalloc(c, sizeof(double) * NVMAX));
-  if (!c->d_smax || !c->d_lam || !c->d_t || !c->d_flags || !c->d_floors || !c->d_queue || !c->d_partial ||
+  if (!c->d_smax || !c->d_slots || !c->d_lam || !c->d_t || !c->d_flags || !c->d_floors || !c->d_queue || !c->d_partial ||
       !c->d_tot || !c->d_part || !c->d_segoff)
     return RY_ENOMEM;
   HIPCHK(c, hipMemcpyAsync(c->d_segoff, c->seg_off.data(), sizeof(int64_t) * c->seg_off.size(),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_smax, 0, sizeof(double) * nslot, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_slots, 0, sizeof(unsigned long long) * nslot * SMAX_SLOTS, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_lam, 0, sizeof(double) * nslot, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_t, 0, sizeof(double) * nslot, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_flags, 0, sizeof(int32_t) * 8, c->stream));
@@ -289,7 +294,8 @@ void time_collect(ry_ctx* c) {
 // --- kernel enqueue helpers -------------------------------------------------
 ry_status enqueue_seg_max(ry_ctx* c) {
   const int nseg = int(c->seg_off.size()) - 1;
-  if (launch_seg_max(c->d_part, c->d_segoff, nseg, c->d_smax, c->stream)) return fail(c, RY_EHIP, "seg_max kernel");
+  if (launch_seg_max(c->d_part, c->d_segoff, nseg, c->d_smax, c->batch ? nullptr : c->d_slots, c->stream))
+    return fail(c, RY_EHIP, "seg_max kernel");
   return RY_OK;
 }
 
@@ -403,7 +409,8 @@ ry_status enqueue_level(ry_ctx* c, int l, int substep, bool last) {
   HydroArgs a = hydro_args(c, l, substep);
   a.lam_dev = c->d_lam;
   a.skip = skip_ptr(c);
-  a.tile_smax = last ? c->d_part + c->seg_off[l - c->cfg.level_min] : nullptr;
+  a.tile_smax = nullptr;
+  a.smax_bits = last ? c->d_slots + int64_t(l - c->cfg.level_min) * SMAX_SLOTS : nullptr;
   if ((s = enqueue_hydro(c, a))) return s;
   if (fine && (s = enqueue_restrict(c, l, skip_ptr(c)))) return s;
   DevLevel& L = c->lev[l - c->cfg.level_min];
@@ -413,6 +420,7 @@ ry_status enqueue_level(ry_ctx* c, int l, int substep, bool last) {
 
 ry_status enqueue_coarse_step(ry_ctx* c, double t_end) {
   FinalizeArgs f{};
+  f.slots = c->d_slots;
   f.smax = c->d_smax;
   f.nslot = c->nlev;
   f.cfl = c->cfg.cfl;
@@ -424,8 +432,6 @@ ry_status enqueue_coarse_step(ry_ctx* c, double t_end) {
   f.done = done_ptr(c);
   f.nstep = nstep_ptr(c);
   f.batch = 0;
-  ry_status s = enqueue_seg_max(c);
-  if (s) return s;
   if (launch_finalize(f, c->stream)) return fail(c, RY_EHIP, "finalize kernel");
   return enqueue_level(c, c->cfg.level_min, 0, true);
 }
@@ -473,11 +479,12 @@ ry_status upload_level_state(ry_ctx* c, DevLevel& D, const double* U_host) {
 }
 
 void drop_graphs(ry_ctx* c) {
-  for (auto& g : c->graph)
-    if (g) {
-      hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto& gs : c->graph)
+    for (auto& g : gs)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
 }
 
 }  // namespace
@@ -1112,16 +1119,24 @@ ry_status ry_hydro_step(ry_ctx* c, int32_t level, double dt) {
   return RY_OK;
 }
 
-static ry_status capture_step(ry_ctx* c, int par, double t_end) {
-  if (c->graph[par]) {
-    hipGraphExecDestroy(c->graph[par]);
-    c->graph[par] = nullptr;
+// Coarse steps per multi-step graph: even, so that every level's buffer
+// parity is back where it started after one launch.  Consecutive kernels
+// inside a graph start back to back; each graph launch costs a gap of a few
+// microseconds, paid once per kGraphSteps steps.
+constexpr int kGraphSteps = 8;
+
+static ry_status capture_step(ry_ctx* c, int multi, int par, double t_end) {
+  hipGraphExec_t& ge = c->graph[multi][par];
+  if (ge) {
+    hipGraphExecDestroy(ge);
+    ge = nullptr;
   }
   std::vector<int> saved;
   for (auto& L : c->lev) saved.push_back(L.cur);
   hipGraph_t g = nullptr;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  ry_status s = enqueue_coarse_step(c, t_end);
+  ry_status s = RY_OK;
+  for (int k = 0; k < (multi ? kGraphSteps : 1) && !s; ++k) s = enqueue_coarse_step(c, t_end);
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   for (size_t i = 0; i < c->lev.size(); ++i) c->lev[i].cur = saved[i];
   if (s) {
@@ -1129,11 +1144,11 @@ static ry_status capture_step(ry_ctx* c, int par, double t_end) {
     return s;
   }
   if (e != hipSuccess) return fail(c, RY_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&c->graph[par], g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) return fail(c, RY_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-  c->graph_par[par] = saved;
-  c->graph_tend[par] = t_end;
+  c->graph_par[multi][par] = saved;
+  c->graph_tend[multi][par] = t_end;
   return RY_OK;
 }
 
@@ -1149,17 +1164,24 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
   if (launch_zero_u32(reinterpret_cast<unsigned int*>(c->d_flags), 3, c->stream))
     return fail(c, RY_EHIP, "zero kernel");
   const bool use_graph = !c->timing;
-  for (int32_t i = 0; i < n_coarse; ++i) {
+  for (int32_t i = 0; i < n_coarse;) {
     if (use_graph) {
       const int par = c->lev[0].cur;
+      const int multi = (n_coarse - i >= kGraphSteps) ? 1 : 0;
       std::vector<int> now;
       for (auto& L : c->lev) now.push_back(L.cur);
-      if (!c->graph[par] || c->graph_par[par] != now || c->graph_tend[par] != t_end)
-        if ((s = capture_step(c, par, t_end))) return s;
-      HIPCHK(c, hipGraphLaunch(c->graph[par], c->stream));
-      c->lev[0].cur ^= 1;
-    } else if ((s = enqueue_coarse_step(c, t_end))) {
-      return s;
+      if (!c->graph[multi][par] || c->graph_par[multi][par] != now || c->graph_tend[multi][par] != t_end)
+        if ((s = capture_step(c, multi, par, t_end))) return s;
+      HIPCHK(c, hipGraphLaunch(c->graph[multi][par], c->stream));
+      if (multi) {
+        i += kGraphSteps;        // an even number of steps: parities unchanged
+      } else {
+        c->lev[0].cur ^= 1;
+        ++i;
+      }
+    } else {
+      if ((s = enqueue_coarse_step(c, t_end))) return s;
+      ++i;
     }
   }
   c->slots_valid = true;

@@ -646,7 +646,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
         Un[v] = (A.U + v * P)[cell] + lam * acc[v];
         (A.Un + v * P)[cell] = Un[v];
       }
-      if (A.tile_smax || A.err) {
+      if (A.tile_smax || A.smax_bits || A.err) {
         s = signal_speed(Un, g, rf, pf);
         const bool bad = !(isfinite(Un[0]) && isfinite(Un[1]) && isfinite(Un[2]) && isfinite(Un[3]) &&
                            isfinite(Un[4])) || !(Un[0] > 0.0) || !(Un[4] > 0.0) || !isfinite(s);
@@ -656,9 +656,15 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
         }
       }
     }
-    if (active && A.tile_smax) {
-      // one partial per tile (no same-address atomics); reduced per level /
-      // box by the segmented max kernel before the next time step
+    if (active && A.smax_bits) {
+      // one atomic maximum per tile on one of the level's slots (a
+      // non-negative double orders like its bit pattern); the maximum does
+      // not depend on the order of arrival
+      const double m = wave_max(s);
+      if (lane == 0) atomicMax(A.smax_bits + (tile & (SMAX_SLOTS - 1)), (unsigned long long)__double_as_longlong(m));
+    } else if (active && A.tile_smax) {
+      // batched boxes: one partial per tile, reduced per box by the
+      // segmented max kernel before the next time step
       const double m = wave_max(s);
       if (lane == 0) A.tile_smax[tile] = m;
     }

@@ -159,8 +159,10 @@ int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* ref
 }
 
 __global__ __launch_bounds__(1024) void seg_max_kernel(const double* __restrict__ part,
-                                                       const int64_t* __restrict__ off, double* __restrict__ out) {
+                                                       const int64_t* __restrict__ off, double* __restrict__ out,
+                                                       unsigned long long* __restrict__ slots) {
   __shared__ double red[16];
+  __shared__ double seg;
   const int64_t a = off[blockIdx.x], b = off[blockIdx.x + 1];
   // four independent accumulators per thread keep four loads in flight
   double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
@@ -178,55 +180,88 @@ __global__ __launch_bounds__(1024) void seg_max_kernel(const double* __restrict_
   if (threadIdx.x < 64) {
     m = (threadIdx.x < 16) ? red[threadIdx.x] : 0.0;
     m = wave_max(m);
-    if (threadIdx.x == 0) out[blockIdx.x] = m;
+    if (threadIdx.x == 0) {
+      out[blockIdx.x] = m;
+      seg = m;
+    }
   }
+  __syncthreads();
+  if (slots && threadIdx.x < SMAX_SLOTS)
+    slots[int64_t(blockIdx.x) * SMAX_SLOTS + threadIdx.x] =
+        threadIdx.x == 0 ? (unsigned long long)__double_as_longlong(seg) : 0ull;
 }
 
-int launch_seg_max(const double* part, const int64_t* off, int nseg, double* out, void* stream) {
+int launch_seg_max(const double* part, const int64_t* off, int nseg, double* out, unsigned long long* slots,
+                   void* stream) {
   if (nseg <= 0) return 0;
-  hipLaunchKernelGGL(seg_max_kernel, dim3(nseg), dim3(1024), 0, (hipStream_t)stream, part, off, out);
+  hipLaunchKernelGGL(seg_max_kernel, dim3(nseg), dim3(1024), 0, (hipStream_t)stream, part, off, out, slots);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // ---------------------------------------------------------------------------
 // Time step on the device: dt from the CFL slots, clipped to t_end; lambda.
 // ---------------------------------------------------------------------------
+// One thread: dt of the next coarse step from the per-level maxima; returns
+// whether that step runs (then the slots are cleared for its own maxima).
+__device__ bool finalize_dt(const FinalizeArgs& A) {
+#pragma clang fp contract(off)
+  if (*A.done) {
+    *A.skip = 1;
+    *A.lam = 0.0;
+    return false;
+  }
+  double best = INFINITY;
+  for (int k = 0; k < A.nslot; ++k) {
+    const double smax = A.smax[k];
+    if (!(smax > 0.0)) continue;
+    const double dtl = A.cfl * A.dx[k] / smax;
+    const double cand = ldexp(dtl, k);
+    if (cand < best) best = cand;
+  }
+  const double t = *A.t;
+  double dt = best;
+  int last = 0;
+  if (dt >= A.t_end - t) {
+    dt = A.t_end - t;
+    last = 1;
+  }
+  if (!(dt > 0.0)) {
+    *A.done = 1;
+    *A.skip = 1;
+    *A.lam = 0.0;
+    return false;
+  }
+  *A.lam = dt / A.dx[0];
+  *A.t = last ? A.t_end : t + dt;
+  *A.skip = 0;
+  *A.nstep += 1;
+  if (last) *A.done = 1;
+  return true;
+}
+
 __global__ void finalize_kernel(FinalizeArgs A) {
 #pragma clang fp contract(off)
   const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
   if (!A.batch) {
-    if (i != 0) return;
-    if (*A.done) {
-      *A.skip = 1;
-      *A.lam = 0.0;
-      return;
-    }
-    double best = INFINITY;
+    // one block of SMAX_SLOTS threads: each level's slots -> smax, then dt
+    __shared__ double red[SMAX_SLOTS / 64];
+    __shared__ int runs;
+    const int tid = threadIdx.x;
     for (int k = 0; k < A.nslot; ++k) {
-      const double smax = A.smax[k];
-      if (!(smax > 0.0)) continue;
-      const double dtl = A.cfl * A.dx[k] / smax;
-      const double cand = ldexp(dtl, k);
-      if (cand < best) best = cand;
+      const double v = wave_max(__longlong_as_double((long long)A.slots[int64_t(k) * SMAX_SLOTS + tid]));
+      if ((tid & 63) == 0) red[tid >> 6] = v;
+      __syncthreads();
+      if (tid == 0) {
+        double r = red[0];
+        for (int w = 1; w < SMAX_SLOTS / 64; ++w) r = fmax(r, red[w]);
+        A.smax[k] = r;
+      }
+      __syncthreads();
     }
-    const double t = *A.t;
-    double dt = best;
-    int last = 0;
-    if (dt >= A.t_end - t) {
-      dt = A.t_end - t;
-      last = 1;
-    }
-    if (!(dt > 0.0)) {
-      *A.done = 1;
-      *A.skip = 1;
-      *A.lam = 0.0;
-      return;
-    }
-    *A.lam = dt / A.dx[0];
-    *A.t = last ? A.t_end : t + dt;
-    *A.skip = 0;
-    *A.nstep += 1;
-    if (last) *A.done = 1;
+    if (tid == 0) runs = finalize_dt(A) ? 1 : 0;
+    __syncthreads();
+    if (runs)
+      for (int k = 0; k < A.nslot; ++k) A.slots[int64_t(k) * SMAX_SLOTS + tid] = 0ull;
   } else {
     if (i >= A.nslot) return;
     const double smax = A.smax[i];
@@ -239,8 +274,11 @@ __global__ void finalize_kernel(FinalizeArgs A) {
 }
 
 int launch_finalize(const FinalizeArgs& a, void* stream) {
-  const int n = a.batch ? a.nslot : 1;
-  hipLaunchKernelGGL(finalize_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a);
+  if (!a.batch) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(SMAX_SLOTS), 0, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  hipLaunchKernelGGL(finalize_kernel, dim3(unsigned((a.nslot + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

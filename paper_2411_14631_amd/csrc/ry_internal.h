@@ -15,6 +15,10 @@ namespace ry {
 constexpr int NVAR = 5;            // hydro variables; passive scalars follow them
 constexpr int NVMAX = NVAR + RY_MAX_SCALARS;
 constexpr int TILE_TAB = 64;       // 4x4x4 oct positions around a 2x2x2-oct tile
+// Slots per level of the maximum signal speed fused into the hydro update:
+// tile t takes an atomic maximum on slot t % SMAX_SLOTS, so that no single
+// address takes every tile's atomic.
+constexpr int SMAX_SLOTS = 256;
 // flux registers per oct: [face 6][variable nv][substep 2]
 constexpr int reg_per_oct(int nv) { return 6 * nv * 2; }
 
@@ -135,6 +139,9 @@ struct HydroArgs {
   double lam_host;            // used when lam_dev == nullptr
   const int32_t* tile_box;
   double* tile_smax;          // CFL epilogue: max signal speed per tile, nullptr = off
+  unsigned long long* smax_bits;  // CFL epilogue: the level's SMAX_SLOTS slots of the maximum
+                                  // signal speed (bit patterns of non-negative doubles, one
+                                  // atomic max per tile); nullptr = off (else tile_smax)
   unsigned long long* floors;
   int32_t* err;
   const int32_t* skip;        // device flag: skip this launch's work
@@ -167,9 +174,13 @@ int launch_restrict(const double* Uf, int64_t plane_f, int64_t n_fine, const int
 int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double gamma,
                double rho_floor, double p_floor, double* part, int32_t* err, void* stream);
 // out[s] = max of part[off[s] .. off[s+1])
-int launch_seg_max(const double* part, const int64_t* off, int nseg, double* out, void* stream);
+// per-segment maxima of part; with slots != nullptr also slot 0 of each
+// segment's SMAX_SLOTS slots = the maximum, the others 0
+int launch_seg_max(const double* part, const int64_t* off, int nseg, double* out, unsigned long long* slots,
+                   void* stream);
 struct FinalizeArgs {
-  const double* smax;              // per level (AMR) or per box (batch)
+  unsigned long long* slots;       // AMR: nslot x SMAX_SLOTS maxima, reduced into smax, then cleared
+  double* smax;                    // per level (AMR) or per box (batch)
   int32_t nslot;
   double cfl;
   double dx[RY_MAX_LEVELS];        // AMR: dx of each level; batch: unused

@@ -119,6 +119,29 @@ def test_amr_graph_equals_host_driven_bit_exact(ry):
         np.testing.assert_array_equal(a.download(lv), b.download(lv))
 
 
+@pytest.mark.parametrize("n", [11, 16])
+def test_multi_step_graphs_equal_eager_bit_exact(ry, n):
+    """Runs long enough to use the multi-step graphs (with a 1-step remainder
+    for n = 11) give the eager result bit for bit, and so does a run whose
+    t_end falls inside a multi-step graph."""
+    prob = cases.amr_blob(level_min=3, level_max=4)
+    a, b = ry.Hydro(prob), ry.Hydro(prob)
+    a.set_timing(True)
+    a.advance(n)
+    b.advance(n)
+    assert a.t == b.t
+    for lv in a.levels:
+        np.testing.assert_array_equal(a.download(lv), b.download(lv))
+    t_end = 0.6 * a.t
+    c, d = ry.Hydro(prob), ry.Hydro(prob)
+    c.set_timing(True)
+    c.advance(n, t_end)
+    d.advance(n, t_end)
+    assert c.t == d.t == t_end
+    for lv in c.levels:
+        np.testing.assert_array_equal(c.download(lv), d.download(lv))
+
+
 def test_amr_eager_timing_equals_graph_bit_exact(ry):
     prob = cases.amr_blob(level_min=3, level_max=4)
     a, b = ry.Hydro(prob), ry.Hydro(prob)
