@@ -269,8 +269,10 @@ bool level_nonempty(const ry_ctx* c, int l) {
 // --- timing helpers -------------------------------------------------------
 void time_begin(ry_ctx* c, const char* name, TimedLaunch& tl) {
   tl.name = name;
-  hipEventCreate(&tl.a);
-  hipEventCreate(&tl.b);
+  // timing-only events: without the system-scope fence on recording, which
+  // would write back and invalidate caches around every timed launch
+  hipEventCreateWithFlags(&tl.a, hipEventDisableSystemFence);
+  hipEventCreateWithFlags(&tl.b, hipEventDisableSystemFence);
   hipEventRecord(tl.a, c->stream);
 }
 void time_end(ry_ctx* c, TimedLaunch& tl) {
@@ -1443,8 +1445,8 @@ static ry_status time_tuning(ry_ctx* c, const ry_tuning& t, double* ms_out) {
   ry_tuning saved = c->tune;
   c->tune = t;
   hipEvent_t a, b;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
+  hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
+  hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
   double best = INFINITY;
   ry_status s = RY_OK;
   for (int rep = 0; rep < 4 && !s; ++rep) {
@@ -1557,8 +1559,8 @@ ry_status ry_copy_probe(ry_ctx* c, size_t bytes, int32_t reps, double* ms) {
   const int64_t n = int64_t(bytes / sizeof(double));
   launch_copy(a, b, n, c->stream);
   hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+  hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
   hipEventRecord(e0, c->stream);
   for (int i = 0; i < reps; ++i) launch_copy(a, b, n, c->stream);
   hipEventRecord(e1, c->stream);

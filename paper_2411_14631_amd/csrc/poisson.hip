@@ -467,8 +467,9 @@ ry_status launch_iteration(ry_poisson* p, bool finalize_only = false) {
   }
   if (p->timing) {
     hipEvent_t a, b;
-    PCHK(p, hipEventCreate(&a));
-    PCHK(p, hipEventCreate(&b));
+    // timing-only events: no system-scope fence (cache write-back) on recording
+    PCHK(p, hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+    PCHK(p, hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
     PCHK(p, hipEventRecord(a, p->stream));
     p->ev.push_back({a, b});
   }
