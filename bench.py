@@ -289,7 +289,7 @@ def main():
                     help="first launch a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on exactly one GPU (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design only", file=sys.stderr)
         sys.exit(2)
     import torch

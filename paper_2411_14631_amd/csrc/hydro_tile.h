@@ -704,7 +704,9 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       }
     }
   }
-  if (active && A.floors) {
+  // floor activations are rare: the shuffle sum runs only in a wavefront
+  // that has any
+  if (active && A.floors && __any(nfl != 0)) {
     const int tot = wave_sum(nfl);
     if (lane == 0 && tot) atomicAdd(A.floors, (unsigned long long)tot);
   }
