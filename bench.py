@@ -387,6 +387,28 @@ def main():
         del handles, z, h
         torch.cuda.empty_cache()
 
+    # two-level AMR: 64^3 base under the 128^3 field, gradient criterion at
+    # the primary threshold (about a quarter refined) and at the literal 0.1
+    twolevel = None
+    if not args.no_zoom:
+        import workloads as W
+        twolevel = {}
+        for theta in (0.70, 0.1):
+            tprob = W.twolevel(128, theta)
+            entry = {}
+            for prec in ("fp64", "mixed"):
+                log(f"bench: two-level AMR theta {theta} {prec}")
+                z = run_zoom(tprob, prec, 3, tune)
+                entry[prec] = {"value": z["cups"] * 3 / z["dt"], "unit": "cell-updates/s",
+                               "hbm_frac": round(BYTES_PER_CELL_UPDATE * z["cups"] * 3 / z["dt"] / 1e9 / HBM_PEAK_GBS,
+                                                 4),
+                               "cell_updates_per_coarse_step": z["cups"], "octs": z["noct"],
+                               "ms_per_coarse_step": round(1e3 * z["dt"] / 3, 3), "floor_activations": z["floors"]}
+                entry["levels"] = {str(k): v for k, v in z["levels"].items()}
+                del z
+            twolevel[f"theta_{theta}"] = entry
+        torch.cuda.empty_cache()
+
     batch = None
     if not args.no_zoom:
         import workloads as W
@@ -436,6 +458,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "zoom_amr": zoom,
+        "twolevel_amr": twolevel,
         "batch_boxes": batch,
         "passive_scalars": scalars,
         "poisson": poisson,
