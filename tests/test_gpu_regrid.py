@@ -175,3 +175,23 @@ def test_zoom_full_size_device_regrid_matches_host_path(ry):
     a.advance(1)
     b.advance(1)
     same_mesh_and_state(a, b)
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.3])
+def test_gradient_criterion_regrid_matches_oracle(ry, theta):
+    """Regrid under the gradient criterion (the two-level mesh's rule: the
+    device flag kernel's neighbour-difference branch) after two coarse
+    steps, and a threshold change, against the oracle: identical meshes and
+    counts, states within the parity bar."""
+    prob = W.twolevel(32, theta)
+    g, o = ry.Hydro(prob), Oracle(prob)
+    step_both(g, o, 2)
+    counts = g.regrid()
+    assert counts == o.regrid()
+    compare(g, o)
+    g.set_refine_param(0.8 * theta)
+    o.set_refine_param(0.8 * theta)
+    assert g.regrid() == o.regrid()
+    compare(g, o)
+    step_both(g, o, 1)
+    compare(g, o)
