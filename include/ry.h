@@ -119,7 +119,8 @@ ry_status ry_advance(ry_ctx* ctx, int32_t n_coarse, double t_end, double* t_io);
  * bottom-up.  By default every step runs on the device (flags, child
  * levels, state remap, tile tables, ghost octs); only counts cross PCIe.
  * RY_ESTATE inside a coarse step; RY_EINVAL (mesh unchanged) if a source
- * the neighbour rule guarantees is missing.  Counts of created / destroyed
+ * the neighbour rule guarantees is missing or, on the device path, a level
+ * reaches 2^28 octs (its counts are 32-bit).  Counts of created / destroyed
  * octs (either may be NULL).  Syncs. */
 ry_status ry_regrid(ry_ctx* ctx, int64_t* n_created, int64_t* n_destroyed);
 /* on = 0: later regrids evaluate flags and build tables on the host from

@@ -865,6 +865,9 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
       if (k + 1 < nl) destroyed += c->lev[k + 1].n_oct;
       continue;
     }
+    // the device regrid counts cells (8 per oct) and tile slots (64 per tile)
+    // in 32-bit integers
+    RG_TRY(L.n < (int64_t(1) << 28), RY_EINVAL, "level too large for the device regrid (use the host path)");
     const LevelView V = view(k);
     if (k > 0) {
       // tiles: octs sharing key >> 3
