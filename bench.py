@@ -197,8 +197,27 @@ def cpu_baseline(budget_s=12.0):
         if el > budget_s or n >= 100:
             break
     cups = 128 ** 3 * n / el
+    # the same oracle on one thread, a few steps
+    lib().ryo_set_num_threads(1)
+    n1 = 0
+    t0 = time.perf_counter()
+    while True:
+        o.advance(1)
+        n1 += 1
+        el1 = time.perf_counter() - t0
+        if el1 > budget_s / 2 or n1 >= 20:
+            break
+    lib().ryo_set_num_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": cups, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"uniform 128^3 periodic box, {n} whole coarse steps ({el:.1f} s wall)"}
+            "sample": f"uniform 128^3 periodic box, {n} whole coarse steps ({el:.1f} s wall)"
+                      + (f" on {model}" if model else ""),
+            "value_one_thread": 128 ** 3 * n1 / el1}
 
 
 def run_scalars(nscalar=2, steps=10, warmup=2):
