@@ -305,20 +305,31 @@ def test_numeric_fault_latched(ry):
 
 
 # ------------------------------------------------------- full-size cases
-def test_uniform128_full_size_two_steps(ry):
+def test_uniform128_full_size_config_steps(ry):
+    """The 128^3 box over its configuration's 10 steps (each side with its
+    own dt), checked after the first step and accumulated after the tenth."""
     prob = W.uniform(128)
     g, o = ry.Hydro(prob), Oracle(prob)
-    g.advance(2)
-    o.advance(2)
+    g.advance(1)
+    o.advance(1)
+    compare_levels(g, o)
+    g.advance(prob.n_steps - 1)
+    o.advance(prob.n_steps - 1)
+    assert abs(g.t - o.t) <= 1e-13 * o.t
     compare_levels(g, o)
 
 
-def test_twolevel128_full_size_one_coarse_step(ry):
+def test_twolevel128_full_size_config_steps(ry):
+    """The two-level mesh (theta 0.70) over its 10 coarse steps."""
     prob = W.twolevel(128, 0.70)
     g, o = ry.Hydro(prob), Oracle(prob)
     assert g.level_info(7)[0] == 65018
     g.advance(1)
     o.advance(1)
+    compare_levels(g, o)
+    g.advance(prob.n_steps - 1)
+    o.advance(prob.n_steps - 1)
+    assert abs(g.t - o.t) <= 1e-13 * o.t
     compare_levels(g, o)
 
 
