@@ -57,39 +57,65 @@ int launch_hydro(const HydroArgs& a, int precision, int nscalar, const ry_tuning
 // Ghost octs: MinMod-limited linear interpolation of the covering coarse
 // cell's conserved variables, written into both state buffers.
 // ---------------------------------------------------------------------------
+// One thread per ghost oct: its 8 cells are the children of one coarse cell
+// Q and share Q's 7 sources, loaded once (NV, the variable count, is a
+// template parameter so that all 7 x NV loads issue before the first use);
+// each variable's 8 results go out as four 16-byte stores per buffer.
+template <int NV>
 __global__ void ghost_kernel(GhostArgs A) {
   if (A.skip && *A.skip) return;
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= A.n_ghost * 8) return;
-  const int64_t gi = i >> 3;
-  const int c = int(i & 7);
-  const double sx = (c & 1) ? 0.25 : -0.25, sy = (c & 2) ? 0.25 : -0.25, sz = (c & 4) ? 0.25 : -0.25;
-  int64_t src[7];
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi >= A.n_ghost) return;
+  const double* base[7];
+  int64_t cell[7], pl[7];
 #pragma unroll
-  for (int k = 0; k < 7; ++k) src[k] = A.gsrc[gi * 7 + k];
-  const int64_t dst = (A.n_oct + gi) * 8 + c;
-  for (int v = 0; v < A.nv; ++v) {
-    double val[7];
+  for (int k = 0; k < 7; ++k) {
+    const int64_t src = A.gsrc[gi * 7 + k];
+    const int up = int(src >> 48);
+    cell[k] = src & ((int64_t(1) << 48) - 1);
+    base[k] = A.src[up];
+    pl[k] = A.src_plane[up];
+  }
+  double val[NV][7];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      const int up = int(src[k] >> 48);
-      const int64_t cell = src[k] & ((int64_t(1) << 48) - 1);
-      val[k] = A.src[up][v * A.src_plane[up] + cell];
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int k = 0; k < 7; ++k) val[v][k] = base[k][v * pl[k] + cell[k]];
+  const int64_t dst = (A.n_oct + gi) * 8;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double q = val[v][0];
+    const double mx = mmod(q - val[v][1], val[v][2] - q);
+    const double my = mmod(q - val[v][3], val[v][4] - q);
+    const double mz = mmod(q - val[v][5], val[v][6] - q);
+    double out[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double sx = (c & 1) ? 0.25 : -0.25, sy = (c & 2) ? 0.25 : -0.25, sz = (c & 4) ? 0.25 : -0.25;
+      out[c] = q + (sx * mx + sy * my + sz * mz);
     }
-    const double q = val[0];
-    const double mx = mmod(q - val[1], val[2] - q);
-    const double my = mmod(q - val[3], val[4] - q);
-    const double mz = mmod(q - val[5], val[6] - q);
-    const double out = q + (sx * mx + sy * my + sz * mz);
-    A.dst0[v * A.plane + dst] = out;
-    A.dst1[v * A.plane + dst] = out;
+    double2* d0 = reinterpret_cast<double2*>(A.dst0 + v * A.plane + dst);
+    double2* d1 = reinterpret_cast<double2*>(A.dst1 + v * A.plane + dst);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      d0[j] = make_double2(out[2 * j], out[2 * j + 1]);
+      d1[j] = make_double2(out[2 * j], out[2 * j + 1]);
+    }
   }
 }
 
 int launch_ghost(const GhostArgs& a, void* stream) {
   if (a.n_ghost == 0) return 0;
-  const int64_t n = a.n_ghost * 8;
-  hipLaunchKernelGGL(ghost_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a);
+  const dim3 grid(unsigned((a.n_ghost + 127) / 128)), block(128);
+  hipStream_t s = (hipStream_t)stream;
+  switch (a.nv) {
+    case 5: hipLaunchKernelGGL(ghost_kernel<5>, grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(ghost_kernel<6>, grid, block, 0, s, a); break;
+    case 7: hipLaunchKernelGGL(ghost_kernel<7>, grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL(ghost_kernel<8>, grid, block, 0, s, a); break;
+    case 9: hipLaunchKernelGGL(ghost_kernel<9>, grid, block, 0, s, a); break;
+    default: return -1;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
