@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_ISSUE = 1024 * 2.4e9 / 4      # 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles
 BYTES_PER_CELL_UPDATE = 80
 METRIC = "hydro cell-updates/s (FP64 vs mixed FP32) + % HBM roofline, 128^3 and zoom AMR"
 
@@ -47,18 +48,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload_key):
-    """HBM bytes per hydro launch measured with rocprofv3 counters, if they
-    were taken on the current kernel source (else None)."""
+def profiled_counters(workload_key):
+    """rocprofv3 counter figures per hydro launch (HBM bytes, VALU
+    instructions), if they were taken on the current kernel source (else {})."""
     path = os.path.join(ROOT, "profiles", "hydro_traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
         d = json.load(f)
     e = d.get(workload_key)
     if not e or e.get("kernel_hash") != kernel_source_hash():
-        return None
-    return e.get("bytes_per_launch")
+        return {}
+    return e
+
+
+def traffic_from_profiles(workload_key):
+    """HBM bytes per hydro launch measured with rocprofv3 counters (or None)."""
+    return profiled_counters(workload_key).get("bytes_per_launch")
 
 
 def time_advance(h, steps, warmup, timing):
@@ -354,6 +360,15 @@ def main():
     alg_bytes = BYTES_PER_CELL_UPDATE * f["cups"]          # one launch per coarse step
     achieved = alg_bytes / (kernel_avg_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles("uniform128_fp64")
+    # VALU issue: wave64 instructions per launch (profiled counter) over the
+    # live kernel time, against 1,024 SIMDs x 2.4 GHz / 4 cycles per wave64
+    # instruction
+    valu_insts = profiled_counters("uniform128_fp64").get("valu_insts_per_launch")
+    valu = None
+    if valu_insts:
+        rate = valu_insts / (kernel_avg_ms * 1e-3)
+        valu = {"unit": "wave64 VALU instructions/s", "instructions_per_launch": valu_insts,
+                "achieved": round(rate, -6), "peak": VALU_PEAK_ISSUE, "frac": round(rate / VALU_PEAK_ISSUE, 4)}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "hydro_kernel<double>", "kernel_avg_ms": round(kernel_avg_ms, 5),
@@ -475,6 +490,7 @@ def main():
                    "timed_value": f["cups"] * args.steps / f["dt_timed"], "floor_activations": f["floors"],
                    "pcie_inclusive_value": f["pcie"]},
         "roofline": roofline,
+        "valu_issue": valu,
         "cpu_baseline": cpu,
         "mixed": mixed,
         "zoom_amr": zoom,
