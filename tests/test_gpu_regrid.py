@@ -195,3 +195,20 @@ def test_gradient_criterion_regrid_matches_oracle(ry, theta):
     compare(g, o)
     step_both(g, o, 1)
     compare(g, o)
+
+
+def test_regrid_between_multi_step_graph_runs(ry):
+    """Runs long enough for the 8-step graphs, a regrid that reallocates
+    every refined level, and another such run: the graphs captured on the
+    old mesh are dropped (same result as the eager path on both meshes)."""
+    prob = cases.amr_blob()
+    a, b = ry.Hydro(prob), ry.Hydro(prob)
+    a.set_timing(True)
+    for h in (a, b):
+        h.advance(9)
+        h.regrid()
+        h.advance(9)
+    assert a.t == b.t
+    for lv in a.levels:
+        assert a.level_info(lv) == b.level_info(lv)
+        np.testing.assert_array_equal(a.download(lv), b.download(lv))
