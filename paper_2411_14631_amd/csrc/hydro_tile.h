@@ -408,6 +408,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     asm volatile("" : "+s"(off));
     Up[v] = A.U + off;
   }
+  const bool off32 = P <= (int64_t(1) << 29);
   double Ua[NRA][NV];
   int iwa[NRA];
 #pragma unroll
@@ -432,15 +433,20 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       }
       const int32_t e = S.tab[slot];
       iwa[rnd] = int(ent & 1023u);
-      if (e >= 0) {
-        // 32-bit cell index (octs of a level stay below 2^29): one 64-bit
-        // address per variable from the plane's base
-        const uint32_t cell = uint32_t(e) * 8u + uint32_t(cb);
+      // 32-bit cell index (octs of a level stay below 2^29).  A slot without
+      // an oct is one no leaf update reads: it takes the (valid, finite)
+      // state of the level's first cell instead of a branch
+      const uint32_t cell = (e >= 0) ? uint32_t(e) * 8u + uint32_t(cb) : 0u;
+      if (off32) {
+        // planes under 4 GiB: one 32-bit byte offset serves every plane
+        // (base in scalar registers + unsigned 32-bit lane offset)
+        const uint32_t boff = cell << 3;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          Ua[rnd][v] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(Up[v]) + boff);
+      } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ua[rnd][v] = Up[v][cell];
-      } else {
-        // a slot no leaf update reads
-        Ua[rnd][0] = 1.0; Ua[rnd][1] = 0.0; Ua[rnd][2] = 0.0; Ua[rnd][3] = 0.0; Ua[rnd][4] = 1.0;
       }
     }
   }
@@ -600,7 +606,14 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     const bool leaf = (e >= 0) && (e < A.n_oct) && !((S.ref[ts] >> ci) & 1);
     double s = 0.0;
     if (leaf) {
-      double acc[NV] = {};
+      // the cell's old state is loaded first: the stores to the new state
+      // below may alias it as far as the compiler knows, and a load issued
+      // after a store would wait for it
+      const uint32_t cell = uint32_t(e) * 8u + uint32_t(ci);
+      double Uo[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Uo[v] = (A.U + v * P)[cell];
+      double acc[NV];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         // the lower face's flux is the thread's own (phase C), the upper
@@ -637,13 +650,12 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
           }
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] += (Fm[v] - Fp[v]);
+        for (int v = 0; v < NV; ++v) acc[v] = (d == 0) ? (Fm[v] - Fp[v]) : acc[v] + (Fm[v] - Fp[v]);
       }
-      const uint32_t cell = uint32_t(e) * 8u + uint32_t(ci);
       double Un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Un[v] = (A.U + v * P)[cell] + lam * acc[v];
+        Un[v] = Uo[v] + lam * acc[v];
         (A.Un + v * P)[cell] = Un[v];
       }
       if (A.tile_smax || A.smax_bits || A.err) {
