@@ -142,10 +142,14 @@ ry_status ry_upload(ry_ctx* ctx, int32_t level, const double* U);
 
 /* Batched independent boxes (single level, periodic or outflow each):
  * cfgs[b] describes box b (level_min == level_max), U0[b] its field as for
- * ry_amr_build.  All boxes share one tile list and one work queue. */
+ * ry_amr_build.  All boxes share one tile list (and, with a persistent
+ * tuning, one work queue).  Default tuning {1, 0, 4, 1, 1}; ry_autotune
+ * picks among the plain and the persistent queue-fed launches. */
 ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* const* U0, ry_ctx** out);
 /* nsteps steps of every box, each box with its own CFL dt computed on the
- * device, as one captured graph of persistent queue-fed launches.  Syncs. */
+ * device, as one captured graph (reused while nsteps and the state parity
+ * repeat) of one hydro launch per step over the tiles of all boxes.
+ * Syncs. */
 ry_status ry_batch_run(ry_ctx* ctx, int32_t nsteps);
 ry_status ry_batch_box_info(const ry_ctx* ctx, int32_t box, int64_t* n_oct, double* t);
 ry_status ry_batch_download(ry_ctx* ctx, int32_t box, double* U);

@@ -1254,7 +1254,10 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
   c->batch = true;
   c->nlev = 1;
   c->nbox = nbox;
-  c->tune = ry_tuning{1, 1, 14, 4, 2};
+  // the plain launch (one wavefront per tile, the hardware dispatcher as the
+  // queue) measures fastest for batches too; the queue-fed persistent
+  // kernel stays an autotuner candidate
+  c->tune = ry_tuning{1, 0, 4, 1, 1};
   ry_status s = init_common(c);
   if (s) {
     delete c;

@@ -347,6 +347,31 @@ def test_zoom_full_size_one_coarse_step(ry):
     assert g.floors() == 0
 
 
+def test_batch_tunings_bit_exact(ry):
+    """The batched launch is independent of its tuning: the plain launch and
+    the persistent queue-fed kernel (several grid sizes, queue batches and
+    waves per tile) give bit-identical boxes, and the autotuner leaves the
+    state untouched."""
+    boxes = [W.batch_box(4, 16, 1.2, 1.5), W.batch_box(5, 32, 0.8, 2.0), W.batch_box(6, 24, 1.0, 0.5)]
+    ref = None
+    for t in ([1, 0, 4, 1, 1], [1, 1, 14, 4, 2], [1, 1, 8, 1, 1], [2, 1, 20, 4, 1], [1, 0, 4, 1, 4], None):
+        bh = ry.BatchHydro(boxes)
+        if t is None:
+            best, times = bh.autotune()
+            assert len(times) >= 4 and all(x > 0 for x in times)
+            assert bh.tuning() == best
+        else:
+            bh.set_tuning(*t)
+        bh.run(3)
+        out = [bh.download(b) for b in range(len(boxes))]
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(out, ref):
+                np.testing.assert_array_equal(a, b)
+        bh.close()
+
+
 def test_batch512_full_size_sampled_boxes(ry):
     """All 512 uneven boxes advanced together 20 steps; 16 boxes spread over
     the list are recomputed one by one by the oracle."""
