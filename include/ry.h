@@ -84,7 +84,9 @@ void ry_destroy(ry_ctx* ctx);
  * nbase[0]*nbase[1]*nbase[2] values, x fastest): refinement flags by the
  * configured criterion on leaf cells, the neighbour rule (a cell is refined
  * only when its 26 neighbours exist at its level), Hilbert ordering, values
- * of new cells from `fill`, restriction of refined cells, upload.  Syncs. */
+ * of new cells from `fill`, restriction of refined cells, upload.
+ * RY_EINVAL if a level's octs plus ghost octs reach 2^29 (the kernels index
+ * a level's cells in 32 bits).  Syncs. */
 ry_status ry_amr_build(ry_ctx* ctx, const double* U_base, ry_fill_fn fill, void* user);
 
 ry_status ry_level_info(const ry_ctx* ctx, int32_t level, int64_t* n_oct, int64_t* n_leaf_cells);
@@ -119,8 +121,9 @@ ry_status ry_advance(ry_ctx* ctx, int32_t n_coarse, double t_end, double* t_io);
  * bottom-up.  By default every step runs on the device (flags, child
  * levels, state remap, tile tables, ghost octs); only counts cross PCIe.
  * RY_ESTATE inside a coarse step; RY_EINVAL (mesh unchanged) if a source
- * the neighbour rule guarantees is missing or, on the device path, a level
- * reaches 2^28 octs (its counts are 32-bit).  Counts of created / destroyed
+ * the neighbour rule guarantees is missing, a level's octs plus ghost octs
+ * would reach 2^29, or, on the device path, a level reaches 2^28 octs or
+ * 2^25 tiles (its counts are 32-bit).  Counts of created / destroyed
  * octs (either may be NULL).  Syncs. */
 ry_status ry_regrid(ry_ctx* ctx, int64_t* n_created, int64_t* n_destroyed);
 /* on = 0: later regrids evaluate flags and build tables on the host from
@@ -144,7 +147,8 @@ ry_status ry_upload(ry_ctx* ctx, int32_t level, const double* U);
  * cfgs[b] describes box b (level_min == level_max), U0[b] its field as for
  * ry_amr_build.  All boxes share one tile list (and, with a persistent
  * tuning, one work queue).  Default tuning {1, 0, 4, 1, 1}; ry_autotune
- * picks among the plain and the persistent queue-fed launches. */
+ * picks among the plain and the persistent queue-fed launches.  RY_EINVAL
+ * if the boxes' octs together reach 2^29. */
 ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* const* U0, ry_ctx** out);
 /* nsteps steps of every box, each box with its own CFL dt computed on the
  * device, as one captured graph (reused while nsteps and the state parity

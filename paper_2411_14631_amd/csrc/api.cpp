@@ -845,8 +845,9 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
   int32_t* d_err = static_cast<int32_t*>(A(sizeof(int32_t), true));
   RG_TRY(ok && hipMemsetAsync(d_err, 0, sizeof(int32_t), st) == hipSuccess, RY_ENOMEM, "allocation failed");
 
-  {  // level lmin keeps its octs and tile tables
+  {  // level lmin keeps its octs and tile tables (a complete level: no ghost octs)
     const DevLevel& D = c->lev[0];
+    RG_TRY(D.n_ghost == 0, RY_EINVAL, "base level with ghost octs");
     N[0].n = D.n_oct;
     N[0].key = D.dkey;
     N[0].oc = D.doc;
@@ -877,6 +878,8 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
       int64_t nt = 0;
       RG_TRY(!launch_tile_starts(L.key, L.n, start, st) && scan_total(start, tid, L.n, nt), RY_EHIP,
              "tile kernels");
+      RG_TRY(nt * TILE_TAB < (int64_t(1) << 31), RY_EINVAL,
+             "level too large for the device regrid (use the host path)");
       L.n_tile = int32_t(nt);
       int32_t* first = static_cast<int32_t*>(A(sizeof(int32_t) * (nt + 1), true));
       const int64_t nslot = nt * TILE_TAB;
@@ -928,6 +931,7 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
       }
       // state: kept octs copied, new octs interpolated from level l-1
       const int64_t n_ext = L.n + L.n_ghost;
+      RG_TRY(n_ext < (int64_t(1) << 29), RY_EINVAL, "level octs + ghost octs reach 2^29 (cells are indexed in 32 bits)");
       for (int b = 0; b < 2; ++b) L.U[b] = static_cast<double*>(A(sizeof(double) * nv * 8 * n_ext, false));
       L.reg = static_cast<double*>(A(sizeof(double) * L.n * reg_per_oct(nv), false));
       RG_TRY(ok, RY_ENOMEM, "allocation failed");
@@ -1298,6 +1302,10 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
   }
   all.n_oct = off;
   all.n_tile = int32_t(all.tflag.size());
+  if (off >= (int64_t(1) << 29)) {
+    ry_destroy(c);
+    return RY_EINVAL;                  // cells are indexed in 32 bits
+  }
   all.refined_ext.assign(off, 0);
   c->lev.assign(1, DevLevel());
   DevLevel& D = c->lev[0];
