@@ -491,9 +491,22 @@ void drop_graphs(ry_ctx* c) {
 
 }  // namespace
 
+// No C++ exception crosses the C ABI: a failed host allocation inside an
+// entry point becomes RY_ENOMEM, any other exception RY_EINVAL.
+#define RY_ABI_TRY try {
+#define RY_ABI_CATCH                    \
+  }                                     \
+  catch (const std::bad_alloc&) {       \
+    return RY_ENOMEM;                   \
+  }                                     \
+  catch (...) {                         \
+    return RY_EINVAL;                   \
+  }
+
 extern "C" {
 
 ry_status ry_create(const ry_config* cfg, ry_ctx** out) {
+  RY_ABI_TRY
   if (!out) return RY_EINVAL;
   *out = nullptr;
   ry_status s = validate(cfg, false);
@@ -509,6 +522,7 @@ ry_status ry_create(const ry_config* cfg, ry_ctx** out) {
   }
   *out = c;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 void ry_destroy(ry_ctx* c) {
@@ -525,6 +539,7 @@ void ry_destroy(ry_ctx* c) {
 const char* ry_last_error(const ry_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* user) {
+  RY_ABI_TRY
   if (!c || !U_base || c->batch) return RY_EINVAL;
   if (c->cfg.level_max > c->cfg.level_min && c->cfg.refine != RY_REFINE_NONE && !fill)
     return fail(c, RY_EINVAL, "fill callback required when level_max > level_min");
@@ -575,13 +590,16 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
   c->host_valid = true;
   c->built = true;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_set_refine_param(ry_ctx* c, double value) {
+  RY_ABI_TRY
   if (!c || c->batch || std::isnan(value)) return RY_EINVAL;
   c->cfg.refine_param = value;
   c->dom.refine_param = value;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 }  // extern "C"
@@ -1043,12 +1061,15 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
 extern "C" {
 
 ry_status ry_set_regrid_device(ry_ctx* c, int32_t on) {
+  RY_ABI_TRY
   if (!c || c->batch) return RY_EINVAL;
   c->regrid_device = on != 0;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
+  RY_ABI_TRY
   if (!c || c->batch) return RY_EINVAL;
   if (!c->built) return fail(c, RY_ESTATE, "not built");
   for (int k = 0; k < c->nlev; ++k)
@@ -1056,17 +1077,21 @@ ry_status ry_regrid(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
   ry_status s = sync_and_check(c);
   if (s) return s;
   return c->regrid_device ? regrid_device(c, n_created, n_destroyed) : regrid_host(c, n_created, n_destroyed);
+  RY_ABI_CATCH
 }
 
 ry_status ry_level_info(const ry_ctx* c, int32_t level, int64_t* n_oct, int64_t* n_leaf) {
+  RY_ABI_TRY
   if (!c || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
   const DevLevel& D = c->lev[level - c->cfg.level_min];
   if (n_oct) *n_oct = D.n_oct;
   if (n_leaf) *n_leaf = D.n_leaf;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_get_mesh(const ry_ctx* c, int32_t level, uint64_t* keys, uint8_t* refined) {
+  RY_ABI_TRY
   if (!c || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
   const DevLevel& D = c->lev[level - c->cfg.level_min];
   if (!D.n_oct) return RY_OK;
@@ -1074,9 +1099,11 @@ ry_status ry_get_mesh(const ry_ctx* c, int32_t level, uint64_t* keys, uint8_t* r
   if (keys && hipMemcpy(keys, D.dkey, sizeof(uint64_t) * D.n_oct, hipMemcpyDeviceToHost) != hipSuccess) return RY_EHIP;
   if (refined && hipMemcpy(refined, D.refined, D.n_oct, hipMemcpyDeviceToHost) != hipSuccess) return RY_EHIP;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_cfl_dt(ry_ctx* c, double* dt) {
+  RY_ABI_TRY
   if (!c || !dt || !c->built || c->batch) return RY_EINVAL;
   ry_status s = enqueue_cfl_all(c);
   if (s) return s;
@@ -1093,9 +1120,11 @@ ry_status ry_cfl_dt(ry_ctx* c, double* dt) {
   }
   *dt = best;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_hydro_step(ry_ctx* c, int32_t level, double dt) {
+  RY_ABI_TRY
   if (!c || c->batch) return RY_EINVAL;
   if (!c->built) return fail(c, RY_ESTATE, "not built");
   if (!(dt > 0.0) || !std::isfinite(dt) || !level_nonempty(c, level)) return fail(c, RY_EINVAL, "bad level or dt");
@@ -1126,6 +1155,7 @@ ry_status ry_hydro_step(ry_ctx* c, int32_t level, double dt) {
   c->slots_valid = false;
   drop_graphs(c);
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 // Coarse steps per multi-step graph: even, so that every level's buffer
@@ -1162,6 +1192,7 @@ static ry_status capture_step(ry_ctx* c, int multi, int par, double t_end) {
 }
 
 ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
+  RY_ABI_TRY
   if (!c || !t_io || c->batch || n_coarse < 0) return RY_EINVAL;
   if (!c->built) return fail(c, RY_ESTATE, "not built");
   for (int k = 1; k < c->nlev; ++k)
@@ -1197,9 +1228,11 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
   if ((s = sync_and_check(c))) return s;
   HIPCHK(c, hipMemcpy(t_io, c->d_t, sizeof(double), hipMemcpyDeviceToHost));
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_conserved_totals(ry_ctx* c, double* tot) {
+  RY_ABI_TRY
   if (!c || !tot || !c->built || c->batch) return RY_EINVAL;
   const int nb = totals_blocks();
   const int nv = c->dom.nv;
@@ -1217,18 +1250,22 @@ ry_status ry_conserved_totals(ry_ctx* c, double* tot) {
   if (s) return s;
   HIPCHK(c, hipMemcpy(tot, c->d_tot, sizeof(double) * nv, hipMemcpyDeviceToHost));
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_download(ry_ctx* c, int32_t level, double* U) {
+  RY_ABI_TRY
   if (!c || !U || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
   DevLevel& D = c->lev[level - c->cfg.level_min];
   for (int v = 0; v < c->dom.nv && D.n_oct; ++v)
     HIPCHK(c, hipMemcpyAsync(U + size_t(v) * 8 * D.n_oct, D.U[D.cur] + v * D.plane(), sizeof(double) * 8 * D.n_oct,
                              hipMemcpyDeviceToHost, c->stream));
   return sync_and_check(c);
+  RY_ABI_CATCH
 }
 
 ry_status ry_upload(ry_ctx* c, int32_t level, const double* U) {
+  RY_ABI_TRY
   if (!c || !U || !c->built || c->batch || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
   DevLevel& D = c->lev[level - c->cfg.level_min];
   if (!D.n_oct) return RY_OK;
@@ -1238,10 +1275,12 @@ ry_status ry_upload(ry_ctx* c, int32_t level, const double* U) {
   if ((s = enqueue_cfl_all(c))) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 // --------------------------------------------------------------- batching
 ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* const* U0, ry_ctx** out) {
+  RY_ABI_TRY
   if (!out || !cfgs || !U0 || nbox <= 0) return RY_EINVAL;
   *out = nullptr;
   for (int b = 0; b < nbox; ++b) {
@@ -1343,6 +1382,7 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
   c->built = true;
   *out = c;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 static ry_status enqueue_batch_step(ry_ctx* c) {
@@ -1375,6 +1415,7 @@ static ry_status enqueue_batch_step(ry_ctx* c) {
 }
 
 ry_status ry_batch_run(ry_ctx* c, int32_t nsteps) {
+  RY_ABI_TRY
   if (!c || !c->batch || !c->built || nsteps < 0) return RY_EINVAL;
   ry_status s;
   if (!c->slots_valid && (s = enqueue_cfl_all(c))) return s;
@@ -1410,16 +1451,20 @@ ry_status ry_batch_run(ry_ctx* c, int32_t nsteps) {
   }
   c->slots_valid = true;
   return sync_and_check(c);
+  RY_ABI_CATCH
 }
 
 ry_status ry_batch_box_info(const ry_ctx* c, int32_t box, int64_t* n_oct, double* t) {
+  RY_ABI_TRY
   if (!c || !c->batch || box < 0 || box >= c->nbox) return RY_EINVAL;
   if (n_oct) *n_oct = c->box_noct[box];
   if (t && hipMemcpy(t, c->d_t + box, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return RY_EHIP;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_batch_download(ry_ctx* c, int32_t box, double* U) {
+  RY_ABI_TRY
   if (!c || !c->batch || !U || box < 0 || box >= c->nbox) return RY_EINVAL;
   DevLevel& D = c->lev[0];
   const int64_t n = c->box_noct[box];
@@ -1427,10 +1472,12 @@ ry_status ry_batch_download(ry_ctx* c, int32_t box, double* U) {
     HIPCHK(c, hipMemcpyAsync(U + size_t(v) * 8 * n, D.U[D.cur] + v * D.plane() + c->box_off[box] * 8,
                              sizeof(double) * 8 * n, hipMemcpyDeviceToHost, c->stream));
   return sync_and_check(c);
+  RY_ABI_CATCH
 }
 
 // ---------------------------------------------------------------- tuning
 ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
+  RY_ABI_TRY
   if (!c || !t) return RY_EINVAL;
   if (t->tiles_per_wg != 1 && t->tiles_per_wg != 2 && t->tiles_per_wg != 4) return RY_EINVAL;
   if (t->waves_per_tile != 1 && t->waves_per_tile != 2 && t->waves_per_tile != 4) return RY_EINVAL;
@@ -1445,12 +1492,15 @@ ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
     c->bgraph = nullptr;
   }
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_get_tuning(const ry_ctx* c, ry_tuning* t) {
+  RY_ABI_TRY
   if (!c || !t) return RY_EINVAL;
   *t = c->tune;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 // Time the hydro kernels of one coarse step (every level, weighted by its
@@ -1493,6 +1543,7 @@ static ry_status time_tuning(ry_ctx* c, const ry_tuning& t, double* ms_out) {
 }
 
 ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_cand, int32_t* n_cand) {
+  RY_ABI_TRY
   if (!c || !c->built) return RY_EINVAL;
   if (c->batch) {
     // the batched launch reads per-box lambda: make sure it holds values
@@ -1531,6 +1582,7 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
   if (best) *best = bt;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 // ----------------------------------------------------------- diagnostics
@@ -1543,13 +1595,16 @@ int64_t ry_floor_count(ry_ctx* c) {
 }
 
 ry_status ry_set_timing(ry_ctx* c, int32_t on) {
+  RY_ABI_TRY
   if (!c) return RY_EINVAL;
   c->timing = on != 0;
   if (!c->timing) c->ktime.clear();
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_kernel_time(ry_ctx* c, const char* kernel, int64_t* launches, double* total_ms) {
+  RY_ABI_TRY
   if (!c || !kernel) return RY_EINVAL;
   if (!c->pending.empty()) {
     if (hipStreamSynchronize(c->stream) != hipSuccess) return RY_EHIP;
@@ -1559,9 +1614,11 @@ ry_status ry_kernel_time(ry_ctx* c, const char* kernel, int64_t* launches, doubl
   if (launches) *launches = it == c->ktime.end() ? 0 : it->second.first;
   if (total_ms) *total_ms = it == c->ktime.end() ? 0.0 : it->second.second;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_copy_probe(ry_ctx* c, size_t bytes, int32_t reps, double* ms) {
+  RY_ABI_TRY
   if (!c || !ms || bytes < 1024 || reps < 1) return RY_EINVAL;
   double *a = nullptr, *b = nullptr;
   HIPCHK(c, hipMalloc(&a, bytes));
@@ -1587,6 +1644,7 @@ ry_status ry_copy_probe(ry_ctx* c, size_t bytes, int32_t reps, double* ms) {
   hipFree(a);
   hipFree(b);
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 // ------------------------------------------------------- host-only mesh
@@ -1597,6 +1655,7 @@ struct ry_mesh {
 };
 
 ry_status ry_mesh_build(const ry_config* cfg, const double* U_base, ry_fill_fn fill, void* user, ry_mesh** out) {
+  RY_ABI_TRY
   if (!out || !U_base) return RY_EINVAL;
   *out = nullptr;
   ry_status s = validate(cfg, false);
@@ -1613,10 +1672,12 @@ ry_status ry_mesh_build(const ry_config* cfg, const double* U_base, ry_fill_fn f
   }
   *out = m;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_mesh_level(const ry_mesh* m, int32_t level, int64_t* n_oct, uint64_t* keys, uint8_t* refined,
                         int64_t* n_ghost) {
+  RY_ABI_TRY
   if (!m || level < m->cfg.level_min || level > m->cfg.level_max) return RY_EINVAL;
   const HostLevel& H = m->levels[level - m->cfg.level_min];
   if (n_oct) *n_oct = H.n;
@@ -1624,6 +1685,7 @@ ry_status ry_mesh_level(const ry_mesh* m, int32_t level, int64_t* n_oct, uint64_
   if (refined && H.n) std::memcpy(refined, H.refined.data(), H.n);
   if (n_ghost) *n_ghost = m->tables[level - m->cfg.level_min].n_ghost;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 void ry_mesh_free(ry_mesh* m) { delete m; }

@@ -25,6 +25,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -515,9 +516,22 @@ void collect_times(ry_poisson* p) {
 
 }  // namespace
 
+// No C++ exception crosses the C ABI: a failed host allocation inside an
+// entry point becomes RY_ENOMEM, any other exception RY_EINVAL.
+#define RY_ABI_TRY try {
+#define RY_ABI_CATCH                    \
+  }                                     \
+  catch (const std::bad_alloc&) {       \
+    return RY_ENOMEM;                   \
+  }                                     \
+  catch (...) {                         \
+    return RY_EINVAL;                   \
+  }
+
 extern "C" {
 
 ry_status ry_poisson_create(const ry_poisson_config* cfg, ry_poisson** out) {
+  RY_ABI_TRY
   if (!cfg || !out) return RY_EINVAL;
   *out = nullptr;
   for (int a = 0; a < 3; ++a)
@@ -529,7 +543,8 @@ ry_status ry_poisson_create(const ry_poisson_config* cfg, ry_poisson** out) {
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return RY_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return RY_EHIP;
-  ry_poisson* p = new ry_poisson();
+  ry_poisson* p = new (std::nothrow) ry_poisson();
+  if (!p) return RY_ENOMEM;
   p->cfg = *cfg;
   p->g = {cfg->n[0], cfg->n[1], cfg->n[2], cfg->bc};
   p->N = N;
@@ -574,6 +589,7 @@ ry_status ry_poisson_create(const ry_poisson_config* cfg, ry_poisson** out) {
   }
   *out = p;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 void ry_poisson_destroy(ry_poisson* p) {
@@ -584,6 +600,7 @@ void ry_poisson_destroy(ry_poisson* p) {
 }
 
 ry_status ry_poisson_set_rhs(ry_poisson* p, const double* b, const double* x0) {
+  RY_ABI_TRY
   if (!p || !b) return RY_EINVAL;
   const size_t bytes = sizeof(double) * size_t(p->N);
   double *x = p->v[0], *r = p->v[1], *u = p->v[2], *w0 = p->v[3], *z = p->v[5];
@@ -602,9 +619,11 @@ ry_status ry_poisson_set_rhs(ry_poisson* p, const double* b, const double* x0) {
   p->ready = true;
   p->iter_hi = 0;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_poisson_solve(ry_poisson* p, double eps, int32_t max_iter, int32_t* n_iter) {
+  RY_ABI_TRY
   if (!p) return RY_EINVAL;
   if (!p->ready) return pfail(p, RY_ESTATE, "ry_poisson_solve before ry_poisson_set_rhs");
   if (max_iter < 0 || max_iter > RY_POISSON_HIST - 1 || std::isnan(eps)) return RY_EINVAL;
@@ -635,9 +654,11 @@ ry_status ry_poisson_solve(ry_poisson* p, double eps, int32_t max_iter, int32_t*
   if (n_iter) *n_iter = s.iter;
   if (p->timing) collect_times(p);
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_poisson_iterate(ry_poisson* p, int32_t n) {
+  RY_ABI_TRY
   if (!p || n < 0) return RY_EINVAL;
   if (!p->ready) return pfail(p, RY_ESTATE, "ry_poisson_iterate before ry_poisson_set_rhs");
   if (p->iter_hi + n > RY_POISSON_HIST - 1) return pfail(p, RY_EINVAL, "iteration history full");
@@ -657,9 +678,11 @@ ry_status ry_poisson_iterate(ry_poisson* p, int32_t n) {
   }
   p->iter_hi += n;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_poisson_eps_history(ry_poisson* p, double* eps, int32_t cap, int32_t* n) {
+  RY_ABI_TRY
   if (!p || !eps || cap < 0) return RY_EINVAL;
   Scalars s{};
   PCHK(p, hipStreamSynchronize(p->stream));
@@ -668,9 +691,11 @@ ry_status ry_poisson_eps_history(ry_poisson* p, double* eps, int32_t cap, int32_
   if (k > 0) PCHK(p, hipMemcpy(eps, p->hist, sizeof(double) * k, hipMemcpyDeviceToHost));
   if (n) *n = k;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_poisson_download(ry_poisson* p, int32_t which, double* host) {
+  RY_ABI_TRY
   if (!p || !host || which < 0 || which >= RY_PV_COUNT) return RY_EINVAL;
   Scalars s{};
   PCHK(p, hipStreamSynchronize(p->stream));
@@ -686,9 +711,11 @@ ry_status ry_poisson_download(ry_poisson* p, int32_t which, double* host) {
   }
   PCHK(p, hipMemcpy(host, p->v[slot], sizeof(double) * size_t(p->N), hipMemcpyDeviceToHost));
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_poisson_scalars(ry_poisson* p, double* alpha_prev, double* gamma_prev, int32_t* iter) {
+  RY_ABI_TRY
   if (!p) return RY_EINVAL;
   Scalars s{};
   PCHK(p, hipStreamSynchronize(p->stream));
@@ -697,9 +724,11 @@ ry_status ry_poisson_scalars(ry_poisson* p, double* alpha_prev, double* gamma_pr
   if (gamma_prev) *gamma_prev = s.gamma_prev;
   if (iter) *iter = s.iter;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_poisson_set_timing(ry_poisson* p, int32_t on) {
+  RY_ABI_TRY
   if (!p) return RY_EINVAL;
   PCHK(p, hipStreamSynchronize(p->stream));
   collect_times(p);
@@ -707,15 +736,18 @@ ry_status ry_poisson_set_timing(ry_poisson* p, int32_t on) {
   p->t_launches = 0;
   p->t_ms = 0.0;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 ry_status ry_poisson_kernel_time(ry_poisson* p, int32_t* launches, double* total_ms) {
+  RY_ABI_TRY
   if (!p) return RY_EINVAL;
   PCHK(p, hipStreamSynchronize(p->stream));
   collect_times(p);
   if (launches) *launches = int32_t(p->t_launches);
   if (total_ms) *total_ms = p->t_ms;
   return RY_OK;
+  RY_ABI_CATCH
 }
 
 const char* ry_poisson_last_error(const ry_poisson* p) { return p ? p->err.c_str() : "null solver"; }
