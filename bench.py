@@ -198,6 +198,7 @@ def cpu_baseline(budget_s=12.0):
     prob = W.uniform(128)
     o = Oracle(prob)
     cores = lib().ryo_num_threads()
+    e0 = o.totals()[4]
     n = 0
     t0 = time.perf_counter()
     while True:
@@ -207,6 +208,9 @@ def cpu_baseline(budget_s=12.0):
         if el > budget_s or n >= 100:
             break
     cups = 128 ** 3 * n / el
+    # the oracle's state after these n steps: the reference for the GPU
+    # forms' accuracy on the same workload (reported below, untimed)
+    ref = {"U": o.download(prob.level_min), "t": o.t, "drift": abs(o.totals()[4] - e0) / abs(e0), "n": n}
     # the same oracle on one thread, a few steps
     lib().ryo_set_num_threads(1)
     n1 = 0
@@ -227,7 +231,39 @@ def cpu_baseline(budget_s=12.0):
     return {"value": cups, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"uniform 128^3 periodic box, {n} whole coarse steps ({el:.1f} s wall)"
                       + (f" on {model}" if model else ""),
-            "value_one_thread": 128 ** 3 * n1 / el1}
+            "value_one_thread": 128 ** 3 * n1 / el1,
+            "gpu_vs_oracle": gpu_vs_oracle(prob, ref)}
+
+
+def gpu_vs_oracle(prob, ref):
+    """Both GPU forms advanced as many steps as the oracle took: relative
+    L1 and max errors of density and pressure against the oracle's state,
+    the time reached, and each code's total-energy drift."""
+    import numpy as np
+    import torch
+    from paper_2411_14631_amd import Hydro
+    g = prob.gamma
+
+    def rho_p(U):
+        return U[0], (g - 1.0) * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0])
+
+    rr, pr = rho_p(ref["U"])
+    out = {"steps": ref["n"], "oracle_energy_drift": float(ref["drift"])}
+    for prec in ("fp64", "mixed"):
+        h = Hydro(prob, prec)
+        e0 = h.totals()[4]
+        h.advance(ref["n"])
+        rg, pg = rho_p(h.download(prob.level_min))
+        out[prec] = {"l1_rho_rel": float(np.abs(rg - rr).sum() / np.abs(rr).sum()),
+                     "max_rho_rel": float(np.max(np.abs(rg - rr) / np.abs(rr))),
+                     "l1_p_rel": float(np.abs(pg - pr).sum() / np.abs(pr).sum()),
+                     "max_p_rel": float(np.max(np.abs(pg - pr) / np.abs(pr))),
+                     "t_rel": float(abs(h.t - ref["t"]) / ref["t"]),
+                     "energy_drift": float(abs(h.totals()[4] - e0) / abs(e0))}
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_scalars(nscalar=2, steps=10, warmup=2):
