@@ -68,7 +68,7 @@ struct ry_ctx {
   double* d_t = nullptr;                  // 1 / per box
   int32_t* d_flags = nullptr;             // [0]=skip [1]=done [2]=nstep [3]=err
   unsigned long long* d_floors = nullptr;
-  unsigned int* d_queue = nullptr;        // 8 counters
+  unsigned int* d_queue = nullptr;        // 8 counters, QUEUE_STRIDE apart
   double* d_partial = nullptr;
   double* d_tot = nullptr;
   double* d_dx_box = nullptr;
@@ -239,7 +239,7 @@ ry_status alloc_scalars(ry_ctx* c, int nslot) {
   c->d_t = static_cast<double*>(dalloc(c, sizeof(double) * nslot));
   c->d_flags = static_cast<int32_t*>(dalloc(c, sizeof(int32_t) * 8));
   c->d_floors = static_cast<unsigned long long*>(dalloc(c, sizeof(unsigned long long)));
-  c->d_queue = static_cast<unsigned int*>(dalloc(c, sizeof(unsigned int) * 8));
+  c->d_queue = static_cast<unsigned int*>(dalloc(c, sizeof(unsigned int) * 8 * QUEUE_STRIDE));
   c->d_partial = static_cast<double*>(dalloc(c, sizeof(double) * NVMAX * totals_blocks()));
   c->d_tot = static_cast<double*>(dalloc(c, sizeof(double) * NVMAX));
   if (!c->d_smax || !c->d_slots || !c->d_lam || !c->d_t || !c->d_flags || !c->d_floors || !c->d_queue || !c->d_partial ||
@@ -253,7 +253,7 @@ ry_status alloc_scalars(ry_ctx* c, int nslot) {
   HIPCHK(c, hipMemsetAsync(c->d_t, 0, sizeof(double) * nslot, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_flags, 0, sizeof(int32_t) * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_floors, 0, sizeof(unsigned long long), c->stream));
-  HIPCHK(c, hipMemsetAsync(c->d_queue, 0, sizeof(unsigned int) * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_queue, 0, sizeof(unsigned int) * 8 * QUEUE_STRIDE, c->stream));
   return RY_OK;
 }
 
@@ -381,7 +381,7 @@ HydroArgs hydro_args(ry_ctx* c, int l, int substep) {
 }
 
 ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a) {
-  if (c->tune.persistent && launch_zero_u32(c->d_queue, 8, c->stream)) return fail(c, RY_EHIP, "zero kernel");
+  if (c->tune.persistent && launch_zero_u32(c->d_queue, 8 * QUEUE_STRIDE, c->stream)) return fail(c, RY_EHIP, "zero kernel");
   TimedLaunch tl;
   if (c->timing) time_begin(c, "hydro", tl);
   if (launch_hydro(a, c->cfg.precision, c->cfg.nscalar, c->tune, c->num_cu, c->stream))

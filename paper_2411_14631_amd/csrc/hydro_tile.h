@@ -759,31 +759,54 @@ __global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(
   const int q = nitems >> 3, r = nitems & 7;
   int cur = blockIdx.x & 7;
   int exhausted = 0;
-  while (true) {
-    if (threadIdx.x == 0) {
-      int item = -1;
-      while (exhausted < 8) {
-        const int qlen = q + (cur < r ? 1 : 0);
-        const unsigned int k = atomicAdd(&A.queue[cur], 1u);
-        if (int(k) < qlen) {
-          item = cur * q + (cur < r ? cur : r) + int(k);
-          break;
-        }
-        cur = (cur + 1) & 7;
-        ++exhausted;
-      }
-      s_item = item;
+  auto qlen = [&](int c) { return q + (c < r ? 1 : 0); };
+  auto item_of = [&](int c, unsigned int k) { return c * q + (c < r ? c : r) + int(k); };
+  // a blocking pop (thread 0): the next item of this XCD's queue, then of
+  // the others once it is exhausted; -1 when every queue is
+  auto pop = [&]() {
+    while (exhausted < 8) {
+      const unsigned int k = atomicAdd(&A.queue[cur * QUEUE_STRIDE], 1u);
+      if (int(k) < qlen(cur)) return item_of(cur, k);
+      cur = (cur + 1) & 7;
+      ++exhausted;
     }
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item < 0) break;
+    return -1;
+  };
+  if (threadIdx.x == 0) s_item = pop();
+  __syncthreads();
+  // the item is uniform: tile indices, table rows and tile flags stay in
+  // scalar registers
+  int item = __builtin_amdgcn_readfirstlane(s_item);
+  __syncthreads();
+  while (item >= 0) {
+    // claim the next slot of the current queue before this item's tiles and
+    // look at the answer after them: the atomic's round trip overlaps the
+    // tiles' own loads
+    unsigned int k = 0;
+    const int kc = cur;
+    if (threadIdx.x == 0 && exhausted < 8) k = atomicAdd(&A.queue[kc * QUEUE_STRIDE], 1u);
     for (int j = 0; j < batch; ++j) {
       const int grp = item * batch + j;
       if (grp >= ngroups) break;
       const int tile = grp * TPW + w;
       hydro_tile<Real, NT, 0>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
     }
+    if (threadIdx.x == 0) {
+      int next = -1;
+      if (exhausted < 8) {
+        if (int(k) < qlen(kc)) {
+          next = item_of(kc, k);
+        } else {
+          cur = (cur + 1) & 7;
+          ++exhausted;
+          next = pop();
+        }
+      }
+      s_item = next;
+    }
+    __syncthreads();
+    item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
   }
 }
 

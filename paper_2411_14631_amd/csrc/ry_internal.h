@@ -19,6 +19,9 @@ constexpr int TILE_TAB = 64;       // 4x4x4 oct positions around a 2x2x2-oct til
 // tile t takes an atomic maximum on slot t % SMAX_SLOTS, so that no single
 // address takes every tile's atomic.
 constexpr int SMAX_SLOTS = 256;
+// persistent-kernel work queues: 8 counters (one per XCD), 128 B apart so
+// that no two share a cache line
+constexpr int QUEUE_STRIDE = 32;
 // flux registers per oct: [face 6][variable nv][substep 2]
 constexpr int reg_per_oct(int nv) { return 6 * nv * 2; }
 
@@ -145,7 +148,7 @@ struct HydroArgs {
   unsigned long long* floors;
   int32_t* err;
   const int32_t* skip;        // device flag: skip this launch's work
-  unsigned int* queue;        // persistent mode: 8 per-XCD counters
+  unsigned int* queue;        // persistent mode: 8 per-XCD counters, QUEUE_STRIDE apart
 };
 
 struct GhostArgs {
