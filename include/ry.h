@@ -171,8 +171,11 @@ typedef struct {
 } ry_tuning;
 ry_status ry_set_tuning(ry_ctx* ctx, const ry_tuning* t);
 ry_status ry_get_tuning(const ry_ctx* ctx, ry_tuning* t);
-/* Time every candidate tuning on the current state (state unchanged) and
- * keep the fastest; candidate timings are written to times_ms (n_cand). */
+/* Time every candidate tuning on the current state (state unchanged):
+ * each candidate once (its times in times_ms, n_cand of them), then the
+ * three fastest and the default {1, 0, 4, 1, 1} again in six interleaved
+ * rounds; the lowest median wins, but the default stays unless beaten by
+ * more than 2%. */
 ry_status ry_autotune(ry_ctx* ctx, ry_tuning* best, double* times_ms, int32_t max_cand, int32_t* n_cand);
 
 /* Diagnostics. */
