@@ -302,6 +302,11 @@ ry_status enqueue_seg_max(ry_ctx* c) {
 }
 
 // Maximum signal speed of every level (box) from the current state.
+// CFL partials of a level: one per tile (batched boxes: the hydro epilogue)
+// and one per 256-thread block of `cfl_kernel` (32 octs); a level whose
+// tiles skip fully refined octs can have fewer tiles than blocks
+int64_t part_slots(const DevLevel& L) { return std::max<int64_t>(L.n_tile, (8 * L.n_oct + 255) / 256); }
+
 ry_status enqueue_cfl_all(ry_ctx* c) {
   if (launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_part), c->seg_off.back(), c->stream))
     return fail(c, RY_EHIP, "zero kernel");
@@ -576,7 +581,7 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
     return fail(c, RY_ENOMEM, "device allocation failed");
   }
   c->seg_off.assign(1, 0);
-  for (int k = 0; k < c->nlev; ++k) c->seg_off.push_back(c->seg_off.back() + c->lev[k].n_tile);
+  for (int k = 0; k < c->nlev; ++k) c->seg_off.push_back(c->seg_off.back() + part_slots(c->lev[k]));
   ry_status s = alloc_scalars(c, std::max(c->nlev, 1));
   if (s) {
     free_all(c);
@@ -751,7 +756,7 @@ ry_status finish_regrid(ry_ctx* c) {
   dfree(c, c->d_part);
   dfree(c, c->d_segoff);
   c->seg_off.assign(1, 0);
-  for (int k = 0; k < nl; ++k) c->seg_off.push_back(c->seg_off.back() + c->lev[k].n_tile);
+  for (int k = 0; k < nl; ++k) c->seg_off.push_back(c->seg_off.back() + part_slots(c->lev[k]));
   c->d_part = static_cast<double*>(dalloc(c, sizeof(double) * std::max<int64_t>(c->seg_off.back(), 1)));
   c->d_segoff = static_cast<int64_t*>(dalloc(c, sizeof(int64_t) * c->seg_off.size()));
   if (!c->d_part || !c->d_segoff) {

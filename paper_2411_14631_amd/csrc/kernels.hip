@@ -47,6 +47,7 @@ static int launch_hydro_scalars(const HydroArgs& a, int nscalar, const ry_tuning
 int launch_hydro(const HydroArgs& a, int precision, int nscalar, const ry_tuning& t, int num_cu, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (!hydro_tuning_supported(precision, nscalar, t)) return -1;
+  if (a.n_tile == 0) return 0;   // a level whose octs are all fully refined has no tile to update
   if (nscalar > 0)
     return precision == RY_MIXED ? launch_hydro_scalars<float>(a, nscalar, t, num_cu, s)
                                  : launch_hydro_scalars<double>(a, nscalar, t, num_cu, s);

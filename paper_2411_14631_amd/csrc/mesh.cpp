@@ -343,10 +343,24 @@ static std::string build_level_tables(const DomainSpec& d, const std::vector<Hos
     T.n_oct = H.n;
     if (H.n == 0) return "";
     for (int64_t o = 0; o < H.n; ++o) T.n_leaf += 8 - __builtin_popcount(H.refined[o]);
-    // tiles: groups of octs sharing key >> 3 (an aligned 2x2x2 block of octs)
-    std::vector<int64_t> tile_start;
-    for (int64_t o = 0; o < H.n; ++o)
-      if (o == 0 || (H.key[o] >> 3) != (H.key[o - 1] >> 3)) tile_start.push_back(o);
+    // tiles: groups of octs sharing key >> 3 (an aligned 2x2x2 block of
+    // octs).  On refined levels a tile is kept only when one of its cells is
+    // a leaf: a tile of fully refined octs updates nothing (the restriction
+    // overwrites its cells) and records no flux register (a refined cell
+    // never borders a coarser leaf).  The base level keeps every tile: the
+    // device regrid keeps its tables while its refinement changes
+    std::vector<int64_t> tile_start, tile_end;
+    for (int64_t o0 = 0; o0 < H.n;) {
+      int64_t o1 = o0 + 1;
+      while (o1 < H.n && (H.key[o1] >> 3) == (H.key[o0] >> 3)) ++o1;
+      bool leaf = (k == 0);
+      for (int64_t o = o0; o < o1 && !leaf; ++o) leaf = H.refined[o] != 0xFF;
+      if (leaf) {
+        tile_start.push_back(o0);
+        tile_end.push_back(o1);
+      }
+      o0 = o1;
+    }
     T.n_tile = int32_t(tile_start.size());
     T.tab.assign(size_t(T.n_tile) * TILE_TAB, -1);
     T.tflag.assign(T.n_tile, 0);
@@ -354,8 +368,7 @@ static std::string build_level_tables(const DomainSpec& d, const std::vector<Hos
     std::vector<std::array<int64_t, 3>> ghost_pos;
     const int64_t nox = d.noct(l, 0), noy = d.noct(l, 1), noz = d.noct(l, 2);
     for (int32_t t = 0; t < T.n_tile; ++t) {
-      const int64_t o0 = tile_start[t];
-      const int64_t o1 = (t + 1 < T.n_tile) ? tile_start[t + 1] : H.n;
+      const int64_t o0 = tile_start[t], o1 = tile_end[t];
       const int64_t bx = H.ox[o0] & ~1, by = H.oy[o0] & ~1, bz = H.oz[o0] & ~1;
       bool present[8] = {false, false, false, false, false, false, false, false};
       for (int64_t o = o0; o < o1; ++o)
