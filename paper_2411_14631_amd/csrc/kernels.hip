@@ -127,12 +127,15 @@ __global__ void restrict_kernel(const double* __restrict__ Uf, int64_t pf, int64
                                 const int32_t* __restrict__ parent, double* __restrict__ Uc, int64_t pc, int nv,
                                 const int32_t* skip) {
   if (skip && *skip) return;
+  // variable-major: consecutive threads read consecutive octs of one plane
+  // (64 contiguous bytes each, as four 16-byte loads)
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nf * nv) return;
-  const int64_t k = i / nv;
-  const int v = int(i - k * nv);
-  const double* s = Uf + v * pf + 8 * k;
-  Uc[v * pc + parent[k]] = 0.125 * (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
+  const int v = int(i / nf);
+  const int64_t k = i - int64_t(v) * nf;
+  const double2* s = reinterpret_cast<const double2*>(Uf + v * pf + 8 * k);
+  const double2 a = s[0], b = s[1], c = s[2], d = s[3];
+  Uc[v * pc + parent[k]] = 0.125 * (((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y)));
 }
 
 int launch_restrict(const double* Uf, int64_t pf, int64_t nf, const int32_t* parent, double* Uc, int64_t pc,
