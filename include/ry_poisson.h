@@ -2,10 +2,10 @@
  * ry_poisson.h -- C ABI of the uniform-level Poisson solver of the MI355X
  * library: the preconditioned pipelined conjugate-gradient method (PPCG,
  * Ghysels & Vanroose 2014, Algorithm 4) that the paper adopts in place of
- * plain CG for the cell-level Poisson equation (Sec. 2.4), with the paper's
+ * plain CG for the cell-level Poisson equation (Sec. 2.3), with the paper's
  * seven-point preconditioner (13/12 at the centre, 1/6 on each face
- * neighbour, Sec. 2.4) and its error measure eps_i = sqrt((r_i.u_i) /
- * (r_0.u_0)), u = M^-1 r (Sec. 3.1).
+ * neighbour, Sec. 2.3) and its error measure eps_i = sqrt((r_i.u_i) /
+ * (r_0.u_0)), u = M^-1 r (Eq. 3, Sec. 3.2).
  *
  * Problem: A x = b on an n0 x n1 x n2 grid (x fastest), A = the 7-point
  * negative Laplacian with unit spacing (6 on the diagonal, -1 to each face

@@ -6,15 +6,15 @@
  * the product path.  Everything is plain loops in the order the methods
  * state them; dot products are summed sequentially in cell order.
  *
- *   - Operator and preconditioner: the paper, Sec. 2.4 (seven-point
+ *   - Operator and preconditioner: the paper, Sec. 2.3 (seven-point
  *     preconditioner stencil 13/12 centre, 1/6 neighbours); the operator is
  *     the standard 7-point negative Laplacian.
  *   - PCG: Hestenes & Stiefel (1952) with a preconditioner (e.g. Saad 2003,
  *     Iterative Methods for Sparse Linear Systems, Alg. 9.1).
  *   - PPCG: Ghysels & Vanroose (2014), Algorithm 4, the method the paper
- *     adopts (Sec. 2.4).
+ *     adopts (Sec. 2.3).
  *   - Stopping rule: the paper's error measure eps_i = sqrt(gamma_i /
- *     gamma_0), gamma = r.u (Sec. 3.1, the equation for eps).
+ *     gamma_0), gamma = r.u (Eq. 3, Sec. 3.2).
  */
 #include "poisson.h"
 

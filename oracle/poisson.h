@@ -8,7 +8,7 @@
  * baseline leg of the benchmark use it.  It shares no code with the GPU
  * library.
  *
- * What the paper fixes (Sec. 2.4, "Additional improvements"; Sec. 3.1 and
+ * What the paper fixes (Sec. 2.3, "Additional improvements"; Sec. 3.2 and
  * the equation defining the solution error):
  *   - the cell-level Poisson equation is solved by conjugate gradients in
  *     RAMSES and by PPCG (Ghysels & Vanroose 2014, Algorithm 4: pipelined

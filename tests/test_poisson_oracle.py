@@ -5,7 +5,7 @@ eigenpairs (Fourier modes on the periodic grid, sine modes under zero
 Dirichlet) and by symmetry; the solvers by a dense LAPACK solve, an FFT
 solve, SciPy's conjugate-gradient iterates, finite termination on a
 two-eigenvalue right-hand side, monotone energy-norm error and the
-iteration saving the paper reports for the preconditioner (Sec. 3.1).
+iteration saving the paper reports for the preconditioner (Sec. 3.2).
 """
 import numpy as np
 import pytest
@@ -181,7 +181,7 @@ def test_recursive_residual_tracks_true_residual():
 
 def test_preconditioner_halves_iterations():
     """The paper reports ~1.86x fewer iterations to eps = 1e-4 with the
-    preconditioned pipelined solver (Sec. 3.1); the ratio is a property of
+    preconditioned pipelined solver (Sec. 3.2); the ratio is a property of
     the operator pair, close to 2 for any smooth right-hand side."""
     n = (32, 32, 32)
     b = smooth_rhs(n, 21, sigma=4.0)
