@@ -10,7 +10,7 @@
  * The paper (RAMSES-yOMP) fixes the mesh (octree of 2^3-cell octs, level
  * l+1 halves the cell size: Sec. 1), the Hilbert ordering of octs (Sec. 1),
  * the subcycling rule dt(l+1) = dt(l)/2 (Sec. 2.3, next to Eq. 1) and the
- * OpenMP static schedule over grid loops (Sec. 2.1).  It does not state the
+ * OpenMP static schedule over grid loops (Sec. 2.2).  It does not state the
  * hydro scheme; each step below follows the published method it names:
  *   - primitive variables and floors ............ ideal gas, E = p/(g-1)+rho v^2/2
  *   - MinMod-limited slopes, half-step predictor  van Leer (1979); Toro (2009) ch. 13-14
@@ -391,6 +391,22 @@ static int64_t refined_child(const ryo_ctx* c, int l, const int64_t p_in[3]) {
   return find_oct(LVc(c, l + 1), p[0], p[1], p[2]);
 }
 
+/* Is cell position p of level l a leaf cell of l?  Positions outside an
+ * outflow face (read through the zero-gradient clamp) are not, nor are
+ * positions whose oct does not exist at l (ghosts) or refined cells. */
+static int is_leaf_cell(const ryo_ctx* c, int l, const int64_t p_in[3]) {
+  int64_t p[3] = {p_in[0], p_in[1], p_in[2]};
+  for (int a = 0; a < 3; a++) {
+    int64_t N = ncells(c, l, a);
+    if ((p[a] < 0 && c->cfg.bc[2 * a] != RYO_BC_PERIODIC) || (p[a] >= N && c->cfg.bc[2 * a + 1] != RYO_BC_PERIODIC))
+      return 0;
+  }
+  bc_cell(c, l, p);
+  const level_t* L = LVc(c, l);
+  int64_t o = find_oct(L, p[0] >> 1, p[1] >> 1, p[2] >> 1);
+  return o >= 0 && !(L->refined[o] & (1u << cell_of(p)));
+}
+
 /* Time- and area-averaged flux of a coarse-fine face, from the registers of
  * the fine oct: Fbar = (q_1 + q_2) / 8 (Berger & Colella 1989). */
 static void register_flux(const ryo_ctx* c, int lf, int64_t child, int face, double F[NV]) {
@@ -404,6 +420,12 @@ static void register_flux(const ryo_ctx* c, int lf, int64_t child, int face, dou
 /* ------------------------------------------------------------------------ */
 /* Flux computation and conservative update of one level (one substep).      */
 /* ------------------------------------------------------------------------ */
+/* Floor activations are counted once per event of the step, whatever the
+ * order of the computation (this oracle recomputes every stencil value
+ * for each use): a leaf cell's own primitive conversion, each face state of
+ * a face that an update uses -- counted by the face's upper cell when that
+ * is a leaf, otherwise by its lower cell -- and, once per parent step, each
+ * ghost cell of the level (ghost_census). */
 static void update_level(ryo_ctx* c, int l, double lam, int substep) {
   level_t* L = LV(c, l);
   const int64_t n = L->n;
@@ -411,13 +433,18 @@ static void update_level(ryo_ctx* c, int l, double lam, int substep) {
   int64_t floors = 0;
 #pragma omp parallel for schedule(static) reduction(+ : floors)
   for (int64_t o = 0; o < n; o++) {
-    int64_t fl = 0;
+    int64_t fl = 0, rep = 0;   /* counted events; repeated evaluations (not counted) */
     for (int ci = 0; ci < 8; ci++) {
       if (L->refined[o] & (1u << ci)) continue;   /* refined cells: restriction */
       int64_t p[3] = {2 * (int64_t)L->oc[3 * o] + (ci & 1), 2 * (int64_t)L->oc[3 * o + 1] + ((ci >> 1) & 1),
                       2 * (int64_t)L->oc[3 * o + 2] + ((ci >> 2) & 1)};
+      {
+        double Uc[NV], Wc[NV];
+        value_at(c, l, p[0], p[1], p[2], Uc);
+        cons_to_prim(c, Uc, Wc, &fl);
+      }
       pred_t P0, Pm[3], Pp[3];
-      predict(c, l, p[0], p[1], p[2], h, &P0, &fl);
+      predict(c, l, p[0], p[1], p[2], h, &P0, &rep);
       double Fm[3][NV], Fp[3][NV];
       for (int d = 0; d < 3; d++) {
         int64_t m[3] = {p[0], p[1], p[2]}, q[3] = {p[0], p[1], p[2]};
@@ -427,15 +454,15 @@ static void update_level(ryo_ctx* c, int l, double lam, int substep) {
         if (chm >= 0) {
           register_flux(c, l + 1, chm, 2 * d + 1, Fm[d]);
         } else {
-          predict(c, l, m[0], m[1], m[2], h, &Pm[d], &fl);
+          predict(c, l, m[0], m[1], m[2], h, &Pm[d], &rep);
           face_flux(c, &Pm[d], &P0, d, Fm[d], &fl);
         }
         int64_t chp = refined_child(c, l, q);
         if (chp >= 0) {
           register_flux(c, l + 1, chp, 2 * d + 0, Fp[d]);
         } else {
-          predict(c, l, q[0], q[1], q[2], h, &Pp[d], &fl);
-          face_flux(c, &P0, &Pp[d], d, Fp[d], &fl);
+          predict(c, l, q[0], q[1], q[2], h, &Pp[d], &rep);
+          face_flux(c, &P0, &Pp[d], d, Fp[d], is_leaf_cell(c, l, q) ? &rep : &fl);
         }
       }
       int64_t cell = 8 * o + ci;
@@ -463,10 +490,10 @@ static void update_level(ryo_ctx* c, int l, double lam, int substep) {
           int64_t q[3] = {p[0], p[1], p[2]};
           q[d] += up ? 1 : -1;
           pred_t Pa, Pb;
-          predict(c, l, p[0], p[1], p[2], h, &Pa, &fl);
-          predict(c, l, q[0], q[1], q[2], h, &Pb, &fl);
-          if (up) face_flux(c, &Pa, &Pb, d, f[k], &fl);
-          else face_flux(c, &Pb, &Pa, d, f[k], &fl);
+          predict(c, l, p[0], p[1], p[2], h, &Pa, &rep);
+          predict(c, l, q[0], q[1], q[2], h, &Pb, &rep);
+          if (up) face_flux(c, &Pa, &Pb, d, f[k], &rep);
+          else face_flux(c, &Pb, &Pa, d, f[k], &rep);
           k++;
         }
         for (int v = 0; v < c->nv; v++)
@@ -495,10 +522,61 @@ static void restrict_level(ryo_ctx* c, int l, double* dst) {
   }
 }
 
+/* Floor activations of the ghost cells of level l (l > level_min) at the
+ * start of a parent step: every cell of every oct position that a 26-
+ * neighbour of an existing level-l oct occupies but no level-l oct does
+ * (inside the domain or across a periodic face), with its MinMod-linear
+ * interpolated state converted once. */
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+static void ghost_census(ryo_ctx* c, int l) {
+  const level_t* L = LVc(c, l);
+  int64_t cap = 26 * L->n, m = 0;
+  uint64_t* pos = (uint64_t*)malloc((cap ? cap : 1) * sizeof(uint64_t));
+  if (!pos) return;
+  for (int64_t o = 0; o < L->n; o++)
+    for (int dz = -1; dz <= 1; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+          if (!dx && !dy && !dz) continue;
+          int64_t q[3] = {L->oc[3 * o] + dx, L->oc[3 * o + 1] + dy, L->oc[3 * o + 2] + dz};
+          int out = 0;
+          for (int a = 0; a < 3; a++) {
+            int64_t N = ncells(c, l, a) / 2;
+            if (q[a] < 0) {
+              if (c->cfg.bc[2 * a] != RYO_BC_PERIODIC) out = 1;
+              else q[a] += N;
+            } else if (q[a] >= N) {
+              if (c->cfg.bc[2 * a + 1] != RYO_BC_PERIODIC) out = 1;
+              else q[a] -= N;
+            }
+          }
+          if (out || find_oct(L, q[0], q[1], q[2]) >= 0) continue;
+          pos[m++] = (uint64_t)q[0] | ((uint64_t)q[1] << 21) | ((uint64_t)q[2] << 42);
+        }
+  qsort(pos, (size_t)m, sizeof(uint64_t), cmp_u64);
+  int64_t fl = 0;
+  for (int64_t i = 0; i < m; i++) {
+    if (i > 0 && pos[i] == pos[i - 1]) continue;
+    int64_t q[3] = {(int64_t)(pos[i] & 0x1FFFFF), (int64_t)((pos[i] >> 21) & 0x1FFFFF), (int64_t)(pos[i] >> 42)};
+    for (int ci = 0; ci < 8; ci++) {
+      int64_t p[3] = {2 * q[0] + (ci & 1), 2 * q[1] + ((ci >> 1) & 1), 2 * q[2] + ((ci >> 2) & 1)};
+      double U[NV], W[NV];
+      coarse_interp(c, l, p, U);
+      cons_to_prim(c, U, W, &fl);
+    }
+  }
+  free(pos);
+  c->floors += fl;
+}
+
 /* Fine-first recursion: level l+1 takes two half steps, then level l takes
  * its step, then the refined cells of l are restricted from l+1. */
 static void advance_level(ryo_ctx* c, int l, double dt, int substep) {
   if (l < c->cfg.level_max && LV(c, l + 1)->n > 0) {
+    ghost_census(c, l + 1);
     advance_level(c, l + 1, 0.5 * dt, 0);
     advance_level(c, l + 1, 0.5 * dt, 1);
   }
@@ -806,7 +884,7 @@ int ryo_cfl_dt(ryo_ctx* c, double* dt_coarse) {
         if (L->refined[o] & (1u << ci)) continue;
         double U[NV], W[NV];
         for (int v = 0; v < c->nv; v++) U[v] = L->U[v * 8 * L->n + 8 * o + ci];
-        cons_to_prim(c, U, W, &fl);
+        cons_to_prim(c, U, W, &fl);   /* the time step's conversions: not counted */
         double cs = sqrt(g * W[4] / W[0]);
         double s = fabs(W[1]) + fabs(W[2]) + fabs(W[3]) + 3.0 * cs;
         if (s > smax) smax = s;
@@ -817,7 +895,7 @@ int ryo_cfl_dt(ryo_ctx* c, double* dt_coarse) {
     double cand = ldexp(dtl, l - c->cfg.level_min);
     if (cand < best) best = cand;
   }
-  c->floors += fl;
+  (void)fl;
   *dt_coarse = best;
   return RYO_OK;
 }

@@ -76,6 +76,13 @@ int  ryo_coarse_step(ryo_ctx* c, double dt_coarse);
 int  ryo_advance(ryo_ctx* c, int32_t n_coarse, double t_end, double* t_io, int32_t* n_done);
 /* tot: 5 + nscalar sums over leaf cells of U dx^3. */
 int  ryo_conserved_totals(const ryo_ctx* c, double* tot);
+/* Floor activations (density and pressure counted separately) since the
+ * build, each event of a step counted once: a leaf cell's own primitive
+ * conversion; both face states of each face an update uses (counted by the
+ * face's upper cell when that is a leaf, else by its lower cell); once per
+ * parent step, every ghost cell of a refined level (the cells of the oct
+ * positions next to the level's octs that hold no oct of the level).  The
+ * time-step computation is not counted. */
 int64_t ryo_floor_count(const ryo_ctx* c);
 void ryo_reset_floor_count(ryo_ctx* c);
 const char* ryo_last_error(const ryo_ctx* c);
