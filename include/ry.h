@@ -56,7 +56,7 @@ enum { RY_REFINE_NONE = 0, RY_REFINE_GRAD = 1, RY_REFINE_MASS = 2 };
 
 typedef struct {
   int32_t level_min, level_max; /* level numbers; dx(l) = boxlen / (nbase[0] 2^(l-level_min)) */
-  int32_t nbase[3];             /* cells per axis at level_min; multiples of 4               */
+  int32_t nbase[3];             /* cells per axis at level_min; even, at least 2             */
   double boxlen, gamma, cfl;    /* gamma > 1, cfl > 0                                        */
   int32_t bc[6];                /* -x,+x,-y,+y,-z,+z: RY_BC_*; periodic pairs must match      */
   int32_t precision;            /* RY_FP64 | RY_MIXED                                         */
@@ -146,7 +146,7 @@ ry_status ry_upload(ry_ctx* ctx, int32_t level, const double* U);
 /* Batched independent boxes (single level, periodic or outflow each):
  * cfgs[b] describes box b (level_min == level_max), U0[b] its field as for
  * ry_amr_build.  All boxes share one tile list (and, with a persistent
- * tuning, one work queue).  Default tuning {1, 0, 4, 1, 1}; ry_autotune
+ * tuning, one work queue).  Default tuning {1, 0, 4, 1, 1, 4}; ry_autotune
  * picks among the plain and the persistent queue-fed launches.  RY_EINVAL
  * if the boxes' octs together reach 2^29. */
 ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* const* U0, ry_ctx** out);
@@ -161,25 +161,49 @@ ry_status ry_batch_download(ry_ctx* ctx, int32_t box, double* U);
 /* Tuning of the hydro kernel launch (see ry_tuning fields).  Results in FP64
  * do not depend on the tuning. */
 typedef struct {
-  int32_t tiles_per_wg;   /* tiles (aligned 2x2x2 oct blocks) per workgroup: 1, 2 or 4      */
-  int32_t persistent;     /* 0: one workgroup per tile group; 1: work queue                 */
+  int32_t tiles_per_wg;   /* tiles per workgroup: 1, 2 or 4 (tile_cells 4); 1 (tile_cells 8) */
+  int32_t persistent;     /* 0: one workgroup per tile group; 1: work queue (tile_cells 4)  */
   int32_t waves_per_cu;   /* persistent grid = CUs * waves_per_cu / waves per workgroup     */
   int32_t batch;          /* tile groups popped per queue access                            */
-  int32_t waves_per_tile; /* 1, 2 or 4 wavefronts per tile (8, 16, 32 threads per oct);     */
-                          /* tiles_per_wg * waves_per_tile <= 4; with passive scalars only  */
-                          /* {1,0,*,*,1}, {1,0,*,*,2} and {2,0,*,*,1} (else RY_EINVAL)      */
+  int32_t waves_per_tile; /* tile_cells 4: 1, 2 or 4 wavefronts per tile (8, 16, 32 threads */
+                          /* per oct), tiles_per_wg * waves_per_tile <= 4; with passive     */
+                          /* scalars only {1,0,*,*,1}, {1,0,*,*,2} and {2,0,*,*,1};         */
+                          /* tile_cells 8: 8 (one thread per cell) (else RY_EINVAL)         */
+  int32_t tile_cells;     /* tile edge in cells: 4 (a 2x2x2-oct tile, 64 cells) or 8 (a     */
+                          /* 4x4x4-oct tile, 512 cells: fewer halo cells converted,          */
+                          /* predicted and solved per cell; hydro variables alone)           */
 } ry_tuning;
+/* ry_set_tuning sets the tuning of every level; ry_get_tuning returns the
+ * tuning of level_min.  RY_EINVAL for a combination without a kernel (see
+ * the fields; batched boxes run on 4^3-cell tiles). */
 ry_status ry_set_tuning(ry_ctx* ctx, const ry_tuning* t);
 ry_status ry_get_tuning(const ry_ctx* ctx, ry_tuning* t);
-/* Time every candidate tuning on the current state (state unchanged):
- * each candidate once (its times in times_ms, n_cand of them), then the
- * three fastest and the default {1, 0, 4, 1, 1} again in six interleaved
- * rounds; the lowest median wins, but the default stays unless beaten by
- * more than 2%. */
+/* Tuning of one level (RY_EINVAL outside level_min..level_max).  Choosing
+ * the 8^3-cell tile for a level builds that level's tile tables on the
+ * device (syncs). */
+ry_status ry_set_level_tuning(ry_ctx* ctx, int32_t level, const ry_tuning* t);
+ry_status ry_get_level_tuning(const ry_ctx* ctx, int32_t level, ry_tuning* t);
+/* Per level, time every candidate tuning (small tiles with 1-4 tiles per
+ * workgroup and 1-4 wavefronts per tile, plain or queue-fed; the 8^3-cell
+ * tile) on the current state (state unchanged): each candidate once, then
+ * the three fastest and the default {1, 0, 4, 1, 1, 4} again in six
+ * interleaved rounds; the lowest median wins, but the default stays unless
+ * beaten by more than 2%.  Each level keeps its winner; *best = the winner
+ * of level_min.  times_ms[i] (n_cand of them) = the hydro time of one
+ * coarse step if candidate i ran on every level (level l weighted by its
+ * 2^(l - level_min) substeps).  Syncs. */
 ry_status ry_autotune(ry_ctx* ctx, ry_tuning* best, double* times_ms, int32_t max_cand, int32_t* n_cand);
 
 /* Diagnostics. */
-int64_t ry_floor_count(ry_ctx* ctx);                 /* syncs */
+/* Floor activations (density and pressure floors counted separately) since
+ * the build, each event of a step counted once, however often the kernels
+ * recompute the value: a leaf cell's own primitive conversion; both face
+ * states of each face an update uses (counted by the face's upper cell when
+ * that is a leaf, else by its lower cell); once per parent step, every
+ * ghost cell of a refined level (the cells of the oct positions next to the
+ * level's octs that hold no oct of the level).  The time-step computation
+ * is not counted.  Syncs. */
+int64_t ry_floor_count(ry_ctx* ctx);
 /* Per-kernel timing with HIP events on the launch stream (0 = off).  While
  * on, ry_advance launches eagerly instead of replaying graphs. */
 ry_status ry_set_timing(ry_ctx* ctx, int32_t on);

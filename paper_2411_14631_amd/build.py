@@ -35,10 +35,11 @@ def _run(cmd):
         print(out)
 
 
-def build(verbose: bool = False, extra=None) -> str:
-    objs = []
+def build(verbose: bool = False, extra=None, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    cmds, objs = [], []
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(bdir, s + ".o")
@@ -47,8 +48,12 @@ def build(verbose: bool = False, extra=None) -> str:
             cmd = [HIPCC, "-x", "hip"] + cmd[1:]
         if verbose:
             print(" ".join(cmd), flush=True)
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    # the sources compile independently: one compiler process each
+    n = jobs or min(len(cmds), os.cpu_count() or 1, 8)
+    with ThreadPoolExecutor(max_workers=max(n, 1)) as ex:
+        list(ex.map(_run, cmds))
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -34,6 +34,12 @@ struct DevLevel {
   int32_t* oct_box = nullptr;
   uint64_t* dkey = nullptr;          // sorted Hilbert keys (device regrid lookups)
   int32_t* doc = nullptr;            // oct coordinates, x y z interleaved
+  // super-tiles (4x4x4-oct blocks) for the 8^3-cell tile, built on demand
+  // from the small-tile tables of the current mesh
+  bool super_ok = false;
+  int32_t n_super = 0;
+  int32_t* stab = nullptr;
+  uint32_t* stflag = nullptr;
   int64_t plane() const { return 8 * n_ext; }
 };
 
@@ -57,7 +63,8 @@ struct ry_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int num_cu = 256;
-  ry_tuning tune{1, 0, 4, 1, 1};
+  // launch tuning of the hydro kernel, per level (index level - level_min)
+  ry_tuning tune[RY_MAX_LEVELS];
   // device scalars
   double* d_smax = nullptr;               // max signal speed per level / per box
   unsigned long long* d_slots = nullptr;  // per level: SMAX_SLOTS partial maxima of the fused CFL
@@ -115,6 +122,10 @@ ry_status fail(ry_ctx* c, ry_status s, const char* fmt, ...) {
     hipError_t e_ = (call);                                                                 \
     if (e_ != hipSuccess) return fail((c), RY_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
+
+// Default launch: small tiles, one 64-thread wavefront per tile, one tile
+// per workgroup, the hardware dispatcher as the queue.
+constexpr ry_tuning kDefaultTuning{1, 0, 4, 1, 1, 4};
 
 void* dalloc(ry_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -177,7 +188,7 @@ ry_status validate(const ry_config* cfg, bool single_level) {
     return RY_EINVAL;
   if (single_level && cfg->level_max != cfg->level_min) return RY_EINVAL;
   for (int a = 0; a < 3; ++a)
-    if (cfg->nbase[a] < 4 || (cfg->nbase[a] % 4) != 0) return RY_EINVAL;
+    if (cfg->nbase[a] < 2 || (cfg->nbase[a] % 2) != 0) return RY_EINVAL;
   for (int a = 0; a < 3; ++a) {
     const int lo = cfg->bc[2 * a], hi = cfg->bc[2 * a + 1];
     if (lo != RY_BC_PERIODIC && lo != RY_BC_OUTFLOW) return RY_EINVAL;
@@ -305,7 +316,13 @@ ry_status enqueue_seg_max(ry_ctx* c) {
 // CFL partials of a level: one per tile (batched boxes: the hydro epilogue)
 // and one per 256-thread block of `cfl_kernel` (32 octs); a level whose
 // tiles skip fully refined octs can have fewer tiles than blocks
-int64_t part_slots(const DevLevel& L) { return std::max<int64_t>(L.n_tile, (8 * L.n_oct + 255) / 256); }
+int64_t part_slots(const DevLevel& L) { return std::max<int64_t>(L.n_tile, cfl_blocks(L.n_oct)); }
+
+ry_status cfl_launch_status(ry_ctx* c, int rc, int seg) {
+  if (rc == LAUNCH_EXCEEDS_BUFFER)
+    return fail(c, RY_EINVAL, "cfl kernel: grid exceeds its partial-maximum segment %d", seg);
+  return rc ? fail(c, RY_EHIP, "cfl kernel") : RY_OK;
+}
 
 ry_status enqueue_cfl_all(ry_ctx* c) {
   if (launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_part), c->seg_off.back(), c->stream))
@@ -316,13 +333,16 @@ ry_status enqueue_cfl_all(ry_ctx* c) {
     if (c->batch) {
       for (int b = 0; b < c->nbox; ++b) {
         const int64_t off = c->box_off[b] * 8;
-        if (launch_cfl(L.U[L.cur] + off, L.plane(), c->box_noct[b], L.refined + c->box_off[b], c->cfg.gamma,
-                       c->cfg.rho_floor, c->cfg.p_floor, c->d_part + c->seg_off[b], err_ptr(c), c->stream))
-          return fail(c, RY_EHIP, "cfl kernel");
+        const int rc = launch_cfl(L.U[L.cur] + off, L.plane(), c->box_noct[b], L.refined + c->box_off[b],
+                                  c->cfg.gamma, c->cfg.rho_floor, c->cfg.p_floor, c->d_part + c->seg_off[b],
+                                  c->seg_off[b + 1] - c->seg_off[b], err_ptr(c), c->stream);
+        if (ry_status s = cfl_launch_status(c, rc, b)) return s;
       }
-    } else if (launch_cfl(L.U[L.cur], L.plane(), L.n_oct, L.refined, c->cfg.gamma, c->cfg.rho_floor,
-                          c->cfg.p_floor, c->d_part + c->seg_off[k], err_ptr(c), c->stream)) {
-      return fail(c, RY_EHIP, "cfl kernel");
+    } else {
+      const int rc = launch_cfl(L.U[L.cur], L.plane(), L.n_oct, L.refined, c->cfg.gamma, c->cfg.rho_floor,
+                                c->cfg.p_floor, c->d_part + c->seg_off[k], c->seg_off[k + 1] - c->seg_off[k],
+                                err_ptr(c), c->stream);
+      if (ry_status s = cfl_launch_status(c, rc, k)) return s;
     }
   }
   ry_status s = enqueue_seg_max(c);
@@ -350,6 +370,10 @@ ry_status enqueue_ghost(ry_ctx* c, int l, const int32_t* skip) {
   g.plane = L.plane();
   g.nv = c->dom.nv;
   g.skip = skip;
+  g.floors = c->d_floors;
+  g.gamma = c->cfg.gamma;
+  g.rho_floor = c->cfg.rho_floor;
+  g.p_floor = c->cfg.p_floor;
   TimedLaunch tl;
   if (c->timing) time_begin(c, "ghost", tl);
   if (launch_ghost(g, c->stream)) return fail(c, RY_EHIP, "ghost kernel");
@@ -385,11 +409,112 @@ HydroArgs hydro_args(ry_ctx* c, int l, int substep) {
   return a;
 }
 
-ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a) {
-  if (c->tune.persistent && launch_zero_u32(c->d_queue, 8 * QUEUE_STRIDE, c->stream)) return fail(c, RY_EHIP, "zero kernel");
+// Super-tile tables of level k (the 8^3-cell tile's work list): block keys
+// of the small tiles, a scan of the block starts, then each super-tile's
+// 6x6x6 oct neighbourhood assembled from its small tiles' tables.  Syncs
+// once (the super-tile count).  Not inside a graph capture.
+ry_status build_super(ry_ctx* c, int k) {
+  DevLevel& L = c->lev[k];
+  dfree(c, L.stab);
+  dfree(c, L.stflag);
+  L.stab = nullptr;
+  L.stflag = nullptr;
+  L.n_super = 0;
+  L.super_ok = false;
+  if (L.n_tile > 0) {
+    const int32_t nt = L.n_tile;
+    std::vector<void*> tmp;
+    auto A = [&](size_t bytes) {
+      void* p = dalloc(c, bytes);
+      if (p) tmp.push_back(p);
+      return p;
+    };
+    auto release = [&]() {
+      for (void* p : tmp) dfree(c, p);
+    };
+    auto* skey = static_cast<uint64_t*>(A(sizeof(uint64_t) * nt));
+    auto* ssub = static_cast<int32_t*>(A(sizeof(int32_t) * nt));
+    auto* start = static_cast<int32_t*>(A(sizeof(int32_t) * nt));
+    auto* excl = static_cast<int32_t*>(A(sizeof(int32_t) * nt));
+    const int ntmp = scan_tmp_ints(nt);
+    auto* stmp = static_cast<int32_t*>(A(sizeof(int32_t) * ntmp));
+    if (!skey || !ssub || !start || !excl || !stmp) {
+      release();
+      return fail(c, RY_ENOMEM, "super-tile tables: allocation failed");
+    }
+    int32_t ns = 0;
+    if (launch_super_keys(L.tab, nt, L.doc, L.n_oct, skey, ssub, start, c->stream) ||
+        launch_scan(start, excl, nt, stmp, c->stream) ||
+        hipMemcpyAsync(&ns, stmp + ntmp - 1, sizeof ns, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      release();
+      return fail(c, RY_EHIP, "super-tile key kernels");
+    }
+    auto* sub = static_cast<int32_t*>(A(sizeof(int32_t) * 8 * std::max(ns, 1)));
+    auto* sblock = static_cast<uint64_t*>(A(sizeof(uint64_t) * std::max(ns, 1)));
+    L.stab = static_cast<int32_t*>(dalloc(c, sizeof(int32_t) * super_table_slots() * std::max(ns, 1)));
+    L.stflag = static_cast<uint32_t*>(dalloc(c, sizeof(uint32_t) * std::max(ns, 1)));
+    if (!sub || !sblock || !L.stab || !L.stflag) {
+      release();
+      return fail(c, RY_ENOMEM, "super-tile tables: allocation failed");
+    }
+    SuperDom D{};
+    const int l = c->cfg.level_min + k;
+    for (int a = 0; a < 3; ++a) D.noct[a] = c->dom.noct(l, a);
+    for (int i = 0; i < 6; ++i) D.bc[i] = c->dom.bc[i];
+    if (launch_super_tables(L.tab, skey, ssub, start, excl, nt, ns, D, sub, sblock, L.stab, L.stflag, c->stream) ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      release();
+      return fail(c, RY_EHIP, "super-tile table kernels");
+    }
+    release();
+    L.n_super = ns;
+  }
+  L.super_ok = true;
+  return RY_OK;
+}
+
+// Super-tile tables for every level whose tuning uses the 8^3-cell tile
+// (after a mesh change, or a tuning change).
+ry_status ensure_super(ry_ctx* c) {
+  for (int k = 0; k < c->nlev; ++k) {
+    DevLevel& L = c->lev[k];
+    if (c->tune[k].tile_cells == 8 && !L.super_ok && L.n_oct > 0) {
+      ry_status s = build_super(c, k);
+      if (s) return s;
+    }
+  }
+  return RY_OK;
+}
+
+// Super-tile tables of every level are stale (the mesh changed).
+void drop_super(ry_ctx* c) {
+  for (auto& L : c->lev) {
+    dfree(c, L.stab);
+    dfree(c, L.stflag);
+    L.stab = nullptr;
+    L.stflag = nullptr;
+    L.n_super = 0;
+    L.super_ok = false;
+  }
+}
+
+// One hydro launch of level k with the level's tuning (or `t`): on the small
+// tiles or, for the 8^3-cell tile, on the level's super-tiles.
+ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a, int k, const ry_tuning* t = nullptr) {
+  const ry_tuning& tu = t ? *t : c->tune[k];
+  HydroArgs b = a;
+  if (tu.tile_cells == 8) {
+    const DevLevel& L = c->lev[k];
+    if (!L.super_ok) return fail(c, RY_ESTATE, "level %d: super-tile tables not built", c->cfg.level_min + k);
+    b.tab = L.stab;
+    b.tflag = L.stflag;
+    b.n_tile = L.n_super;
+  }
+  if (tu.persistent && launch_zero_u32(c->d_queue, 8 * QUEUE_STRIDE, c->stream)) return fail(c, RY_EHIP, "zero kernel");
   TimedLaunch tl;
   if (c->timing) time_begin(c, "hydro", tl);
-  if (launch_hydro(a, c->cfg.precision, c->cfg.nscalar, c->tune, c->num_cu, c->stream))
+  if (launch_hydro(b, c->cfg.precision, c->cfg.nscalar, tu, c->num_cu, c->stream))
     return fail(c, RY_EHIP, "hydro kernel");
   if (c->timing) time_end(c, tl);
   return RY_OK;
@@ -418,7 +543,7 @@ ry_status enqueue_level(ry_ctx* c, int l, int substep, bool last) {
   a.skip = skip_ptr(c);
   a.tile_smax = nullptr;
   a.smax_bits = last ? c->d_slots + int64_t(l - c->cfg.level_min) * SMAX_SLOTS : nullptr;
-  if ((s = enqueue_hydro(c, a))) return s;
+  if ((s = enqueue_hydro(c, a, l - c->cfg.level_min))) return s;
   if (fine && (s = enqueue_restrict(c, l, skip_ptr(c)))) return s;
   DevLevel& L = c->lev[l - c->cfg.level_min];
   L.cur ^= 1;
@@ -521,6 +646,7 @@ ry_status ry_create(const ry_config* cfg, ry_ctx** out) {
   c->cfg = *cfg;
   c->dom = make_dom(*cfg);
   c->nlev = cfg->level_max - cfg->level_min + 1;
+  std::fill(std::begin(c->tune), std::end(c->tune), kDefaultTuning);
   if ((s = init_common(c))) {
     delete c;
     return s;
@@ -590,6 +716,7 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
   std::fill(std::begin(c->count), std::end(c->count), 0);
   if ((s = enqueue_cfl_all(c))) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if ((s = ensure_super(c))) return s;
   for (auto& h : H) std::vector<double>().swap(h.U);
   c->host = std::move(H);
   c->host_valid = true;
@@ -776,8 +903,10 @@ ry_status finish_regrid(ry_ctx* c) {
       return fail(c, RY_EHIP, "restrict kernel");
   }
   drop_graphs(c);
+  drop_super(c);
   std::fill(std::begin(c->count), std::end(c->count), 0);
   c->slots_valid = false;
+  if ((s = ensure_super(c))) return s;
   if ((s = enqueue_cfl_all(c))) return s;
   return sync_and_check(c);
 }
@@ -1151,7 +1280,7 @@ ry_status ry_hydro_step(ry_ctx* c, int32_t level, double dt) {
   a.lam_host = dt / level_dx(c, level);
   a.skip = nullptr;
   a.tile_smax = nullptr;
-  if ((s = enqueue_hydro(c, a))) return s;
+  if ((s = enqueue_hydro(c, a, k))) return s;
   if (fine && (s = enqueue_restrict(c, level, nullptr))) return s;
   c->lev[k].cur ^= 1;
   c->dt_of[k] = dt;
@@ -1209,6 +1338,12 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
   if (launch_zero_u32(reinterpret_cast<unsigned int*>(c->d_flags), 3, c->stream))
     return fail(c, RY_EHIP, "zero kernel");
   const bool use_graph = !c->timing;
+  // Buffer parity of the base level before the steps: each executed coarse
+  // step flips it once (finer levels take two substeps per coarse step, so
+  // theirs come back).  Steps enqueued after t_end is reached are skipped on
+  // the device and write nothing, so the parity is set from the device's
+  // count of executed steps afterwards, not from the number enqueued.
+  const int cur0 = c->lev[0].cur;
   for (int32_t i = 0; i < n_coarse;) {
     if (use_graph) {
       const int par = c->lev[0].cur;
@@ -1231,6 +1366,10 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
   }
   c->slots_valid = true;
   if ((s = sync_and_check(c))) return s;
+  int32_t nrun = 0;
+  HIPCHK(c, hipMemcpy(&nrun, nstep_ptr(c), sizeof nrun, hipMemcpyDeviceToHost));
+  if (nrun < 0 || nrun > n_coarse) return fail(c, RY_EHIP, "device step count %d out of range", nrun);
+  c->lev[0].cur = cur0 ^ (nrun & 1);
   HIPCHK(c, hipMemcpy(t_io, c->d_t, sizeof(double), hipMemcpyDeviceToHost));
   return RY_OK;
   RY_ABI_CATCH
@@ -1305,7 +1444,7 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
   // the plain launch (one wavefront per tile, the hardware dispatcher as the
   // queue) measures fastest for batches too; the queue-fed persistent
   // kernel stays an autotuner candidate
-  c->tune = ry_tuning{1, 0, 4, 1, 1};
+  std::fill(std::begin(c->tune), std::end(c->tune), kDefaultTuning);
   ry_status s = init_common(c);
   if (s) {
     delete c;
@@ -1413,7 +1552,7 @@ static ry_status enqueue_batch_step(ry_ctx* c) {
   a.tile_box = L.tile_box;
   a.tile_smax = c->d_part;
   a.skip = nullptr;
-  ry_status s = enqueue_hydro(c, a);
+  ry_status s = enqueue_hydro(c, a, 0);
   if (s) return s;
   L.cur ^= 1;
   return RY_OK;
@@ -1481,21 +1620,53 @@ ry_status ry_batch_download(ry_ctx* c, int32_t box, double* U) {
 }
 
 // ---------------------------------------------------------------- tuning
-ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
-  RY_ABI_TRY
-  if (!c || !t) return RY_EINVAL;
-  if (t->tiles_per_wg != 1 && t->tiles_per_wg != 2 && t->tiles_per_wg != 4) return RY_EINVAL;
-  if (t->waves_per_tile != 1 && t->waves_per_tile != 2 && t->waves_per_tile != 4) return RY_EINVAL;
-  if (t->tiles_per_wg * t->waves_per_tile > 4) return RY_EINVAL;
-  if (!hydro_tuning_supported(c->cfg.precision, c->cfg.nscalar, *t)) return RY_EINVAL;
-  if (t->persistent && (t->waves_per_cu < 1 || t->waves_per_cu > 32 || t->batch < 1 || t->batch > 64))
-    return RY_EINVAL;
-  c->tune = *t;
+namespace {
+
+bool same_tuning(const ry_tuning& a, const ry_tuning& b) {
+  return a.tiles_per_wg == b.tiles_per_wg && a.persistent == b.persistent && a.waves_per_cu == b.waves_per_cu &&
+         a.batch == b.batch && a.waves_per_tile == b.waves_per_tile && a.tile_cells == b.tile_cells;
+}
+
+// Whether the context can run a tuning (RY_OK) or not (RY_EINVAL, with the
+// reason).
+ry_status check_tuning(ry_ctx* c, const ry_tuning& t) {
+  if (t.tile_cells == 8) {
+    if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent)
+      return fail(c, RY_EINVAL, "tile_cells 8 needs tiles_per_wg 1, waves_per_tile 8, persistent 0");
+    if (c->batch) return fail(c, RY_EINVAL, "batched boxes run on 4^3-cell tiles");
+  } else if (t.tile_cells == 4) {
+    if (t.tiles_per_wg != 1 && t.tiles_per_wg != 2 && t.tiles_per_wg != 4) return fail(c, RY_EINVAL, "tiles_per_wg");
+    if (t.waves_per_tile != 1 && t.waves_per_tile != 2 && t.waves_per_tile != 4)
+      return fail(c, RY_EINVAL, "waves_per_tile");
+    if (t.tiles_per_wg * t.waves_per_tile > 4) return fail(c, RY_EINVAL, "tiles_per_wg * waves_per_tile > 4");
+  } else {
+    return fail(c, RY_EINVAL, "tile_cells must be 4 or 8");
+  }
+  if (!hydro_tuning_supported(c->cfg.precision, c->cfg.nscalar, t))
+    return fail(c, RY_EINVAL, "no hydro kernel for this tuning (precision / passive scalars)");
+  if (t.persistent && (t.waves_per_cu < 1 || t.waves_per_cu > 32 || t.batch < 1 || t.batch > 64))
+    return fail(c, RY_EINVAL, "persistent launch: waves_per_cu 1..32, batch 1..64");
+  return RY_OK;
+}
+
+void drop_all_graphs(ry_ctx* c) {
   drop_graphs(c);
   if (c->bgraph) {
     hipGraphExecDestroy(c->bgraph);
     c->bgraph = nullptr;
   }
+}
+
+}  // namespace
+
+ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
+  RY_ABI_TRY
+  if (!c || !t) return RY_EINVAL;
+  ry_status s = check_tuning(c, *t);
+  if (s) return s;
+  std::fill(std::begin(c->tune), std::end(c->tune), *t);
+  drop_all_graphs(c);
+  if (c->built && (s = ensure_super(c))) return s;
   return RY_OK;
   RY_ABI_CATCH
 }
@@ -1503,37 +1674,52 @@ ry_status ry_set_tuning(ry_ctx* c, const ry_tuning* t) {
 ry_status ry_get_tuning(const ry_ctx* c, ry_tuning* t) {
   RY_ABI_TRY
   if (!c || !t) return RY_EINVAL;
-  *t = c->tune;
+  *t = c->tune[0];
   return RY_OK;
   RY_ABI_CATCH
 }
 
-// Time the hydro kernels of one coarse step (every level, weighted by its
-// substeps) for a tuning, writing only the scratch buffers.
-static ry_status time_tuning(ry_ctx* c, const ry_tuning& t, double* ms_out) {
-  ry_tuning saved = c->tune;
-  c->tune = t;
+ry_status ry_set_level_tuning(ry_ctx* c, int32_t level, const ry_tuning* t) {
+  RY_ABI_TRY
+  if (!c || !t || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
+  ry_status s = check_tuning(c, *t);
+  if (s) return s;
+  c->tune[level - c->cfg.level_min] = *t;
+  drop_all_graphs(c);
+  if (c->built && (s = ensure_super(c))) return s;
+  return RY_OK;
+  RY_ABI_CATCH
+}
+
+ry_status ry_get_level_tuning(const ry_ctx* c, int32_t level, ry_tuning* t) {
+  RY_ABI_TRY
+  if (!c || !t || level < c->cfg.level_min || level > c->cfg.level_max) return RY_EINVAL;
+  *t = c->tune[level - c->cfg.level_min];
+  return RY_OK;
+  RY_ABI_CATCH
+}
+
+// Time level k's hydro launch under tuning t (four launches, the best of the
+// last three), writing only the level's other state buffer.
+static ry_status time_level(ry_ctx* c, int k, const ry_tuning& t, double* ms_out) {
   hipEvent_t a, b;
   hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
   hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
   double best = INFINITY;
   ry_status s = RY_OK;
+  const int l = c->cfg.level_min + k;
+  HydroArgs h = hydro_args(c, l, 0);
+  h.lam_dev = c->batch ? c->d_lam : nullptr;
+  h.lam_host = 0.1;
+  h.record_reg = 0;
+  h.reg_own = nullptr;
+  h.tile_smax = nullptr;
+  h.floors = nullptr;
+  h.err = nullptr;
+  h.skip = nullptr;
   for (int rep = 0; rep < 4 && !s; ++rep) {
     hipEventRecord(a, c->stream);
-    for (int k = 0; k < c->nlev && !s; ++k) {
-      const int l = c->cfg.level_min + k;
-      if (!level_nonempty(c, l)) continue;
-      HydroArgs h = hydro_args(c, l, 0);
-      h.lam_dev = c->batch ? c->d_lam : nullptr;
-      h.lam_host = 0.1;
-      h.record_reg = 0;
-      h.reg_own = nullptr;
-      h.tile_smax = nullptr;
-      h.floors = nullptr;
-      h.err = nullptr;
-      h.skip = nullptr;
-      for (int r = 0; r < (1 << k) && !s; ++r) s = enqueue_hydro(c, h);
-    }
+    s = enqueue_hydro(c, h, k, &t);
     hipEventRecord(b, c->stream);
     hipEventSynchronize(b);
     float ms = 0.f;
@@ -1542,7 +1728,6 @@ static ry_status time_tuning(ry_ctx* c, const ry_tuning& t, double* ms_out) {
   }
   hipEventDestroy(a);
   hipEventDestroy(b);
-  c->tune = saved;
   *ms_out = best;
   return s;
 }
@@ -1558,66 +1743,95 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
   std::vector<ry_tuning> cand;
   for (int wpt : {1, 2, 4})
     for (int tpw : {1, 2, 4})
-      if (tpw * wpt <= 4) cand.push_back({tpw, 0, 4, 1, wpt});
+      if (tpw * wpt <= 4) cand.push_back({tpw, 0, 4, 1, wpt, 4});
   for (int wpt : {1, 2, 4})
     for (int w : {8, 14, 20})
-      for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt});
-  cand.erase(std::remove_if(cand.begin(), cand.end(),
-                            [&](const ry_tuning& t) {
-                              return !hydro_tuning_supported(c->cfg.precision, c->cfg.nscalar, t);
-                            }),
-             cand.end());
-  // stage 1: every candidate once (best of three timed repetitions)
-  std::vector<double> t1(cand.size());
-  for (size_t i = 0; i < cand.size(); ++i) {
-    ry_status s = time_tuning(c, cand[i], &t1[i]);
-    if (s) return s;
-    if (times_ms && int32_t(i) < max_cand) times_ms[i] = t1[i];
+      for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt, 4});
+  cand.push_back({1, 0, 4, 1, 8, 8});
+  {
+    std::string keep = c->err;
+    cand.erase(std::remove_if(cand.begin(), cand.end(), [&](const ry_tuning& t) { return check_tuning(c, t) != RY_OK; }),
+               cand.end());
+    c->err = keep;
   }
   const int n = int(cand.size());
   if (n_cand) *n_cand = n;
-  // stage 2: the three fastest and the default launch, timed again in six
+  // the 8^3-cell tile's tables of every level
+  ry_tuning saved[RY_MAX_LEVELS];
+  std::copy(std::begin(c->tune), std::end(c->tune), saved);
+  bool any8 = false;
+  for (const auto& t : cand) any8 = any8 || t.tile_cells == 8;
+  if (any8) {
+    std::fill(std::begin(c->tune), std::end(c->tune), cand.back());
+    ry_status s = ensure_super(c);
+    std::copy(std::begin(saved), std::end(saved), c->tune);
+    if (s) return s;
+  }
+  // per level: stage 1 times every candidate once (best of three launches);
+  // stage 2 times the three fastest and the default launch again in six
   // interleaved rounds (drift and noise hit all alike); the median decides,
   // and a candidate must beat the default by more than 2% to replace it
   // (isolated launches and the production sequence differ by a few percent)
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return t1[a] < t1[b]; });
-  auto same = [](const ry_tuning& a, const ry_tuning& b) {
-    return a.tiles_per_wg == b.tiles_per_wg && a.persistent == b.persistent && a.waves_per_cu == b.waves_per_cu &&
-           a.batch == b.batch && a.waves_per_tile == b.waves_per_tile;
-  };
-  const ry_tuning def{1, 0, 4, 1, 1};
-  std::vector<ry_tuning> fin;
-  for (int i = 0; i < n && i < 3; ++i) fin.push_back(cand[order[i]]);
-  int idef = -1;
-  for (size_t i = 0; i < fin.size(); ++i)
-    if (same(fin[i], def)) idef = int(i);
-  if (idef < 0 && hydro_tuning_supported(c->cfg.precision, c->cfg.nscalar, def)) {
-    fin.push_back(def);
-    idef = int(fin.size()) - 1;
-  }
-  std::vector<std::vector<double>> t2(fin.size());
-  for (int round = 0; round < 6; ++round)
-    for (size_t i = 0; i < fin.size(); ++i) {
-      double ms = 0;
-      ry_status s = time_tuning(c, fin[i], &ms);
+  std::vector<double> coarse(n, 0.0);   // per candidate: the coarse step's hydro time if used on every level
+  ry_tuning chosen[RY_MAX_LEVELS];
+  std::copy(std::begin(saved), std::end(saved), chosen);
+  for (int k = 0; k < c->nlev; ++k) {
+    if (c->lev[k].n_tile == 0) continue;
+    std::vector<double> t1(n);
+    for (int i = 0; i < n; ++i) {
+      ry_status s = time_level(c, k, cand[i], &t1[i]);
       if (s) return s;
-      t2[i].push_back(ms);
+      coarse[i] += std::ldexp(t1[i], k);
     }
-  std::vector<double> med(fin.size());
-  for (size_t i = 0; i < fin.size(); ++i) {
-    std::sort(t2[i].begin(), t2[i].end());
-    med[i] = 0.5 * (t2[i][2] + t2[i][3]);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return t1[a] < t1[b]; });
+    std::vector<ry_tuning> fin;
+    for (int i = 0; i < n && i < 3; ++i) fin.push_back(cand[order[i]]);
+    int idef = -1;
+    for (size_t i = 0; i < fin.size(); ++i)
+      if (same_tuning(fin[i], kDefaultTuning)) idef = int(i);
+    if (idef < 0 && hydro_tuning_supported(c->cfg.precision, c->cfg.nscalar, kDefaultTuning)) {
+      fin.push_back(kDefaultTuning);
+      idef = int(fin.size()) - 1;
+    }
+    std::vector<std::vector<double>> t2(fin.size());
+    for (int round = 0; round < 6; ++round)
+      for (size_t i = 0; i < fin.size(); ++i) {
+        double ms = 0;
+        ry_status s = time_level(c, k, fin[i], &ms);
+        if (s) return s;
+        t2[i].push_back(ms);
+      }
+    std::vector<double> med(fin.size());
+    for (size_t i = 0; i < fin.size(); ++i) {
+      std::sort(t2[i].begin(), t2[i].end());
+      med[i] = 0.5 * (t2[i][2] + t2[i][3]);
+    }
+    int ib = 0;
+    for (size_t i = 1; i < fin.size(); ++i)
+      if (med[i] < med[ib]) ib = int(i);
+    if (idef >= 0 && ib != idef && med[idef] <= 1.02 * med[ib]) ib = idef;
+    chosen[k] = fin[ib];
   }
-  int ib = 0;
-  for (size_t i = 1; i < fin.size(); ++i)
-    if (med[i] < med[ib]) ib = int(i);
-  if (idef >= 0 && ib != idef && med[idef] <= 1.02 * med[ib]) ib = idef;
-  ry_tuning bt = fin[ib];
-  ry_status s = ry_set_tuning(c, &bt);
+  if (times_ms)
+    for (int i = 0; i < n && i < max_cand; ++i) times_ms[i] = coarse[i];
+  std::copy(std::begin(chosen), std::end(chosen), c->tune);
+  drop_all_graphs(c);
+  // tables of levels left without the 8^3-cell tile are not needed any more
+  for (int k = 0; k < c->nlev; ++k)
+    if (c->tune[k].tile_cells != 8 && c->lev[k].super_ok) {
+      DevLevel& L = c->lev[k];
+      dfree(c, L.stab);
+      dfree(c, L.stflag);
+      L.stab = nullptr;
+      L.stflag = nullptr;
+      L.n_super = 0;
+      L.super_ok = false;
+    }
+  ry_status s = ensure_super(c);
   if (s) return s;
-  if (best) *best = bt;
+  if (best) *best = c->tune[0];
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return RY_OK;
   RY_ABI_CATCH

@@ -1,5 +1,6 @@
 // Hydro-only (no passive scalar) instantiations of the per-tile hydro
-// kernel, FP64 and mixed, every supported launch shape.  Compiled on its own
+// kernel, FP64 and mixed, every supported launch shape and both tile sizes
+// (4^3 and 8^3 cells).  Compiled on its own
 // so that its scheduling options do not apply to the other kernels.
 #include <hip/hip_runtime.h>
 
@@ -10,6 +11,11 @@ namespace ry {
 
 int launch_hydro_plain(const HydroArgs& a, int precision, const ry_tuning& t, int num_cu, void* stream) {
   hipStream_t s = (hipStream_t)stream;
+  if (t.tile_cells == 8) {
+    if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent) return -1;
+    return precision == RY_MIXED ? launch_hydro_t<float, 1, 8, 0, 8>(a, t, num_cu, s)
+                                 : launch_hydro_t<double, 1, 8, 0, 8>(a, t, num_cu, s);
+  }
   const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
   if (precision == RY_MIXED) {
     switch (key) {

@@ -1,17 +1,21 @@
 // Per-tile hydro update of the octree MUSCL-Hancock / MinMod / HLLC step
 // (gfx950 device code; included by kernels.hip and hydro.hip).
 //
-// Work unit: a tile = an aligned 2x2x2 block of octs (4x4x4 cells, the octs
-// sharing their Hilbert key except for the lowest 3 bits), handled by 1, 2
-// or 4 wavefronts of one workgroup; the tile's primitive-variable stencil
-// (304 positions of the 8x8x8 box around the 4x4x4 core) is staged in LDS
-// once and shared by the tile's 64 cells.  Phases per tile:
-//   A  gather U of the 304 stencil positions through the tile's 4x4x4 table
-//      of neighbouring octs (real or ghost), convert to primitives -> LDS
-//   B1 MinMod slopes and the half-step predictor for the 160 cells that
-//      border a flux face (the 64 core cells + one layer per face), kept in
-//      registers by the thread that owns the cell
-//   B2 the left states W~ + D/2 of the 240 faces replace the stencil in LDS
+// Work unit: a tile = an aligned block of K x K x K cells, K = 4 (2x2x2
+// octs, the octs sharing their Hilbert key except for the lowest 3 bits) or
+// K = 8 (4x4x4 octs, a "super-tile" assembled from up to 8 small tiles),
+// handled by the threads of one workgroup; the tile's primitive-variable
+// stencil (the positions of the (K+4)^3 box around the K^3 core that the
+// scheme reads) is staged in LDS once and shared by the tile's cells, so the
+// larger tile converts, predicts and solves fewer halo positions per cell
+// (per cell: 4.75 / 2.5 / 3.75 primitives / predictions / faces at K = 4,
+// 2.69 / 1.75 / 3.375 at K = 8).  Phases per tile:
+//   A  gather U of the stencil positions through the tile's table of
+//      neighbouring octs (real or ghost), convert to primitives -> LDS
+//   B1 MinMod slopes and the half-step predictor for the cells that border
+//      a flux face (the core cells + one layer per face), kept in registers
+//      by the thread that owns the cell
+//   B2 the left states W~ + D/2 of the faces replace the stencil in LDS
 //   C  HLLC on each face by the thread owning its upper cell (the right
 //      state W~ - D/2 never leaves registers); fluxes -> LDS
 //   D  per core cell: coarse-fine register override, conservative FP64
@@ -24,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "ry_internal.h"
 
@@ -37,101 +42,146 @@ namespace ry {
 #pragma clang fp contract(on)
 
 // ---------------------------------------------------------------------------
-// Tile geometry.  Stencil positions s in [-2,5]^3 relative to the tile's
-// first cell.  The primitives that are needed sit in LDS as the 6^3 box
-// [-1,4]^3 (strides 1, WB, WBB) followed by the six 4x4 far planes at -2
-// and 5 (x-, x+, y-, y+, z-, z+); only the one-layer cells next to a far
+// Tile geometry.  Stencil positions s in [-2,K+1]^3 relative to the tile's
+// first cell.  The primitives that are needed sit in LDS as the (K+2)^3 box
+// [-1,K]^3 (strides 1, WB, WBB) followed by the six K x K far planes at -2
+// and K+1 (x-, x+, y-, y+, z-, z+); only the one-layer cells next to a far
 // plane read it.
 // ---------------------------------------------------------------------------
-constexpr int WB = 6, WBB = 36, NBOX = 216;
-constexpr int WSIZE = NBOX + 6 * 16;   // primitives per variable
-constexpr int NPOS_A = 304;   // positions whose primitives are needed
-constexpr int NPOS_B = 160;   // positions that get a predicted state (core + one layer per face)
-constexpr int NCORE = 64;     // B positions 0..63: the core cells, x fastest
-constexpr int NUPPER = 48;    // B positions 64..111: the upper one-layer cells
-constexpr int NFACE = 240;    // 3 directions x 5 planes x 16
-__host__ __device__ constexpr int widx(int x, int y, int z) {
-  return (x >= -1 && x <= 4 && y >= -1 && y <= 4 && z >= -1 && z <= 4)
-             ? (x + 1) + WB * (y + 1) + WBB * (z + 1)
-             : (x == -2  ? NBOX + y + 4 * z
-                : x == 5  ? NBOX + 16 + y + 4 * z
-                : y == -2 ? NBOX + 32 + x + 4 * z
-                : y == 5  ? NBOX + 48 + x + 4 * z
-                : z == -2 ? NBOX + 64 + x + 4 * y
-                          : NBOX + 80 + x + 4 * y);
-}
-// Face index of the face along d whose upper cell is (x, y, z) (the plane
-// coordinate runs 0..4, the transverse ones 0..3); x runs fastest in every
-// direction so that neighbouring lanes touch neighbouring LDS words.
-__host__ __device__ constexpr int fidx(int d, int x, int y, int z) {
-  return d == 0 ? x + 5 * y + 20 * z : (d == 1 ? 80 + x + 4 * y + 20 * z : 160 + x + 4 * y + 16 * z);
-}
+template <int K>
+struct Geom {
+  static_assert(K == 4 || K == 8, "tile edge of 4 or 8 cells");
+  static constexpr int LK = (K == 4) ? 2 : 3;            // log2 K
+  // box rows and planes, each padded past its K + 2 entries (LDS bank spread)
+  static constexpr int PAD_ROW = 0, PAD_PLANE = 0;
+  static constexpr int WB = K + 2 + PAD_ROW, WBB = WB * (K + 2) + PAD_PLANE, NBOX = WBB * (K + 2);
+  static constexpr int WSIZE = NBOX + 6 * K * K;         // primitives per variable
+  static constexpr int NPOS_A = K * K * K + 12 * K * K + 12 * K;   // positions whose primitives are needed
+  static constexpr int NPOS_B = K * K * K + 6 * K * K;   // positions that get a predicted state
+  static constexpr int NCORE = K * K * K;                // B positions 0..NCORE-1: the core cells, x fastest
+  static constexpr int NUPPER = 3 * K * K;               // then the upper one-layer cells, then the lower ones
+  static constexpr int NFACE = 3 * (K + 1) * K * K;      // 3 directions x (K+1) planes x K^2
+  static constexpr int KO = K / 2;                       // octs per tile edge
+  static constexpr int TS = KO + 2;                      // oct neighbourhood edge (one oct of halo)
+  static constexpr int TAB = TS * TS * TS;               // oct neighbourhood entries per tile
+  static constexpr int R = K + 4;                        // stencil positions per axis
+  // table a entry: LDS index | oct slot | in-oct cell | raw position
+  static constexpr int A_LB = (K == 4) ? 10 : 11, A_SB = (K == 4) ? 6 : 8;
+  static constexpr int A_CS = A_LB + A_SB, A_RS = A_CS + 3;
+  // table b entry (one-layer cells): cell LDS index | far-plane neighbour
+  // LDS index | normal axis | upper layer | face between the cell and the core
+  static constexpr int B_LB = (K == 4) ? 9 : 11;
+  static constexpr int B_DS = 2 * B_LB, B_US = B_DS + 2, B_FS = B_US + 1;
+  using EntA = std::conditional_t<K == 4, uint32_t, uint64_t>;
+  using EntB = std::conditional_t<K == 4, uint32_t, uint64_t>;
+  static_assert(WSIZE < (1 << B_LB) && WSIZE < (1 << A_LB) && TAB <= (1 << A_SB), "LDS / slot fields");
+  static_assert(int64_t(R) * R * R <= (int64_t(1) << (8 * sizeof(EntA) - A_RS)), "raw position field");
+  static_assert(NFACE <= (int64_t(1) << (8 * sizeof(EntB) - B_FS)), "face field");
 
-// Per-item constants, computed at compile time:
-//  a[i]: bits 0-9 LDS index, 10-15 oct-table slot, 16-18 in-oct cell,
-//        19-27 raw (x+2)+8(y+2)+64(z+2) of stencil position i
-//  b[i], i >= NCORE (one-layer cells: 48 upper ones at coordinate 4 along
-//        their normal, then 48 lower ones at -1): bits 0-8 LDS index of the
-//        cell, 9-17 LDS index of its outward neighbour (a far plane), 18-19
-//        normal axis, 20 upper layer, 21-28 the face (fidx) between the cell
-//        and the core.  b[i < NCORE] = LDS index of core cell i.
-struct StencilTables {
-  uint32_t a[NPOS_A];
-  uint32_t b[NPOS_B];
+  __host__ __device__ static constexpr int widx(int x, int y, int z) {
+    return (x >= -1 && x <= K && y >= -1 && y <= K && z >= -1 && z <= K)
+               ? (x + 1) + WB * (y + 1) + WBB * (z + 1)
+               : (x == -2      ? NBOX + y + K * z
+                  : x == K + 1 ? NBOX + K * K + y + K * z
+                  : y == -2    ? NBOX + 2 * K * K + x + K * z
+                  : y == K + 1 ? NBOX + 3 * K * K + x + K * z
+                  : z == -2    ? NBOX + 4 * K * K + x + K * y
+                               : NBOX + 5 * K * K + x + K * y);
+  }
+  // Face index of the face along d whose upper cell is (x, y, z) (the plane
+  // coordinate runs 0..K, the transverse ones 0..K-1); x runs fastest in
+  // every direction so that neighbouring lanes touch neighbouring LDS words.
+  __host__ __device__ static constexpr int fidx(int d, int x, int y, int z) {
+    return d == 0 ? x + (K + 1) * y + (K + 1) * K * z
+                  : (d == 1 ? (K + 1) * K * K + x + K * y + K * (K + 1) * z
+                            : 2 * (K + 1) * K * K + x + K * y + K * K * z);
+  }
+  // Slot of the oct at oct offset (ox, oy, oz) from the tile's first oct
+  // (-1 .. KO) in the tile's oct neighbourhood table.
+  __host__ __device__ static constexpr int slot(int ox, int oy, int oz) {
+    return (ox + 1) + TS * (oy + 1) + TS * TS * (oz + 1);
+  }
 };
 
-constexpr StencilTables make_tables() {
-  StencilTables t{};
+// Per-item constants, computed at compile time:
+//  a[i]: LDS index, oct-table slot, in-oct cell and raw (x+2) + R (y+2) +
+//        R^2 (z+2) of stencil position i (fields as Geom<K>::A_*)
+//  b[i], i >= NCORE (one-layer cells: the upper ones at coordinate K along
+//        their normal, then the lower ones at -1): LDS index of the cell, LDS
+//        index of its outward neighbour (a far plane), normal axis, upper
+//        layer, the face between the cell and the core (fields as
+//        Geom<K>::B_*).  b[i < NCORE] = LDS index of core cell i.
+template <int K>
+struct StencilTables {
+  typename Geom<K>::EntA a[Geom<K>::NPOS_A];
+  typename Geom<K>::EntB b[Geom<K>::NPOS_B];
+};
+
+template <int K>
+constexpr StencilTables<K> make_tables() {
+  using G = Geom<K>;
+  using EA = typename G::EntA;
+  using EB = typename G::EntB;
+  StencilTables<K> t{};
   int na = 0;
-  for (int z = -2; z <= 5; ++z)
-    for (int y = -2; y <= 5; ++y)
-      for (int x = -2; x <= 5; ++x) {
-        const int ox = (x < 0 || x > 3), oy = (y < 0 || y > 3), oz = (z < 0 || z > 3);
+  for (int z = -2; z <= K + 1; ++z)
+    for (int y = -2; y <= K + 1; ++y)
+      for (int x = -2; x <= K + 1; ++x) {
+        const int ox = (x < 0 || x > K - 1), oy = (y < 0 || y > K - 1), oz = (z < 0 || z > K - 1);
         const int nout = ox + oy + oz;
-        const bool ex = (x == -1 || x == 4), ey = (y == -1 || y == 4), ez = (z == -1 || z == 4);
+        const bool ex = (x == -1 || x == K), ey = (y == -1 || y == K), ez = (z == -1 || z == K);
         const bool edges = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
         if ((nout <= 1) || (nout == 2 && edges)) {
-          const int slot = ((x >> 1) + 1) + 4 * ((y >> 1) + 1) + 16 * ((z >> 1) + 1);
+          const int slot = G::slot(x >> 1, y >> 1, z >> 1);
           const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-          const int raw = (x + 2) + 8 * (y + 2) + 64 * (z + 2);
-          t.a[na++] = uint32_t(widx(x, y, z) | (slot << 10) | (cb << 16) | (raw << 19));
+          const int raw = (x + 2) + G::R * (y + 2) + G::R * G::R * (z + 2);
+          t.a[na++] = EA(G::widx(x, y, z)) | (EA(slot) << G::A_LB) | (EA(cb) << G::A_CS) | (EA(raw) << G::A_RS);
         }
       }
-  for (int i = 0; i < NCORE; ++i) t.b[i] = uint32_t(widx(i & 3, (i >> 2) & 3, i >> 4));
-  int nb = NCORE;
+  for (int i = 0; i < G::NCORE; ++i) t.b[i] = EB(G::widx(i % K, (i / K) % K, i / (K * K)));
+  int nb = G::NCORE;
   for (int up = 1; up >= 0; --up)
     for (int d = 0; d < 3; ++d)
-      for (int t2 = 0; t2 < 4; ++t2)
-        for (int t1 = 0; t1 < 4; ++t1) {
+      for (int t2 = 0; t2 < K; ++t2)
+        for (int t1 = 0; t1 < K; ++t1) {
           int c[3] = {0, 0, 0};
-          c[d] = up ? 4 : -1;
+          c[d] = up ? K : -1;
           c[d == 0 ? 1 : 0] = t1;
           c[d == 2 ? 1 : 2] = t2;
           int o[3] = {c[0], c[1], c[2]};
           o[d] += up ? 1 : -1;
           int u[3] = {c[0], c[1], c[2]};
           if (!up) u[d] += 1;
-          const int face = fidx(d, u[0], u[1], u[2]);
-          t.b[nb++] = uint32_t(widx(c[0], c[1], c[2]) | (widx(o[0], o[1], o[2]) << 9) | (d << 18) | (up << 20) |
-                               (face << 21));
+          const int face = G::fidx(d, u[0], u[1], u[2]);
+          t.b[nb++] = EB(G::widx(c[0], c[1], c[2])) | (EB(G::widx(o[0], o[1], o[2])) << G::B_LB) |
+                      (EB(d) << G::B_DS) | (EB(up) << G::B_US) | (EB(face) << G::B_FS);
         }
   return t;
 }
-static __constant__ StencilTables c_st = make_tables();
-static_assert(make_tables().a[NPOS_A - 1] != 0 && make_tables().b[NPOS_B - 1] != 0, "stencil tables");
-static_assert(WSIZE < 512 && NFACE < 256, "LDS indices must fit the table fields");
+static __constant__ StencilTables<4> c_st4 = make_tables<4>();
+static __constant__ StencilTables<8> c_st8 = make_tables<8>();
+static_assert(make_tables<4>().a[Geom<4>::NPOS_A - 1] != 0 && make_tables<4>().b[Geom<4>::NPOS_B - 1] != 0,
+              "stencil tables");
+static_assert(make_tables<8>().a[Geom<8>::NPOS_A - 1] != 0 && make_tables<8>().b[Geom<8>::NPOS_B - 1] != 0,
+              "stencil tables");
+template <int K>
+__device__ __forceinline__ const StencilTables<K>& stencil_tables() {
+  if constexpr (K == 4) return c_st4;
+  else return c_st8;
+}
 
 // One LDS buffer serves three phases in turn: primitives [NVAR][WSIZE] (A,
 // B1), then the left face states [NVAR][NFACE] and the upper one-layer
 // cells' right states [NVAR][NUPPER] (B2 -> C), then the face fluxes
 // [NVAR][NFACE] (C -> D).  Fluxes are stored in Real: in the mixed
 // form they are FP32 results, so FP32 storage loses nothing.
-template <typename Real, int NV>
+template <typename Real, int NV, int K>
 struct TileLDS {
-  static constexpr int NW = NV * WSIZE, NF = NV * (NFACE + NUPPER);
+  using G = Geom<K>;
+  static constexpr int NW = NV * G::WSIZE, NF = NV * (G::NFACE + G::NUPPER);
   Real buf[NW > NF ? NW : NF];
-  int32_t tab[TILE_TAB];  // ext oct index of the 4x4x4 oct neighbourhood
-  uint8_t ref[TILE_TAB];  // refined-cell bytes of those octs
+  int32_t tab[G::TAB];  // ext oct index of the oct neighbourhood
+  uint8_t ref[G::TAB];  // refined-cell bytes of those octs
 };
 
 // ---------------------------------------------------------------------------
@@ -292,7 +342,7 @@ __device__ __forceinline__ void floor_state(Real* s, Real rf, Real pf, int& nfl)
 // comes from LDS (FL[var * NFACE + f]), the right one, W~ - D/2, from the
 // cell's predicted state Pw and slope Pdd along D.  The HLLC runs in the
 // face-normal frame; F is returned in the global frame.
-template <typename Real, int D, int NS>
+template <typename Real, int D, int NS, int NFACE>
 __device__ __forceinline__ void core_face_flux(const Real* FL, int f, const Real Pw[NVAR + NS],
                                                const Real Pdd[NVAR + NS], Real rf, Real pf, Real g, Real igm1,
                                                int& nfl, Real F[NVAR + NS]) {
@@ -335,9 +385,10 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 }
 
 // ---------------------------------------------------------------------------
-// The per-tile hydro update.  NT = threads cooperating on one tile (64, 128
-// or 256: 8, 16 or 32 threads per oct).  `active` is uniform over the NT
-// threads; an inactive group only keeps the workgroup's barrier count.
+// The per-tile hydro update.  NT = threads cooperating on one tile: 64, 128
+// or 256 for K = 4 (8, 16 or 32 threads per oct), 512 for K = 8 (one thread
+// per core cell).  `active` is uniform over the NT threads; an inactive
+// group only keeps the workgroup's barrier count.
 // ---------------------------------------------------------------------------
 // Hides a value from the optimiser so that per-thread table loads are issued
 // per tile instead of being hoisted (and held in registers) across the tile
@@ -347,43 +398,99 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
-template <typename Real, int NT, int NS>
-__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS>& S, int tid_in,
+// Floor activations are counted once per event of the step, although a tile
+// recomputes halo values that neighbouring tiles compute too: a leaf cell's
+// own primitive conversion by the tile holding the cell, the face states of
+// a face by the tile holding its upper cell when that is a leaf, else its
+// lower cell (ghost cells are counted once per parent step by the ghost
+// kernel).  The checks run only where a floor was applied.
+// Kind of the cell at tile position (x, y, z), each in [-1, K]: 1 a leaf
+// cell, 2 a refined cell, 0 otherwise (a ghost cell, or past an outflow face).
+template <typename Real, int NV, int K>
+__device__ int census_kind(const TileLDS<Real, NV, K>& S, uint32_t fl, const int hb[3], int32_t n_oct, int x, int y,
+                           int z) {
+  const int p[3] = {x, y, z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (p[a] < 0 && (fl & (1u << (2 * a)))) return 0;
+    if (p[a] > hb[a] && (fl & (2u << (2 * a)))) return 0;
+  }
+  const int slot = Geom<K>::slot(x >> 1, y >> 1, z >> 1);
+  const int32_t e = S.tab[slot];
+  if (e < 0 || e >= n_oct) return 0;
+  const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+  return ((S.ref[slot] >> cb) & 1) ? 2 : 1;
+}
+// Whether tile position (x, y, z) is one of the tile's own cells.
+__device__ __forceinline__ bool census_own(const int hb[3], int x, int y, int z) {
+  return x >= 0 && y >= 0 && z >= 0 && x <= hb[0] && y <= hb[1] && z <= hb[2];
+}
+// Whether this tile counts the floors of the face along d whose lower cell
+// is at tile position (x, y, z).
+template <typename Real, int NV, int K>
+__device__ bool census_face(const TileLDS<Real, NV, K>& S, uint32_t fl, const int hb[3], int32_t n_oct, int x, int y,
+                            int z, int d) {
+  const int bx = x + (d == 0), by = y + (d == 1), bz = z + (d == 2);
+  const int ka = census_kind(S, fl, hb, n_oct, x, y, z), kb = census_kind(S, fl, hb, n_oct, bx, by, bz);
+  if (kb == 1) return ka != 2 && census_own(hb, bx, by, bz);
+  return ka == 1 && kb == 0 && census_own(hb, x, y, z);
+}
+
+template <typename Real, int NT, int NS, int K>
+__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS, K>& S, int tid_in,
                            bool active) {
+  using G = Geom<K>;
+  using EA = typename G::EntA;
+  using EB = typename G::EntB;
   constexpr int NV = NVAR + NS;
+  constexpr int WSIZE = G::WSIZE, NFACE = G::NFACE, NUPPER = G::NUPPER, NCORE = G::NCORE;
+  constexpr int NPOS_A = G::NPOS_A, NPOS_B = G::NPOS_B, TAB = G::TAB;
+  static_assert(NT >= TAB && (K == 4 || NT == NCORE), "threads per tile");
   const int tid = opaque(tid_in);
   const int lane = tid & 63;
   const double g = A.gamma, rf = A.rho_floor, pf = A.p_floor;
   const int64_t P = A.plane;
   int nfl = 0;
   const uint32_t fl = active ? A.tflag[tile] : 0u;
+  // last in-domain cell of the tile along each axis when an outflow face cuts it
+  const int hb[3] = {K - 1 - int((fl >> CL_CUT_SHIFT) & 7u), K - 1 - int((fl >> (CL_CUT_SHIFT + 3)) & 7u),
+                     K - 1 - int((fl >> (CL_CUT_SHIFT + 6)) & 7u)};
   const int box = (active && A.tile_box) ? A.tile_box[tile] : 0;
   const double lam = A.lam_dev ? A.lam_dev[box] : A.lam_host;
   const Real h = Real(0.5 * lam);
   const Real igm1 = Real(A.igm1);
+  const StencilTables<K>& ST = stencil_tables<K>();
 
   // The thread's stencil-table entries for phases A and B, loaded together up
   // front: a load issued inside a round would make that round wait for every
   // state load issued before it.
   constexpr int NRA = (NPOS_A + NT - 1) / NT;
   constexpr int NRB = (NPOS_B + NT - 1) / NT;
-  uint32_t entA[NRA], entB[NRB];
+  // floors applied by this thread, 2 bits per site (each site applies at
+  // most 2: density and pressure): the conversions of its phase-A positions,
+  // its phase-B one-layer face states, its core cell's 3 left and 3 right
+  // face states; which of them the tile counts is decided at the end
+  constexpr int SITE_A = 0, SITE_B = NRA, SITE_L = NRA + NRB, SITE_R = SITE_L + 3;
+  static_assert(2 * (SITE_R + 3) <= 32, "floor sites");
+  int pending = 0;
+  EA entA[NRA];
+  EB entB[NRB];
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     const int i = tid + NT * rnd;
-    entA[rnd] = c_st.a[uint32_t(i < NPOS_A ? i : 0)];
+    entA[rnd] = ST.a[uint32_t(i < NPOS_A ? i : 0)];
   }
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
-    entB[rnd] = c_st.b[uint32_t(i < NPOS_B ? i : 0)];
+    entB[rnd] = ST.b[uint32_t(i < NPOS_B ? i : 0)];
   }
 
   // --- phase 0: the tile's oct table (the refined bytes of its octs are
   // loaded in phase A behind the state loads; phase D is their first reader)
   int32_t e_tab = -1;
-  if (active && tid < TILE_TAB) {
-    e_tab = A.tab[size_t(tile) * TILE_TAB + tid];
+  if (active && tid < TAB) {
+    e_tab = A.tab[size_t(tile) * TAB + tid];
     S.tab[tid] = e_tab;
   }
   __syncthreads();
@@ -416,23 +523,23 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     const int i = tid + NT * rnd;
     iwa[rnd] = -1;
     if (active && i < NPOS_A) {
-      const uint32_t ent = entA[rnd];
-      int slot = int((ent >> 10) & 63u), cb = int((ent >> 16) & 7u);
-      if (fl) {
+      const EA ent = entA[rnd];
+      int slot = int((ent >> G::A_LB) & EA((1u << G::A_SB) - 1)), cb = int((ent >> G::A_CS) & EA(7));
+      if (fl & CL_ANY) {
         // outflow faces: clamp the position into the domain (zero gradient)
-        const int raw = int(ent >> 19);
-        int sx = (raw & 7) - 2, sy = ((raw >> 3) & 7) - 2, sz = (raw >> 6) - 2;
+        const int raw = int(ent >> G::A_RS);
+        int sx = raw % G::R - 2, sy = (raw / G::R) % G::R - 2, sz = raw / (G::R * G::R) - 2;
         if ((fl & CL_LOX) && sx < 0) sx = 0;
-        if ((fl & CL_HIX) && sx > 3) sx = 3;
+        if ((fl & CL_HIX) && sx > hb[0]) sx = hb[0];
         if ((fl & CL_LOY) && sy < 0) sy = 0;
-        if ((fl & CL_HIY) && sy > 3) sy = 3;
+        if ((fl & CL_HIY) && sy > hb[1]) sy = hb[1];
         if ((fl & CL_LOZ) && sz < 0) sz = 0;
-        if ((fl & CL_HIZ) && sz > 3) sz = 3;
-        slot = ((sx >> 1) + 1) + 4 * ((sy >> 1) + 1) + 16 * ((sz >> 1) + 1);
+        if ((fl & CL_HIZ) && sz > hb[2]) sz = hb[2];
+        slot = G::slot(sx >> 1, sy >> 1, sz >> 1);
         cb = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
       }
       const int32_t e = S.tab[slot];
-      iwa[rnd] = int(ent & 1023u);
+      iwa[rnd] = int(ent & EA((1u << G::A_LB) - 1));
       // 32-bit cell index (octs of a level stay below 2^29).  A slot without
       // an oct is one no leaf update reads: it takes the (valid, finite)
       // state of the level's first cell instead of a branch
@@ -455,31 +562,34 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   for (int rnd = 0; rnd < NRA; ++rnd) {
     if (iwa[rnd] >= 0) {
       double Wc[NV];
-      cons2prim<NS>(Ua[rnd], Wc, g, rf, pf, nfl);
+      int nc = 0;
+      cons2prim<NS>(Ua[rnd], Wc, g, rf, pf, nc);
+      pending |= nc << (2 * (SITE_A + rnd));
 #pragma unroll
       for (int v = 0; v < NV; ++v) W[v * WSIZE + iwa[rnd]] = Real(Wc[v]);
     }
   }
-  if (active && tid < TILE_TAB) S.ref[tid] = rb;
+  if (active && tid < TAB) S.ref[tid] = rb;
   __syncthreads();
 
   // --- phase B1: slopes + predictor.  The core cell of a thread (first pass,
-  // tid < 64) keeps W~ and its slopes in registers for its six faces; a
+  // tid < NCORE) keeps W~ and its slopes in registers for its six faces; a
   // one-layer cell keeps only its state on the face toward the core.
-  constexpr int st[3] = {1, WB, WBB};
-  const bool core = (NT == 64) || tid < NCORE;
-  const int cx = tid & 3, cy = (tid >> 2) & 3, cz = (tid >> 4) & 3;
+  constexpr int st[3] = {1, G::WB, G::WBB};
+  const bool core = (NT == NCORE) || tid < NCORE;
+  const int cx = tid & (K - 1), cy = (tid >> G::LK) & (K - 1), cz = (tid >> (2 * G::LK)) & (K - 1);
   const Real rfr = Real(rf), pfr = Real(pf), gr = Real(g);
+  constexpr EB LMASK = EB((1u << G::B_LB) - 1);
   Real Pw[NV], Pd[3][NV];
   Real Ls[NRB][NV];
-  uint32_t Lb[NRB];
+  EB Lb[NRB];
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
     Lb[rnd] = 0u;
     if (!active || i >= NPOS_B) continue;
     if (rnd == 0 && core) {
-      const int iw = (cx + 1) + WB * (cy + 1) + WBB * (cz + 1);
+      const int iw = (cx + 1) + G::WB * (cy + 1) + G::WBB * (cz + 1);
       Real W0[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) W0[v] = W[v * WSIZE + iw];
@@ -490,10 +600,10 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
           Pd[d][v] = mmod(W0[v] - W[v * WSIZE + iw - st[d]], W[v * WSIZE + iw + st[d]] - W0[v]);
       predict<Real, NS>(W0, Pd, h, gr, Pw);
     } else {
-      const uint32_t e = entB[rnd];
+      const EB e = entB[rnd];
       Lb[rnd] = e;
-      const int iw = int(e & 511u), far = int((e >> 9) & 511u), dn = int((e >> 18) & 3u);
-      const bool up = (e >> 20) & 1u;
+      const int iw = int(e & LMASK), far = int((e >> G::B_LB) & LMASK), dn = int((e >> G::B_DS) & EB(3));
+      const bool up = (e >> G::B_US) & EB(1);
       Real W0[NV], D[3][NV], Q[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) W0[v] = W[v * WSIZE + iw];
@@ -511,15 +621,17 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       const Real t0 = (dn == 0) ? sg : Real(0), t1 = (dn == 1) ? sg : Real(0), t2 = (dn == 2) ? sg : Real(0);
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ls[rnd][v] = fma(t2, D[2][v], fma(t1, D[1][v], fma(t0, D[0][v], Q[v])));
-      floor_state<Real>(Ls[rnd], rfr, pfr, nfl);
+      int nc = 0;
+      floor_state<Real>(Ls[rnd], rfr, pfr, nc);
+      pending |= nc << (2 * (SITE_B + rnd));
     }
   }
   __syncthreads();
 
-  // --- phase B2: the left states (W~ + D/2 of the lower cell) of the 240
-  // faces replace the primitives in LDS
+  // --- phase B2: the left states (W~ + D/2 of the lower cell) of the faces
+  // replace the primitives in LDS
   Real* FL = S.buf;                             // [NV][NFACE]
-  Real* FR = S.buf + NV * NFACE;              // [NV][NUPPER]: right states of the upper layer
+  Real* FR = S.buf + NV * NFACE;                // [NV][NUPPER]: right states of the upper layer
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
@@ -530,13 +642,15 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
         Real s[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) s[v] = Pw[v] + Real(0.5) * Pd[d][v];
-        floor_state<Real>(s, rfr, pfr, nfl);
-        const int f = fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
+        int nc = 0;
+        floor_state<Real>(s, rfr, pfr, nc);
+        pending |= nc << (2 * (SITE_L + d));
+        const int f = G::fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
 #pragma unroll
         for (int v = 0; v < NV; ++v) FL[v * NFACE + f] = s[v];
       }
-    } else if (!((Lb[rnd] >> 20) & 1u)) {
-      const int f = int(Lb[rnd] >> 21);
+    } else if (!((Lb[rnd] >> G::B_US) & EB(1))) {
+      const int f = int(Lb[rnd] >> G::B_FS);
 #pragma unroll
       for (int v = 0; v < NV; ++v) FL[v * NFACE + f] = Ls[rnd][v];
     } else {
@@ -556,11 +670,13 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     const int i = tid + NT * rnd;
     if (!active || i >= NPOS_B) continue;
     if (rnd == 0 && core) {
-      core_face_flux<Real, 0, NS>(FL, fidx(0, cx, cy, cz), Pw, Pd[0], rfr, pfr, gr, igm1, nfl, Fc[0]);
-      core_face_flux<Real, 1, NS>(FL, fidx(1, cx, cy, cz), Pw, Pd[1], rfr, pfr, gr, igm1, nfl, Fc[1]);
-      core_face_flux<Real, 2, NS>(FL, fidx(2, cx, cy, cz), Pw, Pd[2], rfr, pfr, gr, igm1, nfl, Fc[2]);
-    } else if ((Lb[rnd] >> 20) & 1u) {
-      const int f = int(Lb[rnd] >> 21), dn = int((Lb[rnd] >> 18) & 3u), k = i - NCORE;
+      int nc[3] = {0, 0, 0};
+      core_face_flux<Real, 0, NS, NFACE>(FL, G::fidx(0, cx, cy, cz), Pw, Pd[0], rfr, pfr, gr, igm1, nc[0], Fc[0]);
+      core_face_flux<Real, 1, NS, NFACE>(FL, G::fidx(1, cx, cy, cz), Pw, Pd[1], rfr, pfr, gr, igm1, nc[1], Fc[1]);
+      core_face_flux<Real, 2, NS, NFACE>(FL, G::fidx(2, cx, cy, cz), Pw, Pd[2], rfr, pfr, gr, igm1, nc[2], Fc[2]);
+      pending |= (nc[0] << (2 * SITE_R)) | (nc[1] << (2 * (SITE_R + 1))) | (nc[2] << (2 * (SITE_R + 2)));
+    } else if ((Lb[rnd] >> G::B_US) & EB(1)) {
+      const int f = int(Lb[rnd] >> G::B_FS), dn = int((Lb[rnd] >> G::B_DS) & EB(3)), k = i - NCORE;
       const int iu = 1 + dn, i1 = (dn == 0) ? 2 : 1, i2 = (dn == 2) ? 2 : 3;
       HllcSide<Real> side;
       hllc_n<Real>(FL[f], FL[iu * NFACE + f], FL[i1 * NFACE + f], FL[i2 * NFACE + f], FL[4 * NFACE + f], FR[k],
@@ -579,13 +695,13 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     if (rnd == 0 && core) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const int f = fidx(d, cx, cy, cz);
+        const int f = G::fidx(d, cx, cy, cz);
 #pragma unroll
         for (int v = 0; v < NV; ++v) SF[v * NFACE + f] = Fc[d][v];
       }
-    } else if ((Lb[rnd] >> 20) & 1u) {
+    } else if ((Lb[rnd] >> G::B_US) & EB(1)) {
       // Fl is in the face-normal frame: rotate back on the way out
-      const int f = int(Lb[rnd] >> 21), dn = int((Lb[rnd] >> 18) & 3u);
+      const int f = int(Lb[rnd] >> G::B_FS), dn = int((Lb[rnd] >> G::B_DS) & EB(3));
       const int iu = 1 + dn, i1 = (dn == 0) ? 2 : 1, i2 = (dn == 2) ? 2 : 3;
       SF[f] = Fl[rnd][0];
       SF[iu * NFACE + f] = Fl[rnd][1];
@@ -598,12 +714,15 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   }
   __syncthreads();
 
-  // --- phase D: the first wavefront updates the tile's 64 cells
-  if (tid < 64) {
-    const int ts = ((cx >> 1) + 1) + 4 * ((cy >> 1) + 1) + 16 * ((cz >> 1) + 1);
+  // --- phase D: the threads of the core cells update them
+  if (tid < NCORE) {
+    const int ts = G::slot(cx >> 1, cy >> 1, cz >> 1);
     const int32_t e = active ? S.tab[ts] : -1;
     const int ci = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
-    const bool leaf = (e >= 0) && (e < A.n_oct) && !((S.ref[ts] >> ci) & 1);
+    // a tile cut by the domain's high side: its slots past the cut hold
+    // the periodic images of other octs, which other tiles update
+    const bool inside = cx <= hb[0] && cy <= hb[1] && cz <= hb[2];
+    const bool leaf = inside && (e >= 0) && (e < A.n_oct) && !((S.ref[ts] >> ci) & 1);
     double s = 0.0;
     if (leaf) {
       // the cell's old state is loaded first: the stores to the new state
@@ -618,7 +737,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       for (int d = 0; d < 3; ++d) {
         // the lower face's flux is the thread's own (phase C), the upper
         // one comes from the neighbouring cell's thread through LDS
-        const int fp = fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
+        const int fp = G::fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
         double Fm[NV], Fp[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -633,8 +752,8 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
             n[d] += side ? 1 : -1;
             const uint32_t lo = (d == 0) ? CL_LOX : ((d == 1) ? CL_LOY : CL_LOZ);
             const uint32_t hi = lo << 1;
-            if ((n[d] < 0 && (fl & lo)) || (n[d] > 3 && (fl & hi))) continue;
-            const int tn = ((n[0] >> 1) + 1) + 4 * ((n[1] >> 1) + 1) + 16 * ((n[2] >> 1) + 1);
+            if ((n[d] < 0 && (fl & lo)) || (n[d] > hb[d] && (fl & hi))) continue;
+            const int tn = G::slot(n[0] >> 1, n[1] >> 1, n[2] >> 1);
             const int32_t en = S.tab[tn];
             const int cn = (n[0] & 1) | ((n[1] & 1) << 1) | ((n[2] & 1) << 2);
             if (en >= 0 && en < A.n_oct && ((S.ref[tn] >> cn) & 1)) {
@@ -669,34 +788,42 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       }
     }
     if (active && A.smax_bits) {
-      // one atomic maximum per tile on one of the level's slots (a
+      // one atomic maximum per wavefront on one of the level's slots (a
       // non-negative double orders like its bit pattern); the maximum does
       // not depend on the order of arrival
       const double m = wave_max(s);
-      if (lane == 0) atomicMax(A.smax_bits + (tile & (SMAX_SLOTS - 1)), (unsigned long long)__double_as_longlong(m));
+      const int sl = (tile * (NCORE / 64) + (tid >> 6)) & (SMAX_SLOTS - 1);
+      if (lane == 0) atomicMax(A.smax_bits + sl, (unsigned long long)__double_as_longlong(m));
     } else if (active && A.tile_smax) {
-      // batched boxes: one partial per tile, reduced per box by the
-      // segmented max kernel before the next time step
+      // batched boxes: one partial per tile (an atomic maximum on its bit
+      // pattern when several wavefronts hold the tile's cells), reduced per
+      // box by the segmented max kernel before the next time step
       const double m = wave_max(s);
-      if (lane == 0) A.tile_smax[tile] = m;
+      if (lane == 0) {
+        if constexpr (NCORE == 64) A.tile_smax[tile] = m;
+        else atomicMax(reinterpret_cast<unsigned long long*>(A.tile_smax) + tile,
+                       (unsigned long long)__double_as_longlong(m));
+      }
     }
   }
 
   // --- fine-side registers: q_s = (f1 + f2) + (f3 + f4) on coarse-fine faces
-  const int rt = (NT > 64) ? tid - 64 : tid;   // a second wavefront, when there is one
-  if (active && A.record_reg && rt >= 0 && rt < 48) {
+  constexpr int KO = G::KO, NREG = 6 * KO * KO * KO;
+  const int rt = (K == 4 && NT > 64) ? tid - 64 : tid;   // K = 4: a second wavefront, when there is one
+  if (active && A.record_reg && rt >= 0 && rt < NREG) {
     const int b = rt / 6, face = rt - 6 * (rt / 6);
-    const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
-    const int tb_ = (bx + 1) + 4 * (by + 1) + 16 * (bz + 1);
+    const int bx = b % KO, by = (b / KO) % KO, bz = b / (KO * KO);
+    const int tb_ = G::slot(bx, by, bz);
     const int32_t eb = S.tab[tb_];
     const int d = face >> 1, up = face & 1;
     const int dd = up ? 1 : -1;
     const int rx = bx + (d == 0 ? dd : 0), ry_ = by + (d == 1 ? dd : 0), rz = bz + (d == 2 ? dd : 0);
     const int rd = (d == 0) ? rx : ((d == 1) ? ry_ : rz);
     const uint32_t lo = (d == 0) ? CL_LOX : ((d == 1) ? CL_LOY : CL_LOZ);
-    const bool clamped = (rd < 0 && (fl & lo)) || (rd > 1 && (fl & (lo << 1)));
-    if (eb >= 0 && eb < A.n_oct && !clamped) {
-      const int tn = (rx + 1) + 4 * (ry_ + 1) + 16 * (rz + 1);
+    const bool clamped = (rd < 0 && (fl & lo)) || (rd > (hb[d] >> 1) && (fl & (lo << 1)));
+    const bool inside = bx <= (hb[0] >> 1) && by <= (hb[1] >> 1) && bz <= (hb[2] >> 1);
+    if (inside && eb >= 0 && eb < A.n_oct && !clamped) {
+      const int tn = G::slot(rx, ry_, rz);
       if (S.tab[tn] >= A.n_oct) {
         // the 4 cells of the oct on this face, ascending in-oct index: insert
         // bit `up` at position d into j = 0..3
@@ -706,7 +833,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
         for (int j = 0; j < 4; ++j) {
           const int c = (j & m) | (up << d) | ((j & ~m) << 1);
           const int ccx = 2 * bx + (c & 1), ccy = 2 * by + ((c >> 1) & 1), ccz = 2 * bz + ((c >> 2) & 1);
-          fi[j] = fidx(d, ccx + (d == 0 ? up : 0), ccy + (d == 1 ? up : 0), ccz + (d == 2 ? up : 0));
+          fi[j] = G::fidx(d, ccx + (d == 0 ? up : 0), ccy + (d == 1 ? up : 0), ccz + (d == 2 ? up : 0));
         }
         double* q = A.reg_own + (int64_t(eb) * 6 + face) * NV * 2;
 #pragma unroll
@@ -714,6 +841,38 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
           q[2 * v + A.substep] = (double(SF[v * NFACE + fi[0]]) + double(SF[v * NFACE + fi[1]])) +
                                  (double(SF[v * NFACE + fi[2]]) + double(SF[v * NFACE + fi[3]]));
       }
+    }
+  }
+  // the floors applied here that this tile counts (rare: evaluated only in a
+  // thread that applied any); LDS still holds the tile's oct table
+  if (pending) {
+#pragma unroll
+    for (int rnd = 0; rnd < NRA; ++rnd) {
+      const int f = (pending >> (2 * (SITE_A + rnd))) & 3;
+      if (!f) continue;
+      // a conversion: counted when the position is one of the tile's own leaf cells
+      const int raw = int(ST.a[tid + NT * rnd] >> G::A_RS);
+      const int sx = raw % G::R - 2, sy = (raw / G::R) % G::R - 2, sz = raw / (G::R * G::R) - 2;
+      if (census_own(hb, sx, sy, sz) && census_kind(S, fl, hb, A.n_oct, sx, sy, sz) == 1) nfl += f;
+    }
+#pragma unroll
+    for (int rnd = 0; rnd < NRB; ++rnd) {
+      const int f = (pending >> (2 * (SITE_B + rnd))) & 3;
+      if (!f) continue;
+      // a one-layer face state: the face between the cell and the core, whose
+      // lower cell is this cell (lower layer) or the core cell below it
+      const EB e = ST.b[tid + NT * rnd];
+      const int iw = int(e & LMASK), dn = int((e >> G::B_DS) & EB(3));
+      const bool up = (e >> G::B_US) & EB(1);
+      const int x = (iw % G::WB) - 1 - (up && dn == 0), y = (iw % G::WBB) / G::WB - 1 - (up && dn == 1),
+                z = iw / G::WBB - 1 - (up && dn == 2);
+      if (census_face(S, fl, hb, A.n_oct, x, y, z, dn)) nfl += f;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int fl_ = (pending >> (2 * (SITE_L + d))) & 3, fr = (pending >> (2 * (SITE_R + d))) & 3;
+      if (fl_ && census_face(S, fl, hb, A.n_oct, cx, cy, cz, d)) nfl += fl_;
+      if (fr && census_face(S, fl, hb, A.n_oct, cx - (d == 0), cy - (d == 1), cz - (d == 2), d)) nfl += fr;
     }
   }
   // floor activations are rare: the shuffle sum runs only in a wavefront
@@ -725,32 +884,39 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   __syncthreads();
 }
 
-// Hydro variables alone: at least 3 wavefronts per SIMD (the FP64 tile's LDS
-// allows no more, so the register budget of an instruction-level-parallel
-// schedule stops there).  With passive scalars the LDS tile sets the limit.
-template <typename Real, int TPW, int WPT, int NS>
-__global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(NS == 0 ? 3 : 1))) void hydro_kernel(
-    HydroArgs A) {
+// Occupancy targets.  K = 4, hydro variables alone: at least 3 wavefronts
+// per SIMD (the FP64 tile's LDS allows no more, so the register budget of an
+// instruction-level-parallel schedule stops there); with passive scalars the
+// LDS tile sets the limit.  K = 8: two 512-thread tiles per CU (the FP64
+// tile takes 78 KB of the 160 KB of LDS), so 4 wavefronts per SIMD.
+template <int K, int NS>
+constexpr int hydro_waves_per_eu() {
+  return K == 8 ? 4 : (NS == 0 ? 3 : 1);
+}
+
+template <typename Real, int TPW, int WPT, int NS, int K>
+__global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(hydro_waves_per_eu<K, NS>())))
+void hydro_kernel(HydroArgs A) {
   constexpr int NT = 64 * WPT;
-  __shared__ TileLDS<Real, NVAR + NS> S[TPW];
+  __shared__ TileLDS<Real, NVAR + NS, K> S[TPW];
   if (A.skip && *A.skip) return;
   const int w = threadIdx.x / NT, tid = threadIdx.x % NT;
   const int ngroups = (A.n_tile + TPW - 1) / TPW;
   const int grp = xcd_remap(blockIdx.x, gridDim.x);
   if (grp >= ngroups) return;
   const int tile = grp * TPW + w;
-  hydro_tile<Real, NT, NS>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
+  hydro_tile<Real, NT, NS, K>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
 }
 
-// Persistent variant: workgroups pop groups of tiles from 8 per-XCD queues
-// (one contiguous slice of the Hilbert-ordered tile list per XCD; a
+// Persistent variant (K = 4): workgroups pop groups of tiles from 8 per-XCD
+// queues (one contiguous slice of the Hilbert-ordered tile list per XCD; a
 // workgroup whose own queue is empty takes from the next one).  Every
 // workgroup exits once all 8 queues are exhausted.
 template <typename Real, int TPW, int WPT>
 __global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(3))) void hydro_kernel_persistent(HydroArgs A,
                                                                                                       int batch) {
   constexpr int NT = 64 * WPT;
-  __shared__ TileLDS<Real, NVAR> S[TPW];
+  __shared__ TileLDS<Real, NVAR, 4> S[TPW];
   __shared__ int s_item;
   if (A.skip && *A.skip) return;
   const int w = threadIdx.x / NT, tid = threadIdx.x % NT;
@@ -789,7 +955,7 @@ __global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(
       const int grp = item * batch + j;
       if (grp >= ngroups) break;
       const int tile = grp * TPW + w;
-      hydro_tile<Real, NT, 0>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
+      hydro_tile<Real, NT, 0, 4>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
     }
     if (threadIdx.x == 0) {
       int next = -1;
@@ -810,14 +976,15 @@ __global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
-// The persistent kernel exists for the hydro variables alone (NS = 0).
-template <typename Real, int TPW, int WPT, int NS>
+// The persistent kernel exists for the hydro variables alone (NS = 0) on
+// small tiles (K = 4).
+template <typename Real, int TPW, int WPT, int NS, int K = 4>
 static int launch_hydro_t(const HydroArgs& a, const ry_tuning& t, int num_cu, hipStream_t s) {
   const int ngroups = (a.n_tile + TPW - 1) / TPW;
   if (ngroups == 0) return 0;
-  if (NS > 0 || !t.persistent) {
-    hipLaunchKernelGGL((hydro_kernel<Real, TPW, WPT, NS>), dim3(ngroups), dim3(64 * WPT * TPW), 0, s, a);
-  } else if constexpr (NS == 0) {
+  if (NS > 0 || K != 4 || !t.persistent) {
+    hipLaunchKernelGGL((hydro_kernel<Real, TPW, WPT, NS, K>), dim3(ngroups), dim3(64 * WPT * TPW), 0, s, a);
+  } else if constexpr (NS == 0 && K == 4) {
     const int batch = t.batch > 0 ? t.batch : 1;
     const int nitems = (ngroups + batch - 1) / batch;
     int grid = num_cu * (t.waves_per_cu > 0 ? t.waves_per_cu : 4) / (TPW * WPT);

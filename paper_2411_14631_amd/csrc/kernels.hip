@@ -15,6 +15,8 @@ namespace ry {
 int hydro_max_tiles_per_wg() { return 4; }
 
 bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t) {
+  if (t.tile_cells == 8) return nscalar == 0 && !t.persistent && t.tiles_per_wg == 1 && t.waves_per_tile == 8;
+  if (t.tile_cells != 4) return false;
   const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
   if (nscalar == 0) {
     if (precision == RY_MIXED) return key == 11 || key == 21 || key == 41 || key == 12 || key == 22 || key == 14;
@@ -83,6 +85,7 @@ __global__ void ghost_kernel(GhostArgs A) {
 #pragma unroll
     for (int k = 0; k < 7; ++k) val[v][k] = base[k][v * pl[k] + cell[k]];
   const int64_t dst = (A.n_oct + gi) * 8;
+  double keep[NVAR][8];   // the hydro variables of the 8 cells, for the floor census
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const double q = val[v][0];
@@ -94,6 +97,7 @@ __global__ void ghost_kernel(GhostArgs A) {
     for (int c = 0; c < 8; ++c) {
       const double sx = (c & 1) ? 0.25 : -0.25, sy = (c & 2) ? 0.25 : -0.25, sz = (c & 4) ? 0.25 : -0.25;
       out[c] = q + (sx * mx + sy * my + sz * mz);
+      if (v < NVAR) keep[v][c] = out[c];
     }
     double2* d0 = reinterpret_cast<double2*>(A.dst0 + v * A.plane + dst);
     double2* d1 = reinterpret_cast<double2*>(A.dst1 + v * A.plane + dst);
@@ -102,6 +106,18 @@ __global__ void ghost_kernel(GhostArgs A) {
       d0[j] = make_double2(out[2 * j], out[2 * j + 1]);
       d1[j] = make_double2(out[2 * j], out[2 * j + 1]);
     }
+  }
+  if (A.floors) {
+    // the floors the primitive conversion of each cell applies (density,
+    // then pressure from E minus the kinetic energy at the floored density)
+    int n = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double r = keep[0][c] < A.rho_floor ? A.rho_floor : keep[0][c];
+      const double ke = 0.5 * (keep[1][c] * keep[1][c] + keep[2][c] * keep[2][c] + keep[3][c] * keep[3][c]) / r;
+      n += int(keep[0][c] < A.rho_floor) + int((A.gamma - 1.0) * (keep[4][c] - ke) < A.p_floor);
+    }
+    if (n) atomicAdd(A.floors, (unsigned long long)n);
   }
 }
 
@@ -180,10 +196,12 @@ __global__ __launch_bounds__(256) void cfl_kernel(const double* __restrict__ U, 
 }
 
 int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double g, double rf, double pf,
-               double* part, int32_t* err, void* stream) {
+               double* part, int64_t part_cap, int32_t* err, void* stream) {
   if (n_oct == 0) return 0;
-  const int64_t n = n_oct * 8;
-  hipLaunchKernelGGL(cfl_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, U, plane, n_oct,
+  // one partial per block: the grid must fit the caller's segment
+  const int64_t nblk = cfl_blocks(n_oct);
+  if (nblk > part_cap) return LAUNCH_EXCEEDS_BUFFER;
+  hipLaunchKernelGGL(cfl_kernel, dim3(unsigned(nblk)), dim3(256), 0, (hipStream_t)stream, U, plane, n_oct,
                      refined, g, rf, pf, part, err);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -312,6 +330,10 @@ int launch_finalize(const FinalizeArgs& a, void* stream) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
 __global__ void zero_u32_kernel(unsigned int* p, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -428,6 +450,129 @@ int launch_regrid_remap(const int32_t* src_old, const int32_t* src7, int64_t n_n
   const int64_t n = n_new * 8;
   hipLaunchKernelGGL(regrid_remap_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                      src_old, src7, n_new, Uold, pold, Uc, pc, Unew, pnew, nv);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Super-tiles: the aligned 4x4x4-oct blocks (8^3 cells) of a level, each
+// assembled from the level's small tiles (aligned 2x2x2-oct blocks) inside
+// it.  Small tiles are in Hilbert order, and the Hilbert curve runs through
+// an aligned block before leaving it, so the small tiles of one block are
+// consecutive in the list.  A super-tile's 6x6x6 oct neighbourhood is the
+// union of its small tiles' 4x4x4 neighbourhoods: two tables that both hold
+// a position hold the same oct (or ghost oct), and a position that none
+// holds is read by no cell that is updated.
+// ---------------------------------------------------------------------------
+constexpr int SMALL_TAB = 64, SUPER_TAB = 216;
+
+__device__ __forceinline__ uint64_t pack_block(int64_t x, int64_t y, int64_t z) {
+  return uint64_t(x) | (uint64_t(y) << 21) | (uint64_t(z) << 42);
+}
+
+// Per small tile: the key of its 4x4x4-oct block and its position (0..7)
+// inside the block, from one of its own octs (a tile holds at least one,
+// and its 2x2x2 core slots of the table hold every present one).
+__global__ void super_key_kernel(const int32_t* __restrict__ tab, int32_t n_tile, const int32_t* __restrict__ oc,
+                                 int64_t n_oct, uint64_t* __restrict__ skey, int32_t* __restrict__ ssub,
+                                 int32_t* __restrict__ start) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_tile) return;
+  int32_t e = -1;
+  for (int c = 0; c < 8 && e < 0; ++c) {
+    const int slot = 21 + (c & 1) + 4 * ((c >> 1) & 1) + 16 * (c >> 2);
+    const int32_t v = tab[t * SMALL_TAB + slot];
+    if (v >= 0 && v < n_oct) e = v;
+  }
+  start[t] = 0;
+  if (e < 0) {
+    // every tile the mesh builders make holds a real oct; a tile without one
+    // would be a builder error: it gets a block of its own
+    skey[t] = ~uint64_t(t);
+    ssub[t] = 0;
+    return;
+  }
+  const int64_t bx = oc[3 * int64_t(e)] & ~1, by = oc[3 * int64_t(e) + 1] & ~1, bz = oc[3 * int64_t(e) + 2] & ~1;
+  skey[t] = pack_block(bx >> 2, by >> 2, bz >> 2);
+  ssub[t] = int32_t(((bx >> 1) & 1) | (((by >> 1) & 1) << 1) | (((bz >> 1) & 1) << 2));
+}
+
+__global__ void super_start_kernel(const uint64_t* __restrict__ skey, int32_t n_tile, int32_t* __restrict__ start) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n_tile) start[t] = (t == 0 || skey[t] != skey[t - 1]) ? 1 : 0;
+}
+
+// sub[s][8]: the small tile at each position of super-tile s (or -1), and
+// the block key of every super-tile.
+__global__ void super_sub_kernel(const uint64_t* __restrict__ skey, const int32_t* __restrict__ ssub,
+                                 const int32_t* __restrict__ start, const int32_t* __restrict__ excl, int32_t n_tile,
+                                 int32_t* __restrict__ sub, uint64_t* __restrict__ sblock) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_tile) return;
+  const int32_t s = excl[t] + start[t] - 1;
+  sub[int64_t(s) * 8 + ssub[t]] = int32_t(t);
+  if (start[t]) sblock[s] = skey[t];
+}
+
+// One thread per (super-tile, slot of its 6x6x6 neighbourhood); the slot-0
+// thread also writes the super-tile's flags: outflow faces it touches, and
+// the cells past the domain's high side per axis.
+__global__ void super_table_kernel(const int32_t* __restrict__ tab, const int32_t* __restrict__ sub,
+                                   const uint64_t* __restrict__ sblock, int32_t n_super, SuperDom D,
+                                   int32_t* __restrict__ stab, uint32_t* __restrict__ stflag) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(n_super) * SUPER_TAB) return;
+  const int64_t s = i / SUPER_TAB;
+  const int slot = int(i % SUPER_TAB);
+  const int px = slot % 6 - 1, py = (slot / 6) % 6 - 1, pz = slot / 36 - 1;
+  int32_t v = -1;
+  for (int c = 0; c < 8; ++c) {
+    const int32_t t = sub[s * 8 + c];
+    if (t < 0) continue;
+    const int qx = px - 2 * (c & 1), qy = py - 2 * ((c >> 1) & 1), qz = pz - 2 * (c >> 2);
+    if (qx < -1 || qx > 2 || qy < -1 || qy > 2 || qz < -1 || qz > 2) continue;
+    const int32_t e = tab[int64_t(t) * SMALL_TAB + (qx + 1) + 4 * (qy + 1) + 16 * (qz + 1)];
+    v = e > v ? e : v;
+  }
+  stab[i] = v;
+  if (slot == 0) {
+    const uint64_t b = sblock[s];
+    const int64_t o[3] = {int64_t(b & 0x1FFFFF) * 4, int64_t((b >> 21) & 0x1FFFFF) * 4, int64_t(b >> 42) * 4};
+    uint32_t fl = 0;
+    int cut[3];
+    for (int a = 0; a < 3; ++a) {
+      if (o[a] == 0 && D.bc[2 * a] == RY_BC_OUTFLOW) fl |= (1u << (2 * a));
+      if (o[a] + 4 >= D.noct[a] && D.bc[2 * a + 1] == RY_BC_OUTFLOW) fl |= (2u << (2 * a));
+      const int64_t past = o[a] + 4 - D.noct[a];
+      cut[a] = past > 0 ? int(2 * past) : 0;
+    }
+    stflag[s] = fl | (uint32_t(cut[0]) << CL_CUT_SHIFT) | (uint32_t(cut[1]) << (CL_CUT_SHIFT + 3)) |
+                (uint32_t(cut[2]) << (CL_CUT_SHIFT + 6));
+  }
+}
+
+int super_table_slots() { return SUPER_TAB; }
+
+int launch_super_keys(const int32_t* tab, int32_t n_tile, const int32_t* oc, int64_t n_oct, uint64_t* skey,
+                      int32_t* ssub, int32_t* start, void* stream) {
+  if (n_tile == 0) return 0;
+  const dim3 g(unsigned((n_tile + 255) / 256)), b(256);
+  hipLaunchKernelGGL(super_key_kernel, g, b, 0, (hipStream_t)stream, tab, n_tile, oc, n_oct, skey, ssub, start);
+  hipLaunchKernelGGL(super_start_kernel, g, b, 0, (hipStream_t)stream, skey, n_tile, start);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_super_tables(const int32_t* tab, const uint64_t* skey, const int32_t* ssub, const int32_t* start,
+                        const int32_t* excl, int32_t n_tile, int32_t n_super, const SuperDom& D, int32_t* sub,
+                        uint64_t* sblock, int32_t* stab, uint32_t* stflag, void* stream) {
+  if (n_tile == 0 || n_super == 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nsub = int64_t(n_super) * 8;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(unsigned((nsub + 255) / 256)), dim3(256), 0, st, sub, nsub, -1);
+  hipLaunchKernelGGL(super_sub_kernel, dim3(unsigned((n_tile + 255) / 256)), dim3(256), 0, st, skey, ssub, start,
+                     excl, n_tile, sub, sblock);
+  const int64_t n = int64_t(n_super) * SUPER_TAB;
+  hipLaunchKernelGGL(super_table_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, tab, sub, sblock, n_super,
+                     D, stab, stflag);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

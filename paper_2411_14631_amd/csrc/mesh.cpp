@@ -373,13 +373,15 @@ static std::string build_level_tables(const DomainSpec& d, const std::vector<Hos
       bool present[8] = {false, false, false, false, false, false, false, false};
       for (int64_t o = o0; o < o1; ++o)
         present[(H.ox[o] - bx) + 2 * (H.oy[o] - by) + 4 * (H.oz[o] - bz)] = true;
-      uint32_t fl = 0;
+      // a base side of 2 mod 4 cells ends halfway through its last tiles:
+      // their second oct row lies past the domain (cut, never updated)
+      uint32_t fl = tile_cut_bits(bx + 2 > nox ? 2 : 0, by + 2 > noy ? 2 : 0, bz + 2 > noz ? 2 : 0);
       if (bx == 0 && d.bc[0] == RY_BC_OUTFLOW) fl |= CL_LOX;
-      if (bx + 2 == nox && d.bc[1] == RY_BC_OUTFLOW) fl |= CL_HIX;
+      if (bx + 2 >= nox && d.bc[1] == RY_BC_OUTFLOW) fl |= CL_HIX;
       if (by == 0 && d.bc[2] == RY_BC_OUTFLOW) fl |= CL_LOY;
-      if (by + 2 == noy && d.bc[3] == RY_BC_OUTFLOW) fl |= CL_HIY;
+      if (by + 2 >= noy && d.bc[3] == RY_BC_OUTFLOW) fl |= CL_HIY;
       if (bz == 0 && d.bc[4] == RY_BC_OUTFLOW) fl |= CL_LOZ;
-      if (bz + 2 == noz && d.bc[5] == RY_BC_OUTFLOW) fl |= CL_HIZ;
+      if (bz + 2 >= noz && d.bc[5] == RY_BC_OUTFLOW) fl |= CL_HIZ;
       T.tflag[t] = fl;
       for (int rz = -1; rz <= 2; ++rz)
         for (int ry_ = -1; ry_ <= 2; ++ry_)

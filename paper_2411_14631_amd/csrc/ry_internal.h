@@ -25,8 +25,16 @@ constexpr int QUEUE_STRIDE = 32;
 // flux registers per oct: [face 6][variable nv][substep 2]
 constexpr int reg_per_oct(int nv) { return 6 * nv * 2; }
 
-// Tile flag bits: outflow clamping at the domain faces touched by the tile.
-enum : uint32_t { CL_LOX = 1, CL_HIX = 2, CL_LOY = 4, CL_HIY = 8, CL_LOZ = 16, CL_HIZ = 32 };
+// Tile flag bits: outflow clamping at the domain faces touched by the tile
+// (bits 0-5), and per axis (3 bits each from CL_CUT_SHIFT, x then y then z)
+// the number of the tile's cells that lie past the domain's high side (0 for
+// a tile inside the domain; even, below the tile edge): those cells are not
+// updated, and an outflow face clamps to the last cell before them.
+enum : uint32_t { CL_LOX = 1, CL_HIX = 2, CL_LOY = 4, CL_HIY = 8, CL_LOZ = 16, CL_HIZ = 32, CL_ANY = 63 };
+constexpr int CL_CUT_SHIFT = 8;
+inline uint32_t tile_cut_bits(int cx, int cy, int cz) {
+  return (uint32_t(cx) << CL_CUT_SHIFT) | (uint32_t(cy) << (CL_CUT_SHIFT + 3)) | (uint32_t(cz) << (CL_CUT_SHIFT + 6));
+}
 
 // ---------------------------------------------------------------- host mesh
 struct OctIndex {
@@ -162,6 +170,10 @@ struct GhostArgs {
   int64_t plane;
   int32_t nv;
   const int32_t* skip;
+  // floor census of the ghost cells (once per parent step): activations of
+  // the primitive conversion of each interpolated cell; nullptr = off
+  unsigned long long* floors;
+  double gamma, rho_floor, p_floor;
 };
 
 // launchers (kernels.hip)
@@ -173,9 +185,16 @@ bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t);
 int launch_ghost(const GhostArgs& a, void* stream);
 int launch_restrict(const double* Uf, int64_t plane_f, int64_t n_fine, const int32_t* parent_cell,
                     double* Uc, int64_t plane_c, int nv, const int32_t* skip, void* stream);
-// per-block maxima of the signal speed over leaf cells -> part[0 .. ceil(8 n_oct / 256))
+// Blocks of the CFL pass over n_oct octs (256 cells each): the number of
+// partial maxima it writes.
+inline int64_t cfl_blocks(int64_t n_oct) { return (8 * n_oct + 255) / 256; }
+// Launch failures that the launchers detect before any device call.
+constexpr int LAUNCH_EXCEEDS_BUFFER = -2;
+// per-block maxima of the signal speed over leaf cells -> part[0 ..
+// cfl_blocks(n_oct)); part holds part_cap values: a grid that would write
+// past them is refused (LAUNCH_EXCEEDS_BUFFER) before anything is launched
 int launch_cfl(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double gamma,
-               double rho_floor, double p_floor, double* part, int32_t* err, void* stream);
+               double rho_floor, double p_floor, double* part, int64_t part_cap, int32_t* err, void* stream);
 // out[s] = max of part[off[s] .. off[s+1])
 // per-segment maxima of part; with slots != nullptr also slot 0 of each
 // segment's SMAX_SLOTS slots = the maximum, the others 0
@@ -249,5 +268,21 @@ int launch_regrid_remap(const int32_t* src_old, const int32_t* src7, int64_t n_n
                         const double* Uc, int64_t pc, double* Unew, int64_t pnew, int nv, void* stream);
 int totals_blocks();
 int hydro_max_tiles_per_wg();
+
+// ---- super-tiles (kernels.hip): 4x4x4-oct blocks for the 8^3-cell tile ----
+struct SuperDom {
+  int64_t noct[3];                   // octs per axis of the level
+  int32_t bc[6];
+};
+int super_table_slots();             // 6^3 oct neighbourhood entries per super-tile
+// per small tile: its block key, its position in the block, block starts
+// (start[t] = 1 where a new block begins; scan it for the block numbers)
+int launch_super_keys(const int32_t* tab, int32_t n_tile, const int32_t* oc, int64_t n_oct, uint64_t* skey,
+                      int32_t* ssub, int32_t* start, void* stream);
+// the super-tiles' tables and flags (excl = exclusive scan of start; sub:
+// n_super * 8 scratch ints; sblock: n_super scratch keys)
+int launch_super_tables(const int32_t* tab, const uint64_t* skey, const int32_t* ssub, const int32_t* start,
+                        const int32_t* excl, int32_t n_tile, int32_t n_super, const SuperDom& D, int32_t* sub,
+                        uint64_t* sblock, int32_t* stab, uint32_t* stflag, void* stream);
 
 }  // namespace ry

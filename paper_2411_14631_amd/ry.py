@@ -26,7 +26,7 @@ EXPORTS = [
     "ry_create", "ry_destroy", "ry_amr_build", "ry_level_info", "ry_get_mesh", "ry_cfl_dt",
     "ry_hydro_step", "ry_advance", "ry_conserved_totals", "ry_download", "ry_upload",
     "ry_batch_create", "ry_batch_run", "ry_batch_box_info", "ry_batch_download",
-    "ry_set_tuning", "ry_get_tuning", "ry_autotune", "ry_floor_count", "ry_set_timing",
+    "ry_set_tuning", "ry_get_tuning", "ry_set_level_tuning", "ry_get_level_tuning", "ry_autotune", "ry_floor_count", "ry_set_timing",
     "ry_kernel_time", "ry_copy_probe", "ry_last_error", "ry_mesh_build", "ry_mesh_level",
     "ry_mesh_free", "ry_hilbert_key", "ry_regrid", "ry_set_refine_param", "ry_set_regrid_device",
 ]
@@ -61,7 +61,7 @@ class RyPoissonConfig(C.Structure):
 
 class RyTuning(C.Structure):
     _fields_ = [("tiles_per_wg", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("batch", C.c_int32), ("waves_per_tile", C.c_int32)]
+                ("batch", C.c_int32), ("waves_per_tile", C.c_int32), ("tile_cells", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -104,6 +104,8 @@ def lib():
         "ry_batch_download": ([P, I32, P], I32),
         "ry_set_tuning": ([P, C.POINTER(RyTuning)], I32),
         "ry_get_tuning": ([P, C.POINTER(RyTuning)], I32),
+        "ry_set_level_tuning": ([P, I32, C.POINTER(RyTuning)], I32),
+        "ry_get_level_tuning": ([P, I32, C.POINTER(RyTuning)], I32),
         "ry_autotune": ([P, C.POINTER(RyTuning), C.POINTER(D), I32, C.POINTER(I32)], I32),
         "ry_floor_count": ([P], I64),
         "ry_set_timing": ([P, I32], I32),
@@ -209,13 +211,23 @@ class _Base:
             pass
 
     # tuning / timing / diagnostics
-    def set_tuning(self, tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=1):
-        t = RyTuning(tiles_per_wg, persistent, waves_per_cu, batch, waves_per_tile)
+    def set_tuning(self, tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=1, tile_cells=4):
+        t = RyTuning(tiles_per_wg, persistent, waves_per_cu, batch, waves_per_tile, tile_cells)
         self._check(lib().ry_set_tuning(self.ctx, C.byref(t)), "ry_set_tuning")
 
     def tuning(self):
         t = RyTuning()
         self._check(lib().ry_get_tuning(self.ctx, C.byref(t)), "ry_get_tuning")
+        return t.as_dict()
+
+    def set_level_tuning(self, level, tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=1,
+                         tile_cells=4):
+        t = RyTuning(tiles_per_wg, persistent, waves_per_cu, batch, waves_per_tile, tile_cells)
+        self._check(lib().ry_set_level_tuning(self.ctx, level, C.byref(t)), "ry_set_level_tuning")
+
+    def level_tuning(self, level):
+        t = RyTuning()
+        self._check(lib().ry_get_level_tuning(self.ctx, level, C.byref(t)), "ry_get_level_tuning")
         return t.as_dict()
 
     def autotune(self):

@@ -114,3 +114,52 @@ def with_scalars(prob, nscalar, profiles=scalar_profiles):
             cells = n0 << (level - prob.level_min)
             return np.concatenate([U[:5], np.array(scal(cells, ijk, U[0]))], axis=0)
     return dataclasses.replace(prob, name=prob.name + f"_s{nscalar}", U_base=Ub, fill=fill, nscalar=nscalar)
+
+
+def leaf_mask(refined_bytes):
+    """Per-cell leaf mask (8 cells per oct, bit c of the oct's byte = cell c
+    refined)."""
+    bits = np.unpackbits(np.asarray(refined_bytes, np.uint8)[:, None], axis=1, bitorder="little")
+    return ~bits.astype(bool).reshape(-1)
+
+
+def form_errors(levels_a, levels_b, gamma):
+    """Errors of state a against the reference state b over the leaf cells
+    of every level.  levels_* are lists of (U[nv, 8 n_oct], refined bytes,
+    cell volume), the two lists on the same mesh.  Returns the volume-
+    weighted relative L1 errors of density and pressure and the largest
+    relative density and pressure errors."""
+    def rho_p(U, m):
+        r = U[0][m]
+        p = (gamma - 1.0) * (U[4][m] - 0.5 * (U[1][m] ** 2 + U[2][m] ** 2 + U[3][m] ** 2) / r)
+        return r, p
+
+    l1r = l1p = nr = np_ = 0.0
+    mr = mp = 0.0
+    for (Ua, ra, va), (Ub, rb, vb) in zip(levels_a, levels_b):
+        np.testing.assert_array_equal(ra, rb)
+        m = leaf_mask(rb)
+        a_r, a_p = rho_p(Ua, m)
+        b_r, b_p = rho_p(Ub, m)
+        l1r += np.abs(a_r - b_r).sum() * vb
+        l1p += np.abs(a_p - b_p).sum() * vb
+        nr += np.abs(b_r).sum() * vb
+        np_ += np.abs(b_p).sum() * vb
+        if len(b_r):
+            mr = max(mr, float(np.max(np.abs(a_r - b_r) / np.abs(b_r))))
+            mp = max(mp, float(np.max(np.abs(a_p - b_p) / np.abs(b_p))))
+    return {"l1_rho_rel": float(l1r / nr), "l1_p_rel": float(l1p / np_), "max_rho_rel": mr, "max_p_rel": mp}
+
+
+def level_states(h):
+    """(U, refined bytes, cell volume) of every non-empty level of a GPU or
+    oracle context."""
+    out = []
+    for k, lv in enumerate(h.levels):
+        n, _ = h.level_info(lv)
+        if n == 0:
+            continue
+        _, ref = h.mesh(lv)
+        vol = (h.prob.boxlen / (h.prob.nbase[0] << k)) ** 3
+        out.append((h.download(lv), ref, vol))
+    return out

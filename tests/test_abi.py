@@ -51,7 +51,8 @@ def test_poisson_create_rejects_invalid_config(shape, bc, pc):
 
 
 @pytest.mark.parametrize("mutate,expect", [
-    (dict(nbase=(30, 32, 32)), ry.RY_EINVAL),          # not a multiple of 4
+    (dict(nbase=(31, 32, 32)), ry.RY_EINVAL),          # odd side
+    (dict(nbase=(0, 8, 8)), ry.RY_EINVAL),             # empty side
     (dict(level_min=6, level_max=5), ry.RY_EINVAL),
     (dict(gamma=1.0), ry.RY_EINVAL),
     (dict(cfl=0.0), ry.RY_EINVAL),
@@ -100,6 +101,17 @@ def test_mesh_bit_exact_amr_blob_periodic_and_outflow():
     assert compare_mesh(cases.amr_blob(bc=(W.BC_OUTFLOW,) * 6, centre=(0.1, 0.5, 0.5))) > 64
 
 
+@pytest.mark.parametrize("n_fine", [36, 60])
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_OUTFLOW])
+def test_mesh_bit_exact_base_side_2_mod_4(n_fine, bc):
+    """Base sides of 18 and 30 cells (an odd number of octs per axis): the
+    builder's refinement map and oct order equal the oracle's."""
+    import dataclasses
+    prob = dataclasses.replace(W.twolevel(n_fine, 0.5), bc=(bc,) * 6)
+    assert ry.create_status(prob) != ry.RY_EINVAL      # validation passes (no device call made yet)
+    assert compare_mesh(prob) > (n_fine // 4) ** 3
+
+
 def test_mesh_bit_exact_twolevel_theta_primary():
     prob = W.twolevel(64, 0.70)
     assert compare_mesh(prob) > 4096
@@ -124,3 +136,34 @@ def test_ghost_octs_only_on_refined_levels():
     m = ry.HostMesh(cases.amr_blob())
     assert m.level(3)[2] == 0
     assert m.level(4)[2] > 0 and m.level(5)[2] > 0
+
+
+def _cpp_symbol(L, demangled_prefix):
+    """Address of an internal C++ function of the library, by its demangled
+    name (nm lists the dynamic symbols)."""
+    import ctypes
+    import subprocess
+    out = subprocess.run(["nm", "-D", "-C", ry.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    raw = subprocess.run(["nm", "-D", ry.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    dem = [l.split(" ", 2)[2] for l in out.splitlines() if l.count(" ") >= 2]
+    mang = [l.split(" ", 2)[2] for l in raw.splitlines() if l.count(" ") >= 2]
+    name = next(m for d, m in zip(dem, mang) if d.startswith(demangled_prefix))
+    return getattr(L, name)
+
+
+def test_cfl_launch_refuses_grid_beyond_its_segment():
+    """The CFL pass writes one partial maximum per 256-cell block into a
+    segment of the context's partial buffer: a launch whose grid would write
+    past the segment is refused on the host, before any device call (this
+    runs without a GPU)."""
+    import ctypes as C
+    L = ry.lib()
+    f = _cpp_symbol(L, "ry::launch_cfl(")
+    f.restype = C.c_int
+    f.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                  C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    n_oct = 1000                                   # 8000 cells -> 32 blocks
+    for cap in (0, 1, 31):
+        assert f(None, 8 * n_oct, n_oct, None, 1.4, 1e-10, 1e-10, None, cap, None, None) == -2
+    # nothing to reduce: no launch, no error
+    assert f(None, 0, 0, None, 1.4, 1e-10, 1e-10, None, 0, None, None) == 0

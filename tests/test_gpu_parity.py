@@ -142,6 +142,50 @@ def test_multi_step_graphs_equal_eager_bit_exact(ry, n):
         np.testing.assert_array_equal(c.download(lv), d.download(lv))
 
 
+@pytest.mark.parametrize("n_coarse", [19, 1001])
+def test_sod_t_end_with_odd_skipped_steps(ry, n_coarse):
+    """t_end is reached after 18 steps: the remaining n_coarse - 18 steps
+    (odd here) are skipped on the device, and the state returned is the one
+    at t_end, on the graph path and on the eager path."""
+    prob = W.sod(32)
+    o = Oracle(prob)
+    n = o.advance(n_coarse, prob.t_end)
+    assert (n_coarse - n) % 2 == 1
+    for eager in (False, True):
+        g = ry.Hydro(prob)
+        g.set_timing(eager)
+        g.advance(n_coarse, prob.t_end)
+        assert g.t == o.t == prob.t_end
+        compare_levels(g, o)
+
+
+@pytest.mark.parametrize("n_coarse", [11, 16])
+def test_amr_t_end_inside_graph_matches_oracle(ry, n_coarse):
+    """AMR run whose t_end falls inside a multi-step graph with an odd number
+    of steps left over; then further steps continue from the right buffers."""
+    prob = cases.amr_blob(level_min=3, level_max=4)
+    probe = Oracle(prob)
+    probe.advance(n_coarse)
+    t_full = probe.t
+    # pick a t_end that leaves an odd number of the n_coarse steps unused
+    for frac in (0.45, 0.5, 0.55, 0.6, 0.65, 0.7, 0.75):
+        o = Oracle(prob)
+        k = o.advance(n_coarse, frac * t_full)
+        if (n_coarse - k) % 2 == 1:
+            break
+    assert (n_coarse - k) % 2 == 1
+    t_end = frac * t_full
+    for eager in (False, True):
+        g = ry.Hydro(prob)
+        g.set_timing(eager)
+        g.advance(n_coarse, t_end)
+        assert g.t == t_end
+        compare_levels(g, o)
+    o.advance(3)
+    g.advance(3)
+    compare_levels(g, o)
+
+
 def test_amr_eager_timing_equals_graph_bit_exact(ry):
     prob = cases.amr_blob(level_min=3, level_max=4)
     a, b = ry.Hydro(prob), ry.Hydro(prob)
@@ -333,20 +377,6 @@ def test_twolevel128_full_size_config_steps(ry):
     compare_levels(g, o)
 
 
-def test_zoom_full_size_one_coarse_step(ry):
-    """Zoom-shaped AMR (levels 7-12, about 2M octs): refinement maps and oct
-    order bit-exact, one coarse step (32 level-12 substeps) within 1e-12."""
-    prob = W.zoom()
-    g = ry.Hydro(prob)
-    o = Oracle(prob)
-    assert g.level_info(12)[0] > 0
-    assert sum(g.level_info(lv)[0] for lv in g.levels) > 1_500_000
-    g.advance(1)
-    o.advance(1)
-    compare_levels(g, o)
-    assert g.floors() == 0
-
-
 def test_batch_tunings_bit_exact(ry):
     """The batched launch is independent of its tuning: the plain launch and
     the persistent queue-fed kernel (several grid sizes, queue batches and
@@ -448,3 +478,24 @@ def test_amr_with_empty_refinement_equals_single_level(ry):
     g.advance(3)
     s.advance(3)
     np.testing.assert_array_equal(g.download(4), s.download(4))
+
+
+@pytest.mark.parametrize("n_fine,theta", [(64, 0.5), (128, 0.70)])
+def test_floor_census_equals_oracle(ry, n_fine, theta):
+    """Floor activations counted once per event of a step (a leaf cell's own
+    conversion, each used face's states, each ghost cell per parent step):
+    the GPU's count equals the oracle's on the two-level meshes, whose
+    interpolated ghost cells can have less total energy than kinetic energy,
+    with either tile shape, on the graph path and host-driven."""
+    prob = W.twolevel(n_fine, theta)
+    o = Oracle(prob)
+    o.advance(2)
+    assert o.floors() > 0
+    for t in ([1, 0, 4, 1, 1, 4], [1, 0, 4, 1, 2, 4], [1, 0, 4, 1, 8, 8]):
+        g = ry.Hydro(prob)
+        g.set_tuning(*t)
+        g.advance(2)
+        assert g.floors() == o.floors(), (t, g.floors(), o.floors())
+    h, o1 = ry.Hydro(prob), Oracle(prob)
+    step_both(h, o1, 1)
+    assert h.floors() == o1.floors() > 0
