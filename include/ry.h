@@ -208,6 +208,23 @@ int64_t ry_floor_count(ry_ctx* ctx);
  * on, ry_advance launches eagerly instead of replaying graphs. */
 ry_status ry_set_timing(ry_ctx* ctx, int32_t on);
 ry_status ry_kernel_time(ry_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms);
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): the CFL time step
+ * of one level held in the caller's device memory, the same reduction as
+ * ry_cfl_dt's for one level, dt = cfl * dx / max over leaf cells of
+ * (|u|+|v|+|w|+3c) (+inf when no cell is a leaf).  U: device, 5 planes of
+ * `plane` doubles (plane >= 8 * n_oct), cell index 8*oct + (ix + 2 iy +
+ * 4 iz) as in ry_download; refined: device, n_oct bytes, bit c = cell c
+ * refined (refined cells are left out); dt: host, written on RY_OK; stream:
+ * a hipStream_t or NULL.  Allocates nothing: the partial maxima live in a
+ * 512 KiB array in device memory that every GPU the library runs on holds
+ * for the life of the process; n_oct above 2,097,152 (what it covers) ->
+ * RY_EINVAL before any launch.  Calls that overlap on one GPU share that
+ * array and race.  RY_ENUMERIC if a leaf cell is non-finite or has rho <= 0
+ * or E <= 0.  Syncs the stream. */
+ry_status ry_cfl_dt_noalloc(const double* U, int64_t plane, int64_t n_oct, const uint8_t* refined, double gamma,
+                            double cfl, double dx, double rho_floor, double p_floor, double* dt, void* stream);
+
 /* Device bandwidth probe: copy `bytes` within device memory `reps` times,
  * returns the average kernel time in ms.  Used to calibrate counters. */
 ry_status ry_copy_probe(ry_ctx* ctx, size_t bytes, int32_t reps, double* ms);

@@ -11,7 +11,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libry.so")
-SOURCES = ["mesh.cpp", "api.cpp", "kernels.hip", "hydro.hip", "poisson.hip", "regrid.hip"]
+SOURCES = ["mesh.cpp", "api.cpp", "kernels.hip", "hydro.hip", "poisson.hip", "regrid.hip", "noalloc.hip"]
 # per-source options: the hydro-only tile kernels schedule for instruction-
 # level parallelism (their occupancy is bounded by LDS, not registers)
 SOURCE_FLAGS = {"hydro.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}

@@ -27,7 +27,7 @@ EXPORTS = [
     "ry_hydro_step", "ry_advance", "ry_conserved_totals", "ry_download", "ry_upload",
     "ry_batch_create", "ry_batch_run", "ry_batch_box_info", "ry_batch_download",
     "ry_set_tuning", "ry_get_tuning", "ry_set_level_tuning", "ry_get_level_tuning", "ry_autotune", "ry_floor_count", "ry_set_timing",
-    "ry_kernel_time", "ry_copy_probe", "ry_last_error", "ry_mesh_build", "ry_mesh_level",
+    "ry_kernel_time", "ry_cfl_dt_noalloc", "ry_copy_probe", "ry_last_error", "ry_mesh_build", "ry_mesh_level",
     "ry_mesh_free", "ry_hilbert_key", "ry_regrid", "ry_set_refine_param", "ry_set_regrid_device",
 ]
 # Every function declared in include/ry_poisson.h.
