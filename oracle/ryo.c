@@ -522,11 +522,36 @@ static void restrict_level(ryo_ctx* c, int l, double* dst) {
   }
 }
 
-/* Floor activations of the ghost cells of level l (l > level_min) at the
- * start of a parent step: every cell of every oct position that a 26-
- * neighbour of an existing level-l oct occupies but no level-l oct does
- * (inside the domain or across a periodic face), with its MinMod-linear
- * interpolated state converted once. */
+/* Whether an update of level l reads cell position p: whether a leaf cell
+ * of l lies in the stencil around p -- one step along an axis, two steps
+ * along an axis, or one step along each of two axes (the cells whose
+ * predictions the fluxes of a cell use, and their neighbours). */
+static int read_by_update(const ryo_ctx* c, int l, const int64_t p[3]) {
+  for (int d = 0; d < 3; d++)
+    for (int s = -2; s <= 2; s++) {
+      if (s == 0) continue;
+      int64_t q[3] = {p[0], p[1], p[2]};
+      q[d] += s;
+      if (is_leaf_cell(c, l, q)) return 1;
+    }
+  for (int d = 0; d < 3; d++)
+    for (int e = d + 1; e < 3; e++)
+      for (int sd = -1; sd <= 1; sd += 2)
+        for (int se = -1; se <= 1; se += 2) {
+          int64_t q[3] = {p[0], p[1], p[2]};
+          q[d] += sd;
+          q[e] += se;
+          if (is_leaf_cell(c, l, q)) return 1;
+        }
+  return 0;
+}
+
+/* Floor activations of the ghost cells of level l (l > level_min) that the
+ * updates of a parent step read, at its start: the cells of the oct
+ * positions that a 26-neighbour of an existing level-l oct occupies but no
+ * level-l oct does (inside the domain or across a periodic face) that lie
+ * in the stencil of a leaf cell, each MinMod-linear interpolated state
+ * converted once. */
 static int cmp_u64(const void* a, const void* b) {
   uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
   return x < y ? -1 : (x > y ? 1 : 0);
@@ -563,6 +588,7 @@ static void ghost_census(ryo_ctx* c, int l) {
     int64_t q[3] = {(int64_t)(pos[i] & 0x1FFFFF), (int64_t)((pos[i] >> 21) & 0x1FFFFF), (int64_t)(pos[i] >> 42)};
     for (int ci = 0; ci < 8; ci++) {
       int64_t p[3] = {2 * q[0] + (ci & 1), 2 * q[1] + ((ci >> 1) & 1), 2 * q[2] + ((ci >> 2) & 1)};
+      if (!read_by_update(c, l, p)) continue;
       double U[NV], W[NV];
       coarse_interp(c, l, p, U);
       cons_to_prim(c, U, W, &fl);
@@ -1010,6 +1036,7 @@ int ryo_level_info(const ryo_ctx* c, int32_t l, int64_t* n_oct, int64_t* n_leaf)
 int ryo_get_mesh(const ryo_ctx* c, int32_t l, uint64_t* keys, uint8_t* refined) {
   if (!level_ok(c, l)) return RYO_EINVAL;
   const level_t* L = LVc(c, l);
+  if (L->n == 0) return RYO_OK;   /* an empty level may hold no arrays */
   if (keys) memcpy(keys, L->key, L->n * sizeof(uint64_t));
   if (refined) memcpy(refined, L->refined, L->n);
   return RYO_OK;
@@ -1018,21 +1045,21 @@ int ryo_get_mesh(const ryo_ctx* c, int32_t l, uint64_t* keys, uint8_t* refined) 
 int ryo_get_coords(const ryo_ctx* c, int32_t l, int32_t* xyz) {
   if (!level_ok(c, l) || !xyz) return RYO_EINVAL;
   const level_t* L = LVc(c, l);
-  memcpy(xyz, L->oc, L->n * 3 * sizeof(int32_t));
+  if (L->n) memcpy(xyz, L->oc, L->n * 3 * sizeof(int32_t));
   return RYO_OK;
 }
 
 int ryo_download(const ryo_ctx* c, int32_t l, double* U) {
   if (!level_ok(c, l) || !U) return RYO_EINVAL;
   const level_t* L = LVc(c, l);
-  memcpy(U, L->U, L->n * 8 * c->nv * sizeof(double));
+  if (L->n) memcpy(U, L->U, L->n * 8 * c->nv * sizeof(double));
   return RYO_OK;
 }
 
 int ryo_upload(ryo_ctx* c, int32_t l, const double* U) {
   if (!level_ok(c, l) || !U) return RYO_EINVAL;
   level_t* L = LV(c, l);
-  memcpy(L->U, U, L->n * 8 * c->nv * sizeof(double));
+  if (L->n) memcpy(L->U, U, L->n * 8 * c->nv * sizeof(double));
   c->numeric_error = 0;
   return RYO_OK;
 }

@@ -80,9 +80,10 @@ int  ryo_conserved_totals(const ryo_ctx* c, double* tot);
  * build, each event of a step counted once: a leaf cell's own primitive
  * conversion; both face states of each face an update uses (counted by the
  * face's upper cell when that is a leaf, else by its lower cell); once per
- * parent step, every ghost cell of a refined level (the cells of the oct
- * positions next to the level's octs that hold no oct of the level).  The
- * time-step computation is not counted. */
+ * parent step, every ghost cell of a refined level that an update reads
+ * (a ghost cell with a leaf cell one step away along an axis, two steps
+ * along an axis, or one step along each of two axes).  The time-step
+ * computation is not counted. */
 int64_t ryo_floor_count(const ryo_ctx* c);
 void ryo_reset_floor_count(ryo_ctx* c);
 const char* ryo_last_error(const ryo_ctx* c);
