@@ -175,7 +175,8 @@ typedef struct {
 } ry_tuning;
 /* ry_set_tuning sets the tuning of every level; ry_get_tuning returns the
  * tuning of level_min.  RY_EINVAL for a combination without a kernel (see
- * the fields; batched boxes run on 4^3-cell tiles). */
+ * the fields).  Choosing the 8^3-cell tile builds its tile tables on the
+ * device (syncs). */
 ry_status ry_set_tuning(ry_ctx* ctx, const ry_tuning* t);
 ry_status ry_get_tuning(const ry_ctx* ctx, ry_tuning* t);
 /* Tuning of one level (RY_EINVAL outside level_min..level_max).  Choosing

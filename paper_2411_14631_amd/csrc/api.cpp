@@ -40,6 +40,8 @@ struct DevLevel {
   int32_t n_super = 0;
   int32_t* stab = nullptr;
   uint32_t* stflag = nullptr;
+  int32_t* sbox = nullptr;           // batched boxes: box of each super-tile
+  int32_t* spart = nullptr;          // batched boxes: its CFL partial's index
   int64_t plane() const { return 8 * n_ext; }
 };
 
@@ -79,6 +81,7 @@ struct ry_ctx {
   double* d_partial = nullptr;
   double* d_tot = nullptr;
   double* d_dx_box = nullptr;
+  int64_t* d_box_noct = nullptr;          // batch: octs per axis of each box (3 per box)
   bool slots_valid = false;
   // subcycling order state for ry_hydro_step
   int count[RY_MAX_LEVELS] = {0};
@@ -374,6 +377,12 @@ ry_status enqueue_ghost(ry_ctx* c, int l, const int32_t* skip) {
   g.gamma = c->cfg.gamma;
   g.rho_floor = c->cfg.rho_floor;
   g.p_floor = c->cfg.p_floor;
+  g.key = L.dkey;
+  g.refined = L.refined;
+  g.bits = c->dom.hbits0 + (l - c->cfg.level_min);
+  for (int a = 0; a < 3; ++a) g.noct[a] = c->dom.noct(l, a);
+  for (int i = 0; i < 6; ++i) g.bc[i] = c->dom.bc[i];
+  g.coarse_oc = c->lev[l - 1 - c->cfg.level_min].doc;
   TimedLaunch tl;
   if (c->timing) time_begin(c, "ghost", tl);
   if (launch_ghost(g, c->stream)) return fail(c, RY_EHIP, "ghost kernel");
@@ -413,14 +422,19 @@ HydroArgs hydro_args(ry_ctx* c, int l, int substep) {
 // of the small tiles, a scan of the block starts, then each super-tile's
 // 6x6x6 oct neighbourhood assembled from its small tiles' tables.  Syncs
 // once (the super-tile count).  Not inside a graph capture.
-ry_status build_super(ry_ctx* c, int k) {
-  DevLevel& L = c->lev[k];
-  dfree(c, L.stab);
-  dfree(c, L.stflag);
+void free_super(ry_ctx* c, DevLevel& L) {
+  for (void* p : {(void*)L.stab, (void*)L.stflag, (void*)L.sbox, (void*)L.spart}) dfree(c, p);
   L.stab = nullptr;
   L.stflag = nullptr;
+  L.sbox = nullptr;
+  L.spart = nullptr;
   L.n_super = 0;
   L.super_ok = false;
+}
+
+ry_status build_super(ry_ctx* c, int k) {
+  DevLevel& L = c->lev[k];
+  free_super(c, L);
   if (L.n_tile > 0) {
     const int32_t nt = L.n_tile;
     std::vector<void*> tmp;
@@ -442,8 +456,16 @@ ry_status build_super(ry_ctx* c, int k) {
       release();
       return fail(c, RY_ENOMEM, "super-tile tables: allocation failed");
     }
+    SuperDom D{};
+    const int l = c->cfg.level_min + k;
+    for (int a = 0; a < 3; ++a) D.noct[a] = c->dom.noct(l, a);
+    for (int i = 0; i < 6; ++i) D.bc[i] = c->dom.bc[i];
+    if (c->batch) {
+      D.tile_box = L.tile_box;
+      D.box_noct = c->d_box_noct;
+    }
     int32_t ns = 0;
-    if (launch_super_keys(L.tab, nt, L.doc, L.n_oct, skey, ssub, start, c->stream) ||
+    if (launch_super_keys(L.tab, nt, L.doc, L.n_oct, D, skey, ssub, start, c->stream) ||
         launch_scan(start, excl, nt, stmp, c->stream) ||
         hipMemcpyAsync(&ns, stmp + ntmp - 1, sizeof ns, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -458,12 +480,25 @@ ry_status build_super(ry_ctx* c, int k) {
       release();
       return fail(c, RY_ENOMEM, "super-tile tables: allocation failed");
     }
-    SuperDom D{};
-    const int l = c->cfg.level_min + k;
-    for (int a = 0; a < 3; ++a) D.noct[a] = c->dom.noct(l, a);
-    for (int i = 0; i < 6; ++i) D.bc[i] = c->dom.bc[i];
-    if (launch_super_tables(L.tab, skey, ssub, start, excl, nt, ns, D, sub, sblock, L.stab, L.stflag, c->stream) ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
+    if (launch_super_tables(L.tab, skey, ssub, start, excl, nt, ns, D, sub, sblock, L.stab, L.stflag, c->stream)) {
+      release();
+      return fail(c, RY_EHIP, "super-tile table kernels");
+    }
+    if (c->batch) {
+      // each super-tile's box (lambda) and CFL partial slot in its box's segment
+      auto* sfirst = static_cast<int32_t*>(A(sizeof(int32_t) * std::max(c->nbox, 1)));
+      L.sbox = static_cast<int32_t*>(dalloc(c, sizeof(int32_t) * std::max(ns, 1)));
+      L.spart = static_cast<int32_t*>(dalloc(c, sizeof(int32_t) * std::max(ns, 1)));
+      if (!sfirst || !L.sbox || !L.spart) {
+        release();
+        return fail(c, RY_ENOMEM, "super-tile tables: allocation failed");
+      }
+      if (launch_super_boxes(sblock, ns, c->d_segoff, sfirst, L.sbox, L.spart, c->stream)) {
+        release();
+        return fail(c, RY_EHIP, "super-tile box kernels");
+      }
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
       release();
       return fail(c, RY_EHIP, "super-tile table kernels");
     }
@@ -489,14 +524,7 @@ ry_status ensure_super(ry_ctx* c) {
 
 // Super-tile tables of every level are stale (the mesh changed).
 void drop_super(ry_ctx* c) {
-  for (auto& L : c->lev) {
-    dfree(c, L.stab);
-    dfree(c, L.stflag);
-    L.stab = nullptr;
-    L.stflag = nullptr;
-    L.n_super = 0;
-    L.super_ok = false;
-  }
+  for (auto& L : c->lev) free_super(c, L);
 }
 
 // One hydro launch of level k with the level's tuning (or `t`): on the small
@@ -510,6 +538,15 @@ ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a, int k, const ry_tuning* t
     b.tab = L.stab;
     b.tflag = L.stflag;
     b.n_tile = L.n_super;
+    if (c->batch) {
+      b.tile_box = L.sbox;
+      b.tile_part = L.spart;
+    }
+    // the 8^3-cell tile's wavefronts take an atomic maximum of the batch's
+    // per-tile CFL partials: clear them (the segmented maximum of the
+    // previous partials has been taken by now)
+    if (b.tile_smax && launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_part), c->seg_off.back(), c->stream))
+      return fail(c, RY_EHIP, "zero kernel");
   }
   if (tu.persistent && launch_zero_u32(c->d_queue, 8 * QUEUE_STRIDE, c->stream)) return fail(c, RY_EHIP, "zero kernel");
   TimedLaunch tl;
@@ -1453,6 +1490,8 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
   LevelTables all;
   std::vector<double> Uall;
   std::vector<int32_t> oct_box;
+  std::vector<int32_t> oc;                  // oct coordinates in each box, x y z interleaved
+  std::vector<int64_t> box_noct;            // octs per axis of each box
   std::vector<std::vector<double>> Ubox(nbox);
   int64_t off = 0;
   for (int b = 0; b < nbox; ++b) {
@@ -1479,7 +1518,13 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
       all.tflag.push_back(t.tflag[i]);
       all.tile_box.push_back(b);
     }
-    for (int64_t o = 0; o < t.n_oct; ++o) oct_box.push_back(b);
+    for (int64_t o = 0; o < t.n_oct; ++o) {
+      oct_box.push_back(b);
+      oc.push_back(H[0].ox[o]);
+      oc.push_back(H[0].oy[o]);
+      oc.push_back(H[0].oz[o]);
+    }
+    for (int a = 0; a < 3; ++a) box_noct.push_back(cfgs[b].nbase[a] / 2);
     Ubox[b] = H[0].U;
     off += t.n_oct;
   }
@@ -1513,7 +1558,9 @@ ry_status ry_batch_create(const ry_config* cfgs, int32_t nbox, const double* con
     D.refined = upload_vec(c, all.refined_ext, ok);
     D.tile_box = upload_vec(c, all.tile_box, ok);
     D.oct_box = upload_vec(c, oct_box, ok);
+    D.doc = upload_vec(c, oc, ok);
     c->d_dx_box = upload_vec(c, c->box_dx, ok);
+    c->d_box_noct = upload_vec(c, box_noct, ok);
   }
   if (!ok || alloc_scalars(c, nbox)) {
     ry_destroy(c);
@@ -1633,7 +1680,6 @@ ry_status check_tuning(ry_ctx* c, const ry_tuning& t) {
   if (t.tile_cells == 8) {
     if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent)
       return fail(c, RY_EINVAL, "tile_cells 8 needs tiles_per_wg 1, waves_per_tile 8, persistent 0");
-    if (c->batch) return fail(c, RY_EINVAL, "batched boxes run on 4^3-cell tiles");
   } else if (t.tile_cells == 4) {
     if (t.tiles_per_wg != 1 && t.tiles_per_wg != 2 && t.tiles_per_wg != 4) return fail(c, RY_EINVAL, "tiles_per_wg");
     if (t.waves_per_tile != 1 && t.waves_per_tile != 2 && t.waves_per_tile != 4)
@@ -1820,15 +1866,7 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
   drop_all_graphs(c);
   // tables of levels left without the 8^3-cell tile are not needed any more
   for (int k = 0; k < c->nlev; ++k)
-    if (c->tune[k].tile_cells != 8 && c->lev[k].super_ok) {
-      DevLevel& L = c->lev[k];
-      dfree(c, L.stab);
-      dfree(c, L.stflag);
-      L.stab = nullptr;
-      L.stflag = nullptr;
-      L.n_super = 0;
-      L.super_ok = false;
-    }
+    if (c->tune[k].tile_cells != 8 && c->lev[k].super_ok) free_super(c, c->lev[k]);
   ry_status s = ensure_super(c);
   if (s) return s;
   if (best) *best = c->tune[0];

@@ -795,13 +795,15 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       const int sl = (tile * (NCORE / 64) + (tid >> 6)) & (SMAX_SLOTS - 1);
       if (lane == 0) atomicMax(A.smax_bits + sl, (unsigned long long)__double_as_longlong(m));
     } else if (active && A.tile_smax) {
-      // batched boxes: one partial per tile (an atomic maximum on its bit
-      // pattern when several wavefronts hold the tile's cells), reduced per
-      // box by the segmented max kernel before the next time step
+      // batched boxes: one partial per tile (with several wavefronts per
+      // tile, an atomic maximum on its bit pattern into a slot cleared before
+      // the launch), reduced per box by the segmented max kernel before the
+      // next time step
       const double m = wave_max(s);
+      const int slot = A.tile_part ? A.tile_part[tile] : tile;
       if (lane == 0) {
-        if constexpr (NCORE == 64) A.tile_smax[tile] = m;
-        else atomicMax(reinterpret_cast<unsigned long long*>(A.tile_smax) + tile,
+        if constexpr (NCORE == 64) A.tile_smax[slot] = m;
+        else atomicMax(reinterpret_cast<unsigned long long*>(A.tile_smax) + slot,
                        (unsigned long long)__double_as_longlong(m));
       }
     }

@@ -60,6 +60,52 @@ int launch_hydro(const HydroArgs& a, int precision, int nscalar, const ry_tuning
 // Ghost octs: MinMod-limited linear interpolation of the covering coarse
 // cell's conserved variables, written into both state buffers.
 // ---------------------------------------------------------------------------
+// Whether cell position p of a level (its sorted keys, refined bytes, octs
+// per axis, boundaries) is a leaf cell: positions past an outflow face and
+// positions without an oct are not.
+__device__ bool leaf_at(const GhostArgs& A, int64_t x, int64_t y, int64_t z) {
+  int64_t p[3] = {x, y, z};
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = 2 * A.noct[a];
+    if (p[a] < 0) {
+      if (A.bc[2 * a] != RY_BC_PERIODIC) return false;
+      p[a] += n;
+    } else if (p[a] >= n) {
+      if (A.bc[2 * a + 1] != RY_BC_PERIODIC) return false;
+      p[a] -= n;
+    }
+  }
+  const uint64_t k = hilbert3(A.bits, uint32_t(p[0] >> 1), uint32_t(p[1] >> 1), uint32_t(p[2] >> 1));
+  int64_t lo = 0, hi = A.n_oct;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (A.key[mid] < k) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo >= A.n_oct || A.key[lo] != k) return false;
+  const int cb = int((p[0] & 1) | ((p[1] & 1) << 1) | ((p[2] & 1) << 2));
+  return !((A.refined[lo] >> cb) & 1);
+}
+// Whether an update reads cell position p: a leaf cell one step away along
+// an axis, two steps along an axis, or one step along each of two axes.
+__device__ bool read_by_update(const GhostArgs& A, int64_t x, int64_t y, int64_t z) {
+  for (int d = 0; d < 3; ++d)
+    for (int s = -2; s <= 2; ++s) {
+      if (s == 0) continue;
+      if (leaf_at(A, x + (d == 0) * s, y + (d == 1) * s, z + (d == 2) * s)) return true;
+    }
+  for (int d = 0; d < 3; ++d)
+    for (int e = d + 1; e < 3; ++e)
+      for (int sd = -1; sd <= 1; sd += 2)
+        for (int se = -1; se <= 1; se += 2) {
+          int64_t q[3] = {x, y, z};
+          q[d] += sd;
+          q[e] += se;
+          if (leaf_at(A, q[0], q[1], q[2])) return true;
+        }
+  return false;
+}
+
 // One thread per ghost oct: its 8 cells are the children of one coarse cell
 // Q and share Q's 7 sources, loaded once (NV, the variable count, is a
 // template parameter so that all 7 x NV loads issue before the first use);
@@ -109,13 +155,25 @@ __global__ void ghost_kernel(GhostArgs A) {
   }
   if (A.floors) {
     // the floors the primitive conversion of each cell applies (density,
-    // then pressure from E minus the kinetic energy at the floored density)
+    // then pressure from E minus the kinetic energy at the floored density),
+    // counted for the cells an update reads
     int n = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const double r = keep[0][c] < A.rho_floor ? A.rho_floor : keep[0][c];
       const double ke = 0.5 * (keep[1][c] * keep[1][c] + keep[2][c] * keep[2][c] + keep[3][c] * keep[3][c]) / r;
-      n += int(keep[0][c] < A.rho_floor) + int((A.gamma - 1.0) * (keep[4][c] - ke) < A.p_floor);
+      const int f = int(keep[0][c] < A.rho_floor) + int((A.gamma - 1.0) * (keep[4][c] - ke) < A.p_floor);
+      if (f) {
+        // the ghost oct sits on the coarse cell Q it interpolates (level l-1
+        // cell coordinates = level l oct coordinates)
+        const int64_t q = A.gsrc[gi * 7] & ((int64_t(1) << 48) - 1);
+        const int64_t oq = q >> 3;
+        const int qb = int(q & 7);
+        const int64_t gx = 2 * int64_t(A.coarse_oc[3 * oq]) + (qb & 1),
+                      gy = 2 * int64_t(A.coarse_oc[3 * oq + 1]) + ((qb >> 1) & 1),
+                      gz = 2 * int64_t(A.coarse_oc[3 * oq + 2]) + (qb >> 2);
+        if (read_by_update(A, 2 * gx + (c & 1), 2 * gy + ((c >> 1) & 1), 2 * gz + (c >> 2))) n += f;
+      }
     }
     if (n) atomicAdd(A.floors, (unsigned long long)n);
   }
@@ -465,16 +523,32 @@ int launch_regrid_remap(const int32_t* src_old, const int32_t* src7, int64_t n_n
 // ---------------------------------------------------------------------------
 constexpr int SMALL_TAB = 64, SUPER_TAB = 216;
 
-__device__ __forceinline__ uint64_t pack_block(int64_t x, int64_t y, int64_t z) {
-  return uint64_t(x) | (uint64_t(y) << 21) | (uint64_t(z) << 42);
+// Block key: block coordinates (21 bits each) or, in a batch of boxes, the
+// box (from bit 45) and the block coordinates in the box (15 bits each).
+__device__ __forceinline__ uint64_t pack_block(int64_t x, int64_t y, int64_t z, int box) {
+  if (box < 0) return uint64_t(x) | (uint64_t(y) << 21) | (uint64_t(z) << 42);
+  return uint64_t(x) | (uint64_t(y) << 15) | (uint64_t(z) << 30) | (uint64_t(box) << 45);
+}
+__device__ __forceinline__ void unpack_block(uint64_t b, bool batch, int64_t o[3], int& box) {
+  if (!batch) {
+    o[0] = int64_t(b & 0x1FFFFF);
+    o[1] = int64_t((b >> 21) & 0x1FFFFF);
+    o[2] = int64_t(b >> 42);
+    box = -1;
+  } else {
+    o[0] = int64_t(b & 0x7FFF);
+    o[1] = int64_t((b >> 15) & 0x7FFF);
+    o[2] = int64_t((b >> 30) & 0x7FFF);
+    box = int(b >> 45);
+  }
 }
 
 // Per small tile: the key of its 4x4x4-oct block and its position (0..7)
 // inside the block, from one of its own octs (a tile holds at least one,
 // and its 2x2x2 core slots of the table hold every present one).
 __global__ void super_key_kernel(const int32_t* __restrict__ tab, int32_t n_tile, const int32_t* __restrict__ oc,
-                                 int64_t n_oct, uint64_t* __restrict__ skey, int32_t* __restrict__ ssub,
-                                 int32_t* __restrict__ start) {
+                                 int64_t n_oct, const int32_t* __restrict__ tile_box, uint64_t* __restrict__ skey,
+                                 int32_t* __restrict__ ssub, int32_t* __restrict__ start) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n_tile) return;
   int32_t e = -1;
@@ -492,7 +566,7 @@ __global__ void super_key_kernel(const int32_t* __restrict__ tab, int32_t n_tile
     return;
   }
   const int64_t bx = oc[3 * int64_t(e)] & ~1, by = oc[3 * int64_t(e) + 1] & ~1, bz = oc[3 * int64_t(e) + 2] & ~1;
-  skey[t] = pack_block(bx >> 2, by >> 2, bz >> 2);
+  skey[t] = pack_block(bx >> 2, by >> 2, bz >> 2, tile_box ? tile_box[t] : -1);
   ssub[t] = int32_t(((bx >> 1) & 1) | (((by >> 1) & 1) << 1) | (((bz >> 1) & 1) << 2));
 }
 
@@ -535,14 +609,17 @@ __global__ void super_table_kernel(const int32_t* __restrict__ tab, const int32_
   }
   stab[i] = v;
   if (slot == 0) {
-    const uint64_t b = sblock[s];
-    const int64_t o[3] = {int64_t(b & 0x1FFFFF) * 4, int64_t((b >> 21) & 0x1FFFFF) * 4, int64_t(b >> 42) * 4};
+    int64_t o[3];
+    int box;
+    unpack_block(sblock[s], D.box_noct != nullptr, o, box);
     uint32_t fl = 0;
     int cut[3];
     for (int a = 0; a < 3; ++a) {
+      o[a] *= 4;
+      const int64_t n = D.box_noct ? D.box_noct[3 * int64_t(box) + a] : D.noct[a];
       if (o[a] == 0 && D.bc[2 * a] == RY_BC_OUTFLOW) fl |= (1u << (2 * a));
-      if (o[a] + 4 >= D.noct[a] && D.bc[2 * a + 1] == RY_BC_OUTFLOW) fl |= (2u << (2 * a));
-      const int64_t past = o[a] + 4 - D.noct[a];
+      if (o[a] + 4 >= n && D.bc[2 * a + 1] == RY_BC_OUTFLOW) fl |= (2u << (2 * a));
+      const int64_t past = o[a] + 4 - n;
       cut[a] = past > 0 ? int(2 * past) : 0;
     }
     stflag[s] = fl | (uint32_t(cut[0]) << CL_CUT_SHIFT) | (uint32_t(cut[1]) << (CL_CUT_SHIFT + 3)) |
@@ -552,11 +629,39 @@ __global__ void super_table_kernel(const int32_t* __restrict__ tab, const int32_
 
 int super_table_slots() { return SUPER_TAB; }
 
-int launch_super_keys(const int32_t* tab, int32_t n_tile, const int32_t* oc, int64_t n_oct, uint64_t* skey,
-                      int32_t* ssub, int32_t* start, void* stream) {
+// Batched boxes: the first super-tile of every box (super-tiles come box by
+// box), then each super-tile's box and partial slot in its box's segment.
+__global__ void super_first_kernel(const uint64_t* __restrict__ sblock, int32_t n_super, int32_t* __restrict__ sfirst,
+                                   int32_t* __restrict__ sbox) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n_super) return;
+  const int box = int(sblock[s] >> 45);
+  sbox[s] = box;
+  if (s == 0 || int(sblock[s - 1] >> 45) != box) sfirst[box] = int32_t(s);
+}
+__global__ void super_part_kernel(const int32_t* __restrict__ sbox, int32_t n_super, const int64_t* __restrict__ seg_off,
+                                  const int32_t* __restrict__ sfirst, int32_t* __restrict__ spart) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n_super) return;
+  const int box = sbox[s];
+  spart[s] = int32_t(seg_off[box] + (s - sfirst[box]));
+}
+
+int launch_super_boxes(const uint64_t* sblock, int32_t n_super, const int64_t* seg_off, int32_t* sfirst,
+                       int32_t* sbox, int32_t* spart, void* stream) {
+  if (n_super == 0) return 0;
+  const dim3 g(unsigned((n_super + 255) / 256)), b(256);
+  hipLaunchKernelGGL(super_first_kernel, g, b, 0, (hipStream_t)stream, sblock, n_super, sfirst, sbox);
+  hipLaunchKernelGGL(super_part_kernel, g, b, 0, (hipStream_t)stream, sbox, n_super, seg_off, sfirst, spart);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_super_keys(const int32_t* tab, int32_t n_tile, const int32_t* oc, int64_t n_oct, const SuperDom& D,
+                      uint64_t* skey, int32_t* ssub, int32_t* start, void* stream) {
   if (n_tile == 0) return 0;
   const dim3 g(unsigned((n_tile + 255) / 256)), b(256);
-  hipLaunchKernelGGL(super_key_kernel, g, b, 0, (hipStream_t)stream, tab, n_tile, oc, n_oct, skey, ssub, start);
+  hipLaunchKernelGGL(super_key_kernel, g, b, 0, (hipStream_t)stream, tab, n_tile, oc, n_oct, D.tile_box, skey, ssub,
+                     start);
   hipLaunchKernelGGL(super_start_kernel, g, b, 0, (hipStream_t)stream, skey, n_tile, start);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -150,6 +150,7 @@ struct HydroArgs {
   double lam_host;            // used when lam_dev == nullptr
   const int32_t* tile_box;
   double* tile_smax;          // CFL epilogue: max signal speed per tile, nullptr = off
+  const int32_t* tile_part;   // index of each tile's partial in tile_smax (nullptr: the tile index)
   unsigned long long* smax_bits;  // CFL epilogue: the level's SMAX_SLOTS slots of the maximum
                                   // signal speed (bit patterns of non-negative doubles, one
                                   // atomic max per tile); nullptr = off (else tile_smax)
@@ -171,9 +172,16 @@ struct GhostArgs {
   int32_t nv;
   const int32_t* skip;
   // floor census of the ghost cells (once per parent step): activations of
-  // the primitive conversion of each interpolated cell; nullptr = off
+  // the primitive conversion of each interpolated cell that an update reads
+  // (a leaf cell of the level in its stencil); nullptr = off
   unsigned long long* floors;
   double gamma, rho_floor, p_floor;
+  const uint64_t* key;               // the level's sorted Hilbert keys (n_oct of them)
+  const uint8_t* refined;            // its refined-cell bytes
+  int32_t bits;                      // its Hilbert bits per axis
+  int64_t noct[3];                   // its octs per axis
+  int32_t bc[6];
+  const int32_t* coarse_oc;          // oct coordinates of level l-1 (x y z interleaved)
 };
 
 // launchers (kernels.hip)
@@ -273,16 +281,25 @@ int hydro_max_tiles_per_wg();
 struct SuperDom {
   int64_t noct[3];                   // octs per axis of the level
   int32_t bc[6];
+  // batched boxes: the box of every small tile and the octs per axis of
+  // every box (3 per box); nullptr for a level of one domain
+  const int32_t* tile_box;
+  const int64_t* box_noct;
 };
 int super_table_slots();             // 6^3 oct neighbourhood entries per super-tile
 // per small tile: its block key, its position in the block, block starts
 // (start[t] = 1 where a new block begins; scan it for the block numbers)
-int launch_super_keys(const int32_t* tab, int32_t n_tile, const int32_t* oc, int64_t n_oct, uint64_t* skey,
-                      int32_t* ssub, int32_t* start, void* stream);
+int launch_super_keys(const int32_t* tab, int32_t n_tile, const int32_t* oc, int64_t n_oct, const SuperDom& D,
+                      uint64_t* skey, int32_t* ssub, int32_t* start, void* stream);
 // the super-tiles' tables and flags (excl = exclusive scan of start; sub:
 // n_super * 8 scratch ints; sblock: n_super scratch keys)
 int launch_super_tables(const int32_t* tab, const uint64_t* skey, const int32_t* ssub, const int32_t* start,
                         const int32_t* excl, int32_t n_tile, int32_t n_super, const SuperDom& D, int32_t* sub,
                         uint64_t* sblock, int32_t* stab, uint32_t* stflag, void* stream);
+// batched boxes: the box of every super-tile and the index of its CFL
+// partial inside its box's segment (seg_off: the boxes' segment offsets;
+// sfirst: nbox scratch ints)
+int launch_super_boxes(const uint64_t* sblock, int32_t n_super, const int64_t* seg_off, int32_t* sfirst,
+                       int32_t* sbox, int32_t* spart, void* stream);
 
 }  // namespace ry

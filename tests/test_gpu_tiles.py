@@ -141,12 +141,36 @@ def test_autotune_per_level_keeps_results(ry):
         np.testing.assert_array_equal(x, y)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_big_tile_bit_exact(ry, prec):
+    """Batched boxes on 8^3-cell tiles (sides of 8 mod 16 and 2 mod 4 give
+    super-tiles cut by the box's high side): the same boxes and times as on
+    4^3-cell tiles, FP64 also against the oracle; the autotuner may pick
+    either shape."""
+    boxes = [W.batch_box(40, 24, 1.0, 1.5), W.batch_box(41, 18, 0.7, 0.8), W.batch_box(42, 32, 1.2, 2.0),
+             W.batch_box(43, 10, 0.5, 1.0), W.batch_box(44, 16, 1.0, 1.0)]
+    out = []
+    for t in (SMALL, BIG, None):
+        bh = ry.BatchHydro(boxes, prec)
+        if t is None:
+            bh.autotune()
+        else:
+            bh.set_tuning(**t)
+        bh.run(4)
+        out.append(([bh.download(b) for b in range(len(boxes))], [bh.box_info(b)[1] for b in range(len(boxes))]))
+        bh.close()
+    for states, times in out[1:]:
+        assert times == out[0][1]
+        for a, b in zip(states, out[0][0]):
+            np.testing.assert_array_equal(a, b)
+    if prec == "fp64":
+        for b, p in enumerate(boxes):
+            o = Oracle(p)
+            o.advance(4)
+            assert cases.rel_err(out[1][0][b], o.download(p.level_min)) <= TOL, b
+
+
 def test_big_tile_rejected_where_unsupported(ry):
-    boxes = [W.batch_box(0, 16, 1.0, 1.0)]
-    bh = ry.BatchHydro(boxes)
-    with pytest.raises(ry.RyError) as e:
-        bh.set_tuning(**BIG)
-    assert e.value.code == ry.RY_EINVAL
     g = ry.Hydro(cases.with_scalars(cases.amr_blob(), 1))
     with pytest.raises(ry.RyError) as e:
         g.set_tuning(**BIG)
