@@ -11,6 +11,16 @@ its launch stream, and the CPU oracle timed on the host as a baseline.
 A cell-update is one leaf cell advanced by one step of its own level;
 algorithmic HBM bytes are 80 per cell-update (5 FP64 read + 5 written).
 
+Timing: every throughput figure is the median of REPS repetitions of its
+timed steps (each repetition bracketed by device synchronisations); a plain
+device copy timed in the same run gives the achievable HBM bandwidth next to
+the vendor peak.  Every mixed-form figure carries its errors against the
+FP64 form after the workload's own step count (10 coarse steps; 20 for the
+batched boxes): relative L1 and largest relative density and pressure
+errors over leaf cells, and both forms' total-energy drift.  The FP64 form
+is itself pinned to the oracle by the GPU tests, and the CPU-baseline leg
+compares both forms with the oracle directly on the 128^3 box.
+
 The line also carries the uniform-level Poisson solver (PPCG with the
 seven-point preconditioner) on a 256^3 periodic gravity source: iterations
 to eps = 1e-4 against pipelined plain CG, time to solution, and the
@@ -31,6 +41,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+REPS = 5                                # timed repetitions per figure (median reported)
+COPY_PROBE_BYTES = 256 << 20
 VALU_PEAK_ISSUE = 1024 * 2.4e9 / 4      # 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles
 BYTES_PER_CELL_UPDATE = 80
 METRIC = "hydro cell-updates/s (FP64 vs mixed FP32) + % HBM roofline, 128^3 and zoom AMR"
@@ -67,22 +79,40 @@ def traffic_from_profiles(workload_key):
     return profiled_counters(workload_key).get("bytes_per_launch")
 
 
-def time_advance(h, steps, warmup, timing):
+def median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+def timed_reps(h, steps, reps=REPS):
+    """Wall time of `steps` coarse steps (graph replay, the production path),
+    `reps` times; returns (median seconds, all repetitions)."""
     import torch
-    h.set_timing(timing)
-    if warmup:
-        h.advance(warmup)
-    if timing:
-        h.set_timing(False)
-        h.set_timing(True)          # reset the per-kernel accumulators
+    h.set_timing(False)
+    out = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.advance(steps)
+        torch.cuda.synchronize()
+        out.append(time.perf_counter() - t0)
+    return median(out), out
+
+
+def eager_kernel_time(h, steps, name="hydro"):
+    """`steps` coarse steps launched one kernel at a time with HIP events on
+    the library's stream around every launch: (launches, total ms) of the
+    kernels called `name`."""
+    import torch
+    h.set_timing(False)
+    h.set_timing(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     h.advance(steps)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kt = h.kernel_time("hydro") if timing else (0, 0.0)
+    kt = h.kernel_time(name)
     h.set_timing(False)
-    return dt, kt
+    return kt
 
 
 def cell_updates_per_coarse_step(h):
@@ -93,29 +123,27 @@ def cell_updates_per_coarse_step(h):
     return tot
 
 
-def run_uniform(precision, steps, warmup, tune, fixed=None, eager_only=False):
-    import workloads as W
+def level_tunings(h):
+    return {str(lv): h.level_tuning(lv) for lv in h.levels}
+
+
+def tuning_label(t):
+    if t["tile_cells"] == 8:
+        return "8^3-cell tile (4x4x4 octs), 512 threads"
+    return (f"4^3-cell tile (2x2x2 octs), {64 * t['waves_per_tile']} threads per tile, "
+            f"{t['tiles_per_wg']} tile(s) per workgroup" + (", queue-fed" if t["persistent"] else ""))
+
+
+def make(prob, precision, tune, fixed):
     from paper_2411_14631_amd import Hydro
-    prob = W.uniform(128)
+    t0 = time.perf_counter()
     h = Hydro(prob, precision)
-    tuning = None
+    build_s = time.perf_counter() - t0
     if fixed:
         h.set_tuning(*fixed)
     elif tune:
-        tuning, _ = h.autotune()
-    cups = cell_updates_per_coarse_step(h)
-    e0 = h.totals()[4]
-    if eager_only:
-        # every launch of the run with HIP events around it (profiling runs:
-        # the profiler's per-kernel average then covers the same launches)
-        dt_graph, pcie = None, None
-        dt_ev, (nl, ms) = time_advance(h, steps, warmup, timing=True)
-    else:
-        dt_graph, _ = time_advance(h, steps, warmup, timing=False)
-        dt_ev, (nl, ms) = time_advance(h, steps, 0, timing=True)
-        pcie = pcie_inclusive(h, steps)
-    return dict(prob=prob, h=h, cups=cups, dt_graph=dt_graph, dt_timed=dt_ev, launches=nl, kernel_ms=ms,
-                tuning=tuning or h.tuning(), floors=h.floors(), e0=e0, pcie=pcie)
+        h.autotune()
+    return h, build_s
 
 
 def pcie_inclusive(h, steps):
@@ -134,24 +162,79 @@ def pcie_inclusive(h, steps):
     return cell_updates_per_coarse_step(h) * steps / el
 
 
-def run_zoom(prob, precision, steps, tune):
-    from paper_2411_14631_amd import Hydro
-    t0 = time.perf_counter()
-    h = Hydro(prob, precision)
-    build_s = time.perf_counter() - t0
-    if tune:
-        h.autotune()
+def run_amr_pair(prob, tune, fixed, timed_steps, eager_steps=0, keep=False):
+    """Both precision forms of one (AMR or uniform) workload: each advanced
+    its configuration's coarse steps (the first ones capture the graphs),
+    compared, then timed (median of REPS repetitions of `timed_steps`)."""
+    import torch
+    res, hs = {}, {}
+    for prec in ("fp64", "mixed"):
+        h, build_s = make(prob, prec, tune, fixed)
+        e0 = h.totals()[4]
+        h.advance(prob.n_steps)
+        hs[prec] = (h, e0)
+        res[prec] = {"build_s": round(build_s, 2), "tunings": level_tunings(h)}
+    res["mixed"]["vs_fp64"] = compare_forms(hs["fp64"][0], hs["mixed"][0], hs["fp64"][1], hs["mixed"][1])
+    res["mixed"]["vs_fp64"]["coarse_steps"] = prob.n_steps
+    for prec in ("fp64", "mixed"):
+        h = hs[prec][0]
+        cups = cell_updates_per_coarse_step(h)
+        med, reps = timed_reps(h, timed_steps)
+        r = res[prec]
+        r.update({"value": cups * timed_steps / med, "unit": "cell-updates/s",
+                  "ms_per_coarse_step": round(1e3 * med / timed_steps, 4),
+                  "hbm_frac": round(BYTES_PER_CELL_UPDATE * cups * timed_steps / med / 1e9 / HBM_PEAK_GBS, 4),
+                  "cell_updates_per_coarse_step": cups, "timed_coarse_steps": timed_steps,
+                  "repetitions_ms_per_coarse_step": [round(1e3 * x / timed_steps, 4) for x in reps],
+                  "floor_activations": h.floors(),
+                  "octs": sum(h.level_info(lv)[0] for lv in h.levels)})
+        if eager_steps:
+            # the hydro kernels' own time per coarse step (HIP events around
+            # each launch): their rate against HBM without launch gaps
+            nl, ms = eager_kernel_time(h, eager_steps)
+            hk = ms / eager_steps
+            r["hydro_kernels_ms_per_coarse_step"] = round(hk, 4)
+            r["hydro_kernels_hbm_frac"] = round(BYTES_PER_CELL_UPDATE * cups / (hk * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            r["hydro_launches_per_coarse_step"] = nl // eager_steps
+    res["levels"] = {str(lv): hs["fp64"][0].level_info(lv) for lv in hs["fp64"][0].levels}
+    if keep:
+        return res, hs
+    for prec in hs:
+        hs[prec][0].close()
+    del hs
+    torch.cuda.empty_cache()
+    return res, None
+
+
+def run_zoom_only(precision, steps, warmup, tune, fixed, eager):
+    """The zoom hierarchy alone (for profiling): `warmup` untimed coarse
+    steps, then `steps` timed ones, replayed from captured graphs or, with
+    `eager`, launched one by one with HIP events around every kernel (the
+    hydro kernels' summed time per coarse step then gives the hydro
+    kernels' rate against HBM)."""
+    import torch
+    import workloads as W
+    h, _ = make(W.zoom(), precision, tune, fixed)
     cups = cell_updates_per_coarse_step(h)
-    noct = sum(h.level_info(lv)[0] for lv in h.levels)
-    e0 = h.totals()[4]
-    # two untimed steps capture the single-step graphs of both state
-    # parities, so that the timed steps replay graphs (fewer than 8 timed
-    # steps: no multi-step graph is captured inside the timed region)
-    assert steps < 8
-    dt_graph, _ = time_advance(h, steps, 2, timing=False)
-    h.advance(10 - steps - 2)                      # 10 coarse steps in total
-    return dict(h=h, cups=cups, noct=noct, dt=dt_graph, build_s=build_s, e0=e0, floors=h.floors(),
-                levels={lv: h.level_info(lv) for lv in h.levels})
+    if warmup:
+        h.advance(warmup)
+    out = {"workload": "zoom AMR levels 7-12", "precision": precision, "steps": steps,
+           "cell_updates_per_coarse_step": cups, "tunings": level_tunings(h),
+           "levels": {str(lv): h.level_info(lv) for lv in h.levels}}
+    if eager:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nl, ms = eager_kernel_time(h, steps)
+        dt = time.perf_counter() - t0
+        hydro_ms = ms / steps
+        out.update({"hydro_launches": nl, "hydro_ms_per_coarse_step": hydro_ms,
+                    "hydro_achieved_GBps": BYTES_PER_CELL_UPDATE * cups / (hydro_ms * 1e-3) / 1e9})
+        out["hydro_hbm_frac"] = out["hydro_achieved_GBps"] / HBM_PEAK_GBS
+    else:
+        dt, _ = timed_reps(h, steps, 1)
+    out.update({"value": cups * steps / dt, "ms_per_coarse_step": 1e3 * dt / steps})
+    h.close()
+    return out
 
 
 def leaf_fields(h):
@@ -188,6 +271,37 @@ def compare_forms(hf, hm, e0f, e0m):
     ef, em = hf.totals()[4], hm.totals()[4]
     return {"l1_rho_rel": float(l1 / norm), "max_rho_rel": mx_r, "l1_p_rel": float(l1p), "max_p_rel": mx_p,
             "energy_drift_fp64": float(abs(ef - e0f) / abs(e0f)), "energy_drift_mixed": float(abs(em - e0m) / abs(e0m))}
+
+
+def compare_batches(bf, bm, boxes):
+    """Mixed-form boxes against the FP64 boxes after the same steps: relative
+    L1 (cell-volume weighted, each box a unit box) and largest relative
+    errors of density and pressure over every box's cells, and each form's
+    total-energy drift summed over the boxes."""
+    import numpy as np
+    l1r = l1p = nr = npr = e0 = ef = em = 0.0
+    mr = mp = 0.0
+    for b, p in enumerate(boxes):
+        g = p.gamma
+        vol = 1.0 / p.nbase[0] ** 3
+        Uf, Um = bf.download(b), bm.download(b)
+
+        def rho_p(U):
+            return U[0], (g - 1.0) * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0])
+        rf, pf = rho_p(Uf)
+        rm, pm = rho_p(Um)
+        l1r += np.abs(rm - rf).sum() * vol
+        l1p += np.abs(pm - pf).sum() * vol
+        nr += np.abs(rf).sum() * vol
+        npr += np.abs(pf).sum() * vol
+        mr = max(mr, float(np.max(np.abs(rm - rf) / np.abs(rf))))
+        mp = max(mp, float(np.max(np.abs(pm - pf) / np.abs(pf))))
+        e0 += p.U_base[4].sum() * vol
+        ef += Uf[4].sum() * vol
+        em += Um[4].sum() * vol
+    return {"l1_rho_rel": float(l1r / nr), "max_rho_rel": mr, "l1_p_rel": float(l1p / npr), "max_p_rel": mp,
+            "energy_drift_fp64": float(abs(ef - e0) / abs(e0)), "energy_drift_mixed": float(abs(em - e0) / abs(e0)),
+            "steps": 20}
 
 
 def cpu_baseline(budget_s=12.0):
@@ -280,11 +394,12 @@ def run_scalars(nscalar=2, steps=10, warmup=2):
         h = Hydro(prob, prec)
         tuning, _ = h.autotune()
         cups = cell_updates_per_coarse_step(h)
-        dt, _ = time_advance(h, steps, warmup, timing=False)
-        _, (nl, ms) = time_advance(h, steps, 0, timing=True)
+        h.advance(warmup)
+        med, _ = timed_reps(h, steps)
+        nl, ms = eager_kernel_time(h, steps)
         k = ms / max(nl, 1)
         gbs = 16 * (5 + nscalar) * cups / (k * 1e-3) / 1e9
-        res[prec] = {"value": cups * steps / dt, "unit": "cell-updates/s", "kernel_avg_ms": round(k, 5),
+        res[prec] = {"value": cups * steps / med, "unit": "cell-updates/s", "kernel_avg_ms": round(k, 5),
                      "achieved_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tuning": tuning}
         h.close()
         del h
@@ -337,6 +452,19 @@ def run_poisson(n=256, eps=1e-4, timed_iters=20):
     return res
 
 
+def copy_probe():
+    """A plain device copy of COPY_PROBE_BYTES (read + write), timed in this
+    run: the achievable HBM bandwidth next to the vendor peak."""
+    import workloads as W
+    from paper_2411_14631_amd import Hydro
+    probe = Hydro(W.uniform_state(8), "fp64")
+    ms = probe.copy_probe(COPY_PROBE_BYTES, reps=20)
+    probe.close()
+    gbs = 2 * COPY_PROBE_BYTES / (ms * 1e-3) / 1e9
+    return {"bytes_copied": COPY_PROBE_BYTES, "ms": round(ms, 5), "GBps": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "kernel": "ry::copy_kernel (16-byte loads and stores)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,10 +475,11 @@ def main():
     ap.add_argument("--no-poisson", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tuning", type=str, default="",
-                    help="fixed hydro tuning tiles_per_wg,persistent,waves_per_cu,batch,waves_per_tile")
-    ap.add_argument("--only", choices=["fp64", "mixed", "poisson"], default=None)
+                    help="fixed hydro tuning tiles_per_wg,persistent,waves_per_cu,batch,waves_per_tile[,tile_cells]")
+    ap.add_argument("--only", choices=["fp64", "mixed", "poisson", "zoom", "zoom-mixed", "batch", "batch-mixed",
+                                       "twolevel", "twolevel-mixed"], default=None)
     ap.add_argument("--eager-only", action="store_true",
-                    help="with --only fp64/mixed: every step launched eagerly with HIP events (for profiling)")
+                    help="with --only: every step launched eagerly with HIP events (for profiling)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first launch a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -360,11 +489,11 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    import workloads as W
     tune = not args.no_tune
     fixed = [int(x) for x in args.tuning.split(",")] if args.tuning else None
 
     if args.copy_probe_mb:
-        import workloads as W
         from paper_2411_14631_amd import Hydro
         probe = Hydro(W.uniform_state(8), "fp64")
         ms = probe.copy_probe(args.copy_probe_mb << 20, reps=5)
@@ -376,77 +505,127 @@ def main():
         log("bench: poisson 256^3 only")
         print(json.dumps(run_poisson()), flush=True)
         return
+    if args.only in ("batch", "batch-mixed"):
+        # the 512 batched boxes alone (profiling): `warmup` untimed 20-step
+        # runs (graph capture), then one timed 20-step run
+        from paper_2411_14631_amd import BatchHydro
+        prec = "mixed" if args.only == "batch-mixed" else "fp64"
+        boxes = W.batch(512)
+        cells = sum(p.nbase[0] ** 3 for p in boxes)
+        bh = BatchHydro(boxes, prec)
+        if fixed:
+            bh.set_tuning(*fixed)
+        elif tune:
+            bh.autotune()
+        for _ in range(max(args.warmup, 1)):
+            bh.run(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bh.run(20)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"workload": "512 batched boxes", "precision": prec, "tuning": bh.tuning(),
+                          "value": cells * 20 / el, "ms_per_step": 1e3 * el / 20}), flush=True)
+        return
+    if args.only in ("twolevel", "twolevel-mixed"):
+        prec = "mixed" if args.only == "twolevel-mixed" else "fp64"
+        log(f"bench: two-level theta 0.70 {prec} only")
+        h, _ = make(W.twolevel(128, 0.70), prec, tune, fixed)
+        cups = cell_updates_per_coarse_step(h)
+        h.advance(max(args.warmup, 2))
+        med, _ = timed_reps(h, args.steps)
+        print(json.dumps({"workload": "two-level theta 0.70", "precision": prec, "tunings": level_tunings(h),
+                          "value": cups * args.steps / med, "ms_per_coarse_step": 1e3 * med / args.steps}), flush=True)
+        h.close()
+        return
+    if args.only in ("zoom", "zoom-mixed"):
+        prec = "mixed" if args.only == "zoom-mixed" else "fp64"
+        log(f"bench: zoom AMR {prec} only")
+        print(json.dumps(run_zoom_only(prec, args.steps, args.warmup, tune, fixed, args.eager_only)), flush=True)
+        return
     if args.only:
         log(f"bench: uniform 128^3 {args.only} only")
-        r = run_uniform(args.only, args.steps, args.warmup, tune, fixed, args.eager_only)
-        ms = r["kernel_ms"] / max(r["launches"], 1)
-        print(json.dumps({"precision": args.only,
-                          "cell_updates_per_s": r["cups"] * args.steps / (r["dt_graph"] or r["dt_timed"]),
-                          "timed_cell_updates_per_s": r["cups"] * args.steps / r["dt_timed"],
-                          "hydro_kernel_avg_ms": ms, "tuning": r["tuning"]}), flush=True)
+        h, _ = make(W.uniform(128), args.only, tune, fixed)
+        cups = cell_updates_per_coarse_step(h)
+        h.advance(args.warmup)
+        out = {"precision": args.only, "tuning": h.tuning()}
+        if args.eager_only:
+            # every launch of the run with HIP events around it (profiling runs:
+            # the profiler's per-kernel average then covers the same launches)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nl, ms = eager_kernel_time(h, args.steps)
+            out["timed_cell_updates_per_s"] = cups * args.steps / (time.perf_counter() - t0)
+            out["hydro_kernel_avg_ms"] = ms / max(nl, 1)
+        else:
+            med, _ = timed_reps(h, args.steps)
+            out["cell_updates_per_s"] = cups * args.steps / med
+        print(json.dumps(out), flush=True)
         return
 
-    log("bench: uniform 128^3 fp64")
-    f = run_uniform("fp64", args.steps, args.warmup, tune, fixed)
-    log("bench: uniform 128^3 mixed")
-    m = run_uniform("mixed", args.steps, args.warmup, tune, fixed)
+    log("bench: copy probe")
+    probe = copy_probe()
 
-    # value: the production path (one coarse step per captured graph, no
-    # per-kernel events); the kernel average comes from the second timed run
-    # of the same steps with HIP events around every launch
-    value = f["cups"] * args.steps / f["dt_graph"]
-    ms_per_step = 1e3 * f["dt_graph"] / args.steps
-    kernel_avg_ms = f["kernel_ms"] / max(f["launches"], 1)
+    # ---- headline: uniform 128^3, FP64 and mixed
+    uprob = W.uniform(128)
+    hs = {}
+    for prec in ("fp64", "mixed"):
+        log(f"bench: uniform 128^3 {prec}")
+        h, build_s = make(uprob, prec, tune, fixed)
+        e0 = h.totals()[4]
+        h.advance(uprob.n_steps)                 # the configuration's 10 steps (captures the graphs)
+        hs[prec] = (h, e0)
+    mixed_err = compare_forms(hs["fp64"][0], hs["mixed"][0], hs["fp64"][1], hs["mixed"][1])
+    mixed_err["steps"] = uprob.n_steps
+    res = {}
+    for prec in ("fp64", "mixed"):
+        h = hs[prec][0]
+        cups = cell_updates_per_coarse_step(h)
+        h.advance(args.warmup)
+        med, reps = timed_reps(h, args.steps)                 # value: graph replay, the production path
+        nl, ms = eager_kernel_time(h, args.steps)             # the kernel's own time (HIP events)
+        res[prec] = dict(cups=cups, med=med, reps=reps, kernel_ms=ms / max(nl, 1), tuning=h.tuning(),
+                         floors=h.floors(), pcie=pcie_inclusive(h, args.steps) if prec == "fp64" else None)
+    for prec in hs:
+        hs[prec][0].close()
+    del hs, h
+    torch.cuda.empty_cache()
+
+    f, m = res["fp64"], res["mixed"]
+    value = f["cups"] * args.steps / f["med"]
+    ms_per_step = 1e3 * f["med"] / args.steps
     alg_bytes = BYTES_PER_CELL_UPDATE * f["cups"]          # one launch per coarse step
-    achieved = alg_bytes / (kernel_avg_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles("uniform128_fp64")
+    achieved = alg_bytes / (f["kernel_ms"] * 1e-3) / 1e9
+    pkey = f"uniform128_fp64_k{f['tuning']['tile_cells']}"
+    traffic = traffic_from_profiles(pkey)
     # VALU issue: wave64 instructions per launch (profiled counter) over the
     # live kernel time, against 1,024 SIMDs x 2.4 GHz / 4 cycles per wave64
     # instruction
-    valu_insts = profiled_counters("uniform128_fp64").get("valu_insts_per_launch")
+    valu_insts = profiled_counters(pkey).get("valu_insts_per_launch")
     valu = None
     if valu_insts:
-        rate = valu_insts / (kernel_avg_ms * 1e-3)
+        rate = valu_insts / (f["kernel_ms"] * 1e-3)
         valu = {"unit": "wave64 VALU instructions/s", "instructions_per_launch": valu_insts,
                 "achieved": round(rate, -6), "peak": VALU_PEAK_ISSUE, "frac": round(rate / VALU_PEAK_ISSUE, 4)}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "hydro_kernel<double>", "kernel_avg_ms": round(kernel_avg_ms, 5),
-                "alg_bytes_per_launch": alg_bytes}
-
-    m_kernel_ms = m["kernel_ms"] / max(m["launches"], 1)
-    mixed = {"value": m["cups"] * args.steps / m["dt_graph"], "unit": "cell-updates/s",
-             "kernel_avg_ms": round(m_kernel_ms, 5),
-             "hbm_frac": round(BYTES_PER_CELL_UPDATE * m["cups"] / (m_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-             "timed_value": m["cups"] * args.steps / m["dt_timed"], "tuning": m["tuning"]}
-    # mixed vs fp64 after the same number of steps (both ran warmup + 2 x steps)
-    mixed["vs_fp64"] = compare_forms(f["h"], m["h"], f["e0"], m["e0"])
-    mixed["steps_compared"] = args.warmup + 2 * args.steps
-    del f["h"], m["h"]
-    torch.cuda.empty_cache()
+                "kernel": "hydro_kernel<double> (" + tuning_label(f["tuning"]) + ")",
+                "kernel_avg_ms": round(f["kernel_ms"], 5), "alg_bytes_per_launch": alg_bytes,
+                "achievable_GBps": probe["GBps"], "frac_of_achievable": round(achieved / probe["GBps"], 4)}
+    mixed = {"value": m["cups"] * args.steps / m["med"], "unit": "cell-updates/s",
+             "kernel_avg_ms": round(m["kernel_ms"], 5),
+             "hbm_frac": round(BYTES_PER_CELL_UPDATE * m["cups"] / (m["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "tuning": m["tuning"], "repetitions_ms_per_step": [round(1e3 * x / args.steps, 4) for x in m["reps"]],
+             "vs_fp64": mixed_err}
 
     zoom = None
     if not args.no_zoom:
-        import workloads as W
-        zprob = W.zoom()
-        zoom = {}
-        handles = {}
-        for prec in ("fp64", "mixed"):
-            log(f"bench: zoom AMR {prec}")
-            z = run_zoom(zprob, prec, 3, tune)
-            zoom[prec] = {"value": z["cups"] * 3 / z["dt"], "unit": "cell-updates/s",
-                          "hbm_frac": round(BYTES_PER_CELL_UPDATE * z["cups"] * 3 / z["dt"] / 1e9 / HBM_PEAK_GBS, 4),
-                          "cell_updates_per_coarse_step": z["cups"], "octs": z["noct"],
-                          "ms_per_coarse_step": round(1e3 * z["dt"] / 3, 3), "build_s": round(z["build_s"], 1),
-                          "floor_activations": z["floors"]}
-            zoom["levels"] = {str(k): v for k, v in z["levels"].items()}
-            handles[prec] = z
-        zoom["mixed_vs_fp64_after_10_coarse_steps"] = compare_forms(
-            handles["fp64"]["h"], handles["mixed"]["h"], handles["fp64"]["e0"], handles["mixed"]["e0"])
+        log("bench: zoom AMR fp64 + mixed")
+        zoom, zh = run_amr_pair(W.zoom(), tune, fixed, timed_steps=8, eager_steps=2, keep=True)
         # one regrid of each evolved mesh (FP64: all on the device; mixed: the
         # host-flag path, for comparison), then one coarse step on it
         for prec, on_device in (("fp64", True), ("mixed", False)):
-            h = handles[prec]["h"]
+            h = zh[prec][0]
             h.set_regrid_device(on_device)
             before = sum(h.level_info(lv)[0] for lv in h.levels)
             torch.cuda.synchronize()
@@ -459,54 +638,52 @@ def main():
                 "ms": round(1e3 * rg, 2), "octs_before": before, "octs_after": after, "created": created,
                 "destroyed": destroyed,
                 "path": "device" if on_device else "host flags and tables, device state remap"}
-        del handles, z, h
+        for prec in zh:
+            zh[prec][0].close()
+        del zh
         torch.cuda.empty_cache()
 
     # two-level AMR: 64^3 base under the 128^3 field, gradient criterion at
     # the primary threshold (about a quarter refined) and at the literal 0.1
     twolevel = None
     if not args.no_zoom:
-        import workloads as W
         twolevel = {}
         for theta in (0.70, 0.1):
-            tprob = W.twolevel(128, theta)
-            entry = {}
-            for prec in ("fp64", "mixed"):
-                log(f"bench: two-level AMR theta {theta} {prec}")
-                z = run_zoom(tprob, prec, 7, tune)
-                entry[prec] = {"value": z["cups"] * 7 / z["dt"], "unit": "cell-updates/s",
-                               "hbm_frac": round(BYTES_PER_CELL_UPDATE * z["cups"] * 7 / z["dt"] / 1e9 / HBM_PEAK_GBS,
-                                                 4),
-                               "cell_updates_per_coarse_step": z["cups"], "octs": z["noct"],
-                               "ms_per_coarse_step": round(1e3 * z["dt"] / 7, 3), "floor_activations": z["floors"]}
-                entry["levels"] = {str(k): v for k, v in z["levels"].items()}
-                del z
-            twolevel[f"theta_{theta}"] = entry
-        torch.cuda.empty_cache()
+            log(f"bench: two-level AMR theta {theta}")
+            twolevel[f"theta_{theta}"], _ = run_amr_pair(W.twolevel(128, theta), tune, fixed, timed_steps=8,
+                                                         eager_steps=2)
 
     batch = None
     if not args.no_zoom:
-        import workloads as W
         from paper_2411_14631_amd import BatchHydro
         boxes = W.batch(512)
         cells = sum(p.nbase[0] ** 3 for p in boxes)
         batch = {"boxes": 512, "cells": cells, "steps": 20}
+        bhs = {}
         for prec in ("fp64", "mixed"):
             log(f"bench: batch 512 boxes {prec}")
             bh = BatchHydro(boxes, prec)
             btune = bh.autotune()[0] if tune else bh.tuning()
-            bh.run(20)                                  # warm-up: captures the 20-step graph
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            bh.run(20)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            batch[prec] = {"value": cells * 20 / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / 20,
-                           "hbm_frac": round(BYTES_PER_CELL_UPDATE * cells * 20 / el / 1e9 / HBM_PEAK_GBS, 4),
-                           "tuning": btune}
+            bh.run(20)                                  # the workload's 20 steps (captures the graph)
+            bhs[prec] = bh
+            batch[prec] = {"tuning": btune}
+        batch["mixed"]["vs_fp64"] = compare_batches(bhs["fp64"], bhs["mixed"], boxes)
+        for prec in ("fp64", "mixed"):
+            bh = bhs[prec]
+            el = []
+            for _ in range(REPS):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                bh.run(20)
+                torch.cuda.synchronize()
+                el.append(time.perf_counter() - t0)
+            med = median(el)
+            batch[prec].update({"value": cells * 20 / med, "unit": "cell-updates/s", "ms_per_step": 1e3 * med / 20,
+                                "hbm_frac": round(BYTES_PER_CELL_UPDATE * cells * 20 / med / 1e9 / HBM_PEAK_GBS, 4),
+                                "repetitions_ms_per_step": [round(1e3 * x / 20, 4) for x in el]})
             bh.close()
-            del bh
-            torch.cuda.empty_cache()
+        del bhs, bh
+        torch.cuda.empty_cache()
 
     scalars = None
     if not args.no_zoom:
@@ -529,9 +706,10 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "uniform 128^3 periodic lognormal box (262144 octs), FP64, gamma 5/3, CFL 0.8",
                    "cells": 128 ** 3, "cell_updates_per_step": f["cups"], "tuning": f["tuning"],
-                   "timed_value": f["cups"] * args.steps / f["dt_timed"], "floor_activations": f["floors"],
-                   "pcie_inclusive_value": f["pcie"]},
+                   "repetitions": REPS, "repetitions_ms_per_step": [round(1e3 * x / args.steps, 4) for x in f["reps"]],
+                   "floor_activations": f["floors"], "pcie_inclusive_value": f["pcie"]},
         "roofline": roofline,
+        "copy_probe": probe,
         "valu_issue": valu,
         "cpu_baseline": cpu,
         "mixed": mixed,
