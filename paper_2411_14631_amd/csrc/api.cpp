@@ -172,6 +172,16 @@ void free_all(ry_ctx* c) {
   c->lev.clear();
 }
 
+// A level's two state buffers in one allocation, the second nv planes after
+// the first: ghost octs live in the second only and are read through the
+// first with a fixed index shift (HydroArgs::ghost_adj).  Freed through U[0].
+bool alloc_state_pair(ry_ctx* c, double* U[2], int64_t n_ext, int nv) {
+  const size_t n = size_t(nv) * 8 * size_t(n_ext);
+  U[0] = static_cast<double*>(dalloc(c, sizeof(double) * 2 * n));
+  U[1] = U[0] ? U[0] + n : nullptr;
+  return U[0] != nullptr;
+}
+
 template <typename T>
 T* upload_vec(ry_ctx* c, const std::vector<T>& v, bool& ok) {
   T* p = static_cast<T*>(dalloc(c, v.size() * sizeof(T)));
@@ -368,8 +378,7 @@ ry_status enqueue_ghost(ry_ctx* c, int l, const int32_t* skip) {
   g.gsrc = L.gsrc;
   g.n_ghost = L.n_ghost;
   g.n_oct = L.n_oct;
-  g.dst0 = L.U[0];
-  g.dst1 = L.U[1];
+  g.dst = L.U[1];
   g.plane = L.plane();
   g.nv = c->dom.nv;
   g.skip = skip;
@@ -397,6 +406,7 @@ HydroArgs hydro_args(ry_ctx* c, int l, int substep) {
   a.Un = L.U[L.cur ^ 1];
   a.plane = L.plane();
   a.n_oct = int32_t(L.n_oct);
+  a.ghost_adj = (L.n_ghost > 0 && L.cur == 0) ? int32_t(int64_t(c->dom.nv) * L.n_ext) : 0;
   a.n_tile = L.n_tile;
   a.tab = L.tab;
   a.tflag = L.tflag;
@@ -548,7 +558,8 @@ ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a, int k, const ry_tuning* t
     if (b.tile_smax && launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_part), c->seg_off.back(), c->stream))
       return fail(c, RY_EHIP, "zero kernel");
   }
-  if (tu.persistent && launch_zero_u32(c->d_queue, 8 * QUEUE_STRIDE, c->stream)) return fail(c, RY_EHIP, "zero kernel");
+  if (tu.persistent == 1 && launch_zero_u32(c->d_queue, 8 * QUEUE_STRIDE, c->stream))
+    return fail(c, RY_EHIP, "zero kernel");
   TimedLaunch tl;
   if (c->timing) time_begin(c, "hydro", tl);
   if (launch_hydro(b, c->cfg.precision, c->cfg.nscalar, tu, c->num_cu, c->stream))
@@ -730,10 +741,7 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
     D.n_leaf = t.n_leaf;
     D.n_tile = t.n_tile;
     if (D.n_oct == 0) continue;
-    for (int b = 0; b < 2; ++b) {
-      D.U[b] = static_cast<double*>(dalloc(c, sizeof(double) * c->dom.nv * 8 * D.n_ext));
-      if (!D.U[b]) ok = false;
-    }
+    if (!alloc_state_pair(c, D.U, D.n_ext, c->dom.nv)) ok = false;
     if (!ok) break;
     if (upload_level_state(c, D, H[k].U.data())) return c->err.empty() ? RY_EHIP : RY_EHIP;
     upload_level_tables(c, D, t, k, ok);
@@ -863,8 +871,7 @@ ry_status regrid_host(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     D.dkey = nullptr;
     D.doc = nullptr;
     if (k > 0) {
-      dfree(c, D.U[0]);
-      dfree(c, D.U[1]);
+      dfree(c, D.U[0]);   // both buffers
       D.U[0] = D.U[1] = nullptr;
     }
     D.tab = nullptr;
@@ -887,10 +894,7 @@ ry_status regrid_host(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     if (D.n_oct == 0) continue;
     if (k > 0) {
       D.cur = 0;
-      for (int b = 0; b < 2 && ok; ++b) {
-        D.U[b] = static_cast<double*>(dalloc(c, sizeof(double) * nv * 8 * D.n_ext));
-        if (!D.U[b]) ok = false;
-      }
+      if (!alloc_state_pair(c, D.U, D.n_ext, nv)) ok = false;
       if (!ok) break;
       for (int v = 0; v < nv; ++v)
         HIPCHK(c, hipMemcpyAsync(D.U[0] + v * D.plane(), tmp[k] + v * 8 * D.n_oct, sizeof(double) * 8 * D.n_oct,
@@ -1120,8 +1124,13 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
       }
       // state: kept octs copied, new octs interpolated from level l-1
       const int64_t n_ext = L.n + L.n_ghost;
-      RG_TRY(n_ext < (int64_t(1) << 29), RY_EINVAL, "level octs + ghost octs reach 2^29 (cells are indexed in 32 bits)");
-      for (int b = 0; b < 2; ++b) L.U[b] = static_cast<double*>(A(sizeof(double) * nv * 8 * n_ext, false));
+      RG_TRY(level_index_fits(L.n, L.n_ghost, nv), RY_EINVAL,
+             "level octs + ghost octs reach the 32-bit cell index (2^29 octs; (1 + nv) times the octs + ghost octs "
+             "with ghosts)");
+      // both state buffers in one allocation (ghosts in the second, read
+      // through the first with a fixed index shift)
+      L.U[0] = static_cast<double*>(A(sizeof(double) * 2 * nv * 8 * n_ext, false));
+      L.U[1] = L.U[0] ? L.U[0] + size_t(nv) * 8 * n_ext : nullptr;
       L.reg = static_cast<double*>(A(sizeof(double) * L.n * reg_per_oct(nv), false));
       RG_TRY(ok, RY_ENOMEM, "allocation failed");
       const DevLevel& Fo = c->lev[k];
@@ -1188,7 +1197,7 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     for (void* p : {(void*)D.refined, (void*)D.child, (void*)D.parent_cell, (void*)D.gsrc, (void*)D.reg})
       dfree(c, p);
     if (k > 0) {
-      for (void* p : {(void*)D.tab, (void*)D.tflag, (void*)D.dkey, (void*)D.doc, (void*)D.U[0], (void*)D.U[1]})
+      for (void* p : {(void*)D.tab, (void*)D.tflag, (void*)D.dkey, (void*)D.doc, (void*)D.U[0]})
         dfree(c, p);
       D.tab = nullptr;
       D.tflag = nullptr;
@@ -1677,9 +1686,10 @@ bool same_tuning(const ry_tuning& a, const ry_tuning& b) {
 // Whether the context can run a tuning (RY_OK) or not (RY_EINVAL, with the
 // reason).
 ry_status check_tuning(ry_ctx* c, const ry_tuning& t) {
+  if (t.persistent < 0 || t.persistent > 2) return fail(c, RY_EINVAL, "persistent must be 0, 1 or 2");
   if (t.tile_cells == 8) {
-    if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent)
-      return fail(c, RY_EINVAL, "tile_cells 8 needs tiles_per_wg 1, waves_per_tile 8, persistent 0");
+    if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent == 1)
+      return fail(c, RY_EINVAL, "tile_cells 8 needs tiles_per_wg 1, waves_per_tile 8, persistent 0 or 2");
   } else if (t.tile_cells == 4) {
     if (t.tiles_per_wg != 1 && t.tiles_per_wg != 2 && t.tiles_per_wg != 4) return fail(c, RY_EINVAL, "tiles_per_wg");
     if (t.waves_per_tile != 1 && t.waves_per_tile != 2 && t.waves_per_tile != 4)
@@ -1794,6 +1804,11 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
     for (int w : {8, 14, 20})
       for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt, 4});
   cand.push_back({1, 0, 4, 1, 8, 8});
+  // pipelined tile loops: 8^3-cell tiles two workgroups per CU, one-wavefront
+  // 4^3-cell tiles 8 or 12 per CU
+  cand.push_back({1, 2, 16, 1, 8, 8});
+  cand.push_back({1, 2, 8, 1, 1, 4});
+  cand.push_back({1, 2, 12, 1, 1, 4});
   {
     std::string keep = c->err;
     cand.erase(std::remove_if(cand.begin(), cand.end(), [&](const ry_tuning& t) { return check_tuning(c, t) != RY_OK; }),
@@ -1805,10 +1820,11 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
   // the 8^3-cell tile's tables of every level
   ry_tuning saved[RY_MAX_LEVELS];
   std::copy(std::begin(c->tune), std::end(c->tune), saved);
-  bool any8 = false;
-  for (const auto& t : cand) any8 = any8 || t.tile_cells == 8;
-  if (any8) {
-    std::fill(std::begin(c->tune), std::end(c->tune), cand.back());
+  const ry_tuning* t8 = nullptr;
+  for (const auto& t : cand)
+    if (t.tile_cells == 8 && !t8) t8 = &t;
+  if (t8) {
+    std::fill(std::begin(c->tune), std::end(c->tune), *t8);
     ry_status s = ensure_super(c);
     std::copy(std::begin(saved), std::end(saved), c->tune);
     if (s) return s;

@@ -58,7 +58,7 @@ struct Geom {
   static constexpr int WSIZE = NBOX + 6 * K * K;         // primitives per variable
   static constexpr int NPOS_A = K * K * K + 12 * K * K + 12 * K;   // positions whose primitives are needed
   static constexpr int NPOS_B = K * K * K + 6 * K * K;   // positions that get a predicted state
-  static constexpr int NCORE = K * K * K;                // B positions 0..NCORE-1: the core cells, x fastest
+  static constexpr int NCORE = K * K * K;                // A and B positions 0..NCORE-1: the core cells
   static constexpr int NUPPER = 3 * K * K;               // then the upper one-layer cells, then the lower ones
   static constexpr int NFACE = 3 * (K + 1) * K * K;      // 3 directions x (K+1) planes x K^2
   static constexpr int KO = K / 2;                       // octs per tile edge
@@ -96,6 +96,21 @@ struct Geom {
                   : (d == 1 ? (K + 1) * K * K + x + K * y + K * (K + 1) * z
                             : 2 * (K + 1) * K * K + x + K * y + K * K * z);
   }
+  // Core cell of thread t < NCORE, oct-major: 8 consecutive threads hold the
+  // 8 cells of one oct (in-oct index t & 7) and 64 consecutive threads the
+  // octs of one 2x2x2 block of octs, which lie next to each other in memory
+  // (Hilbert order), so a wavefront's state loads and stores cover whole
+  // octs.
+  static constexpr int NBLK = K / 4;                     // 2x2x2-oct blocks per tile edge
+  __host__ __device__ static constexpr int core_x(int t) {
+    return 4 * ((t >> 6) % NBLK) + 2 * ((t >> 3) & 1) + (t & 1);
+  }
+  __host__ __device__ static constexpr int core_y(int t) {
+    return 4 * (((t >> 6) / NBLK) % NBLK) + 2 * ((t >> 4) & 1) + ((t >> 1) & 1);
+  }
+  __host__ __device__ static constexpr int core_z(int t) {
+    return 4 * ((t >> 6) / (NBLK * NBLK)) + 2 * ((t >> 5) & 1) + ((t >> 2) & 1);
+  }
   // Slot of the oct at oct offset (ox, oy, oz) from the tile's first oct
   // (-1 .. KO) in the tile's oct neighbourhood table.
   __host__ __device__ static constexpr int slot(int ox, int oy, int oz) {
@@ -110,7 +125,8 @@ struct Geom {
 //        their normal, then the lower ones at -1): LDS index of the cell, LDS
 //        index of its outward neighbour (a far plane), normal axis, upper
 //        layer, the face between the cell and the core (fields as
-//        Geom<K>::B_*).  b[i < NCORE] = LDS index of core cell i.
+//        Geom<K>::B_*).  b[i < NCORE] = LDS index of core cell i (the
+//        threads' oct-major order, Geom<K>::core_x/y/z).
 template <int K>
 struct StencilTables {
   typename Geom<K>::EntA a[Geom<K>::NPOS_A];
@@ -124,21 +140,28 @@ constexpr StencilTables<K> make_tables() {
   using EB = typename G::EntB;
   StencilTables<K> t{};
   int na = 0;
-  for (int z = -2; z <= K + 1; ++z)
-    for (int y = -2; y <= K + 1; ++y)
-      for (int x = -2; x <= K + 1; ++x) {
-        const int ox = (x < 0 || x > K - 1), oy = (y < 0 || y > K - 1), oz = (z < 0 || z > K - 1);
-        const int nout = ox + oy + oz;
-        const bool ex = (x == -1 || x == K), ey = (y == -1 || y == K), ez = (z == -1 || z == K);
-        const bool edges = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
-        if ((nout <= 1) || (nout == 2 && edges)) {
-          const int slot = G::slot(x >> 1, y >> 1, z >> 1);
-          const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-          const int raw = (x + 2) + G::R * (y + 2) + G::R * G::R * (z + 2);
-          t.a[na++] = EA(G::widx(x, y, z)) | (EA(slot) << G::A_LB) | (EA(cb) << G::A_CS) | (EA(raw) << G::A_RS);
+  auto put = [&](int x, int y, int z) {
+    const int slot = G::slot(x >> 1, y >> 1, z >> 1);
+    const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+    const int raw = (x + 2) + G::R * (y + 2) + G::R * G::R * (z + 2);
+    t.a[na++] = EA(G::widx(x, y, z)) | (EA(slot) << G::A_LB) | (EA(cb) << G::A_CS) | (EA(raw) << G::A_RS);
+  };
+  // the core cells first, in the threads' oct-major order (a thread's first
+  // gathered position is its own cell), then the halo positions oct by oct
+  // (consecutive threads read the cells of one oct)
+  for (int i = 0; i < G::NCORE; ++i) put(G::core_x(i), G::core_y(i), G::core_z(i));
+  for (int sz = -1; sz <= G::KO; ++sz)
+    for (int sy = -1; sy <= G::KO; ++sy)
+      for (int sx = -1; sx <= G::KO; ++sx)
+        for (int cb = 0; cb < 8; ++cb) {
+          const int x = 2 * sx + (cb & 1), y = 2 * sy + ((cb >> 1) & 1), z = 2 * sz + (cb >> 2);
+          const int ox = (x < 0 || x > K - 1), oy = (y < 0 || y > K - 1), oz = (z < 0 || z > K - 1);
+          const int nout = ox + oy + oz;
+          const bool ex = (x == -1 || x == K), ey = (y == -1 || y == K), ez = (z == -1 || z == K);
+          const bool edges = (ox ? ex : true) && (oy ? ey : true) && (oz ? ez : true);
+          if ((nout == 1) || (nout == 2 && edges)) put(x, y, z);
         }
-      }
-  for (int i = 0; i < G::NCORE; ++i) t.b[i] = EB(G::widx(i % K, (i / K) % K, i / (K * K)));
+  for (int i = 0; i < G::NCORE; ++i) t.b[i] = EB(G::widx(G::core_x(i), G::core_y(i), G::core_z(i)));
   int nb = G::NCORE;
   for (int up = 1; up >= 0; --up)
     for (int d = 0; d < 3; ++d)
@@ -160,10 +183,17 @@ constexpr StencilTables<K> make_tables() {
 }
 static __constant__ StencilTables<4> c_st4 = make_tables<4>();
 static __constant__ StencilTables<8> c_st8 = make_tables<8>();
-static_assert(make_tables<4>().a[Geom<4>::NPOS_A - 1] != 0 && make_tables<4>().b[Geom<4>::NPOS_B - 1] != 0,
-              "stencil tables");
-static_assert(make_tables<8>().a[Geom<8>::NPOS_A - 1] != 0 && make_tables<8>().b[Geom<8>::NPOS_B - 1] != 0,
-              "stencil tables");
+// every table entry filled (the position counts match the enumerations)
+template <int K>
+constexpr bool tables_full() {
+  constexpr StencilTables<K> t = make_tables<K>();
+  for (int i = 0; i < Geom<K>::NPOS_A; ++i)
+    if (t.a[i] == 0) return false;
+  for (int i = Geom<K>::NCORE; i < Geom<K>::NPOS_B; ++i)
+    if (t.b[i] == 0) return false;
+  return true;
+}
+static_assert(tables_full<4>() && tables_full<8>(), "stencil tables");
 template <int K>
 __device__ __forceinline__ const StencilTables<K>& stencil_tables() {
   if constexpr (K == 4) return c_st4;
@@ -175,13 +205,16 @@ __device__ __forceinline__ const StencilTables<K>& stencil_tables() {
 // cells' right states [NVAR][NUPPER] (B2 -> C), then the face fluxes
 // [NVAR][NFACE] (C -> D).  Fluxes are stored in Real: in the mixed
 // form they are FP32 results, so FP32 storage loses nothing.
-template <typename Real, int NV, int K>
+template <typename Real, int NV, int K, int NTAB = 1>
 struct TileLDS {
   using G = Geom<K>;
   static constexpr int NW = NV * G::WSIZE, NF = NV * (G::NFACE + G::NUPPER);
   Real buf[NW > NF ? NW : NF];
-  int32_t tab[G::TAB];  // ext oct index of the oct neighbourhood
-  uint8_t ref[G::TAB];  // refined-cell bytes of those octs
+  // ext oct index of the oct neighbourhood (ghost octs shifted as the
+  // current state buffer needs) and the refined-cell bytes of those octs:
+  // the current tile's, and in a pipelined tile loop the next tile's
+  int32_t tab[NTAB][G::TAB];
+  uint8_t ref[NTAB][G::TAB];
 };
 
 // ---------------------------------------------------------------------------
@@ -406,9 +439,9 @@ __device__ __forceinline__ int opaque(int x) {
 // kernel).  The checks run only where a floor was applied.
 // Kind of the cell at tile position (x, y, z), each in [-1, K]: 1 a leaf
 // cell, 2 a refined cell, 0 otherwise (a ghost cell, or past an outflow face).
-template <typename Real, int NV, int K>
-__device__ int census_kind(const TileLDS<Real, NV, K>& S, uint32_t fl, const int hb[3], int32_t n_oct, int x, int y,
-                           int z) {
+template <int K>
+__device__ int census_kind(const int32_t* tab, const uint8_t* ref, uint32_t fl, const int hb[3], int32_t n_oct, int x,
+                           int y, int z) {
   const int p[3] = {x, y, z};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -416,10 +449,10 @@ __device__ int census_kind(const TileLDS<Real, NV, K>& S, uint32_t fl, const int
     if (p[a] > hb[a] && (fl & (2u << (2 * a)))) return 0;
   }
   const int slot = Geom<K>::slot(x >> 1, y >> 1, z >> 1);
-  const int32_t e = S.tab[slot];
+  const int32_t e = tab[slot];
   if (e < 0 || e >= n_oct) return 0;
   const int cb = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-  return ((S.ref[slot] >> cb) & 1) ? 2 : 1;
+  return ((ref[slot] >> cb) & 1) ? 2 : 1;
 }
 // Whether tile position (x, y, z) is one of the tile's own cells.
 __device__ __forceinline__ bool census_own(const int hb[3], int x, int y, int z) {
@@ -427,84 +460,45 @@ __device__ __forceinline__ bool census_own(const int hb[3], int x, int y, int z)
 }
 // Whether this tile counts the floors of the face along d whose lower cell
 // is at tile position (x, y, z).
-template <typename Real, int NV, int K>
-__device__ bool census_face(const TileLDS<Real, NV, K>& S, uint32_t fl, const int hb[3], int32_t n_oct, int x, int y,
-                            int z, int d) {
+template <int K>
+__device__ bool census_face(const int32_t* tab, const uint8_t* ref, uint32_t fl, const int hb[3], int32_t n_oct, int x,
+                            int y, int z, int d) {
   const int bx = x + (d == 0), by = y + (d == 1), bz = z + (d == 2);
-  const int ka = census_kind(S, fl, hb, n_oct, x, y, z), kb = census_kind(S, fl, hb, n_oct, bx, by, bz);
+  const int ka = census_kind<K>(tab, ref, fl, hb, n_oct, x, y, z), kb = census_kind<K>(tab, ref, fl, hb, n_oct, bx, by, bz);
   if (kb == 1) return ka != 2 && census_own(hb, bx, by, bz);
   return ka == 1 && kb == 0 && census_own(hb, x, y, z);
 }
 
-template <typename Real, int NT, int NS, int K>
-__device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS, K>& S, int tid_in,
-                           bool active) {
+// Registers that carry a tile's gathered conserved states into its phase A:
+// loaded there (plain tile), or during the previous tile's update (pipelined
+// tile loop).
+template <int K, int NT, int NV>
+struct GatherRegs {
+  static constexpr int NRA = (Geom<K>::NPOS_A + NT - 1) / NT;
+  double Ua[NRA][NV];
+  int iwa[NRA];   // LDS index of each position, -1 when the thread has none
+};
+
+// Last in-domain cell of a tile along each axis (a tile cut by the domain's
+// high side has fewer than K).
+template <int K>
+__device__ __forceinline__ void tile_hb(uint32_t fl, int hb[3]) {
+  hb[0] = K - 1 - int((fl >> CL_CUT_SHIFT) & 7u);
+  hb[1] = K - 1 - int((fl >> (CL_CUT_SHIFT + 3)) & 7u);
+  hb[2] = K - 1 - int((fl >> (CL_CUT_SHIFT + 6)) & 7u);
+}
+
+// Phase A's loads: the conserved state at the thread's gather positions of
+// a tile whose oct table is in LDS (`tab`), issued without waiting for them.
+template <int K, int NT, int NV>
+__device__ __forceinline__ void gather_issue(const HydroArgs& A, const int32_t* tab, uint32_t fl, const int hb[3],
+                                             int tid, bool active,
+                                             const typename Geom<K>::EntA (&entA)[GatherRegs<K, NT, NV>::NRA],
+                                             GatherRegs<K, NT, NV>& R) {
   using G = Geom<K>;
   using EA = typename G::EntA;
-  using EB = typename G::EntB;
-  constexpr int NV = NVAR + NS;
-  constexpr int WSIZE = G::WSIZE, NFACE = G::NFACE, NUPPER = G::NUPPER, NCORE = G::NCORE;
-  constexpr int NPOS_A = G::NPOS_A, NPOS_B = G::NPOS_B, TAB = G::TAB;
-  static_assert(NT >= TAB && (K == 4 || NT == NCORE), "threads per tile");
-  const int tid = opaque(tid_in);
-  const int lane = tid & 63;
-  const double g = A.gamma, rf = A.rho_floor, pf = A.p_floor;
+  constexpr int NRA = GatherRegs<K, NT, NV>::NRA;
   const int64_t P = A.plane;
-  int nfl = 0;
-  const uint32_t fl = active ? A.tflag[tile] : 0u;
-  // last in-domain cell of the tile along each axis when an outflow face cuts it
-  const int hb[3] = {K - 1 - int((fl >> CL_CUT_SHIFT) & 7u), K - 1 - int((fl >> (CL_CUT_SHIFT + 3)) & 7u),
-                     K - 1 - int((fl >> (CL_CUT_SHIFT + 6)) & 7u)};
-  const int box = (active && A.tile_box) ? A.tile_box[tile] : 0;
-  const double lam = A.lam_dev ? A.lam_dev[box] : A.lam_host;
-  const Real h = Real(0.5 * lam);
-  const Real igm1 = Real(A.igm1);
-  const StencilTables<K>& ST = stencil_tables<K>();
-
-  // The thread's stencil-table entries for phases A and B, loaded together up
-  // front: a load issued inside a round would make that round wait for every
-  // state load issued before it.
-  constexpr int NRA = (NPOS_A + NT - 1) / NT;
-  constexpr int NRB = (NPOS_B + NT - 1) / NT;
-  // floors applied by this thread, 2 bits per site (each site applies at
-  // most 2: density and pressure): the conversions of its phase-A positions,
-  // its phase-B one-layer face states, its core cell's 3 left and 3 right
-  // face states; which of them the tile counts is decided at the end
-  constexpr int SITE_A = 0, SITE_B = NRA, SITE_L = NRA + NRB, SITE_R = SITE_L + 3;
-  static_assert(2 * (SITE_R + 3) <= 32, "floor sites");
-  int pending = 0;
-  EA entA[NRA];
-  EB entB[NRB];
-#pragma unroll
-  for (int rnd = 0; rnd < NRA; ++rnd) {
-    const int i = tid + NT * rnd;
-    entA[rnd] = ST.a[uint32_t(i < NPOS_A ? i : 0)];
-  }
-#pragma unroll
-  for (int rnd = 0; rnd < NRB; ++rnd) {
-    const int i = tid + NT * rnd;
-    entB[rnd] = ST.b[uint32_t(i < NPOS_B ? i : 0)];
-  }
-
-  // --- phase 0: the tile's oct table (the refined bytes of its octs are
-  // loaded in phase A behind the state loads; phase D is their first reader)
-  int32_t e_tab = -1;
-  if (active && tid < TAB) {
-    e_tab = A.tab[size_t(tile) * TAB + tid];
-    S.tab[tid] = e_tab;
-  }
-  __syncthreads();
-  // Wait for the table entries here on every path: otherwise the gather's
-  // conditional state loads leave the compiler's load counting unsure of them,
-  // and each round would wait for the state loads of the rounds before it.
-#pragma unroll
-  for (int rnd = 0; rnd < NRA; ++rnd) asm volatile("" ::"v"(entA[rnd]));
-#pragma unroll
-  for (int rnd = 0; rnd < NRB; ++rnd) asm volatile("" ::"v"(entB[rnd]));
-
-  // --- phase A: gather + primitives (all loads of the thread's positions are
-  // issued before any conversion)
-  Real* W = S.buf;                              // [NV][WSIZE]
   // the planes' base addresses, formed in scalar registers (an empty asm on
   // the plane offset keeps the compiler from folding it back into every
   // per-lane address)
@@ -515,14 +509,12 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     asm volatile("" : "+s"(off));
     Up[v] = A.U + off;
   }
-  const bool off32 = P <= (int64_t(1) << 29);
-  double Ua[NRA][NV];
-  int iwa[NRA];
+  const bool off32 = P + 8 * int64_t(A.ghost_adj) <= (int64_t(1) << 29);
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     const int i = tid + NT * rnd;
-    iwa[rnd] = -1;
-    if (active && i < NPOS_A) {
+    R.iwa[rnd] = -1;
+    if (active && i < G::NPOS_A) {
       const EA ent = entA[rnd];
       int slot = int((ent >> G::A_LB) & EA((1u << G::A_SB) - 1)), cb = int((ent >> G::A_CS) & EA(7));
       if (fl & CL_ANY) {
@@ -538,11 +530,12 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
         slot = G::slot(sx >> 1, sy >> 1, sz >> 1);
         cb = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
       }
-      const int32_t e = S.tab[slot];
-      iwa[rnd] = int(ent & EA((1u << G::A_LB) - 1));
-      // 32-bit cell index (octs of a level stay below 2^29).  A slot without
-      // an oct is one no leaf update reads: it takes the (valid, finite)
-      // state of the level's first cell instead of a branch
+      const int32_t e = tab[slot];
+      R.iwa[rnd] = int(ent & EA((1u << G::A_LB) - 1));
+      // 32-bit cell index (a level's octs, ghost octs and the ghost shift
+      // stay below 2^29 octs).  A slot without an oct is one no leaf update
+      // reads: it takes the (valid, finite) state of the level's first cell
+      // instead of a branch
       const uint32_t cell = (e >= 0) ? uint32_t(e) * 8u + uint32_t(cb) : 0u;
       if (off32) {
         // planes under 4 GiB: one 32-bit byte offset serves every plane
@@ -550,34 +543,151 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
         const uint32_t boff = cell << 3;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          Ua[rnd][v] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(Up[v]) + boff);
+          R.Ua[rnd][v] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(Up[v]) + boff);
       } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Ua[rnd][v] = Up[v][cell];
+        for (int v = 0; v < NV; ++v) R.Ua[rnd][v] = Up[v][cell];
       }
     }
   }
-  const uint8_t rb = (e_tab >= 0) ? A.refined[e_tab] : uint8_t(0);
+}
+
+// A tile's oct table entry as LDS keeps it: a ghost oct is read from the
+// second state buffer (the shifted index stays >= n_oct, so every
+// real/ghost test on the table still holds).
+__device__ __forceinline__ int32_t lds_tab_entry(const HydroArgs& A, int32_t e) {
+  return (e >= A.n_oct) ? e + A.ghost_adj : e;
+}
+
+// PIPE: the tile is one of a workgroup's run of tiles.  Its oct table and
+// refined bytes are already in S.tab[par] / S.ref[par] and its gathered
+// states in R (both loaded during the previous tile); while it runs, it
+// loads the same for tile `next` (-1: none) into S.tab[par ^ 1],
+// S.ref[par ^ 1] and R.  Plain: par = 0, the tile loads its own.
+template <typename Real, int NT, int NS, int K, bool PIPE = false>
+__device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS, K, PIPE ? 2 : 1>& S,
+                                           int tid_in, bool active, GatherRegs<K, NT, NVAR + NS>& R, int par = 0,
+                                           int next = -1) {
+  using G = Geom<K>;
+  using EA = typename G::EntA;
+  using EB = typename G::EntB;
+  constexpr int NV = NVAR + NS;
+  constexpr int WSIZE = G::WSIZE, NFACE = G::NFACE, NUPPER = G::NUPPER, NCORE = G::NCORE;
+  constexpr int NPOS_A = G::NPOS_A, NPOS_B = G::NPOS_B, TAB = G::TAB;
+  static_assert(NT >= TAB && (K == 4 || NT == NCORE), "threads per tile");
+  const int tid = opaque(tid_in);
+  const int lane = tid & 63;
+  const double g = A.gamma, rf = A.rho_floor, pf = A.p_floor;
+  const int64_t P = A.plane;
+  int nfl = 0;
+  const uint32_t fl = active ? A.tflag[tile] : 0u;
+  int hb[3];
+  tile_hb<K>(fl, hb);
+  const int box = (active && A.tile_box) ? A.tile_box[tile] : 0;
+  const double lam = A.lam_dev ? A.lam_dev[box] : A.lam_host;
+  const Real h = Real(0.5 * lam);
+  const Real igm1 = Real(A.igm1);
+  const StencilTables<K>& ST = stencil_tables<K>();
+  const int32_t* tab = S.tab[par];
+  const uint8_t* ref = S.ref[par];
+
+  // The thread's stencil-table entries for phases A and B, loaded together up
+  // front: a load issued inside a round would make that round wait for every
+  // state load issued before it.
+  constexpr int NRA = GatherRegs<K, NT, NV>::NRA;
+  constexpr int NRB = (NPOS_B + NT - 1) / NT;
+  // floors applied by this thread, 2 bits per site (each site applies at
+  // most 2: density and pressure): the conversions of its phase-A positions,
+  // its phase-B one-layer face states, its core cell's 3 left and 3 right
+  // face states; which of them the tile counts is decided at the end
+  constexpr int SITE_A = 0, SITE_B = NRA, SITE_L = NRA + NRB, SITE_R = SITE_L + 3;
+  static_assert(2 * (SITE_R + 3) <= 32, "floor sites");
+  int pending = 0;
+  EB entB[NRB];
+#pragma unroll
+  for (int rnd = 0; rnd < NRB; ++rnd) {
+    const int i = tid + NT * rnd;
+    entB[rnd] = ST.b[uint32_t(i < NPOS_B ? i : 0)];
+  }
+
+  int32_t e_tab = -1;     // plain: this tile's table entry; PIPE: the next tile's
+  uint8_t rb = 0;
+  if constexpr (!PIPE) {
+    EA entA[NRA];
+#pragma unroll
+    for (int rnd = 0; rnd < NRA; ++rnd) {
+      const int i = tid + NT * rnd;
+      entA[rnd] = ST.a[uint32_t(i < NPOS_A ? i : 0)];
+    }
+    // --- phase 0: the tile's oct table (the refined bytes of its octs are
+    // loaded in phase A behind the state loads; phase D is their first reader)
+    if (active && tid < TAB) {
+      e_tab = A.tab[size_t(tile) * TAB + tid];
+      S.tab[0][tid] = lds_tab_entry(A, e_tab);
+    }
+    __syncthreads();
+    // Wait for the table entries here on every path: otherwise the gather's
+    // conditional state loads leave the compiler's load counting unsure of
+    // them, and each round would wait for the state loads of the rounds
+    // before it.
+#pragma unroll
+    for (int rnd = 0; rnd < NRA; ++rnd) asm volatile("" ::"v"(entA[rnd]));
+#pragma unroll
+    for (int rnd = 0; rnd < NRB; ++rnd) asm volatile("" ::"v"(entB[rnd]));
+    // --- phase A: gather + primitives (all loads of the thread's positions
+    // are issued before any conversion)
+    gather_issue<K, NT, NV>(A, tab, fl, hb, tid, active, entA, R);
+    rb = (e_tab >= 0) ? A.refined[e_tab] : uint8_t(0);
+  } else {
+#pragma unroll
+    for (int rnd = 0; rnd < NRB; ++rnd) asm volatile("" ::"v"(entB[rnd]));
+    // the next tile's oct table, on its way while this tile converts
+    if (next >= 0 && tid < TAB) e_tab = A.tab[size_t(next) * TAB + tid];
+  }
+
+  // --- phase A (conversion): primitives into LDS
+  Real* W = S.buf;                              // [NV][WSIZE]
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
-    if (iwa[rnd] >= 0) {
+    if (R.iwa[rnd] >= 0) {
       double Wc[NV];
       int nc = 0;
-      cons2prim<NS>(Ua[rnd], Wc, g, rf, pf, nc);
+      cons2prim<NS>(R.Ua[rnd], Wc, g, rf, pf, nc);
       pending |= nc << (2 * (SITE_A + rnd));
 #pragma unroll
-      for (int v = 0; v < NV; ++v) W[v * WSIZE + iwa[rnd]] = Real(Wc[v]);
+      for (int v = 0; v < NV; ++v) W[v * WSIZE + R.iwa[rnd]] = Real(Wc[v]);
     }
   }
-  if (active && tid < TAB) S.ref[tid] = rb;
+  if constexpr (PIPE) {
+    // consumed: the registers hold nothing until the next tile's gather
+    // (otherwise the lanes that gather nothing there would keep these values
+    // alive through the whole tile); such lanes have iwa = -1 and never
+    // read Ua
+#pragma unroll
+    for (int rnd = 0; rnd < NRA; ++rnd) {
+      R.iwa[rnd] = -1;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R.Ua[rnd][v] = __builtin_nondeterministic_value(R.Ua[rnd][v]);
+    }
+  }
+  if constexpr (!PIPE) {
+    if (active && tid < TAB) S.ref[0][tid] = rb;
+  } else {
+    if (next >= 0 && tid < TAB) S.tab[par ^ 1][tid] = lds_tab_entry(A, e_tab);
+  }
   __syncthreads();
+  if constexpr (PIPE) {
+    // the next tile's refined bytes, stored once phase B1 is done
+    if (next >= 0 && tid < TAB) rb = (e_tab >= 0) ? A.refined[e_tab] : uint8_t(0);
+  }
 
   // --- phase B1: slopes + predictor.  The core cell of a thread (first pass,
   // tid < NCORE) keeps W~ and its slopes in registers for its six faces; a
   // one-layer cell keeps only its state on the face toward the core.
   constexpr int st[3] = {1, G::WB, G::WBB};
   const bool core = (NT == NCORE) || tid < NCORE;
-  const int cx = tid & (K - 1), cy = (tid >> G::LK) & (K - 1), cz = (tid >> (2 * G::LK)) & (K - 1);
+  const int ct = tid & (NCORE - 1);
+  const int cx = G::core_x(ct), cy = G::core_y(ct), cz = G::core_z(ct);
   const Real rfr = Real(rf), pfr = Real(pf), gr = Real(g);
   constexpr EB LMASK = EB((1u << G::B_LB) - 1);
   Real Pw[NV], Pd[3][NV];
@@ -627,6 +737,9 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     }
   }
   __syncthreads();
+  if constexpr (PIPE) {
+    if (next >= 0 && tid < TAB) S.ref[par ^ 1][tid] = rb;
+  }
 
   // --- phase B2: the left states (W~ + D/2 of the lower cell) of the faces
   // replace the primitives in LDS
@@ -688,6 +801,15 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   }
   __syncthreads();
   Real* SF = S.buf;                             // [NV][NFACE]
+  // PIPE: the gather entries of the next tile, read while the fluxes go out
+  EA entN[NRA];
+  if constexpr (PIPE) {
+#pragma unroll
+    for (int rnd = 0; rnd < NRA; ++rnd) {
+      const int i = tid + NT * rnd;
+      entN[rnd] = ST.a[uint32_t(i < NPOS_A ? i : 0)];
+    }
+  }
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
@@ -714,63 +836,75 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
   }
   __syncthreads();
 
-  // --- phase D: the threads of the core cells update them
-  if (tid < NCORE) {
-    const int ts = G::slot(cx >> 1, cy >> 1, cz >> 1);
-    const int32_t e = active ? S.tab[ts] : -1;
-    const int ci = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
-    // a tile cut by the domain's high side: its slots past the cut hold
-    // the periodic images of other octs, which other tiles update
-    const bool inside = cx <= hb[0] && cy <= hb[1] && cz <= hb[2];
-    const bool leaf = inside && (e >= 0) && (e < A.n_oct) && !((S.ref[ts] >> ci) & 1);
-    double s = 0.0;
-    if (leaf) {
-      // the cell's old state is loaded first: the stores to the new state
-      // below may alias it as far as the compiler knows, and a load issued
-      // after a store would wait for it
-      const uint32_t cell = uint32_t(e) * 8u + uint32_t(ci);
-      double Uo[NV];
+  // --- phase D: the threads of the core cells update them.  The cell's old
+  // state is loaded first: the stores to the new state below may alias it
+  // as far as the compiler knows, and a load issued after a store would
+  // wait for it.  PIPE: the next tile's gather is issued behind it, so that
+  // waiting for the old state does not wait for the gather.
+  const int ts = G::slot(cx >> 1, cy >> 1, cz >> 1);
+  const int32_t e = (active && tid < NCORE) ? tab[ts] : -1;
+  const int ci = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
+  // a tile cut by the domain's high side: its slots past the cut hold the
+  // periodic images of other octs, which other tiles update
+  const bool inside = cx <= hb[0] && cy <= hb[1] && cz <= hb[2];
+  const bool leaf = tid < NCORE && inside && (e >= 0) && (e < A.n_oct) && !((ref[ts] >> ci) & 1);
+  const uint32_t cell = uint32_t(e) * 8u + uint32_t(ci);
+  double Uo[NV], acc[NV];
+  if (leaf) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Uo[v] = (A.U + v * P)[cell];
-      double acc[NV];
+    for (int v = 0; v < NV; ++v) Uo[v] = (A.U + v * P)[cell];
+  }
+  if (leaf) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        // the lower face's flux is the thread's own (phase C), the upper
-        // one comes from the neighbouring cell's thread through LDS
-        const int fp = G::fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
-        double Fm[NV], Fp[NV];
+    for (int d = 0; d < 3; ++d) {
+      // the lower face's flux is the thread's own (phase C), the upper one
+      // comes from the neighbouring cell's thread through LDS
+      const int fp = G::fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
+      double Fm[NV], Fp[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          Fm[v] = double(Fc[d][v]);
-          Fp[v] = double(SF[v * NFACE + fp]);
-        }
-        if (A.child) {
-          // a refined neighbour across a face: use its child oct's register
+      for (int v = 0; v < NV; ++v) {
+        Fm[v] = double(Fc[d][v]);
+        Fp[v] = double(SF[v * NFACE + fp]);
+      }
+      if (A.child) {
+        // a refined neighbour across a face: use its child oct's register
 #pragma unroll
-          for (int side = 0; side < 2; ++side) {
-            int n[3] = {cx, cy, cz};
-            n[d] += side ? 1 : -1;
-            const uint32_t lo = (d == 0) ? CL_LOX : ((d == 1) ? CL_LOY : CL_LOZ);
-            const uint32_t hi = lo << 1;
-            if ((n[d] < 0 && (fl & lo)) || (n[d] > hb[d] && (fl & hi))) continue;
-            const int tn = G::slot(n[0] >> 1, n[1] >> 1, n[2] >> 1);
-            const int32_t en = S.tab[tn];
-            const int cn = (n[0] & 1) | ((n[1] & 1) << 1) | ((n[2] & 1) << 2);
-            if (en >= 0 && en < A.n_oct && ((S.ref[tn] >> cn) & 1)) {
-              const int32_t ch = A.child[int64_t(en) * 8 + cn];
-              const int face = 2 * d + (side ? 0 : 1);   // child's face toward this cell
-              const double* q = A.reg_fine + (int64_t(ch) * 6 + face) * NV * 2;
+        for (int side = 0; side < 2; ++side) {
+          int n[3] = {cx, cy, cz};
+          n[d] += side ? 1 : -1;
+          const uint32_t lo = (d == 0) ? CL_LOX : ((d == 1) ? CL_LOY : CL_LOZ);
+          const uint32_t hi = lo << 1;
+          if ((n[d] < 0 && (fl & lo)) || (n[d] > hb[d] && (fl & hi))) continue;
+          const int tn = G::slot(n[0] >> 1, n[1] >> 1, n[2] >> 1);
+          const int32_t en = tab[tn];
+          const int cn = (n[0] & 1) | ((n[1] & 1) << 1) | ((n[2] & 1) << 2);
+          if (en >= 0 && en < A.n_oct && ((ref[tn] >> cn) & 1)) {
+            const int32_t ch = A.child[int64_t(en) * 8 + cn];
+            const int face = 2 * d + (side ? 0 : 1);   // child's face toward this cell
+            const double* q = A.reg_fine + (int64_t(ch) * 6 + face) * NV * 2;
 #pragma unroll
-              for (int v = 0; v < NV; ++v) {
-                const double fb = 0.125 * (q[2 * v] + q[2 * v + 1]);
-                if (side) Fp[v] = fb; else Fm[v] = fb;
-              }
+            for (int v = 0; v < NV; ++v) {
+              const double fb = 0.125 * (q[2 * v] + q[2 * v + 1]);
+              if (side) Fp[v] = fb; else Fm[v] = fb;
             }
           }
         }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = (d == 0) ? (Fm[v] - Fp[v]) : acc[v] + (Fm[v] - Fp[v]);
       }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = (d == 0) ? (Fm[v] - Fp[v]) : acc[v] + (Fm[v] - Fp[v]);
+    }
+  }
+  if constexpr (PIPE) {
+    if (next >= 0) {
+      const uint32_t fln = A.tflag[next];
+      int hbn[3];
+      tile_hb<K>(fln, hbn);
+      gather_issue<K, NT, NV>(A, S.tab[par ^ 1], fln, hbn, tid, true, entN, R);
+    }
+  }
+  if (tid < NCORE) {
+    double s = 0.0;
+    if (leaf) {
       double Un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -816,7 +950,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     const int b = rt / 6, face = rt - 6 * (rt / 6);
     const int bx = b % KO, by = (b / KO) % KO, bz = b / (KO * KO);
     const int tb_ = G::slot(bx, by, bz);
-    const int32_t eb = S.tab[tb_];
+    const int32_t eb = tab[tb_];
     const int d = face >> 1, up = face & 1;
     const int dd = up ? 1 : -1;
     const int rx = bx + (d == 0 ? dd : 0), ry_ = by + (d == 1 ? dd : 0), rz = bz + (d == 2 ? dd : 0);
@@ -826,7 +960,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
     const bool inside = bx <= (hb[0] >> 1) && by <= (hb[1] >> 1) && bz <= (hb[2] >> 1);
     if (inside && eb >= 0 && eb < A.n_oct && !clamped) {
       const int tn = G::slot(rx, ry_, rz);
-      if (S.tab[tn] >= A.n_oct) {
+      if (tab[tn] >= A.n_oct) {
         // the 4 cells of the oct on this face, ascending in-oct index: insert
         // bit `up` at position d into j = 0..3
         const int m = (1 << d) - 1;
@@ -855,7 +989,7 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       // a conversion: counted when the position is one of the tile's own leaf cells
       const int raw = int(ST.a[tid + NT * rnd] >> G::A_RS);
       const int sx = raw % G::R - 2, sy = (raw / G::R) % G::R - 2, sz = raw / (G::R * G::R) - 2;
-      if (census_own(hb, sx, sy, sz) && census_kind(S, fl, hb, A.n_oct, sx, sy, sz) == 1) nfl += f;
+      if (census_own(hb, sx, sy, sz) && census_kind<K>(tab, ref, fl, hb, A.n_oct, sx, sy, sz) == 1) nfl += f;
     }
 #pragma unroll
     for (int rnd = 0; rnd < NRB; ++rnd) {
@@ -868,13 +1002,13 @@ __device__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS
       const bool up = (e >> G::B_US) & EB(1);
       const int x = (iw % G::WB) - 1 - (up && dn == 0), y = (iw % G::WBB) / G::WB - 1 - (up && dn == 1),
                 z = iw / G::WBB - 1 - (up && dn == 2);
-      if (census_face(S, fl, hb, A.n_oct, x, y, z, dn)) nfl += f;
+      if (census_face<K>(tab, ref, fl, hb, A.n_oct, x, y, z, dn)) nfl += f;
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int fl_ = (pending >> (2 * (SITE_L + d))) & 3, fr = (pending >> (2 * (SITE_R + d))) & 3;
-      if (fl_ && census_face(S, fl, hb, A.n_oct, cx, cy, cz, d)) nfl += fl_;
-      if (fr && census_face(S, fl, hb, A.n_oct, cx - (d == 0), cy - (d == 1), cz - (d == 2), d)) nfl += fr;
+      if (fl_ && census_face<K>(tab, ref, fl, hb, A.n_oct, cx, cy, cz, d)) nfl += fl_;
+      if (fr && census_face<K>(tab, ref, fl, hb, A.n_oct, cx - (d == 0), cy - (d == 1), cz - (d == 2), d)) nfl += fr;
     }
   }
   // floor activations are rare: the shuffle sum runs only in a wavefront
@@ -907,7 +1041,52 @@ void hydro_kernel(HydroArgs A) {
   const int grp = xcd_remap(blockIdx.x, gridDim.x);
   if (grp >= ngroups) return;
   const int tile = grp * TPW + w;
-  hydro_tile<Real, NT, NS, K>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
+  GatherRegs<K, NT, NVAR + NS> R;
+  hydro_tile<Real, NT, NS, K>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile, R);
+}
+
+// Pipelined tile loop: each workgroup (one tile at a time) takes a contiguous
+// run of tiles (contiguous runs per XCD), and while it updates one tile it
+// loads the next tile's oct table, refined bytes and gathered states, so that
+// their memory latency overlaps the tile's own work instead of following it.
+template <typename Real, int WPT, int NS, int K>
+__global__ __launch_bounds__(64 * WPT) __attribute__((amdgpu_waves_per_eu(hydro_waves_per_eu<K, NS>()))) void
+hydro_kernel_pipe(HydroArgs A) {
+  constexpr int NT = 64 * WPT;
+  constexpr int NV = NVAR + NS;
+  using G = Geom<K>;
+  using R_t = GatherRegs<K, NT, NV>;
+  __shared__ TileLDS<Real, NV, K, 2> S;
+  if (A.skip && *A.skip) return;
+  const int tid = threadIdx.x;
+  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int first = int(int64_t(A.n_tile) * g / gridDim.x);
+  const int end = int(int64_t(A.n_tile) * (g + 1) / gridDim.x);
+  if (first >= end) return;
+  // prologue: the first tile's table, refined bytes and gather
+  const StencilTables<K>& ST = stencil_tables<K>();
+  typename G::EntA entA[R_t::NRA];
+#pragma unroll
+  for (int rnd = 0; rnd < R_t::NRA; ++rnd) {
+    const int i = tid + NT * rnd;
+    entA[rnd] = ST.a[uint32_t(i < G::NPOS_A ? i : 0)];
+  }
+  if (tid < G::TAB) {
+    const int32_t e = A.tab[size_t(first) * G::TAB + tid];
+    S.tab[0][tid] = lds_tab_entry(A, e);
+    S.ref[0][tid] = (e >= 0) ? A.refined[e] : uint8_t(0);
+  }
+  __syncthreads();
+  const uint32_t fl = A.tflag[first];
+  int hb[3];
+  tile_hb<K>(fl, hb);
+  R_t R;
+  gather_issue<K, NT, NV>(A, S.tab[0], fl, hb, tid, true, entA, R);
+  int par = 0;
+  for (int t = first; t < end; ++t) {
+    hydro_tile<Real, NT, NS, K, true>(A, t, S, tid, true, R, par, t + 1 < end ? t + 1 : -1);
+    par ^= 1;
+  }
 }
 
 // Persistent variant (K = 4): workgroups pop groups of tiles from 8 per-XCD
@@ -957,7 +1136,8 @@ __global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(
       const int grp = item * batch + j;
       if (grp >= ngroups) break;
       const int tile = grp * TPW + w;
-      hydro_tile<Real, NT, 0, 4>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile);
+      GatherRegs<4, NT, NVAR> R;
+      hydro_tile<Real, NT, 0, 4>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile, R);
     }
     if (threadIdx.x == 0) {
       int next = -1;
@@ -978,13 +1158,24 @@ __global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
-// The persistent kernel exists for the hydro variables alone (NS = 0) on
-// small tiles (K = 4).
+// The queue-fed persistent kernel (persistent = 1) exists for the hydro
+// variables alone (NS = 0) on small tiles (K = 4); the pipelined tile loop
+// (persistent = 2) for one tile per workgroup, with num_cu * waves_per_cu /
+// WPT workgroups.
 template <typename Real, int TPW, int WPT, int NS, int K = 4>
 static int launch_hydro_t(const HydroArgs& a, const ry_tuning& t, int num_cu, hipStream_t s) {
   const int ngroups = (a.n_tile + TPW - 1) / TPW;
   if (ngroups == 0) return 0;
-  if (NS > 0 || K != 4 || !t.persistent) {
+  if (t.persistent == 2) {
+    if constexpr (TPW == 1 && NS == 0 && (K == 8 || WPT == 1)) {
+      int64_t grid = int64_t(num_cu) * (t.waves_per_cu > 0 ? t.waves_per_cu : 4) / WPT;
+      if (grid < 1) grid = 1;
+      if (grid > a.n_tile) grid = a.n_tile;
+      hipLaunchKernelGGL((hydro_kernel_pipe<Real, WPT, NS, K>), dim3(unsigned(grid)), dim3(64 * WPT), 0, s, a);
+    } else {
+      return -1;
+    }
+  } else if (NS > 0 || K != 4 || !t.persistent) {
     hipLaunchKernelGGL((hydro_kernel<Real, TPW, WPT, NS, K>), dim3(ngroups), dim3(64 * WPT * TPW), 0, s, a);
   } else if constexpr (NS == 0 && K == 4) {
     const int batch = t.batch > 0 ? t.batch : 1;

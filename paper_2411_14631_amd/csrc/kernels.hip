@@ -15,9 +15,13 @@ namespace ry {
 int hydro_max_tiles_per_wg() { return 4; }
 
 bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t) {
-  if (t.tile_cells == 8) return nscalar == 0 && !t.persistent && t.tiles_per_wg == 1 && t.waves_per_tile == 8;
+  if (t.tile_cells == 8)
+    return nscalar == 0 && (t.persistent == 0 || t.persistent == 2) && t.tiles_per_wg == 1 && t.waves_per_tile == 8;
   if (t.tile_cells != 4) return false;
   const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
+  // the pipelined tile loop: one one-wavefront tile per workgroup, hydro
+  // variables alone
+  if (t.persistent == 2) return nscalar == 0 && key == 11;
   if (nscalar == 0) {
     if (precision == RY_MIXED) return key == 11 || key == 21 || key == 41 || key == 12 || key == 22 || key == 14;
     return key == 11 || key == 21 || key == 41 || key == 12 || key == 22 || key == 14;
@@ -58,7 +62,8 @@ int launch_hydro(const HydroArgs& a, int precision, int nscalar, const ry_tuning
 
 // ---------------------------------------------------------------------------
 // Ghost octs: MinMod-limited linear interpolation of the covering coarse
-// cell's conserved variables, written into both state buffers.
+// cell's conserved variables, written into the level's second state buffer
+// (both hydro substeps of the parent step read them there).
 // ---------------------------------------------------------------------------
 // Whether cell position p of a level (its sorted keys, refined bytes, octs
 // per axis, boundaries) is a leaf cell: positions past an outflow face and
@@ -145,13 +150,9 @@ __global__ void ghost_kernel(GhostArgs A) {
       out[c] = q + (sx * mx + sy * my + sz * mz);
       if (v < NVAR) keep[v][c] = out[c];
     }
-    double2* d0 = reinterpret_cast<double2*>(A.dst0 + v * A.plane + dst);
-    double2* d1 = reinterpret_cast<double2*>(A.dst1 + v * A.plane + dst);
+    double2* d = reinterpret_cast<double2*>(A.dst + v * A.plane + dst);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      d0[j] = make_double2(out[2 * j], out[2 * j + 1]);
-      d1[j] = make_double2(out[2 * j], out[2 * j + 1]);
-    }
+    for (int j = 0; j < 4; ++j) d[j] = make_double2(out[2 * j], out[2 * j + 1]);
   }
   if (A.floors) {
     // the floors the primitive conversion of each cell applies (density,

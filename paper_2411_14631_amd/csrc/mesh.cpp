@@ -484,12 +484,11 @@ std::string build_tables(const DomainSpec& d, const std::vector<HostLevel>& L,
   for (auto& t : pool) t.join();
   for (auto& e : err)
     if (!e.empty()) return e;
-  // the hydro kernel indexes a level's cells (octs and ghost octs, 8 cells
-  // each) in 32 bits
   for (int k = 0; k < nl; ++k)
-    if (out[k].n_oct + out[k].n_ghost >= (int64_t(1) << 29))
+    if (!level_index_fits(out[k].n_oct, out[k].n_ghost, d.nv))
       return "level " + std::to_string(d.lmin + k) + ": " + std::to_string(out[k].n_oct) + " octs + " +
-             std::to_string(out[k].n_ghost) + " ghost octs reach 2^29 (cells are indexed in 32 bits)";
+             std::to_string(out[k].n_ghost) + " ghost octs reach the 32-bit cell index (2^29 octs, " +
+             "(1 + nv) times the octs + ghost octs on a level with ghosts)";
   return "";
 }
 

@@ -135,6 +135,11 @@ struct HydroArgs {
   double* Un;                 // next state
   int64_t plane;              // 8 * n_ext
   int32_t n_oct;              // real octs: ext index < n_oct
+  // ghost octs live only in the level's second state buffer, which follows
+  // the first one in memory (nv planes later): reading through the first,
+  // a ghost oct's index is shifted by ghost_adj = nv * n_ext octs; 0 when
+  // the current buffer is the second one or the level has no ghosts
+  int32_t ghost_adj;
   int32_t n_tile;
   const int32_t* tab;
   const uint32_t* tflag;
@@ -166,8 +171,7 @@ struct GhostArgs {
   const int64_t* gsrc;
   int64_t n_ghost;
   int64_t n_oct;
-  double* dst0;
-  double* dst1;
+  double* dst;                // the level's second state buffer (ghosts live there only)
   int64_t plane;
   int32_t nv;
   const int32_t* skip;
@@ -196,6 +200,14 @@ int launch_restrict(const double* Uf, int64_t plane_f, int64_t n_fine, const int
 // Blocks of the CFL pass over n_oct octs (256 cells each): the number of
 // partial maxima it writes.
 inline int64_t cfl_blocks(int64_t n_oct) { return (8 * n_oct + 255) / 256; }
+// The hydro kernel indexes a level's cells in 32 bits: its octs and ghost
+// octs (8 cells each) and, on a level with ghost octs, the shift by
+// nv * (octs + ghost octs) octs that reads a ghost oct from the second state
+// buffer; all of it stays below 2^29 octs.
+inline bool level_index_fits(int64_t n_oct, int64_t n_ghost, int nv) {
+  const int64_t n_ext = n_oct + n_ghost;
+  return (n_ghost > 0 ? (1 + int64_t(nv)) * n_ext : n_ext) < (int64_t(1) << 29);
+}
 // Launch failures that the launchers detect before any device call.
 constexpr int LAUNCH_EXCEEDS_BUFFER = -2;
 // per-block maxima of the signal speed over leaf cells -> part[0 ..
