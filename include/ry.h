@@ -162,11 +162,7 @@ ry_status ry_batch_download(ry_ctx* ctx, int32_t box, double* U);
  * do not depend on the tuning. */
 typedef struct {
   int32_t tiles_per_wg;   /* tiles per workgroup: 1, 2 or 4 (tile_cells 4); 1 (tile_cells 8) */
-  int32_t persistent;     /* 0: one workgroup per tile group; 1: work queue (tile_cells 4); */
-                          /* 2: pipelined tile loop (one tile per workgroup: tile_cells 8,  */
-                          /* or tile_cells 4 with {1,2,*,*,1}): each workgroup takes a run  */
-                          /* of consecutive tiles and loads the next tile's octs and state  */
-                          /* while it updates the current one (hydro variables alone)      */
+  int32_t persistent;     /* 0: one workgroup per tile group; 1: work queue (tile_cells 4)  */
   int32_t waves_per_cu;   /* persistent grid = CUs * waves_per_cu / waves per workgroup     */
   int32_t batch;          /* tile groups popped per queue access                            */
   int32_t waves_per_tile; /* tile_cells 4: 1, 2 or 4 wavefronts per tile (8, 16, 32 threads */

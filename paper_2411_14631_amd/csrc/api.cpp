@@ -29,6 +29,7 @@ struct DevLevel {
   int32_t* child = nullptr;
   double* reg = nullptr;
   int64_t* gsrc = nullptr;
+  uint32_t* gread = nullptr;         // per ghost oct: the cells an update reads (floor census)
   int32_t* parent_cell = nullptr;
   int32_t* tile_box = nullptr;
   int32_t* oct_box = nullptr;
@@ -386,12 +387,7 @@ ry_status enqueue_ghost(ry_ctx* c, int l, const int32_t* skip) {
   g.gamma = c->cfg.gamma;
   g.rho_floor = c->cfg.rho_floor;
   g.p_floor = c->cfg.p_floor;
-  g.key = L.dkey;
-  g.refined = L.refined;
-  g.bits = c->dom.hbits0 + (l - c->cfg.level_min);
-  for (int a = 0; a < 3; ++a) g.noct[a] = c->dom.noct(l, a);
-  for (int i = 0; i < 6; ++i) g.bc[i] = c->dom.bc[i];
-  g.coarse_oc = c->lev[l - 1 - c->cfg.level_min].doc;
+  g.gread = L.gread;
   TimedLaunch tl;
   if (c->timing) time_begin(c, "ghost", tl);
   if (launch_ghost(g, c->stream)) return fail(c, RY_EHIP, "ghost kernel");
@@ -519,6 +515,25 @@ ry_status build_super(ry_ctx* c, int k) {
   return RY_OK;
 }
 
+// The ghost read masks of every refined level (after a mesh change): for
+// each ghost oct, which of its cells a leaf update reads.
+ry_status build_ghost_read(ry_ctx* c) {
+  for (int k = 0; k < c->nlev; ++k) {
+    DevLevel& L = c->lev[k];
+    if (L.gread) {
+      dfree(c, L.gread);
+      L.gread = nullptr;
+    }
+    if (k == 0 || L.n_ghost == 0 || L.n_tile == 0) continue;
+    L.gread = static_cast<uint32_t*>(dalloc(c, sizeof(uint32_t) * L.n_ghost));
+    if (!L.gread) return fail(c, RY_ENOMEM, "ghost read masks: allocation failed");
+    if (launch_zero_u32(L.gread, L.n_ghost, c->stream) ||
+        launch_ghost_read(L.tab, L.tflag, L.refined, L.n_tile, L.n_oct, L.gread, c->stream))
+      return fail(c, RY_EHIP, "ghost read-mask kernel");
+  }
+  return RY_OK;
+}
+
 // Super-tile tables for every level whose tuning uses the 8^3-cell tile
 // (after a mesh change, or a tuning change).
 ry_status ensure_super(ry_ctx* c) {
@@ -558,8 +573,7 @@ ry_status enqueue_hydro(ry_ctx* c, const HydroArgs& a, int k, const ry_tuning* t
     if (b.tile_smax && launch_zero_u64(reinterpret_cast<unsigned long long*>(c->d_part), c->seg_off.back(), c->stream))
       return fail(c, RY_EHIP, "zero kernel");
   }
-  if (tu.persistent == 1 && launch_zero_u32(c->d_queue, 8 * QUEUE_STRIDE, c->stream))
-    return fail(c, RY_EHIP, "zero kernel");
+  if (tu.persistent && launch_zero_u32(c->d_queue, 8 * QUEUE_STRIDE, c->stream)) return fail(c, RY_EHIP, "zero kernel");
   TimedLaunch tl;
   if (c->timing) time_begin(c, "hydro", tl);
   if (launch_hydro(b, c->cfg.precision, c->cfg.nscalar, tu, c->num_cu, c->stream))
@@ -761,6 +775,7 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
   std::fill(std::begin(c->count), std::end(c->count), 0);
   if ((s = enqueue_cfl_all(c))) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if ((s = build_ghost_read(c))) return s;
   if ((s = ensure_super(c))) return s;
   for (auto& h : H) std::vector<double>().swap(h.U);
   c->host = std::move(H);
@@ -947,6 +962,7 @@ ry_status finish_regrid(ry_ctx* c) {
   drop_super(c);
   std::fill(std::begin(c->count), std::end(c->count), 0);
   c->slots_valid = false;
+  if ((s = build_ghost_read(c))) return s;
   if ((s = ensure_super(c))) return s;
   if ((s = enqueue_cfl_all(c))) return s;
   return sync_and_check(c);
@@ -1686,10 +1702,10 @@ bool same_tuning(const ry_tuning& a, const ry_tuning& b) {
 // Whether the context can run a tuning (RY_OK) or not (RY_EINVAL, with the
 // reason).
 ry_status check_tuning(ry_ctx* c, const ry_tuning& t) {
-  if (t.persistent < 0 || t.persistent > 2) return fail(c, RY_EINVAL, "persistent must be 0, 1 or 2");
+  if (t.persistent < 0 || t.persistent > 1) return fail(c, RY_EINVAL, "persistent must be 0 or 1");
   if (t.tile_cells == 8) {
-    if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent == 1)
-      return fail(c, RY_EINVAL, "tile_cells 8 needs tiles_per_wg 1, waves_per_tile 8, persistent 0 or 2");
+    if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent)
+      return fail(c, RY_EINVAL, "tile_cells 8 needs tiles_per_wg 1, waves_per_tile 8, persistent 0");
   } else if (t.tile_cells == 4) {
     if (t.tiles_per_wg != 1 && t.tiles_per_wg != 2 && t.tiles_per_wg != 4) return fail(c, RY_EINVAL, "tiles_per_wg");
     if (t.waves_per_tile != 1 && t.waves_per_tile != 2 && t.waves_per_tile != 4)
@@ -1804,11 +1820,6 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
     for (int w : {8, 14, 20})
       for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt, 4});
   cand.push_back({1, 0, 4, 1, 8, 8});
-  // pipelined tile loops: 8^3-cell tiles two workgroups per CU, one-wavefront
-  // 4^3-cell tiles 8 or 12 per CU
-  cand.push_back({1, 2, 16, 1, 8, 8});
-  cand.push_back({1, 2, 8, 1, 1, 4});
-  cand.push_back({1, 2, 12, 1, 1, 4});
   {
     std::string keep = c->err;
     cand.erase(std::remove_if(cand.begin(), cand.end(), [&](const ry_tuning& t) { return check_tuning(c, t) != RY_OK; }),

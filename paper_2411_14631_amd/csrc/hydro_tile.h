@@ -205,16 +205,15 @@ __device__ __forceinline__ const StencilTables<K>& stencil_tables() {
 // cells' right states [NVAR][NUPPER] (B2 -> C), then the face fluxes
 // [NVAR][NFACE] (C -> D).  Fluxes are stored in Real: in the mixed
 // form they are FP32 results, so FP32 storage loses nothing.
-template <typename Real, int NV, int K, int NTAB = 1>
+template <typename Real, int NV, int K>
 struct TileLDS {
   using G = Geom<K>;
   static constexpr int NW = NV * G::WSIZE, NF = NV * (G::NFACE + G::NUPPER);
   Real buf[NW > NF ? NW : NF];
   // ext oct index of the oct neighbourhood (ghost octs shifted as the
-  // current state buffer needs) and the refined-cell bytes of those octs:
-  // the current tile's, and in a pipelined tile loop the next tile's
-  int32_t tab[NTAB][G::TAB];
-  uint8_t ref[NTAB][G::TAB];
+  // current state buffer needs) and the refined-cell bytes of those octs
+  int32_t tab[G::TAB];
+  uint8_t ref[G::TAB];
 };
 
 // ---------------------------------------------------------------------------
@@ -469,9 +468,8 @@ __device__ bool census_face(const int32_t* tab, const uint8_t* ref, uint32_t fl,
   return ka == 1 && kb == 0 && census_own(hb, x, y, z);
 }
 
-// Registers that carry a tile's gathered conserved states into its phase A:
-// loaded there (plain tile), or during the previous tile's update (pipelined
-// tile loop).
+// Registers that carry a tile's gathered conserved states from their loads
+// to their conversion (phase A).
 template <int K, int NT, int NV>
 struct GatherRegs {
   static constexpr int NRA = (Geom<K>::NPOS_A + NT - 1) / NT;
@@ -559,15 +557,9 @@ __device__ __forceinline__ int32_t lds_tab_entry(const HydroArgs& A, int32_t e) 
   return (e >= A.n_oct) ? e + A.ghost_adj : e;
 }
 
-// PIPE: the tile is one of a workgroup's run of tiles.  Its oct table and
-// refined bytes are already in S.tab[par] / S.ref[par] and its gathered
-// states in R (both loaded during the previous tile); while it runs, it
-// loads the same for tile `next` (-1: none) into S.tab[par ^ 1],
-// S.ref[par ^ 1] and R.  Plain: par = 0, the tile loads its own.
-template <typename Real, int NT, int NS, int K, bool PIPE = false>
-__device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS, K, PIPE ? 2 : 1>& S,
-                                           int tid_in, bool active, GatherRegs<K, NT, NVAR + NS>& R, int par = 0,
-                                           int next = -1) {
+template <typename Real, int NT, int NS, int K>
+__device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS<Real, NVAR + NS, K>& S, int tid_in,
+                                           bool active, GatherRegs<K, NT, NVAR + NS>& R) {
   using G = Geom<K>;
   using EA = typename G::EntA;
   using EB = typename G::EntB;
@@ -588,8 +580,8 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   const Real h = Real(0.5 * lam);
   const Real igm1 = Real(A.igm1);
   const StencilTables<K>& ST = stencil_tables<K>();
-  const int32_t* tab = S.tab[par];
-  const uint8_t* ref = S.ref[par];
+  const int32_t* tab = S.tab;
+  const uint8_t* ref = S.ref;
 
   // The thread's stencil-table entries for phases A and B, loaded together up
   // front: a load issued inside a round would make that round wait for every
@@ -610,43 +602,43 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
     entB[rnd] = ST.b[uint32_t(i < NPOS_B ? i : 0)];
   }
 
-  int32_t e_tab = -1;     // plain: this tile's table entry; PIPE: the next tile's
-  uint8_t rb = 0;
-  if constexpr (!PIPE) {
-    EA entA[NRA];
+  EA entA[NRA];
 #pragma unroll
-    for (int rnd = 0; rnd < NRA; ++rnd) {
-      const int i = tid + NT * rnd;
-      entA[rnd] = ST.a[uint32_t(i < NPOS_A ? i : 0)];
-    }
-    // --- phase 0: the tile's oct table (the refined bytes of its octs are
-    // loaded in phase A behind the state loads; phase D is their first reader)
-    if (active && tid < TAB) {
-      e_tab = A.tab[size_t(tile) * TAB + tid];
-      S.tab[0][tid] = lds_tab_entry(A, e_tab);
-    }
-    __syncthreads();
-    // Wait for the table entries here on every path: otherwise the gather's
-    // conditional state loads leave the compiler's load counting unsure of
-    // them, and each round would wait for the state loads of the rounds
-    // before it.
-#pragma unroll
-    for (int rnd = 0; rnd < NRA; ++rnd) asm volatile("" ::"v"(entA[rnd]));
-#pragma unroll
-    for (int rnd = 0; rnd < NRB; ++rnd) asm volatile("" ::"v"(entB[rnd]));
-    // --- phase A: gather + primitives (all loads of the thread's positions
-    // are issued before any conversion)
-    gather_issue<K, NT, NV>(A, tab, fl, hb, tid, active, entA, R);
-    rb = (e_tab >= 0) ? A.refined[e_tab] : uint8_t(0);
-  } else {
-#pragma unroll
-    for (int rnd = 0; rnd < NRB; ++rnd) asm volatile("" ::"v"(entB[rnd]));
-    // the next tile's oct table, on its way while this tile converts
-    if (next >= 0 && tid < TAB) e_tab = A.tab[size_t(next) * TAB + tid];
+  for (int rnd = 0; rnd < NRA; ++rnd) {
+    const int i = tid + NT * rnd;
+    entA[rnd] = ST.a[uint32_t(i < NPOS_A ? i : 0)];
   }
+  // --- phase 0: the tile's oct table (the refined bytes of its octs are
+  // loaded in phase A behind the state loads; phase D is their first reader)
+  int32_t e_tab = -1;
+  if (active && tid < TAB) {
+    e_tab = A.tab[size_t(tile) * TAB + tid];
+    S.tab[tid] = lds_tab_entry(A, e_tab);
+  }
+  __syncthreads();
+  // Wait for the table entries here on every path: otherwise the gather's
+  // conditional state loads leave the compiler's load counting unsure of
+  // them, and each round would wait for the state loads of the rounds
+  // before it.
+#pragma unroll
+  for (int rnd = 0; rnd < NRA; ++rnd) asm volatile("" ::"v"(entA[rnd]));
+#pragma unroll
+  for (int rnd = 0; rnd < NRB; ++rnd) asm volatile("" ::"v"(entB[rnd]));
+  // --- phase A: gather + primitives (all loads of the thread's positions
+  // are issued before any conversion)
+  gather_issue<K, NT, NV>(A, tab, fl, hb, tid, active, entA, R);
+  const uint8_t rb = (e_tab >= 0) ? A.refined[e_tab] : uint8_t(0);
 
-  // --- phase A (conversion): primitives into LDS
+  // --- phase A (conversion): primitives into LDS.  A core cell's first
+  // gathered position is the cell itself (the tables' oct-major order): its
+  // conserved state stays in registers for the update (phase D), except in
+  // the FP64 8^3-cell tile, whose register budget (4 wavefronts per SIMD)
+  // it would overrun: there phase D loads it again.
+  constexpr bool KEEP_CORE = (K == 4) || (sizeof(Real) == 4);
   Real* W = S.buf;                              // [NV][WSIZE]
+  double Ucore[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Ucore[v] = KEEP_CORE ? R.Ua[0][v] : 0.0;
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     if (R.iwa[rnd] >= 0) {
@@ -658,28 +650,8 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
       for (int v = 0; v < NV; ++v) W[v * WSIZE + R.iwa[rnd]] = Real(Wc[v]);
     }
   }
-  if constexpr (PIPE) {
-    // consumed: the registers hold nothing until the next tile's gather
-    // (otherwise the lanes that gather nothing there would keep these values
-    // alive through the whole tile); such lanes have iwa = -1 and never
-    // read Ua
-#pragma unroll
-    for (int rnd = 0; rnd < NRA; ++rnd) {
-      R.iwa[rnd] = -1;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) R.Ua[rnd][v] = __builtin_nondeterministic_value(R.Ua[rnd][v]);
-    }
-  }
-  if constexpr (!PIPE) {
-    if (active && tid < TAB) S.ref[0][tid] = rb;
-  } else {
-    if (next >= 0 && tid < TAB) S.tab[par ^ 1][tid] = lds_tab_entry(A, e_tab);
-  }
+  if (active && tid < TAB) S.ref[tid] = rb;
   __syncthreads();
-  if constexpr (PIPE) {
-    // the next tile's refined bytes, stored once phase B1 is done
-    if (next >= 0 && tid < TAB) rb = (e_tab >= 0) ? A.refined[e_tab] : uint8_t(0);
-  }
 
   // --- phase B1: slopes + predictor.  The core cell of a thread (first pass,
   // tid < NCORE) keeps W~ and its slopes in registers for its six faces; a
@@ -737,9 +709,6 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
     }
   }
   __syncthreads();
-  if constexpr (PIPE) {
-    if (next >= 0 && tid < TAB) S.ref[par ^ 1][tid] = rb;
-  }
 
   // --- phase B2: the left states (W~ + D/2 of the lower cell) of the faces
   // replace the primitives in LDS
@@ -801,15 +770,6 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   }
   __syncthreads();
   Real* SF = S.buf;                             // [NV][NFACE]
-  // PIPE: the gather entries of the next tile, read while the fluxes go out
-  EA entN[NRA];
-  if constexpr (PIPE) {
-#pragma unroll
-    for (int rnd = 0; rnd < NRA; ++rnd) {
-      const int i = tid + NT * rnd;
-      entN[rnd] = ST.a[uint32_t(i < NPOS_A ? i : 0)];
-    }
-  }
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
@@ -836,11 +796,10 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   }
   __syncthreads();
 
-  // --- phase D: the threads of the core cells update them.  The cell's old
-  // state is loaded first: the stores to the new state below may alias it
-  // as far as the compiler knows, and a load issued after a store would
-  // wait for it.  PIPE: the next tile's gather is issued behind it, so that
-  // waiting for the old state does not wait for the gather.
+  // --- phase D: the threads of the core cells update them (the old state of
+  // the cell is the one gathered in phase A, or loaded again first: the
+  // stores to the new state may alias it as far as the compiler knows, and
+  // a load issued after a store would wait for it)
   const int ts = G::slot(cx >> 1, cy >> 1, cz >> 1);
   const int32_t e = (active && tid < NCORE) ? tab[ts] : -1;
   const int ci = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
@@ -849,11 +808,11 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   const bool inside = cx <= hb[0] && cy <= hb[1] && cz <= hb[2];
   const bool leaf = tid < NCORE && inside && (e >= 0) && (e < A.n_oct) && !((ref[ts] >> ci) & 1);
   const uint32_t cell = uint32_t(e) * 8u + uint32_t(ci);
-  double Uo[NV], acc[NV];
-  if (leaf) {
+  if (!KEEP_CORE && leaf) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Uo[v] = (A.U + v * P)[cell];
+    for (int v = 0; v < NV; ++v) Ucore[v] = (A.U + v * P)[cell];
   }
+  double acc[NV];
   if (leaf) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -894,21 +853,13 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
       for (int v = 0; v < NV; ++v) acc[v] = (d == 0) ? (Fm[v] - Fp[v]) : acc[v] + (Fm[v] - Fp[v]);
     }
   }
-  if constexpr (PIPE) {
-    if (next >= 0) {
-      const uint32_t fln = A.tflag[next];
-      int hbn[3];
-      tile_hb<K>(fln, hbn);
-      gather_issue<K, NT, NV>(A, S.tab[par ^ 1], fln, hbn, tid, true, entN, R);
-    }
-  }
   if (tid < NCORE) {
     double s = 0.0;
     if (leaf) {
       double Un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Un[v] = Uo[v] + lam * acc[v];
+        Un[v] = Ucore[v] + lam * acc[v];
         (A.Un + v * P)[cell] = Un[v];
       }
       if (A.tile_smax || A.smax_bits || A.err) {
@@ -1045,50 +996,6 @@ void hydro_kernel(HydroArgs A) {
   hydro_tile<Real, NT, NS, K>(A, tile < A.n_tile ? tile : 0, S[w], tid, tile < A.n_tile, R);
 }
 
-// Pipelined tile loop: each workgroup (one tile at a time) takes a contiguous
-// run of tiles (contiguous runs per XCD), and while it updates one tile it
-// loads the next tile's oct table, refined bytes and gathered states, so that
-// their memory latency overlaps the tile's own work instead of following it.
-template <typename Real, int WPT, int NS, int K>
-__global__ __launch_bounds__(64 * WPT) __attribute__((amdgpu_waves_per_eu(hydro_waves_per_eu<K, NS>()))) void
-hydro_kernel_pipe(HydroArgs A) {
-  constexpr int NT = 64 * WPT;
-  constexpr int NV = NVAR + NS;
-  using G = Geom<K>;
-  using R_t = GatherRegs<K, NT, NV>;
-  __shared__ TileLDS<Real, NV, K, 2> S;
-  if (A.skip && *A.skip) return;
-  const int tid = threadIdx.x;
-  const int g = xcd_remap(blockIdx.x, gridDim.x);
-  const int first = int(int64_t(A.n_tile) * g / gridDim.x);
-  const int end = int(int64_t(A.n_tile) * (g + 1) / gridDim.x);
-  if (first >= end) return;
-  // prologue: the first tile's table, refined bytes and gather
-  const StencilTables<K>& ST = stencil_tables<K>();
-  typename G::EntA entA[R_t::NRA];
-#pragma unroll
-  for (int rnd = 0; rnd < R_t::NRA; ++rnd) {
-    const int i = tid + NT * rnd;
-    entA[rnd] = ST.a[uint32_t(i < G::NPOS_A ? i : 0)];
-  }
-  if (tid < G::TAB) {
-    const int32_t e = A.tab[size_t(first) * G::TAB + tid];
-    S.tab[0][tid] = lds_tab_entry(A, e);
-    S.ref[0][tid] = (e >= 0) ? A.refined[e] : uint8_t(0);
-  }
-  __syncthreads();
-  const uint32_t fl = A.tflag[first];
-  int hb[3];
-  tile_hb<K>(fl, hb);
-  R_t R;
-  gather_issue<K, NT, NV>(A, S.tab[0], fl, hb, tid, true, entA, R);
-  int par = 0;
-  for (int t = first; t < end; ++t) {
-    hydro_tile<Real, NT, NS, K, true>(A, t, S, tid, true, R, par, t + 1 < end ? t + 1 : -1);
-    par ^= 1;
-  }
-}
-
 // Persistent variant (K = 4): workgroups pop groups of tiles from 8 per-XCD
 // queues (one contiguous slice of the Hilbert-ordered tile list per XCD; a
 // workgroup whose own queue is empty takes from the next one).  Every
@@ -1158,24 +1065,13 @@ __global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
-// The queue-fed persistent kernel (persistent = 1) exists for the hydro
-// variables alone (NS = 0) on small tiles (K = 4); the pipelined tile loop
-// (persistent = 2) for one tile per workgroup, with num_cu * waves_per_cu /
-// WPT workgroups.
+// The persistent kernel exists for the hydro variables alone (NS = 0) on
+// small tiles (K = 4).
 template <typename Real, int TPW, int WPT, int NS, int K = 4>
 static int launch_hydro_t(const HydroArgs& a, const ry_tuning& t, int num_cu, hipStream_t s) {
   const int ngroups = (a.n_tile + TPW - 1) / TPW;
   if (ngroups == 0) return 0;
-  if (t.persistent == 2) {
-    if constexpr (TPW == 1 && NS == 0 && (K == 8 || WPT == 1)) {
-      int64_t grid = int64_t(num_cu) * (t.waves_per_cu > 0 ? t.waves_per_cu : 4) / WPT;
-      if (grid < 1) grid = 1;
-      if (grid > a.n_tile) grid = a.n_tile;
-      hipLaunchKernelGGL((hydro_kernel_pipe<Real, WPT, NS, K>), dim3(unsigned(grid)), dim3(64 * WPT), 0, s, a);
-    } else {
-      return -1;
-    }
-  } else if (NS > 0 || K != 4 || !t.persistent) {
+  if (NS > 0 || K != 4 || !t.persistent) {
     hipLaunchKernelGGL((hydro_kernel<Real, TPW, WPT, NS, K>), dim3(ngroups), dim3(64 * WPT * TPW), 0, s, a);
   } else if constexpr (NS == 0 && K == 4) {
     const int batch = t.batch > 0 ? t.batch : 1;

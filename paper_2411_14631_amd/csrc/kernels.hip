@@ -16,12 +16,9 @@ int hydro_max_tiles_per_wg() { return 4; }
 
 bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t) {
   if (t.tile_cells == 8)
-    return nscalar == 0 && (t.persistent == 0 || t.persistent == 2) && t.tiles_per_wg == 1 && t.waves_per_tile == 8;
+    return nscalar == 0 && !t.persistent && t.tiles_per_wg == 1 && t.waves_per_tile == 8;
   if (t.tile_cells != 4) return false;
   const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
-  // the pipelined tile loop: one one-wavefront tile per workgroup, hydro
-  // variables alone
-  if (t.persistent == 2) return nscalar == 0 && key == 11;
   if (nscalar == 0) {
     if (precision == RY_MIXED) return key == 11 || key == 21 || key == 41 || key == 12 || key == 22 || key == 14;
     return key == 11 || key == 21 || key == 41 || key == 12 || key == 22 || key == 14;
@@ -65,52 +62,6 @@ int launch_hydro(const HydroArgs& a, int precision, int nscalar, const ry_tuning
 // cell's conserved variables, written into the level's second state buffer
 // (both hydro substeps of the parent step read them there).
 // ---------------------------------------------------------------------------
-// Whether cell position p of a level (its sorted keys, refined bytes, octs
-// per axis, boundaries) is a leaf cell: positions past an outflow face and
-// positions without an oct are not.
-__device__ bool leaf_at(const GhostArgs& A, int64_t x, int64_t y, int64_t z) {
-  int64_t p[3] = {x, y, z};
-  for (int a = 0; a < 3; ++a) {
-    const int64_t n = 2 * A.noct[a];
-    if (p[a] < 0) {
-      if (A.bc[2 * a] != RY_BC_PERIODIC) return false;
-      p[a] += n;
-    } else if (p[a] >= n) {
-      if (A.bc[2 * a + 1] != RY_BC_PERIODIC) return false;
-      p[a] -= n;
-    }
-  }
-  const uint64_t k = hilbert3(A.bits, uint32_t(p[0] >> 1), uint32_t(p[1] >> 1), uint32_t(p[2] >> 1));
-  int64_t lo = 0, hi = A.n_oct;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (A.key[mid] < k) lo = mid + 1;
-    else hi = mid;
-  }
-  if (lo >= A.n_oct || A.key[lo] != k) return false;
-  const int cb = int((p[0] & 1) | ((p[1] & 1) << 1) | ((p[2] & 1) << 2));
-  return !((A.refined[lo] >> cb) & 1);
-}
-// Whether an update reads cell position p: a leaf cell one step away along
-// an axis, two steps along an axis, or one step along each of two axes.
-__device__ bool read_by_update(const GhostArgs& A, int64_t x, int64_t y, int64_t z) {
-  for (int d = 0; d < 3; ++d)
-    for (int s = -2; s <= 2; ++s) {
-      if (s == 0) continue;
-      if (leaf_at(A, x + (d == 0) * s, y + (d == 1) * s, z + (d == 2) * s)) return true;
-    }
-  for (int d = 0; d < 3; ++d)
-    for (int e = d + 1; e < 3; ++e)
-      for (int sd = -1; sd <= 1; sd += 2)
-        for (int se = -1; se <= 1; se += 2) {
-          int64_t q[3] = {x, y, z};
-          q[d] += sd;
-          q[e] += se;
-          if (leaf_at(A, q[0], q[1], q[2])) return true;
-        }
-  return false;
-}
-
 // One thread per ghost oct: its 8 cells are the children of one coarse cell
 // Q and share Q's 7 sources, loaded once (NV, the variable count, is a
 // template parameter so that all 7 x NV loads issue before the first use);
@@ -154,30 +105,82 @@ __global__ void ghost_kernel(GhostArgs A) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) d[j] = make_double2(out[2 * j], out[2 * j + 1]);
   }
-  if (A.floors) {
+  if (A.floors && A.gread) {
     // the floors the primitive conversion of each cell applies (density,
     // then pressure from E minus the kinetic energy at the floored density),
     // counted for the cells an update reads
+    const uint32_t rd = A.gread[gi];
     int n = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const double r = keep[0][c] < A.rho_floor ? A.rho_floor : keep[0][c];
       const double ke = 0.5 * (keep[1][c] * keep[1][c] + keep[2][c] * keep[2][c] + keep[3][c] * keep[3][c]) / r;
       const int f = int(keep[0][c] < A.rho_floor) + int((A.gamma - 1.0) * (keep[4][c] - ke) < A.p_floor);
-      if (f) {
-        // the ghost oct sits on the coarse cell Q it interpolates (level l-1
-        // cell coordinates = level l oct coordinates)
-        const int64_t q = A.gsrc[gi * 7] & ((int64_t(1) << 48) - 1);
-        const int64_t oq = q >> 3;
-        const int qb = int(q & 7);
-        const int64_t gx = 2 * int64_t(A.coarse_oc[3 * oq]) + (qb & 1),
-                      gy = 2 * int64_t(A.coarse_oc[3 * oq + 1]) + ((qb >> 1) & 1),
-                      gz = 2 * int64_t(A.coarse_oc[3 * oq + 2]) + (qb >> 2);
-        if (read_by_update(A, 2 * gx + (c & 1), 2 * gy + ((c >> 1) & 1), 2 * gz + (c >> 2))) n += f;
-      }
+      if ((rd >> c) & 1u) n += f;
     }
     if (n) atomicAdd(A.floors, (unsigned long long)n);
   }
+}
+
+// One thread per (tile, slot) of the small-tile tables: a slot holding a
+// ghost oct gets the bits of its cells that lie in the stencil of a leaf
+// cell of the tile's core (one or two steps along an axis, or one step along
+// each of two axes).  Every leaf cell is in exactly one tile's core, and its
+// stencil stays within that tile's oct neighbourhood, so the union over the
+// tiles is exact.  Cells past the domain's high side of a cut tile are other
+// tiles' cells and are skipped.
+__global__ void ghost_read_kernel(const int32_t* __restrict__ tab, const uint32_t* __restrict__ tflag,
+                                  const uint8_t* __restrict__ refined, int32_t n_tile, int64_t n_oct,
+                                  uint32_t* __restrict__ gread) {
+  using G = Geom<4>;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(n_tile) * G::TAB) return;
+  const int64_t tile = i / G::TAB;
+  const int slot = int(i % G::TAB);
+  const int32_t* t = tab + tile * G::TAB;
+  const int32_t e = t[slot];
+  if (e < n_oct) return;
+  const uint32_t fl = tflag[tile];
+  const int hb[3] = {3 - int((fl >> CL_CUT_SHIFT) & 7u), 3 - int((fl >> (CL_CUT_SHIFT + 3)) & 7u),
+                     3 - int((fl >> (CL_CUT_SHIFT + 6)) & 7u)};
+  const int sx = slot % G::TS - 1, sy = (slot / G::TS) % G::TS - 1, sz = slot / (G::TS * G::TS) - 1;
+  auto leaf = [&](int x, int y, int z) {
+    if (x < 0 || y < 0 || z < 0 || x > hb[0] || y > hb[1] || z > hb[2]) return false;
+    const int32_t q = t[G::slot(x >> 1, y >> 1, z >> 1)];
+    return q >= 0 && q < n_oct && !((refined[q] >> ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2))) & 1);
+  };
+  uint32_t m = 0;
+  for (int c = 0; c < 8; ++c) {
+    const int p[3] = {2 * sx + (c & 1), 2 * sy + ((c >> 1) & 1), 2 * sz + (c >> 2)};
+    bool rd = false;
+    for (int d = 0; d < 3 && !rd; ++d)
+      for (int st = -2; st <= 2 && !rd; ++st) {
+        if (st == 0) continue;
+        int q[3] = {p[0], p[1], p[2]};
+        q[d] += st;
+        rd = leaf(q[0], q[1], q[2]);
+      }
+    for (int d = 0; d < 3 && !rd; ++d)
+      for (int d2 = d + 1; d2 < 3 && !rd; ++d2)
+        for (int s1 = -1; s1 <= 1 && !rd; s1 += 2)
+          for (int s2 = -1; s2 <= 1 && !rd; s2 += 2) {
+            int q[3] = {p[0], p[1], p[2]};
+            q[d] += s1;
+            q[d2] += s2;
+            rd = leaf(q[0], q[1], q[2]);
+          }
+    if (rd) m |= 1u << c;
+  }
+  if (m) atomicOr(gread + (e - n_oct), m);
+}
+
+int launch_ghost_read(const int32_t* tab, const uint32_t* tflag, const uint8_t* refined, int32_t n_tile,
+                      int64_t n_oct, uint32_t* gread, void* stream) {
+  const int64_t n = int64_t(n_tile) * Geom<4>::TAB;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(ghost_read_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, tab,
+                     tflag, refined, n_tile, n_oct, gread);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_ghost(const GhostArgs& a, void* stream) {

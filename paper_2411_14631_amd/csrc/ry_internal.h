@@ -180,12 +180,7 @@ struct GhostArgs {
   // (a leaf cell of the level in its stencil); nullptr = off
   unsigned long long* floors;
   double gamma, rho_floor, p_floor;
-  const uint64_t* key;               // the level's sorted Hilbert keys (n_oct of them)
-  const uint8_t* refined;            // its refined-cell bytes
-  int32_t bits;                      // its Hilbert bits per axis
-  int64_t noct[3];                   // its octs per axis
-  int32_t bc[6];
-  const int32_t* coarse_oc;          // oct coordinates of level l-1 (x y z interleaved)
+  const uint32_t* gread;             // per ghost oct: bit c set when an update reads its cell c
 };
 
 // launchers (kernels.hip)
@@ -195,6 +190,11 @@ int launch_hydro_plain(const HydroArgs& a, int precision, const ry_tuning& t, in
 // whether a hydro kernel exists for this precision / scalar count / tuning
 bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t);
 int launch_ghost(const GhostArgs& a, void* stream);
+// The ghost read masks of a level from its small-tile tables: for every
+// ghost oct, bit c set when a leaf cell of a tile's core has the oct's cell
+// c in its stencil (gread zeroed before, n_ghost entries; OR-accumulated).
+int launch_ghost_read(const int32_t* tab, const uint32_t* tflag, const uint8_t* refined, int32_t n_tile,
+                      int64_t n_oct, uint32_t* gread, void* stream);
 int launch_restrict(const double* Uf, int64_t plane_f, int64_t n_fine, const int32_t* parent_cell,
                     double* Uc, int64_t plane_c, int nv, const int32_t* skip, void* stream);
 // Blocks of the CFL pass over n_oct octs (256 cells each): the number of

@@ -499,3 +499,21 @@ def test_floor_census_equals_oracle(ry, n_fine, theta):
     h, o1 = ry.Hydro(prob), Oracle(prob)
     step_both(h, o1, 1)
     assert h.floors() == o1.floors() > 0
+
+
+def test_floor_census_equals_oracle_deep_hierarchy(ry):
+    """The census on a four-level zoom mesh (32^3 base, levels 5-8), where a
+    ghost oct's covering leaf can sit two or more levels up: after 12 coarse
+    steps the GPU counts what the oracle counts, on both tile shapes, and
+    the states agree at the parity bar."""
+    prob = W.zoom(level_min=5, level_max=8)
+    o = Oracle(prob)
+    o.advance(12)
+    assert o.floors() > 0
+    for t in ([1, 0, 4, 1, 1, 4], [1, 0, 4, 1, 8, 8]):
+        g = ry.Hydro(prob)
+        g.set_tuning(*t)
+        g.advance(12)
+        assert g.floors() == o.floors(), (t, g.floors(), o.floors())
+        for lv in g.levels:
+            assert cases.rel_err(g.download(lv), o.download(lv)) <= 1e-12, (t, lv)

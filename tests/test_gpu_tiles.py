@@ -1,11 +1,10 @@
 """GPU checks of the tile shapes: the 4^3-cell tile (2x2x2 octs) and the
 8^3-cell tile (4x4x4 octs assembled from small tiles), chosen for all
-levels or level by level, with plain or pipelined launches, give
-bit-identical FP64 results (each face flux is the same expression of the
-same primitives whichever tile computes it), and match the oracle at the
-parity bar; base sides of 2 mod 4 cells (an odd number of octs per axis:
-tiles cut by the domain's high side) on both boundary rules; the batched
-boxes with such sides.
+levels or level by level, give bit-identical FP64 results (each face flux
+is the same expression of the same primitives whichever tile computes it),
+and match the oracle at the parity bar; base sides of 2 mod 4 cells (an odd
+number of octs per axis: tiles cut by the domain's high side) on both
+boundary rules; the batched boxes with such sides.
 """
 from __future__ import annotations
 
@@ -24,14 +23,6 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 SMALL = dict(tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=1, tile_cells=4)
 BIG = dict(tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=8, tile_cells=8)
-# pipelined tile loops (each workgroup a run of tiles, the next tile loaded
-# during the current one's update): full grids, and grids of few workgroups
-# (long runs of tiles per workgroup)
-PIPE8 = dict(BIG, persistent=2, waves_per_cu=16)
-PIPE4 = dict(SMALL, persistent=2, waves_per_cu=12)
-PIPE8_FEW = dict(BIG, persistent=2, waves_per_cu=1)
-PIPE4_FEW = dict(SMALL, persistent=2, waves_per_cu=1)
-PIPES = {"pipe8": PIPE8, "pipe4": PIPE4, "pipe8_few": PIPE8_FEW, "pipe4_few": PIPE4_FEW}
 
 
 @pytest.fixture(scope="module")
@@ -229,88 +220,3 @@ def test_batch_accepts_sides_2_mod_4(ry):
         assert cases.rel_err(bh.download(b), o.download(p.level_min)) <= TOL, b
         assert abs(bh.box_info(b)[1] - o.t) <= 1e-14 * o.t
 
-
-# ------------------------------------------------------ pipelined tile loops
-@pytest.mark.parametrize("name", sorted(PROBLEMS))
-@pytest.mark.parametrize("pipe", sorted(PIPES))
-def test_pipelined_bit_exact(ry, name, pipe):
-    """The pipelined loop (next tile's table, refined bytes and gather loaded
-    during the current tile's update; ghost octs read from the second state
-    buffer on both parities) gives the plain launch's states and floor
-    counts bit for bit, over several coarse steps."""
-    prob = PROBLEMS[name]()
-    t = PIPES[pipe]
-    plain = run(ry, prob, 4, tuning=BIG if t["tile_cells"] == 8 else SMALL)
-    piped = run(ry, prob, 4, tuning=t)
-    assert piped.tuning() == t
-    for a, b in zip(states(plain), states(piped)):
-        np.testing.assert_array_equal(a, b)
-    assert piped.floors() == plain.floors()
-
-
-@pytest.mark.parametrize("pipe", ["pipe8", "pipe4"])
-def test_pipelined_mixed_and_outflow_cut(ry, pipe):
-    """Mixed form, and outflow boxes with sides of 2 mod 4 cells (tiles cut by
-    the high side, clamped gathers), pipelined against plain."""
-    t = PIPES[pipe]
-    ref_t = BIG if t["tile_cells"] == 8 else SMALL
-    for prob, prec in ((cases.amr_blob(), "mixed"), (outflow(W.random_smooth(30, seed=3, mach=1.2)), "fp64"),
-                       (outflow(W.twolevel(36, 0.5)), "fp64")):
-        a = run(ry, prob, 3, prec, tuning=ref_t)
-        b = run(ry, prob, 3, prec, tuning=t)
-        for x, y in zip(states(a), states(b)):
-            np.testing.assert_array_equal(x, y)
-
-
-def test_pipelined_per_level_and_regrid(ry):
-    """Pipelined and plain launches mixed over the levels, graph and
-    host-driven paths, and a regrid between runs."""
-    prob = cases.amr_blob(level_min=3, level_max=5)
-    ref = run(ry, prob, 3)
-    for per in ({3: PIPE8, 4: PIPE4, 5: PIPE4}, {3: PIPE4, 4: BIG, 5: PIPE8}, {4: PIPE8_FEW, 5: PIPE4_FEW}):
-        h = run(ry, prob, 3, per_level=per)
-        for a, b in zip(states(ref), states(h)):
-            np.testing.assert_array_equal(a, b)
-    g = ry.Hydro(prob)
-    g.set_tuning(**PIPE4)
-    for _ in range(3):
-        g.coarse_step(g.cfl_dt())
-    for a, b in zip(states(ref), states(g)):
-        np.testing.assert_array_equal(a, b)
-    ref.regrid()
-    g2 = run(ry, prob, 3, tuning=PIPE8)
-    g2.regrid()
-    ref.advance(2)
-    g2.advance(2)
-    for a, b in zip(states(ref), states(g2)):
-        np.testing.assert_array_equal(a, b)
-
-
-@pytest.mark.parametrize("pipe", ["pipe8", "pipe4", "pipe8_few"])
-def test_batch_pipelined_bit_exact(ry, pipe):
-    """Batched boxes (per-box time steps from the tiles' CFL partials) on the
-    pipelined loop: the plain launch's states and times."""
-    boxes = [W.batch_box(40, 24, 1.0, 1.5), W.batch_box(41, 18, 0.7, 0.8), W.batch_box(42, 32, 1.2, 2.0),
-             W.batch_box(43, 10, 0.5, 1.0), W.batch_box(44, 16, 1.0, 1.0)]
-    out = []
-    for t in (SMALL, PIPES[pipe]):
-        bh = ry.BatchHydro(boxes)
-        bh.set_tuning(**t)
-        bh.run(4)
-        out.append(([bh.download(b) for b in range(len(boxes))], [bh.box_info(b)[1] for b in range(len(boxes))]))
-        bh.close()
-    assert out[0][1] == out[1][1]
-    for a, b in zip(out[0][0], out[1][0]):
-        np.testing.assert_array_equal(a, b)
-
-
-def test_pipelined_rejected_where_unsupported(ry):
-    h = ry.Hydro(cases.amr_blob())
-    for bad in (dict(PIPE4, waves_per_tile=2), dict(PIPE4, tiles_per_wg=2), dict(BIG, persistent=3)):
-        with pytest.raises(ry.RyError) as e:
-            h.set_tuning(**bad)
-        assert e.value.code == ry.RY_EINVAL
-    g = ry.Hydro(cases.with_scalars(cases.amr_blob(), 1))
-    with pytest.raises(ry.RyError) as e:
-        g.set_tuning(**PIPE4)
-    assert e.value.code == ry.RY_EINVAL
