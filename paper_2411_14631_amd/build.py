@@ -1,4 +1,6 @@
-"""Build the HIP library (gfx950) in-tree: paper_2411_14631_amd/libry.so.
+"""Build the HIP library (gfx950) in-tree: paper_2411_14631_amd/libry.so, and
+its debug build libry_debug.so (-DRY_DEBUG: device index bounds checks that
+latch an error instead of accessing out of bounds).
 
 All sources go through hipcc.  Host code is compiled without floating-point
 contraction (the refinement map must be a pure function of the input
@@ -11,6 +13,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libry.so")
+LIB_DEBUG = os.path.join(HERE, "libry_debug.so")
 SOURCES = ["mesh.cpp", "api.cpp", "kernels.hip", "hydro.hip", "poisson.hip", "regrid.hip", "noalloc.hip"]
 # per-source options: the hydro-only tile kernels schedule for instruction-
 # level parallelism (their occupancy is bounded by LDS, not registers)
@@ -35,9 +38,12 @@ def _run(cmd):
         print(out)
 
 
-def build(verbose: bool = False, extra=None, jobs: int = 0) -> str:
+def build(verbose: bool = False, extra=None, jobs: int = 0, debug: bool = False) -> str:
     from concurrent.futures import ThreadPoolExecutor
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build_debug" if debug else "_build")
+    lib = LIB_DEBUG if debug else LIB
+    if debug:
+        extra = list(extra or []) + ["-DRY_DEBUG"]
     os.makedirs(bdir, exist_ok=True)
     cmds, objs = [], []
     for s in SOURCES:
@@ -54,13 +60,14 @@ def build(verbose: bool = False, extra=None, jobs: int = 0) -> str:
     n = jobs or min(len(cmds), os.cpu_count() or 1, 8)
     with ThreadPoolExecutor(max_workers=max(n, 1)) as ex:
         list(ex.map(_run, cmds))
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     _run(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build(verbose=True, debug=True))

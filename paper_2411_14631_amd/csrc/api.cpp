@@ -388,6 +388,7 @@ ry_status enqueue_ghost(ry_ctx* c, int l, const int32_t* skip) {
   g.rho_floor = c->cfg.rho_floor;
   g.p_floor = c->cfg.p_floor;
   g.gread = L.gread;
+  g.err = err_ptr(c);
   TimedLaunch tl;
   if (c->timing) time_begin(c, "ghost", tl);
   if (launch_ghost(g, c->stream)) return fail(c, RY_EHIP, "ghost kernel");
@@ -402,6 +403,7 @@ HydroArgs hydro_args(ry_ctx* c, int l, int substep) {
   a.Un = L.U[L.cur ^ 1];
   a.plane = L.plane();
   a.n_oct = int32_t(L.n_oct);
+  a.n_ext = int32_t(L.n_ext);
   a.ghost_adj = (L.n_ghost > 0 && L.cur == 0) ? int32_t(int64_t(c->dom.nv) * L.n_ext) : 0;
   a.n_tile = L.n_tile;
   a.tab = L.tab;
@@ -586,7 +588,7 @@ ry_status enqueue_restrict(ry_ctx* c, int l, const int32_t* skip) {
   DevLevel& L = c->lev[l - c->cfg.level_min];
   DevLevel& F = c->lev[l + 1 - c->cfg.level_min];
   if (launch_restrict(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur ^ 1], L.plane(), c->dom.nv, skip,
-                      c->stream))
+                      err_ptr(c), c->stream))
     return fail(c, RY_EHIP, "restrict kernel");
   return RY_OK;
 }
@@ -635,6 +637,7 @@ ry_status sync_and_check(ry_ctx* c) {
   if (c->timing) time_collect(c);
   int32_t e = 0;
   HIPCHK(c, hipMemcpy(&e, err_ptr(c), sizeof e, hipMemcpyDeviceToHost));
+  if (e & ERR_BOUNDS) return fail(c, RY_EHIP, "device index outside its buffer (debug build bounds check)");
   if (e) return fail(c, RY_ENUMERIC, "non-finite or non-positive density/energy latched on the device");
   return RY_OK;
 }
@@ -955,7 +958,7 @@ ry_status finish_regrid(ry_ctx* c) {
     DevLevel& F = c->lev[k + 1];
     if (F.n_oct == 0) continue;
     if (launch_restrict(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur], L.plane(), nv, nullptr,
-                        c->stream))
+                        err_ptr(c), c->stream))
       return fail(c, RY_EHIP, "restrict kernel");
   }
   drop_graphs(c);

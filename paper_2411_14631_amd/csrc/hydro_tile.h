@@ -528,7 +528,9 @@ __device__ __forceinline__ void gather_issue(const HydroArgs& A, const int32_t* 
         slot = G::slot(sx >> 1, sy >> 1, sz >> 1);
         cb = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
       }
-      const int32_t e = tab[slot];
+      int32_t e = tab[slot];
+      if (!debug_in_bounds(e < A.n_oct || (e >= A.n_oct + A.ghost_adj && e < A.n_ext + A.ghost_adj), A.err))
+        e = -1;
       R.iwa[rnd] = int(ent & EA((1u << G::A_LB) - 1));
       // 32-bit cell index (a level's octs, ghost octs and the ghost shift
       // stay below 2^29 octs).  A slot without an oct is one no leaf update
@@ -613,6 +615,7 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   int32_t e_tab = -1;
   if (active && tid < TAB) {
     e_tab = A.tab[size_t(tile) * TAB + tid];
+    if (!debug_in_bounds(e_tab >= -1 && e_tab < A.n_ext, A.err)) e_tab = -1;
     S.tab[tid] = lds_tab_entry(A, e_tab);
   }
   __syncthreads();

@@ -80,13 +80,15 @@ __global__ void ghost_kernel(GhostArgs A) {
     cell[k] = src & ((int64_t(1) << 48) - 1);
     base[k] = A.src[up];
     pl[k] = A.src_plane[up];
+    if (!debug_in_bounds(up < RY_MAX_LEVELS && cell[k] >= 0 && cell[k] < pl[k], A.err)) cell[k] = 0;
   }
   double val[NV][7];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int k = 0; k < 7; ++k) val[v][k] = base[k][v * pl[k] + cell[k]];
-  const int64_t dst = (A.n_oct + gi) * 8;
+  int64_t dst = (A.n_oct + gi) * 8;
+  if (!debug_in_bounds(dst + 8 <= A.plane, A.err)) return;
   double keep[NVAR][8];   // the hydro variables of the 8 cells, for the floor census
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -203,7 +205,7 @@ int launch_ghost(const GhostArgs& a, void* stream) {
 // ---------------------------------------------------------------------------
 __global__ void restrict_kernel(const double* __restrict__ Uf, int64_t pf, int64_t nf,
                                 const int32_t* __restrict__ parent, double* __restrict__ Uc, int64_t pc, int nv,
-                                const int32_t* skip) {
+                                const int32_t* skip, int32_t* err) {
   if (skip && *skip) return;
   // variable-major: consecutive threads read consecutive octs of one plane
   // (64 contiguous bytes each, as four 16-byte loads)
@@ -213,15 +215,17 @@ __global__ void restrict_kernel(const double* __restrict__ Uf, int64_t pf, int64
   const int64_t k = i - int64_t(v) * nf;
   const double2* s = reinterpret_cast<const double2*>(Uf + v * pf + 8 * k);
   const double2 a = s[0], b = s[1], c = s[2], d = s[3];
-  Uc[v * pc + parent[k]] = 0.125 * (((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y)));
+  const int32_t q = parent[k];
+  if (!debug_in_bounds(q >= 0 && q < pc, err)) return;
+  Uc[v * pc + q] = 0.125 * (((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y)));
 }
 
 int launch_restrict(const double* Uf, int64_t pf, int64_t nf, const int32_t* parent, double* Uc, int64_t pc,
-                    int nv, const int32_t* skip, void* stream) {
+                    int nv, const int32_t* skip, int32_t* err, void* stream) {
   if (nf == 0) return 0;
   const int64_t n = nf * nv;
   hipLaunchKernelGGL(restrict_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, Uf, pf,
-                     nf, parent, Uc, pc, nv, skip);
+                     nf, parent, Uc, pc, nv, skip, err);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

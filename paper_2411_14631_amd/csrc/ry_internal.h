@@ -135,6 +135,7 @@ struct HydroArgs {
   double* Un;                 // next state
   int64_t plane;              // 8 * n_ext
   int32_t n_oct;              // real octs: ext index < n_oct
+  int32_t n_ext;              // octs + ghost octs (debug bounds checks)
   // ghost octs live only in the level's second state buffer, which follows
   // the first one in memory (nv planes later): reading through the first,
   // a ghost oct's index is shifted by ghost_adj = nv * n_ext octs; 0 when
@@ -181,6 +182,7 @@ struct GhostArgs {
   unsigned long long* floors;
   double gamma, rho_floor, p_floor;
   const uint32_t* gread;             // per ghost oct: bit c set when an update reads its cell c
+  int32_t* err;                      // error word (debug bounds checks)
 };
 
 // launchers (kernels.hip)
@@ -196,10 +198,30 @@ int launch_ghost(const GhostArgs& a, void* stream);
 int launch_ghost_read(const int32_t* tab, const uint32_t* tflag, const uint8_t* refined, int32_t n_tile,
                       int64_t n_oct, uint32_t* gread, void* stream);
 int launch_restrict(const double* Uf, int64_t plane_f, int64_t n_fine, const int32_t* parent_cell,
-                    double* Uc, int64_t plane_c, int nv, const int32_t* skip, void* stream);
+                    double* Uc, int64_t plane_c, int nv, const int32_t* skip, int32_t* err, void* stream);
 // Blocks of the CFL pass over n_oct octs (256 cells each): the number of
 // partial maxima it writes.
 inline int64_t cfl_blocks(int64_t n_oct) { return (8 * n_oct + 255) / 256; }
+
+// Device index checks of a debug build (compiled with -DRY_DEBUG): an index
+// outside its buffer sets bit ERR_BOUNDS of the error word, and the caller
+// redirects the access to index 0 instead of making it; the next syncing
+// call reports it.  A release build compiles the checks away.
+constexpr int32_t ERR_NUMERIC = 1, ERR_BOUNDS = 2;
+#ifdef RY_DEBUG
+constexpr bool kDebugChecks = true;
+#else
+constexpr bool kDebugChecks = false;
+#endif
+__device__ __forceinline__ bool debug_in_bounds(bool ok, int32_t* err) {
+  if constexpr (kDebugChecks) {
+    if (!ok) {
+      if (err) atomicOr(err, ERR_BOUNDS);
+      return false;
+    }
+  }
+  return true;
+}
 // The hydro kernel indexes a level's cells in 32 bits: its octs and ghost
 // octs (8 cells each) and, on a level with ghost octs, the shift by
 // nv * (octs + ghost octs) octs that reads a ghost oct from the second state

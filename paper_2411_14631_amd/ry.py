@@ -9,13 +9,16 @@ to another implementation.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import math
 import os
 
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libry.so")
+# RY_DEBUG_LIB=1 loads the debug build (device index bounds checks that latch
+# an error instead of accessing out of bounds; slower)
+LIB_PATH = os.path.join(HERE, "libry_debug.so" if os.environ.get("RY_DEBUG_LIB") == "1" else "libry.so")
 
 RY_OK, RY_EINVAL, RY_ENOMEM, RY_EHIP, RY_ESTATE, RY_ENUMERIC = 0, -1, -2, -3, -4, -5
 RY_FP64, RY_MIXED = 0, 1
@@ -193,6 +196,14 @@ def _config(prob, precision, stream_handle, mem):
     return cfg
 
 
+def _read_json(path):
+    """The tuning cache (an empty one when the file does not exist yet)."""
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
 class _Base:
     def _check(self, rc, what):
         if rc != RY_OK:
@@ -230,12 +241,47 @@ class _Base:
         self._check(lib().ry_get_level_tuning(self.ctx, level, C.byref(t)), "ry_get_level_tuning")
         return t.as_dict()
 
-    def autotune(self):
+    def autotune(self, cache=None):
+        """Time the launch candidates and keep the fastest per level
+        (ry_autotune): (level-0 tuning, per-candidate times).  With `cache`,
+        a JSON file: a result stored there for the same workload (its mesh),
+        precision and GPU architecture is applied without timing (times are
+        then empty); a new result is added to the file."""
+        key = self._tune_key() if cache else None
+        if key:
+            stored = _read_json(cache).get(key)
+            if stored:
+                for lv, t in zip(self._tune_levels(), stored):
+                    self._apply_level_tuning(lv, t)
+                return self._first_tuning(), []
         best = RyTuning()
         times = (C.c_double * 64)()
         n = C.c_int32()
         self._check(lib().ry_autotune(self.ctx, C.byref(best), times, 64, C.byref(n)), "ry_autotune")
+        if key:
+            d = _read_json(cache)
+            d[key] = [self._level_tuning_of(lv) for lv in self._tune_levels()]
+            tmp = f"{cache}.{os.getpid()}.tmp"
+            with open(tmp, "w") as f:
+                json.dump(d, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
         return best.as_dict(), list(times[: n.value])
+
+    def _arch(self):
+        return self.torch.cuda.get_device_properties(self.torch.cuda.current_device()).gcnArchName
+
+    # the tuned levels and their tunings (a batch context has one)
+    def _tune_levels(self):
+        return [None]
+
+    def _level_tuning_of(self, lv):
+        return self.tuning()
+
+    def _apply_level_tuning(self, lv, t):
+        self.set_tuning(**t)
+
+    def _first_tuning(self):
+        return self.tuning()
 
     def set_timing(self, on=True):
         self._check(lib().ry_set_timing(self.ctx, 1 if on else 0), "ry_set_timing")
@@ -280,6 +326,23 @@ class Hydro(_Base):
     @property
     def levels(self):
         return range(self.prob.level_min, self.prob.level_max + 1)
+
+    def _tune_key(self):
+        mesh = [self.level_info(lv) for lv in self.levels]
+        prec = "mixed" if self._cfg.precision == RY_MIXED else "fp64"
+        return f"{self.prob.name}|{mesh}|{prec}|{self._arch()}"
+
+    def _tune_levels(self):
+        return list(self.levels)
+
+    def _level_tuning_of(self, lv):
+        return self.level_tuning(lv)
+
+    def _apply_level_tuning(self, lv, t):
+        self.set_level_tuning(lv, **t)
+
+    def _first_tuning(self):
+        return self.level_tuning(self.prob.level_min)
 
     def level_info(self, level):
         n, leaf = C.c_int64(), C.c_int64()
@@ -352,6 +415,7 @@ class BatchHydro(_Base):
         import torch
         self.torch = torch
         self.probs = probs
+        self._precision = precision
         self.ctx = C.c_void_p()
         self.stream = torch.cuda.Stream(device=device)
         self.mem = _TorchMemory(torch, device) if torch_memory else None
@@ -364,6 +428,11 @@ class BatchHydro(_Base):
 
     def run(self, nsteps):
         self._check(lib().ry_batch_run(self.ctx, nsteps), "ry_batch_run")
+
+    def _tune_key(self):
+        import hashlib
+        names = hashlib.sha256("|".join(p.name for p in self.probs).encode()).hexdigest()[:16]
+        return f"batch{len(self.probs)}:{names}|{self._precision}|{self._arch()}"
 
     def box_info(self, b):
         n, t = C.c_int64(), C.c_double()

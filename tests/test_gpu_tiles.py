@@ -141,6 +141,32 @@ def test_autotune_per_level_keeps_results(ry):
         np.testing.assert_array_equal(x, y)
 
 
+def test_autotune_cache(ry, tmp_path):
+    """A tuning stored in the cache file for a workload, precision and GPU
+    architecture is applied without timing; other keys time and add theirs."""
+    import json
+    path = str(tmp_path / "tune.json")
+    prob = cases.amr_blob()
+    a = ry.Hydro(prob)
+    best, times = a.autotune(cache=path)
+    assert times
+    chosen = [a.level_tuning(lv) for lv in a.levels]
+    b = ry.Hydro(prob)
+    best_b, times_b = b.autotune(cache=path)
+    assert times_b == [] and best_b == best
+    assert [b.level_tuning(lv) for lv in b.levels] == chosen
+    m = ry.Hydro(prob, "mixed")
+    assert m.autotune(cache=path)[1]
+    boxes = [W.batch_box(60, 16, 1.0, 1.5), W.batch_box(61, 24, 0.7, 0.8)]
+    b1 = ry.BatchHydro(boxes)
+    assert b1.autotune(cache=path)[1]
+    b2 = ry.BatchHydro(boxes)
+    assert b2.autotune(cache=path)[1] == [] and b2.tuning() == b1.tuning()
+    assert len(json.load(open(path))) == 3
+    for h in (b1, b2):
+        h.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_big_tile_bit_exact(ry, prec):
     """Batched boxes on 8^3-cell tiles (sides of 8 mod 16 and 2 mod 4 give
