@@ -129,7 +129,7 @@ def level_tunings(h):
 
 def tuning_label(t):
     if t["tile_cells"] == 8:
-        return "8^3-cell tile (4x4x4 octs), 512 threads"
+        return f"8^3-cell tile (4x4x4 octs), {64 * t['waves_per_tile']} threads"
     return (f"4^3-cell tile (2x2x2 octs), {64 * t['waves_per_tile']} threads per tile, "
             f"{t['tiles_per_wg']} tile(s) per workgroup" + (", queue-fed" if t["persistent"] else ""))
 

@@ -168,7 +168,8 @@ typedef struct {
   int32_t waves_per_tile; /* tile_cells 4: 1, 2 or 4 wavefronts per tile (8, 16, 32 threads */
                           /* per oct), tiles_per_wg * waves_per_tile <= 4; with passive     */
                           /* scalars only {1,0,*,*,1}, {1,0,*,*,2} and {2,0,*,*,1};         */
-                          /* tile_cells 8: 8 (one thread per cell) (else RY_EINVAL)         */
+                          /* tile_cells 8: 8 (one thread per cell) or 4 (two cells per      */
+                          /* thread) (else RY_EINVAL)                                        */
   int32_t tile_cells;     /* tile edge in cells: 4 (a 2x2x2-oct tile, 64 cells) or 8 (a     */
                           /* 4x4x4-oct tile, 512 cells: fewer halo cells converted,          */
                           /* predicted and solved per cell; hydro variables alone)           */

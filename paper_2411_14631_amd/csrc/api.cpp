@@ -1707,8 +1707,8 @@ bool same_tuning(const ry_tuning& a, const ry_tuning& b) {
 ry_status check_tuning(ry_ctx* c, const ry_tuning& t) {
   if (t.persistent < 0 || t.persistent > 1) return fail(c, RY_EINVAL, "persistent must be 0 or 1");
   if (t.tile_cells == 8) {
-    if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent)
-      return fail(c, RY_EINVAL, "tile_cells 8 needs tiles_per_wg 1, waves_per_tile 8, persistent 0");
+    if (t.tiles_per_wg != 1 || (t.waves_per_tile != 8 && t.waves_per_tile != 4) || t.persistent)
+      return fail(c, RY_EINVAL, "tile_cells 8 needs tiles_per_wg 1, waves_per_tile 8 or 4, persistent 0");
   } else if (t.tile_cells == 4) {
     if (t.tiles_per_wg != 1 && t.tiles_per_wg != 2 && t.tiles_per_wg != 4) return fail(c, RY_EINVAL, "tiles_per_wg");
     if (t.waves_per_tile != 1 && t.waves_per_tile != 2 && t.waves_per_tile != 4)
@@ -1823,6 +1823,7 @@ ry_status ry_autotune(ry_ctx* c, ry_tuning* best, double* times_ms, int32_t max_
     for (int w : {8, 14, 20})
       for (int bt : {1, 4}) cand.push_back({1, 1, w, bt, wpt, 4});
   cand.push_back({1, 0, 4, 1, 8, 8});
+  cand.push_back({1, 0, 4, 1, 4, 8});
   {
     std::string keep = c->err;
     cand.erase(std::remove_if(cand.begin(), cand.end(), [&](const ry_tuning& t) { return check_tuning(c, t) != RY_OK; }),

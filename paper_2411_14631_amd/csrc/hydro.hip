@@ -12,9 +12,14 @@ namespace ry {
 int launch_hydro_plain(const HydroArgs& a, int precision, const ry_tuning& t, int num_cu, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (t.tile_cells == 8) {
-    if (t.tiles_per_wg != 1 || t.waves_per_tile != 8 || t.persistent) return -1;
-    return precision == RY_MIXED ? launch_hydro_t<float, 1, 8, 0, 8>(a, t, num_cu, s)
-                                 : launch_hydro_t<double, 1, 8, 0, 8>(a, t, num_cu, s);
+    if (t.tiles_per_wg != 1 || t.persistent) return -1;
+    if (t.waves_per_tile == 8)
+      return precision == RY_MIXED ? launch_hydro_t<float, 1, 8, 0, 8>(a, t, num_cu, s)
+                                   : launch_hydro_t<double, 1, 8, 0, 8>(a, t, num_cu, s);
+    if (t.waves_per_tile == 4)
+      return precision == RY_MIXED ? launch_hydro_t<float, 1, 4, 0, 8>(a, t, num_cu, s)
+                                   : launch_hydro_t<double, 1, 4, 0, 8>(a, t, num_cu, s);
+    return -1;
   }
   const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
   if (precision == RY_MIXED) {

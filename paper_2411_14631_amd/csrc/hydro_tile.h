@@ -52,15 +52,24 @@ template <int K>
 struct Geom {
   static_assert(K == 4 || K == 8, "tile edge of 4 or 8 cells");
   static constexpr int LK = (K == 4) ? 2 : 3;            // log2 K
-  // box rows and planes, each padded past its K + 2 entries (LDS bank spread)
-  static constexpr int PAD_ROW = 0, PAD_PLANE = 0;
+  // box rows and planes, padded past their K + 2 entries to spread the
+  // 8^3-cell tile's LDS accesses over the banks: a 64-bit access serves 16
+  // lanes per pass, and 16 consecutive threads hold a 4x2x2-cell block
+  // (oct-major order); with a row stride of 12 and a plane stride of 120 the
+  // 16 cells of such a block, and of each of its shifts by one cell, fall on
+  // 16 distinct bank pairs
+  static constexpr int PAD_ROW = (K == 8) ? 2 : 0, PAD_PLANE = 0;
   static constexpr int WB = K + 2 + PAD_ROW, WBB = WB * (K + 2) + PAD_PLANE, NBOX = WBB * (K + 2);
   static constexpr int WSIZE = NBOX + 6 * K * K;         // primitives per variable
   static constexpr int NPOS_A = K * K * K + 12 * K * K + 12 * K;   // positions whose primitives are needed
   static constexpr int NPOS_B = K * K * K + 6 * K * K;   // positions that get a predicted state
   static constexpr int NCORE = K * K * K;                // A and B positions 0..NCORE-1: the core cells
   static constexpr int NUPPER = 3 * K * K;               // then the upper one-layer cells, then the lower ones
-  static constexpr int NFACE = 3 * (K + 1) * K * K;      // 3 directions x (K+1) planes x K^2
+  // faces: 3 directions x (K+1) planes x K^2 (K = 4); K = 8 pads each
+  // direction's array for the same bank spread (layouts in fidx)
+  static constexpr int FD0 = (K == 8) ? 66 * (K + 1) : (K + 1) * K * K;
+  static constexpr int FD1 = (K == 8) ? 68 * (K + 1) : (K + 1) * K * K;
+  static constexpr int NFACE = (K == 8) ? FD0 + 2 * FD1 : 3 * (K + 1) * K * K;
   static constexpr int KO = K / 2;                       // octs per tile edge
   static constexpr int TS = KO + 2;                      // oct neighbourhood edge (one oct of halo)
   static constexpr int TAB = TS * TS * TS;               // oct neighbourhood entries per tile
@@ -89,9 +98,14 @@ struct Geom {
                                : NBOX + 5 * K * K + x + K * y);
   }
   // Face index of the face along d whose upper cell is (x, y, z) (the plane
-  // coordinate runs 0..K, the transverse ones 0..K-1); x runs fastest in
-  // every direction so that neighbouring lanes touch neighbouring LDS words.
+  // coordinate runs 0..K, the transverse ones 0..K-1).  K = 4: x runs
+  // fastest in every direction.  K = 8: the index of a 4x2x2-cell block's
+  // faces (16 consecutive threads) covers 16 distinct residues mod 16 in
+  // every direction -- y + 8 z + 66 x along x, x + 8 z + 68 y along y,
+  // x + 8 y + 68 z along z -- so a 64-bit access meets no bank conflict.
   __host__ __device__ static constexpr int fidx(int d, int x, int y, int z) {
+    if constexpr (K == 8)
+      return d == 0 ? y + 8 * z + 66 * x : (d == 1 ? FD0 + x + 8 * z + 68 * y : FD0 + FD1 + x + 8 * y + 68 * z);
     return d == 0 ? x + (K + 1) * y + (K + 1) * K * z
                   : (d == 1 ? (K + 1) * K * K + x + K * y + K * (K + 1) * z
                             : 2 * (K + 1) * K * K + x + K * y + K * K * z);
@@ -214,6 +228,11 @@ struct TileLDS {
   // current state buffer needs) and the refined-cell bytes of those octs
   int32_t tab[G::TAB];
   uint8_t ref[G::TAB];
+  // the threads' signal speeds (tiles of several wavefronts: one wavefront
+  // reduces them after the tile's last barrier), in the upper one-layer
+  // states' part of buf (unused after phase C) when it holds them
+  static constexpr bool SMAX_IN_BUF = (K == 8) && sizeof(Real) * NV * G::NUPPER >= sizeof(double) * G::NCORE;
+  double smx[(K == 8 && !SMAX_IN_BUF) ? G::NCORE : 1];
 };
 
 // ---------------------------------------------------------------------------
@@ -256,12 +275,13 @@ __device__ __forceinline__ float sound_speed(float gp, float rho) { return gp * 
 // activations.  Passive scalars: s = (rho s) / rho.
 template <int NS>
 __device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NVAR + NS], double g, double rf,
-                                          double pf, int& nfl) {
+                                          double pf, int& nfl, double* ir_out = nullptr) {
   // floors as max(): a non-finite state never gets here unnoticed (the CFL
   // pass flags it on upload, the update flags it where it is produced)
   const bool lo_r = U[0] < rf;
   const double rho = fmax(U[0], rf);
   const double ir = rcp(rho);
+  if (ir_out) *ir_out = ir;
   const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir;
   const double p0 = (g - 1.0) * (U[4] - ke);
   const bool lo_p = p0 < pf;
@@ -346,12 +366,11 @@ __device__ __forceinline__ void hllc_n(Real rl, Real ul, Real al, Real bl, Real 
 }
 
 // Unsplit half-step predictor of the primitives W0 with undivided slopes
-// D[axis][var] and h = lambda / 2.
+// D[axis][var] and h = lambda / 2; ir = 1 / W0[0].
 template <typename Real, int NS>
 __device__ __forceinline__ void predict(const Real W0[NVAR + NS], const Real D[3][NVAR + NS], Real h, Real g,
-                                        Real P[NVAR + NS]) {
+                                        Real P[NVAR + NS], Real ir) {
   const Real r = W0[0], u = W0[1], vv = W0[2], w = W0[3], p = W0[4];
-  const Real ir = rcp(r);
   P[0] = r - h * (u * D[0][0] + r * D[0][1] + vv * D[1][0] + r * D[1][2] + w * D[2][0] + r * D[2][3]);
   P[1] = u - h * (u * D[0][1] + vv * D[1][1] + w * D[2][1] + D[0][4] * ir);
   P[2] = vv - h * (u * D[0][2] + vv * D[1][2] + w * D[2][2] + D[1][4] * ir);
@@ -486,6 +505,26 @@ __device__ __forceinline__ void tile_hb(uint32_t fl, int hb[3]) {
   hb[2] = K - 1 - int((fl >> (CL_CUT_SHIFT + 6)) & 7u);
 }
 
+// A state plane as a raw buffer resource (base in scalar registers, no
+// range limit: the callers keep every byte offset below 4 GiB), so that a
+// per-lane 32-bit byte offset addresses it with no 64-bit address
+// arithmetic per lane.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), short(0), int(0xffffffffu), 0x00020000);
+}
+__device__ __forceinline__ double plane_load(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+}
+__device__ __forceinline__ void plane_store(__amdgpu_buffer_rsrc_t r, uint32_t boff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                        r, boff, 0, 0);
+}
+// Whether every byte offset into a level's state planes that the tile code
+// forms fits 32 bits (planes and the ghost shift under 2^29 cells).
+__device__ __forceinline__ bool level_off32(const HydroArgs& A) {
+  return A.plane + 8 * int64_t(A.ghost_adj) <= (int64_t(1) << 29);
+}
+
 // Phase A's loads: the conserved state at the thread's gather positions of
 // a tile whose oct table is in LDS (`tab`), issued without waiting for them.
 template <int K, int NT, int NV>
@@ -507,7 +546,10 @@ __device__ __forceinline__ void gather_issue(const HydroArgs& A, const int32_t* 
     asm volatile("" : "+s"(off));
     Up[v] = A.U + off;
   }
-  const bool off32 = P + 8 * int64_t(A.ghost_adj) <= (int64_t(1) << 29);
+  const bool off32 = level_off32(A);
+  __amdgpu_buffer_rsrc_t Ur[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Ur[v] = plane_rsrc(Up[v]);
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     const int i = tid + NT * rnd;
@@ -539,11 +581,9 @@ __device__ __forceinline__ void gather_issue(const HydroArgs& A, const int32_t* 
       const uint32_t cell = (e >= 0) ? uint32_t(e) * 8u + uint32_t(cb) : 0u;
       if (off32) {
         // planes under 4 GiB: one 32-bit byte offset serves every plane
-        // (base in scalar registers + unsigned 32-bit lane offset)
         const uint32_t boff = cell << 3;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-          R.Ua[rnd][v] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(Up[v]) + boff);
+        for (int v = 0; v < NV; ++v) R.Ua[rnd][v] = plane_load(Ur[v], boff);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) R.Ua[rnd][v] = Up[v][cell];
@@ -568,7 +608,10 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   constexpr int NV = NVAR + NS;
   constexpr int WSIZE = G::WSIZE, NFACE = G::NFACE, NUPPER = G::NUPPER, NCORE = G::NCORE;
   constexpr int NPOS_A = G::NPOS_A, NPOS_B = G::NPOS_B, TAB = G::TAB;
-  static_assert(NT >= TAB && (K == 4 || NT == NCORE), "threads per tile");
+  static_assert(NT >= TAB && (K == 4 || NT == NCORE || 2 * NT == NCORE), "threads per tile");
+  // core cells per thread: one (NT >= NCORE; threads past NCORE hold none),
+  // or two (8^3-cell tile on 256 threads: cells tid and tid + 256)
+  constexpr int NCR = (NT >= NCORE) ? 1 : NCORE / NT;
   const int tid = opaque(tid_in);
   const int lane = tid & 63;
   const double g = A.gamma, rf = A.rho_floor, pf = A.p_floor;
@@ -594,9 +637,10 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   // most 2: density and pressure): the conversions of its phase-A positions,
   // its phase-B one-layer face states, its core cell's 3 left and 3 right
   // face states; which of them the tile counts is decided at the end
-  constexpr int SITE_A = 0, SITE_B = NRA, SITE_L = NRA + NRB, SITE_R = SITE_L + 3;
-  static_assert(2 * (SITE_R + 3) <= 32, "floor sites");
-  int pending = 0;
+  constexpr int SITE_A = 0, SITE_B = NRA, SITE_L = NRA + NRB, SITE_R = SITE_L + 3 * NCR;
+  static_assert(2 * (SITE_R + 3 * NCR) <= 64, "floor sites");
+  using Pend = std::conditional_t<(2 * (SITE_R + 3 * NCR) <= 32), uint32_t, uint64_t>;
+  Pend pending = 0;
   EB entB[NRB];
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
@@ -637,18 +681,23 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   // conserved state stays in registers for the update (phase D), except in
   // the FP64 8^3-cell tile, whose register budget (4 wavefronts per SIMD)
   // it would overrun: there phase D loads it again.
-  constexpr bool KEEP_CORE = (K == 4) || (sizeof(Real) == 4);
+  constexpr bool KEEP_CORE = (K == 4) || (sizeof(Real) == 4) || (NCR > 1);
   Real* W = S.buf;                              // [NV][WSIZE]
-  double Ucore[NV];
+  double Ucore[NCR][NV];
+  // 1 / rho of the thread's core cells, from their conversion (the FP64
+  // predictor divides by the same density)
+  double irc[NCR];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Ucore[v] = KEEP_CORE ? R.Ua[0][v] : 0.0;
+  for (int r = 0; r < NCR; ++r)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ucore[r][v] = KEEP_CORE ? R.Ua[r][v] : 0.0;
 #pragma unroll
   for (int rnd = 0; rnd < NRA; ++rnd) {
     if (R.iwa[rnd] >= 0) {
       double Wc[NV];
       int nc = 0;
-      cons2prim<NS>(R.Ua[rnd], Wc, g, rf, pf, nc);
-      pending |= nc << (2 * (SITE_A + rnd));
+      cons2prim<NS>(R.Ua[rnd], Wc, g, rf, pf, nc, rnd < NCR ? &irc[rnd < NCR ? rnd : 0] : nullptr);
+      pending |= Pend(nc) << (2 * (SITE_A + rnd));
 #pragma unroll
       for (int v = 0; v < NV; ++v) W[v * WSIZE + R.iwa[rnd]] = Real(Wc[v]);
     }
@@ -660,12 +709,18 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   // tid < NCORE) keeps W~ and its slopes in registers for its six faces; a
   // one-layer cell keeps only its state on the face toward the core.
   constexpr int st[3] = {1, G::WB, G::WBB};
-  const bool core = (NT == NCORE) || tid < NCORE;
-  const int ct = tid & (NCORE - 1);
-  const int cx = G::core_x(ct), cy = G::core_y(ct), cz = G::core_z(ct);
+  const bool core = (NT <= NCORE) || tid < NCORE;
+  int cxs[NCR], cys[NCR], czs[NCR];
+#pragma unroll
+  for (int r = 0; r < NCR; ++r) {
+    const int ct = (tid + NT * r) & (NCORE - 1);
+    cxs[r] = G::core_x(ct);
+    cys[r] = G::core_y(ct);
+    czs[r] = G::core_z(ct);
+  }
   const Real rfr = Real(rf), pfr = Real(pf), gr = Real(g);
   constexpr EB LMASK = EB((1u << G::B_LB) - 1);
-  Real Pw[NV], Pd[3][NV];
+  Real Pw[NCR][NV], Pd[NCR][3][NV];
   Real Ls[NRB][NV];
   EB Lb[NRB];
 #pragma unroll
@@ -673,8 +728,9 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
     const int i = tid + NT * rnd;
     Lb[rnd] = 0u;
     if (!active || i >= NPOS_B) continue;
-    if (rnd == 0 && core) {
-      const int iw = (cx + 1) + G::WB * (cy + 1) + G::WBB * (cz + 1);
+    if (rnd < NCR && core) {
+      const int r = rnd < NCR ? rnd : 0;
+      const int iw = (cxs[r] + 1) + G::WB * (cys[r] + 1) + G::WBB * (czs[r] + 1);
       Real W0[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) W0[v] = W[v * WSIZE + iw];
@@ -682,8 +738,10 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          Pd[d][v] = mmod(W0[v] - W[v * WSIZE + iw - st[d]], W[v * WSIZE + iw + st[d]] - W0[v]);
-      predict<Real, NS>(W0, Pd, h, gr, Pw);
+          Pd[r][d][v] = mmod(W0[v] - W[v * WSIZE + iw - st[d]], W[v * WSIZE + iw + st[d]] - W0[v]);
+      // FP64: the conversion's 1 / rho (the same quotient of the same density)
+      const Real ir = (sizeof(Real) == 8) ? Real(irc[r]) : rcp(W0[0]);
+      predict<Real, NS>(W0, Pd[r], h, gr, Pw[r], ir);
     } else {
       const EB e = entB[rnd];
       Lb[rnd] = e;
@@ -699,7 +757,7 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
 #pragma unroll
         for (int v = 0; v < NV; ++v) D[d][v] = mmod(W0[v] - W[v * WSIZE + lo], W[v * WSIZE + hi] - W0[v]);
       }
-      predict<Real, NS>(W0, D, h, gr, Q);
+      predict<Real, NS>(W0, D, h, gr, Q, rcp(W0[0]));
       // the face state Q +- D/2 along the normal: the weights of the two other
       // axes are zero, so their fused terms add exact zeros
       const Real sg = up ? Real(-0.5) : Real(0.5);
@@ -708,7 +766,7 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
       for (int v = 0; v < NV; ++v) Ls[rnd][v] = fma(t2, D[2][v], fma(t1, D[1][v], fma(t0, D[0][v], Q[v])));
       int nc = 0;
       floor_state<Real>(Ls[rnd], rfr, pfr, nc);
-      pending |= nc << (2 * (SITE_B + rnd));
+      pending |= Pend(nc) << (2 * (SITE_B + rnd));
     }
   }
   __syncthreads();
@@ -721,16 +779,17 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
     if (!active || i >= NPOS_B) continue;
-    if (rnd == 0 && core) {
+    if (rnd < NCR && core) {
+      const int r = rnd < NCR ? rnd : 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         Real s[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s[v] = Pw[v] + Real(0.5) * Pd[d][v];
+        for (int v = 0; v < NV; ++v) s[v] = Pw[r][v] + Real(0.5) * Pd[r][d][v];
         int nc = 0;
         floor_state<Real>(s, rfr, pfr, nc);
-        pending |= nc << (2 * (SITE_L + d));
-        const int f = G::fidx(d, cx + (d == 0), cy + (d == 1), cz + (d == 2));
+        pending |= Pend(nc) << (2 * (SITE_L + 3 * r + d));
+        const int f = G::fidx(d, cxs[r] + (d == 0), cys[r] + (d == 1), czs[r] + (d == 2));
 #pragma unroll
         for (int v = 0; v < NV; ++v) FL[v * NFACE + f] = s[v];
       }
@@ -748,18 +807,24 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   // --- phase C: HLLC on the faces whose upper cell the thread holds (a core
   // cell: its three lower faces; an upper one-layer cell: its face, read in
   // the face-normal frame straight from LDS)
-  Real Fc[3][NV];
+  Real Fc[NCR][3][NV];
   Real Fl[NRB][NV];
 #pragma unroll
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
     if (!active || i >= NPOS_B) continue;
-    if (rnd == 0 && core) {
+    if (rnd < NCR && core) {
+      const int r = rnd < NCR ? rnd : 0;
+      const int cx = cxs[r], cy = cys[r], cz = czs[r];
       int nc[3] = {0, 0, 0};
-      core_face_flux<Real, 0, NS, NFACE>(FL, G::fidx(0, cx, cy, cz), Pw, Pd[0], rfr, pfr, gr, igm1, nc[0], Fc[0]);
-      core_face_flux<Real, 1, NS, NFACE>(FL, G::fidx(1, cx, cy, cz), Pw, Pd[1], rfr, pfr, gr, igm1, nc[1], Fc[1]);
-      core_face_flux<Real, 2, NS, NFACE>(FL, G::fidx(2, cx, cy, cz), Pw, Pd[2], rfr, pfr, gr, igm1, nc[2], Fc[2]);
-      pending |= (nc[0] << (2 * SITE_R)) | (nc[1] << (2 * (SITE_R + 1))) | (nc[2] << (2 * (SITE_R + 2)));
+      core_face_flux<Real, 0, NS, NFACE>(FL, G::fidx(0, cx, cy, cz), Pw[r], Pd[r][0], rfr, pfr, gr, igm1, nc[0],
+                                         Fc[r][0]);
+      core_face_flux<Real, 1, NS, NFACE>(FL, G::fidx(1, cx, cy, cz), Pw[r], Pd[r][1], rfr, pfr, gr, igm1, nc[1],
+                                         Fc[r][1]);
+      core_face_flux<Real, 2, NS, NFACE>(FL, G::fidx(2, cx, cy, cz), Pw[r], Pd[r][2], rfr, pfr, gr, igm1, nc[2],
+                                         Fc[r][2]);
+      pending |= (Pend(nc[0]) << (2 * (SITE_R + 3 * r))) | (Pend(nc[1]) << (2 * (SITE_R + 3 * r + 1))) |
+                 (Pend(nc[2]) << (2 * (SITE_R + 3 * r + 2)));
     } else if ((Lb[rnd] >> G::B_US) & EB(1)) {
       const int f = int(Lb[rnd] >> G::B_FS), dn = int((Lb[rnd] >> G::B_DS) & EB(3)), k = i - NCORE;
       const int iu = 1 + dn, i1 = (dn == 0) ? 2 : 1, i2 = (dn == 2) ? 2 : 3;
@@ -777,12 +842,13 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   for (int rnd = 0; rnd < NRB; ++rnd) {
     const int i = tid + NT * rnd;
     if (!active || i >= NPOS_B) continue;
-    if (rnd == 0 && core) {
+    if (rnd < NCR && core) {
+      const int r = rnd < NCR ? rnd : 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const int f = G::fidx(d, cx, cy, cz);
+        const int f = G::fidx(d, cxs[r], cys[r], czs[r]);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) SF[v * NFACE + f] = Fc[d][v];
+        for (int v = 0; v < NV; ++v) SF[v * NFACE + f] = Fc[r][d][v];
       }
     } else if ((Lb[rnd] >> G::B_US) & EB(1)) {
       // Fl is in the face-normal frame: rotate back on the way out
@@ -803,20 +869,42 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   // the cell is the one gathered in phase A, or loaded again first: the
   // stores to the new state may alias it as far as the compiler knows, and
   // a load issued after a store would wait for it)
-  const int ts = G::slot(cx >> 1, cy >> 1, cz >> 1);
-  const int32_t e = (active && tid < NCORE) ? tab[ts] : -1;
-  const int ci = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
-  // a tile cut by the domain's high side: its slots past the cut hold the
-  // periodic images of other octs, which other tiles update
-  const bool inside = cx <= hb[0] && cy <= hb[1] && cz <= hb[2];
-  const bool leaf = tid < NCORE && inside && (e >= 0) && (e < A.n_oct) && !((ref[ts] >> ci) & 1);
-  const uint32_t cell = uint32_t(e) * 8u + uint32_t(ci);
-  if (!KEEP_CORE && leaf) {
+  // the thread holds core cells (with more threads than core cells, the
+  // threads past them hold none)
+  const bool cthr = (NT <= NCORE) || tid < NCORE;
+  using LDS = TileLDS<Real, NV, K>;
+  double* smx = LDS::SMAX_IN_BUF ? reinterpret_cast<double*>(S.buf + NV * NFACE) : S.smx;
+  int32_t e[NCR];
+  uint32_t cell[NCR];
+  bool leaf[NCR];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Ucore[v] = (A.U + v * P)[cell];
+  for (int r = 0; r < NCR; ++r) {
+    const int cx = cxs[r], cy = cys[r], cz = czs[r];
+    const int ts = G::slot(cx >> 1, cy >> 1, cz >> 1);
+    e[r] = (active && cthr) ? tab[ts] : -1;
+    const int ci = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
+    // a tile cut by the domain's high side: its slots past the cut hold the
+    // periodic images of other octs, which other tiles update
+    const bool inside = cx <= hb[0] && cy <= hb[1] && cz <= hb[2];
+    leaf[r] = cthr && inside && (e[r] >= 0) && (e[r] < A.n_oct) && !((ref[ts] >> ci) & 1);
+    cell[r] = uint32_t(e[r]) * 8u + uint32_t(ci);
   }
-  double acc[NV];
-  if (leaf) {
+  // planes addressed by 32-bit byte offsets where they fit (as the gather)
+  const bool off32 = level_off32(A);
+  if (!KEEP_CORE) {
+#pragma unroll
+    for (int r = 0; r < NCR; ++r)
+      if (leaf[r]) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          Ucore[r][v] = off32 ? plane_load(plane_rsrc(A.U + v * P), cell[r] << 3) : (A.U + v * P)[cell[r]];
+      }
+  }
+  double acc[NCR][NV];
+#pragma unroll
+  for (int r = 0; r < NCR; ++r) {
+    if (!leaf[r]) continue;
+    const int cx = cxs[r], cy = cys[r], cz = czs[r];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       // the lower face's flux is the thread's own (phase C), the upper one
@@ -825,7 +913,7 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
       double Fm[NV], Fp[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Fm[v] = double(Fc[d][v]);
+        Fm[v] = double(Fc[r][d][v]);
         Fp[v] = double(SF[v * NFACE + fp]);
       }
       if (A.child) {
@@ -853,54 +941,59 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] = (d == 0) ? (Fm[v] - Fp[v]) : acc[v] + (Fm[v] - Fp[v]);
+      for (int v = 0; v < NV; ++v) acc[r][v] = (d == 0) ? (Fm[v] - Fp[v]) : acc[r][v] + (Fm[v] - Fp[v]);
     }
   }
-  if (tid < NCORE) {
+  if (cthr) {
     double s = 0.0;
-    if (leaf) {
+#pragma unroll
+    for (int r = 0; r < NCR; ++r) {
+      if (!leaf[r]) continue;
       double Un[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        Un[v] = Ucore[v] + lam * acc[v];
-        (A.Un + v * P)[cell] = Un[v];
+      for (int v = 0; v < NV; ++v) Un[v] = Ucore[r][v] + lam * acc[r][v];
+      if (off32) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) plane_store(plane_rsrc(A.Un + v * P), cell[r] << 3, Un[v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) (A.Un + v * P)[cell[r]] = Un[v];
       }
       if (A.tile_smax || A.smax_bits || A.err) {
-        s = signal_speed(Un, g, rf, pf);
+        const double sr = signal_speed(Un, g, rf, pf);
         const bool bad = !(isfinite(Un[0]) && isfinite(Un[1]) && isfinite(Un[2]) && isfinite(Un[3]) &&
-                           isfinite(Un[4])) || !(Un[0] > 0.0) || !(Un[4] > 0.0) || !isfinite(s);
-        if (bad) {
-          atomicOr(A.err, 1);
-          s = 0.0;
-        }
+                           isfinite(Un[4])) || !(Un[0] > 0.0) || !(Un[4] > 0.0) || !isfinite(sr);
+        if (bad) atomicOr(A.err, 1);
+        s = (r == 0) ? (bad ? 0.0 : sr) : fmax(s, bad ? 0.0 : sr);
       }
     }
-    if (active && A.smax_bits) {
+    if constexpr (NCORE > 64) {
+      // several wavefronts: the first reduces the tile's speeds after the
+      // tile's last barrier
+      smx[tid] = s;
+    } else if (active && A.smax_bits) {
       // one atomic maximum per wavefront on one of the level's slots (a
       // non-negative double orders like its bit pattern); the maximum does
       // not depend on the order of arrival
       const double m = wave_max(s);
-      const int sl = (tile * (NCORE / 64) + (tid >> 6)) & (SMAX_SLOTS - 1);
+      const int sl = tile & (SMAX_SLOTS - 1);
       if (lane == 0) atomicMax(A.smax_bits + sl, (unsigned long long)__double_as_longlong(m));
     } else if (active && A.tile_smax) {
-      // batched boxes: one partial per tile (with several wavefronts per
-      // tile, an atomic maximum on its bit pattern into a slot cleared before
-      // the launch), reduced per box by the segmented max kernel before the
-      // next time step
+      // batched boxes: one partial per tile, reduced per box by the
+      // segmented max kernel before the next time step
       const double m = wave_max(s);
       const int slot = A.tile_part ? A.tile_part[tile] : tile;
-      if (lane == 0) {
-        if constexpr (NCORE == 64) A.tile_smax[slot] = m;
-        else atomicMax(reinterpret_cast<unsigned long long*>(A.tile_smax) + slot,
-                       (unsigned long long)__double_as_longlong(m));
-      }
+      if (lane == 0) A.tile_smax[slot] = m;
     }
   }
 
   // --- fine-side registers: q_s = (f1 + f2) + (f3 + f4) on coarse-fine faces
   constexpr int KO = G::KO, NREG = 6 * KO * KO * KO;
-  const int rt = (K == 4 && NT > 64) ? tid - 64 : tid;   // K = 4: a second wavefront, when there is one
-  if (active && A.record_reg && rt >= 0 && rt < NREG) {
+  const int rt0 = (K == 4 && NT > 64) ? tid - 64 : tid;   // K = 4: a second wavefront, when there is one
+#pragma unroll
+  for (int rr = 0; rr < (NREG + NT - 1) / NT; ++rr) {
+    const int rt = rt0 + NT * rr;
+    if (!(active && A.record_reg && rt >= 0 && rt < NREG)) continue;
     const int b = rt / 6, face = rt - 6 * (rt / 6);
     const int bx = b % KO, by = (b / KO) % KO, bz = b / (KO * KO);
     const int tb_ = G::slot(bx, by, bz);
@@ -938,7 +1031,7 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
   if (pending) {
 #pragma unroll
     for (int rnd = 0; rnd < NRA; ++rnd) {
-      const int f = (pending >> (2 * (SITE_A + rnd))) & 3;
+      const int f = int(pending >> (2 * (SITE_A + rnd))) & 3;
       if (!f) continue;
       // a conversion: counted when the position is one of the tile's own leaf cells
       const int raw = int(ST.a[tid + NT * rnd] >> G::A_RS);
@@ -947,7 +1040,7 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
     }
 #pragma unroll
     for (int rnd = 0; rnd < NRB; ++rnd) {
-      const int f = (pending >> (2 * (SITE_B + rnd))) & 3;
+      const int f = int(pending >> (2 * (SITE_B + rnd))) & 3;
       if (!f) continue;
       // a one-layer face state: the face between the cell and the core, whose
       // lower cell is this cell (lower layer) or the core cell below it
@@ -959,11 +1052,16 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
       if (census_face<K>(tab, ref, fl, hb, A.n_oct, x, y, z, dn)) nfl += f;
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int fl_ = (pending >> (2 * (SITE_L + d))) & 3, fr = (pending >> (2 * (SITE_R + d))) & 3;
-      if (fl_ && census_face<K>(tab, ref, fl, hb, A.n_oct, cx, cy, cz, d)) nfl += fl_;
-      if (fr && census_face<K>(tab, ref, fl, hb, A.n_oct, cx - (d == 0), cy - (d == 1), cz - (d == 2), d)) nfl += fr;
-    }
+    for (int r = 0; r < NCR; ++r)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int cx = cxs[r], cy = cys[r], cz = czs[r];
+        const int fl_ = int(pending >> (2 * (SITE_L + 3 * r + d))) & 3;
+        const int fr = int(pending >> (2 * (SITE_R + 3 * r + d))) & 3;
+        if (fl_ && census_face<K>(tab, ref, fl, hb, A.n_oct, cx, cy, cz, d)) nfl += fl_;
+        if (fr && census_face<K>(tab, ref, fl, hb, A.n_oct, cx - (d == 0), cy - (d == 1), cz - (d == 2), d))
+          nfl += fr;
+      }
   }
   // floor activations are rare: the shuffle sum runs only in a wavefront
   // that has any
@@ -972,6 +1070,25 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
     if (lane == 0 && tot) atomicAdd(A.floors, (unsigned long long)tot);
   }
   __syncthreads();
+  if constexpr (NCORE > 64) {
+    if (active && tid < 64 && (A.smax_bits || A.tile_smax)) {
+      double m = smx[tid];
+#pragma unroll
+      for (int k = 1; k < NT / 64; ++k) m = fmax(m, smx[tid + 64 * k]);
+      m = wave_max(m);
+      if (lane == 0) {
+        if (A.smax_bits) {
+          atomicMax(A.smax_bits + (tile & (SMAX_SLOTS - 1)), (unsigned long long)__double_as_longlong(m));
+        } else {
+          // batched boxes: the tile's partial (an atomic maximum on its bit
+          // pattern into a slot cleared before the launch)
+          const int slot = A.tile_part ? A.tile_part[tile] : tile;
+          atomicMax(reinterpret_cast<unsigned long long*>(A.tile_smax) + slot,
+                    (unsigned long long)__double_as_longlong(m));
+        }
+      }
+    }
+  }
 }
 
 // Occupancy targets.  K = 4, hydro variables alone: at least 3 wavefronts
@@ -979,13 +1096,13 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
 // instruction-level-parallel schedule stops there); with passive scalars the
 // LDS tile sets the limit.  K = 8: two 512-thread tiles per CU (the FP64
 // tile takes 78 KB of the 160 KB of LDS), so 4 wavefronts per SIMD.
-template <int K, int NS>
+template <typename Real, int K, int NS, int WPT>
 constexpr int hydro_waves_per_eu() {
-  return K == 8 ? 4 : (NS == 0 ? 3 : 1);
+  return K == 8 ? (WPT == 8 ? 4 : (sizeof(Real) == 4 ? 3 : 2)) : (NS == 0 ? 3 : 1);
 }
 
 template <typename Real, int TPW, int WPT, int NS, int K>
-__global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(hydro_waves_per_eu<K, NS>())))
+__global__ __launch_bounds__(64 * WPT * TPW) __attribute__((amdgpu_waves_per_eu(hydro_waves_per_eu<Real, K, NS, WPT>())))
 void hydro_kernel(HydroArgs A) {
   constexpr int NT = 64 * WPT;
   __shared__ TileLDS<Real, NVAR + NS, K> S[TPW];

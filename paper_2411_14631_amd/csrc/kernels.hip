@@ -16,7 +16,7 @@ int hydro_max_tiles_per_wg() { return 4; }
 
 bool hydro_tuning_supported(int precision, int nscalar, const ry_tuning& t) {
   if (t.tile_cells == 8)
-    return nscalar == 0 && !t.persistent && t.tiles_per_wg == 1 && t.waves_per_tile == 8;
+    return nscalar == 0 && !t.persistent && t.tiles_per_wg == 1 && (t.waves_per_tile == 8 || t.waves_per_tile == 4);
   if (t.tile_cells != 4) return false;
   const int key = t.tiles_per_wg * 10 + t.waves_per_tile;
   if (nscalar == 0) {

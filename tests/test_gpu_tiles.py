@@ -23,6 +23,8 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 SMALL = dict(tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=1, tile_cells=4)
 BIG = dict(tiles_per_wg=1, persistent=0, waves_per_cu=4, batch=1, waves_per_tile=8, tile_cells=8)
+# the 8^3-cell tile on 4 wavefronts: two core cells per thread
+BIG4 = dict(BIG, waves_per_tile=4)
 
 
 @pytest.fixture(scope="module")
@@ -82,22 +84,24 @@ PROBLEMS = {
 def test_big_tile_matches_oracle_and_small_tile_bit_exact(ry, name):
     prob = PROBLEMS[name]()
     small = run(ry, prob, 4, tuning=SMALL)
-    big = run(ry, prob, 4, tuning=BIG)
-    assert big.tuning()["tile_cells"] == 8
-    for a, b in zip(states(small), states(big)):
-        np.testing.assert_array_equal(a, b)
     o = Oracle(prob)
     o.advance(4)
-    compare_levels(big, o)
-    assert big.floors() == small.floors()
+    for t in (BIG, BIG4):
+        big = run(ry, prob, 4, tuning=t)
+        assert big.tuning()["tile_cells"] == 8
+        for a, b in zip(states(small), states(big)):
+            np.testing.assert_array_equal(a, b)
+        compare_levels(big, o)
+        assert big.floors() == small.floors()
 
 
 def test_big_tile_mixed_form_bit_exact(ry):
     prob = cases.amr_blob()
     a = run(ry, prob, 3, "mixed", tuning=SMALL)
-    b = run(ry, prob, 3, "mixed", tuning=BIG)
-    for x, y in zip(states(a), states(b)):
-        np.testing.assert_array_equal(x, y)
+    for t in (BIG, BIG4):
+        b = run(ry, prob, 3, "mixed", tuning=t)
+        for x, y in zip(states(a), states(b)):
+            np.testing.assert_array_equal(x, y)
 
 
 def test_per_level_tile_shapes_bit_exact(ry):
@@ -106,7 +110,7 @@ def test_per_level_tile_shapes_bit_exact(ry):
     tile tables of the new mesh."""
     prob = cases.amr_blob(level_min=3, level_max=5)
     ref = run(ry, prob, 3)
-    for per in ({3: BIG}, {4: BIG}, {5: BIG}, {3: BIG, 5: BIG}, {4: BIG, 5: BIG}):
+    for per in ({3: BIG}, {4: BIG}, {5: BIG}, {3: BIG, 5: BIG}, {4: BIG, 5: BIG}, {3: BIG4, 4: BIG4, 5: BIG}):
         h = run(ry, prob, 3, per_level=per)
         for lv, t in per.items():
             assert h.level_tuning(lv)["tile_cells"] == 8
@@ -176,7 +180,7 @@ def test_batch_big_tile_bit_exact(ry, prec):
     boxes = [W.batch_box(40, 24, 1.0, 1.5), W.batch_box(41, 18, 0.7, 0.8), W.batch_box(42, 32, 1.2, 2.0),
              W.batch_box(43, 10, 0.5, 1.0), W.batch_box(44, 16, 1.0, 1.0)]
     out = []
-    for t in (SMALL, BIG, None):
+    for t in (SMALL, BIG, BIG4, None):
         bh = ry.BatchHydro(boxes, prec)
         if t is None:
             bh.autotune()
@@ -203,7 +207,7 @@ def test_big_tile_rejected_where_unsupported(ry):
     assert e.value.code == ry.RY_EINVAL
     h = ry.Hydro(cases.amr_blob())
     with pytest.raises(ry.RyError) as e:
-        h.set_tuning(**dict(BIG, waves_per_tile=4))
+        h.set_tuning(**dict(BIG, waves_per_tile=2))
     assert e.value.code == ry.RY_EINVAL
 
 
