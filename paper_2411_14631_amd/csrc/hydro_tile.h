@@ -415,10 +415,30 @@ __device__ __forceinline__ void core_face_flux(const Real* FL, int f, const Real
   for (int k = NVAR; k < NVAR + NS; ++k) F[k] = side.scalar_flux(FL[k * NFACE + f], wr[k]);
 }
 
+// Maximum over a wavefront's 64 lanes (all active), returned to every lane:
+// DPP steps within each row of 16 lanes (lane pairs, quads, half-rows,
+// rows), two row broadcasts that carry rows 0-2 into row 3, then lane 63
+// read out.  The maximum does not depend on the order of combination.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_max_step(double x) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
+  const int lo = int(uint32_t(b)), hi = int(uint32_t(b >> 32));
+  const int tlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
+  const int thi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+  const unsigned long long t = (static_cast<unsigned long long>(uint32_t(thi)) << 32) | uint32_t(tlo);
+  return fmax(x, __longlong_as_double(static_cast<long long>(t)));
+}
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = dpp_max_step<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v = dpp_max_step<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+  v = dpp_max_step<0x141, 0xf>(v);   // row_half_mirror
+  v = dpp_max_step<0x140, 0xf>(v);   // row_mirror: every lane holds its row's maximum
+  v = dpp_max_step<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_max_step<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), 63));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b >> 32)), 63));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
