@@ -391,7 +391,10 @@ static std::string build_level_tables(const DomainSpec& d, const std::vector<Hos
             for (int b = 0; b < 8 && !needed; ++b) {
               if (!present[b]) continue;
               const int px = b & 1, py = (b >> 1) & 1, pz = b >> 2;
-              needed = std::abs(rx - px) <= 1 && std::abs(ry_ - py) <= 1 && std::abs(rz - pz) <= 1;
+              // a face or edge neighbour of a present oct (the stencil reads
+              // no cell diagonally across a corner of an oct)
+              const int ax = std::abs(rx - px), ay = std::abs(ry_ - py), az = std::abs(rz - pz);
+              needed = ax <= 1 && ay <= 1 && az <= 1 && ax + ay + az <= 2;
             }
             if (!needed) continue;
             int64_t qx = bx + rx, qy = by + ry_, qz = bz + rz;

@@ -278,7 +278,10 @@ __global__ void tile_table_kernel(LevelView L, RegridDom D, const int32_t* __res
   bool needed = false;
   for (int64_t o = o0; o < o1 && !needed; ++o) {
     const int px = int(L.oc[3 * o] - bx), py = int(L.oc[3 * o + 1] - by), pz = int(L.oc[3 * o + 2] - bz);
-    needed = abs(rx - px) <= 1 && abs(ry_ - py) <= 1 && abs(rz - pz) <= 1;
+    // a face or edge neighbour of a present oct (no stencil reads across an
+    // oct's corner)
+    const int ax = abs(rx - px), ay = abs(ry_ - py), az = abs(rz - pz);
+    needed = ax <= 1 && ay <= 1 && az <= 1 && ax + ay + az <= 2;
   }
   if (slot == 0) {
     uint32_t fl = 0;
