@@ -12,7 +12,10 @@ A cell-update is one leaf cell advanced by one step of its own level;
 algorithmic HBM bytes are 80 per cell-update (5 FP64 read + 5 written).
 
 Timing: every throughput figure is the median of REPS repetitions of its
-timed steps (each repetition bracketed by device synchronisations); a plain
+timed steps (each repetition bracketed by device synchronisations), taken
+after the warm-up steps and an untimed settling period of the workload's own
+steps (--settle-ms, 200 ms by default: the GPU's clocks need tens of
+milliseconds of load to reach their sustained level); a plain
 device copy timed in the same run gives the achievable HBM bandwidth next to
 the vendor peak.  Every mixed-form figure carries its errors against the
 FP64 form after the workload's own step count (10 coarse steps; 20 for the
@@ -83,6 +86,33 @@ def median(v):
     v = sorted(v)
     n = len(v)
     return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+# Untimed settling before each timed section: the workload's own steps, back
+# to back, for at least this many milliseconds, so that the GPU's clocks have
+# reached their sustained level (on the 128^3 box the step time falls from
+# 0.119 to 0.098 ms over the first ~25 ms of back-to-back steps, then stays).
+SETTLE_MS = 200.0
+
+
+def set_settle_ms(ms):
+    global SETTLE_MS
+    SETTLE_MS = float(ms)
+
+
+def settle(step, ms=None):
+    """Run `step()` (a few of the workload's steps) until `ms` milliseconds
+    of wall time have passed; returns the number of calls."""
+    import torch
+    ms = SETTLE_MS if ms is None else ms
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        step()
+        torch.cuda.synchronize()
+        n += 1
+    return n
 
 
 def timed_reps(h, steps, reps=REPS):
@@ -179,6 +209,7 @@ def run_amr_pair(prob, tune, fixed, timed_steps, eager_steps=0, keep=False):
     for prec in ("fp64", "mixed"):
         h = hs[prec][0]
         cups = cell_updates_per_coarse_step(h)
+        settle(lambda: h.advance(8))
         med, reps = timed_reps(h, timed_steps)
         r = res[prec]
         r.update({"value": cups * timed_steps / med, "unit": "cell-updates/s",
@@ -218,6 +249,7 @@ def run_zoom_only(precision, steps, warmup, tune, fixed, eager):
     cups = cell_updates_per_coarse_step(h)
     if warmup:
         h.advance(warmup)
+    settle(lambda: h.advance(1))
     out = {"workload": "zoom AMR levels 7-12", "precision": precision, "steps": steps,
            "cell_updates_per_coarse_step": cups, "tunings": level_tunings(h),
            "levels": {str(lv): h.level_info(lv) for lv in h.levels}}
@@ -395,6 +427,7 @@ def run_scalars(nscalar=2, steps=10, warmup=2):
         tuning, _ = h.autotune()
         cups = cell_updates_per_coarse_step(h)
         h.advance(warmup)
+        settle(lambda: h.advance(8))
         med, _ = timed_reps(h, steps)
         nl, ms = eager_kernel_time(h, steps)
         k = ms / max(nl, 1)
@@ -458,6 +491,7 @@ def copy_probe():
     import workloads as W
     from paper_2411_14631_amd import Hydro
     probe = Hydro(W.uniform_state(8), "fp64")
+    settle(lambda: probe.copy_probe(COPY_PROBE_BYTES, reps=20))
     ms = probe.copy_probe(COPY_PROBE_BYTES, reps=20)
     probe.close()
     gbs = 2 * COPY_PROBE_BYTES / (ms * 1e-3) / 1e9
@@ -470,6 +504,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--settle-ms", type=float, default=SETTLE_MS,
+                    help="untimed back-to-back steps before each timed section, in ms of wall time "
+                         "(GPU clocks reach their sustained level)")
     ap.add_argument("--no-zoom", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-poisson", action="store_true")
@@ -483,6 +520,7 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first launch a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
+    set_settle_ms(args.settle_ms)
     if args.gpus != 1:
         print(f"bench.py: the library runs on exactly one GPU (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design only", file=sys.stderr)
@@ -519,6 +557,7 @@ def main():
             bh.autotune()
         for _ in range(max(args.warmup, 1)):
             bh.run(20)
+        settle(lambda: bh.run(20))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         bh.run(20)
@@ -533,6 +572,7 @@ def main():
         h, _ = make(W.twolevel(128, 0.70), prec, tune, fixed)
         cups = cell_updates_per_coarse_step(h)
         h.advance(max(args.warmup, 2))
+        settle(lambda: h.advance(8))
         med, _ = timed_reps(h, args.steps)
         print(json.dumps({"workload": "two-level theta 0.70", "precision": prec, "tunings": level_tunings(h),
                           "value": cups * args.steps / med, "ms_per_coarse_step": 1e3 * med / args.steps}), flush=True)
@@ -548,6 +588,7 @@ def main():
         h, _ = make(W.uniform(128), args.only, tune, fixed)
         cups = cell_updates_per_coarse_step(h)
         h.advance(args.warmup)
+        settle(lambda: h.advance(8))
         out = {"precision": args.only, "tuning": h.tuning()}
         if args.eager_only:
             # every launch of the run with HIP events around it (profiling runs:
@@ -582,6 +623,7 @@ def main():
         h = hs[prec][0]
         cups = cell_updates_per_coarse_step(h)
         h.advance(args.warmup)
+        settle(lambda: h.advance(8))
         med, reps = timed_reps(h, args.steps)                 # value: graph replay, the production path
         nl, ms = eager_kernel_time(h, args.steps)             # the kernel's own time (HIP events)
         res[prec] = dict(cups=cups, med=med, reps=reps, kernel_ms=ms / max(nl, 1), tuning=h.tuning(),
@@ -670,6 +712,7 @@ def main():
         batch["mixed"]["vs_fp64"] = compare_batches(bhs["fp64"], bhs["mixed"], boxes)
         for prec in ("fp64", "mixed"):
             bh = bhs[prec]
+            settle(lambda: bh.run(20))
             el = []
             for _ in range(REPS):
                 torch.cuda.synchronize()
@@ -706,7 +749,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "uniform 128^3 periodic lognormal box (262144 octs), FP64, gamma 5/3, CFL 0.8",
                    "cells": 128 ** 3, "cell_updates_per_step": f["cups"], "tuning": f["tuning"],
-                   "repetitions": REPS, "repetitions_ms_per_step": [round(1e3 * x / args.steps, 4) for x in f["reps"]],
+                   "repetitions": REPS, "settle_ms_before_timing": SETTLE_MS, "repetitions_ms_per_step": [round(1e3 * x / args.steps, 4) for x in f["reps"]],
                    "floor_activations": f["floors"], "pcie_inclusive_value": f["pcie"]},
         "roofline": roofline,
         "copy_probe": probe,
