@@ -203,7 +203,10 @@ def run_amr_pair(prob, tune, fixed, timed_steps, eager_steps=0, keep=False):
         e0 = h.totals()[4]
         h.advance(prob.n_steps)
         hs[prec] = (h, e0)
-        res[prec] = {"build_s": round(build_s, 2), "tunings": level_tunings(h)}
+        # floor activations over the configuration's coarse steps (the later
+        # settling and timed steps add their own)
+        res[prec] = {"build_s": round(build_s, 2), "tunings": level_tunings(h),
+                     "floor_activations": h.floors(), "floor_activations_steps": prob.n_steps}
     res["mixed"]["vs_fp64"] = compare_forms(hs["fp64"][0], hs["mixed"][0], hs["fp64"][1], hs["mixed"][1])
     res["mixed"]["vs_fp64"]["coarse_steps"] = prob.n_steps
     for prec in ("fp64", "mixed"):
@@ -217,7 +220,6 @@ def run_amr_pair(prob, tune, fixed, timed_steps, eager_steps=0, keep=False):
                   "hbm_frac": round(BYTES_PER_CELL_UPDATE * cups * timed_steps / med / 1e9 / HBM_PEAK_GBS, 4),
                   "cell_updates_per_coarse_step": cups, "timed_coarse_steps": timed_steps,
                   "repetitions_ms_per_coarse_step": [round(1e3 * x / timed_steps, 4) for x in reps],
-                  "floor_activations": h.floors(),
                   "octs": sum(h.level_info(lv)[0] for lv in h.levels)})
         if eager_steps:
             # the hydro kernels' own time per coarse step (HIP events around
@@ -615,7 +617,7 @@ def main():
         h, build_s = make(uprob, prec, tune, fixed)
         e0 = h.totals()[4]
         h.advance(uprob.n_steps)                 # the configuration's 10 steps (captures the graphs)
-        hs[prec] = (h, e0)
+        hs[prec] = (h, e0, h.floors())
     mixed_err = compare_forms(hs["fp64"][0], hs["mixed"][0], hs["fp64"][1], hs["mixed"][1])
     mixed_err["steps"] = uprob.n_steps
     res = {}
@@ -627,7 +629,7 @@ def main():
         med, reps = timed_reps(h, args.steps)                 # value: graph replay, the production path
         nl, ms = eager_kernel_time(h, args.steps)             # the kernel's own time (HIP events)
         res[prec] = dict(cups=cups, med=med, reps=reps, kernel_ms=ms / max(nl, 1), tuning=h.tuning(),
-                         floors=h.floors(), pcie=pcie_inclusive(h, args.steps) if prec == "fp64" else None)
+                         floors=hs[prec][2], pcie=pcie_inclusive(h, args.steps) if prec == "fp64" else None)
     for prec in hs:
         hs[prec][0].close()
     del hs, h
@@ -750,7 +752,8 @@ def main():
         "config": {"workload": "uniform 128^3 periodic lognormal box (262144 octs), FP64, gamma 5/3, CFL 0.8",
                    "cells": 128 ** 3, "cell_updates_per_step": f["cups"], "tuning": f["tuning"],
                    "repetitions": REPS, "settle_ms_before_timing": SETTLE_MS, "repetitions_ms_per_step": [round(1e3 * x / args.steps, 4) for x in f["reps"]],
-                   "floor_activations": f["floors"], "pcie_inclusive_value": f["pcie"]},
+                   "floor_activations": f["floors"], "floor_activations_steps": uprob.n_steps,
+                   "pcie_inclusive_value": f["pcie"]},
         "roofline": roofline,
         "copy_probe": probe,
         "valu_issue": valu,
