@@ -242,6 +242,22 @@ struct TileLDS {
 // the median of (a, b, 0): max(min(a,b), min(max(a,b), 0)) in FP64 (four
 // min/max), one v_med3 in FP32.
 __device__ __forceinline__ double mmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
+
+// max(x, f) for a wavefront-uniform floor f, as the bare hardware
+// instruction with f in scalar registers: the library maximum first quiets
+// each operand it cannot prove canonical (a value from memory, a kernel
+// argument), one more instruction per operand and use.  Identical for every
+// operand but a signalling NaN, which no state here holds.
+__device__ __forceinline__ double floor_max(double x, double f) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(x), "s"(f));
+  return r;
+}
+__device__ __forceinline__ float floor_max(float x, float f) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(x), "s"(f));
+  return r;
+}
 __device__ __forceinline__ float mmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 
 // Reciprocal and quotient (operands here are normal numbers).  The hardware
@@ -279,7 +295,7 @@ __device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NV
   // floors as max(): a non-finite state never gets here unnoticed (the CFL
   // pass flags it on upload, the update flags it where it is produced)
   const bool lo_r = U[0] < rf;
-  const double rho = fmax(U[0], rf);
+  const double rho = floor_max(U[0], rf);
   const double ir = rcp(rho);
   if (ir_out) *ir_out = ir;
   const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir;
@@ -290,7 +306,7 @@ __device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NV
   W[1] = U[1] * ir;
   W[2] = U[2] * ir;
   W[3] = U[3] * ir;
-  W[4] = fmax(p0, pf);
+  W[4] = floor_max(p0, pf);
 #pragma unroll
   for (int k = 0; k < NS; ++k) W[NVAR + k] = U[NVAR + k] * ir;
 }
@@ -299,11 +315,11 @@ __device__ __forceinline__ void cons2prim(const double U[NVAR + NS], double W[NV
 // primitives), with one refined reciprocal and one refined reciprocal
 // square root: within a few ulp of the definition.
 __device__ __forceinline__ double signal_speed(const double U[NVAR], double g, double rf, double pf) {
-  const double rho = fmax(U[0], rf);
+  const double rho = floor_max(U[0], rf);
   const double ir = rcp(rho);
   const double ke = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir;
   double p = (g - 1.0) * (U[4] - ke);
-  p = fmax(p, pf);
+  p = floor_max(p, pf);
   return (fabs(U[1]) + fabs(U[2]) + fabs(U[3])) * ir + 3.0 * sound_speed(g * p, rho);
 }
 
@@ -385,8 +401,8 @@ __device__ __forceinline__ void predict(const Real W0[NVAR + NS], const Real D[3
 template <typename Real>
 __device__ __forceinline__ void floor_state(Real* s, Real rf, Real pf, int& nfl) {
   nfl += int(s[0] < rf) + int(s[4] < pf);
-  s[0] = fmax(s[0], rf);
-  s[4] = fmax(s[4], pf);
+  s[0] = floor_max(s[0], rf);
+  s[4] = floor_max(s[4], pf);
 }
 
 // Flux through the lower face along axis D of a core cell: the left state
@@ -426,7 +442,11 @@ __device__ __forceinline__ double dpp_max_step(double x) {
   const int tlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
   const int thi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
   const unsigned long long t = (static_cast<unsigned long long>(uint32_t(thi)) << 32) | uint32_t(tlo);
-  return fmax(x, __longlong_as_double(static_cast<long long>(t)));
+  // the bare maximum (the moved bits are a value the library maximum would
+  // first quiet); the operands are never signalling NaNs
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(x), "v"(__longlong_as_double(static_cast<long long>(t))));
+  return r;
 }
 __device__ __forceinline__ double wave_max(double v) {
   v = dpp_max_step<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]

@@ -17,6 +17,7 @@ import cases  # noqa: E402
 
 SMALL = (1, 0, 4, 1, 1, 4)
 BIG = (1, 0, 4, 1, 8, 8)
+BIG4 = (1, 0, 4, 1, 4, 8)   # the 8^3-cell tile on 4 wavefronts (two cells per thread)
 
 
 def outflow(p):
@@ -29,7 +30,7 @@ def main():
              cases.amr_blob(), cases.amr_blob(bc=(W.BC_OUTFLOW,) * 6, centre=(0.1, 0.5, 0.5)),
              outflow(W.twolevel(36, 0.5)), W.twolevel(64, 0.70), W.zoom(level_min=5, level_max=8)]
     for p in probs:
-        for t in (SMALL, BIG):
+        for t in (SMALL, BIG, BIG4):
             for prec in ("fp64", "mixed"):
                 h = ry.Hydro(p, prec)
                 h.set_tuning(*t)
@@ -41,7 +42,7 @@ def main():
                 h.close()
         print("clean:", p.name, flush=True)
     boxes = [W.batch_box(50, 24, 1.0, 1.5), W.batch_box(51, 18, 0.7, 0.8), W.batch_box(52, 16, 1.2, 2.0)]
-    for t in (SMALL, BIG):
+    for t in (SMALL, BIG, BIG4):
         bh = ry.BatchHydro(boxes)
         bh.set_tuning(*t)
         bh.run(4)
