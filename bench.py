@@ -56,10 +56,17 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the hydro kernel's sources with comments and blank space
+    removed (a comment edit leaves the profiled counters valid; any change
+    of code does not)."""
+    import re
     h = hashlib.sha256()
     for f in ("hydro_tile.h", "hydro.hip", "ry_internal.h"):
-        with open(os.path.join(ROOT, "paper_2411_14631_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2411_14631_amd", "csrc", f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

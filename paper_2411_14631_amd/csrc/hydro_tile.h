@@ -1135,7 +1135,10 @@ __device__ __forceinline__ void hydro_tile(const HydroArgs& A, int tile, TileLDS
 // per SIMD (the FP64 tile's LDS allows no more, so the register budget of an
 // instruction-level-parallel schedule stops there); with passive scalars the
 // LDS tile sets the limit.  K = 8: two 512-thread tiles per CU (the FP64
-// tile takes 78 KB of the 160 KB of LDS), so 4 wavefronts per SIMD.
+// tile takes 81.5 KB of the 160 KB of LDS), so 4 wavefronts per SIMD; on
+// 256 threads (two cells per thread) the FP64 tile keeps 2 tiles per CU, 2
+// wavefronts per SIMD with up to 256 registers, the mixed tile 3 tiles per
+// CU (its LDS allows them) at 3 wavefronts per SIMD.
 template <typename Real, int K, int NS, int WPT>
 constexpr int hydro_waves_per_eu() {
   return K == 8 ? (WPT == 8 ? 4 : (sizeof(Real) == 4 ? 3 : 2)) : (NS == 0 ? 3 : 1);
