@@ -87,11 +87,11 @@ struct ry_ctx {
   // subcycling order state for ry_hydro_step
   int count[RY_MAX_LEVELS] = {0};
   double dt_of[RY_MAX_LEVELS] = {0};
-  // graphs of 1 and of kGraphSteps coarse steps: [steps == kGraphSteps][parity
-  // of the base level buffer]
-  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-  std::vector<int> graph_par[2][2];
-  double graph_tend[2][2] = {{0, 0}, {0, 0}};
+  // graphs of 1, 2, 4, 8 and 16 coarse steps: [log2 of the step count]
+  // [parity of the base level buffer]
+  hipGraphExec_t graph[5][2] = {};
+  std::vector<int> graph_par[5][2];
+  double graph_tend[5][2] = {};
   // batch
   int nbox = 0;
   std::vector<int64_t> box_off, box_noct;
@@ -1357,14 +1357,15 @@ ry_status ry_hydro_step(ry_ctx* c, int32_t level, double dt) {
   RY_ABI_CATCH
 }
 
-// Coarse steps per multi-step graph: even, so that every level's buffer
-// parity is back where it started after one launch.  Consecutive kernels
-// inside a graph start back to back; each graph launch costs a gap of a few
-// microseconds, paid once per kGraphSteps steps.
-constexpr int kGraphSteps = 8;
+// Coarse steps per captured graph: 2^g for g = 0..4.  A run of n steps
+// launches the largest graphs that fit (20 steps: 16 + 4), so that the gap of
+// a few microseconds each graph launch costs is paid about once per 16
+// steps; every graph but the 1-step one has an even step count, so every
+// level's buffer parity is back where it started after it.
+constexpr int kGraphLevels = 5;
 
-static ry_status capture_step(ry_ctx* c, int multi, int par, double t_end) {
-  hipGraphExec_t& ge = c->graph[multi][par];
+static ry_status capture_step(ry_ctx* c, int gi, int par, double t_end) {
+  hipGraphExec_t& ge = c->graph[gi][par];
   if (ge) {
     hipGraphExecDestroy(ge);
     ge = nullptr;
@@ -1374,7 +1375,7 @@ static ry_status capture_step(ry_ctx* c, int multi, int par, double t_end) {
   hipGraph_t g = nullptr;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   ry_status s = RY_OK;
-  for (int k = 0; k < (multi ? kGraphSteps : 1) && !s; ++k) s = enqueue_coarse_step(c, t_end);
+  for (int k = 0; k < (1 << gi) && !s; ++k) s = enqueue_coarse_step(c, t_end);
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   for (size_t i = 0; i < c->lev.size(); ++i) c->lev[i].cur = saved[i];
   if (s) {
@@ -1385,8 +1386,8 @@ static ry_status capture_step(ry_ctx* c, int multi, int par, double t_end) {
   e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) return fail(c, RY_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-  c->graph_par[multi][par] = saved;
-  c->graph_tend[multi][par] = t_end;
+  c->graph_par[gi][par] = saved;
+  c->graph_tend[gi][par] = t_end;
   return RY_OK;
 }
 
@@ -1412,18 +1413,15 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
   for (int32_t i = 0; i < n_coarse;) {
     if (use_graph) {
       const int par = c->lev[0].cur;
-      const int multi = (n_coarse - i >= kGraphSteps) ? 1 : 0;
+      int gi = kGraphLevels - 1;
+      while ((1 << gi) > n_coarse - i) --gi;
       std::vector<int> now;
       for (auto& L : c->lev) now.push_back(L.cur);
-      if (!c->graph[multi][par] || c->graph_par[multi][par] != now || c->graph_tend[multi][par] != t_end)
-        if ((s = capture_step(c, multi, par, t_end))) return s;
-      HIPCHK(c, hipGraphLaunch(c->graph[multi][par], c->stream));
-      if (multi) {
-        i += kGraphSteps;        // an even number of steps: parities unchanged
-      } else {
-        c->lev[0].cur ^= 1;
-        ++i;
-      }
+      if (!c->graph[gi][par] || c->graph_par[gi][par] != now || c->graph_tend[gi][par] != t_end)
+        if ((s = capture_step(c, gi, par, t_end))) return s;
+      HIPCHK(c, hipGraphLaunch(c->graph[gi][par], c->stream));
+      i += 1 << gi;
+      if (gi == 0) c->lev[0].cur ^= 1;   // the other graphs take an even number of steps
     } else {
       if ((s = enqueue_coarse_step(c, t_end))) return s;
       ++i;

@@ -119,11 +119,11 @@ def test_amr_graph_equals_host_driven_bit_exact(ry):
         np.testing.assert_array_equal(a.download(lv), b.download(lv))
 
 
-@pytest.mark.parametrize("n", [11, 16])
+@pytest.mark.parametrize("n", [11, 16, 23])
 def test_multi_step_graphs_equal_eager_bit_exact(ry, n):
-    """Runs long enough to use the multi-step graphs (with a 1-step remainder
-    for n = 11) give the eager result bit for bit, and so does a run whose
-    t_end falls inside a multi-step graph."""
+    """Runs that use the multi-step graphs (11 = 8 + 2 + 1 steps, 16 = one
+    16-step graph, 23 = 16 + 4 + 2 + 1) give the eager result bit for bit,
+    and so does a run whose t_end falls inside a multi-step graph."""
     prob = cases.amr_blob(level_min=3, level_max=4)
     a, b = ry.Hydro(prob), ry.Hydro(prob)
     a.set_timing(True)

@@ -199,7 +199,7 @@ def test_gradient_criterion_regrid_matches_oracle(ry, theta):
 
 
 def test_regrid_between_multi_step_graph_runs(ry):
-    """Runs long enough for the 8-step graphs, a regrid that reallocates
+    """Runs long enough for the multi-step graphs (9 = 8 + 1 steps), a regrid that reallocates
     every refined level, and another such run: the graphs captured on the
     old mesh are dropped (same result as the eager path on both meshes)."""
     prob = cases.amr_blob()
