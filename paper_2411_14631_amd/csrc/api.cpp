@@ -77,6 +77,13 @@ struct ry_ctx {
   double* d_lam = nullptr;                // 1 / per box
   double* d_t = nullptr;                  // 1 / per box
   int32_t* d_flags = nullptr;             // [0]=skip [1]=done [2]=nstep [3]=err
+  // pinned host copy of the flags and the time read back after ry_advance
+  // (one round trip for both), allocated on first use
+  struct Readback {
+    int32_t flags[4];
+    double t;
+  };
+  Readback* h_rb = nullptr;
   unsigned long long* d_floors = nullptr;
   unsigned int* d_queue = nullptr;        // 8 counters, QUEUE_STRIDE apart
   double* d_partial = nullptr;
@@ -725,6 +732,7 @@ void ry_destroy(ry_ctx* c) {
   if (!c) return;
   free_all(c);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  if (c->h_rb) hipHostFree(c->h_rb);
   for (auto& tl : c->pending) {
     hipEventDestroy(tl.a);
     hipEventDestroy(tl.b);
@@ -1428,12 +1436,22 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
     }
   }
   c->slots_valid = true;
-  if ((s = sync_and_check(c))) return s;
-  int32_t nrun = 0;
-  HIPCHK(c, hipMemcpy(&nrun, nstep_ptr(c), sizeof nrun, hipMemcpyDeviceToHost));
+  // one round trip for the error word, the device's step count and the time
+  if (!c->h_rb && hipHostMalloc(reinterpret_cast<void**>(&c->h_rb), sizeof(ry_ctx::Readback)) != hipSuccess) {
+    c->h_rb = nullptr;
+    return fail(c, RY_ENOMEM, "pinned readback buffer");
+  }
+  HIPCHK(c, hipMemcpyAsync(c->h_rb->flags, c->d_flags, sizeof c->h_rb->flags, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&c->h_rb->t, c->d_t, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) time_collect(c);
+  const int32_t e = c->h_rb->flags[3];
+  if (e & ERR_BOUNDS) return fail(c, RY_EHIP, "device index outside its buffer (debug build bounds check)");
+  if (e) return fail(c, RY_ENUMERIC, "non-finite or non-positive density/energy latched on the device");
+  const int32_t nrun = c->h_rb->flags[2];
   if (nrun < 0 || nrun > n_coarse) return fail(c, RY_EHIP, "device step count %d out of range", nrun);
   c->lev[0].cur = cur0 ^ (nrun & 1);
-  HIPCHK(c, hipMemcpy(t_io, c->d_t, sizeof(double), hipMemcpyDeviceToHost));
+  *t_io = c->h_rb->t;
   return RY_OK;
   RY_ABI_CATCH
 }
