@@ -1407,8 +1407,14 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
     if (c->count[k] != 0) return fail(c, RY_ESTATE, "ry_advance called inside a coarse step");
   ry_status s;
   if (!c->slots_valid && (s = enqueue_cfl_all(c))) return s;
-  const double t0 = *t_io;
-  HIPCHK(c, hipMemcpyAsync(c->d_t, &t0, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // the time goes up and comes back through a pinned buffer (asynchronous
+  // copies; the ones from pageable memory are staged)
+  if (!c->h_rb && hipHostMalloc(reinterpret_cast<void**>(&c->h_rb), sizeof(ry_ctx::Readback)) != hipSuccess) {
+    c->h_rb = nullptr;
+    return fail(c, RY_ENOMEM, "pinned readback buffer");
+  }
+  c->h_rb->t = *t_io;
+  HIPCHK(c, hipMemcpyAsync(c->d_t, &c->h_rb->t, sizeof(double), hipMemcpyHostToDevice, c->stream));
   if (launch_zero_u32(reinterpret_cast<unsigned int*>(c->d_flags), 3, c->stream))
     return fail(c, RY_EHIP, "zero kernel");
   const bool use_graph = !c->timing;
@@ -1437,10 +1443,6 @@ ry_status ry_advance(ry_ctx* c, int32_t n_coarse, double t_end, double* t_io) {
   }
   c->slots_valid = true;
   // one round trip for the error word, the device's step count and the time
-  if (!c->h_rb && hipHostMalloc(reinterpret_cast<void**>(&c->h_rb), sizeof(ry_ctx::Readback)) != hipSuccess) {
-    c->h_rb = nullptr;
-    return fail(c, RY_ENOMEM, "pinned readback buffer");
-  }
   HIPCHK(c, hipMemcpyAsync(c->h_rb->flags, c->d_flags, sizeof c->h_rb->flags, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(&c->h_rb->t, c->d_t, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
