@@ -1009,6 +1009,8 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     double* U[2] = {nullptr, nullptr};
   };
   std::vector<NewLevel> N(nl);
+  std::vector<unsigned long long*> H(nl, nullptr);   // position hash of each new level
+  std::vector<uint64_t> HE(nl, 0);                    // its entries
   std::vector<void*> fresh, temps;   // new level arrays / scratch of this call
   bool ok = true;
   auto A = [&](size_t bytes, bool temp) -> void* {
@@ -1039,6 +1041,8 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     v.n = N[k].n;
     v.bits = c->dom.hbits0 + k;
     for (int a = 0; a < 3; ++a) v.noct[a] = int32_t(c->dom.noct(lmin + k, a));
+    v.hash = H[k];
+    v.hmask = HE[k] ? HE[k] - 1 : 0;
     return v;
   };
   auto old_view = [&](int k) {
@@ -1063,7 +1067,12 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     return true;
   };
   int32_t* d_err = static_cast<int32_t*>(A(sizeof(int32_t), true));
-  RG_TRY(ok && hipMemsetAsync(d_err, 0, sizeof(int32_t), st) == hipSuccess, RY_ENOMEM, "allocation failed");
+  // per level: children of the new level found in the old one
+  auto* d_kept = static_cast<unsigned long long*>(A(sizeof(unsigned long long) * nl, true));
+  RG_TRY(ok && hipMemsetAsync(d_err, 0, sizeof(int32_t), st) == hipSuccess &&
+             hipMemsetAsync(d_kept, 0, sizeof(unsigned long long) * nl, st) == hipSuccess,
+         RY_ENOMEM, "allocation failed");
+  std::vector<int64_t> n_new(nl, 0), n_prev(nl, 0);   // child level sizes, new and old
 
   {  // level lmin keeps its octs and tile tables (a complete level: no ghost octs)
     const DevLevel& D = c->lev[0];
@@ -1089,6 +1098,10 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     // the device regrid counts cells (8 per oct) and tile slots (64 per tile)
     // in 32-bit integers
     RG_TRY(L.n < (int64_t(1) << 28), RY_EINVAL, "level too large for the device regrid (use the host path)");
+    HE[k] = pos_hash_entries(L.n);
+    H[k] = static_cast<unsigned long long*>(A(16 * HE[k], true));
+    RG_TRY(ok, RY_ENOMEM, "allocation failed");
+    RG_TRY(!launch_pos_hash(L.oc, L.n, H[k], HE[k], st), RY_EHIP, "position hash kernel");
     const LevelView V = view(k);
     if (k > 0) {
       // tiles: octs sharing key >> 3
@@ -1181,6 +1194,8 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
       NewLevel& F = N[k + 1];
       F.n = n_fine;
       const int64_t n_old = c->lev[k + 1].n_oct;
+      n_new[k + 1] = n_fine;
+      n_prev[k + 1] = n_old;
       if (n_fine > 0) {
         F.key = static_cast<uint64_t*>(A(sizeof(uint64_t) * n_fine, false));
         F.oc = static_cast<int32_t*>(A(sizeof(int32_t) * 3 * n_fine, false));
@@ -1188,21 +1203,19 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
         L.child = static_cast<int32_t*>(A(sizeof(int32_t) * 8 * L.n, false));
         src_old = static_cast<int32_t*>(A(sizeof(int32_t) * n_fine, true));
         src7 = static_cast<int32_t*>(A(sizeof(int32_t) * 7 * n_fine, true));
-        RG_TRY(ok, RY_ENOMEM, "allocation failed");
-        RG_TRY(!launch_regrid_children(V, old_view(k + 1), RD, c->dom.hbits0 + k + 1, L.flag, off, F.key, F.oc,
-                                       F.parent, L.child, src_old, src7, d_err, st),
+        // the old child level's octs, found by position
+        LevelView Fo = old_view(k + 1);
+        if (n_old > 0) {
+          const uint64_t he = pos_hash_entries(n_old);
+          auto* ho = static_cast<unsigned long long*>(A(16 * he, true));
+          RG_TRY(ok, RY_ENOMEM, "allocation failed");
+          RG_TRY(!launch_pos_hash(Fo.oc, n_old, ho, he, st), RY_EHIP, "position hash kernel");
+          Fo.hash = ho;
+          Fo.hmask = he - 1;
+        }
+        RG_TRY(!launch_regrid_children(V, Fo, RD, c->dom.hbits0 + k + 1, L.flag, off, F.key, F.oc, F.parent,
+                                       L.child, src_old, src7, d_err, d_kept + k + 1, st),
                RY_EHIP, "regrid children kernel");
-        std::vector<int32_t> so(n_fine);
-        RG_TRY(hipMemcpyAsync(so.data(), src_old, sizeof(int32_t) * n_fine, hipMemcpyDeviceToHost, st) ==
-                       hipSuccess &&
-                   hipStreamSynchronize(st) == hipSuccess,
-               RY_EHIP, "regrid children kernel");
-        int64_t kept = 0;
-        for (int32_t v : so) kept += v >= 0;
-        created += n_fine - kept;
-        destroyed += n_old - kept;
-      } else {
-        destroyed += n_old;
       }
     } else {
       RG_TRY(hipMemsetAsync(L.flag, 0, L.n, st) == hipSuccess, RY_EHIP, "flag clear");
@@ -1213,9 +1226,16 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     RG_TRY(!launch_refined_ext(L.flag, L.n, L.n + L.n_ghost, L.refined, st), RY_EHIP, "refined kernel");
   }
   int32_t herr = 0;
+  std::vector<unsigned long long> kept(nl, 0);
   RG_TRY(hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, st) == hipSuccess &&
+             hipMemcpyAsync(kept.data(), d_kept, sizeof(unsigned long long) * nl, hipMemcpyDeviceToHost, st) ==
+                 hipSuccess &&
              hipStreamSynchronize(st) == hipSuccess,
          RY_EHIP, "regrid kernels");
+  for (int k = 1; k < nl; ++k) {
+    created += n_new[k] - int64_t(kept[k]);
+    destroyed += n_prev[k] - int64_t(kept[k]);
+  }
   RG_TRY(herr == 0, RY_EINVAL, herr & 1 ? "interpolation source missing" : "ghost source missing");
 #undef RG_TRY
   // install: release the old arrays (level lmin keeps state, keys, tables)

@@ -124,54 +124,69 @@ __global__ void ghost_kernel(GhostArgs A) {
   }
 }
 
-// One thread per (tile, slot) of the small-tile tables: a slot holding a
-// ghost oct gets the bits of its cells that lie in the stencil of a leaf
-// cell of the tile's core (one or two steps along an axis, or one step along
-// each of two axes).  Every leaf cell is in exactly one tile's core, and its
-// stencil stays within that tile's oct neighbourhood, so the union over the
-// tiles is exact.  Cells past the domain's high side of a cut tile are other
-// tiles' cells and are skipped.
+// One wavefront per small tile, one lane per (tile, slot) of its table: a
+// slot holding a ghost oct gets the bits of its cells that lie in the
+// stencil of a leaf cell of the tile's core (one or two steps along an axis,
+// or one step along each of two axes).  Every leaf cell is in exactly one
+// tile's core, and its stencil stays within that tile's oct neighbourhood,
+// so the union over the tiles is exact.  Cells past the domain's high side
+// of a cut tile are other tiles' cells and are skipped.
+//
+// The core's 4x4x4 cells are the wavefront's 64 lanes: a ballot gives the
+// leaf set, which goes into eight 64-bit words, one per cell layer z, bit
+// x + 8y, with every coordinate shifted by 2 so that the core sits at 2..5
+// and its dilation by the stencil (at most 2 cells) stays inside 0..7 and
+// inside each word's rows.  The read set is that dilation (the stencil's
+// offsets are symmetric); each ghost lane then takes its 8 cells' bits.
 __global__ void ghost_read_kernel(const int32_t* __restrict__ tab, const uint32_t* __restrict__ tflag,
                                   const uint8_t* __restrict__ refined, int32_t n_tile, int64_t n_oct,
                                   uint32_t* __restrict__ gread) {
   using G = Geom<4>;
+  static_assert(G::TAB == 64 && G::TS == 4, "one lane per slot and per core cell");
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= int64_t(n_tile) * G::TAB) return;
-  const int64_t tile = i / G::TAB;
-  const int slot = int(i % G::TAB);
-  const int32_t* t = tab + tile * G::TAB;
-  const int32_t e = t[slot];
-  if (e < n_oct) return;
+  if (i >= int64_t(n_tile) * G::TAB) return;   // whole wavefronts: blocks of whole wavefronts, 64 slots a tile
+  const int tile = __builtin_amdgcn_readfirstlane(int(i / G::TAB));
+  const int lane = int(i % G::TAB);
+  const int32_t* t = tab + int64_t(tile) * G::TAB;
   const uint32_t fl = tflag[tile];
   const int hb[3] = {3 - int((fl >> CL_CUT_SHIFT) & 7u), 3 - int((fl >> (CL_CUT_SHIFT + 3)) & 7u),
                      3 - int((fl >> (CL_CUT_SHIFT + 6)) & 7u)};
-  const int sx = slot % G::TS - 1, sy = (slot / G::TS) % G::TS - 1, sz = slot / (G::TS * G::TS) - 1;
-  auto leaf = [&](int x, int y, int z) {
-    if (x < 0 || y < 0 || z < 0 || x > hb[0] || y > hb[1] || z > hb[2]) return false;
-    const int32_t q = t[G::slot(x >> 1, y >> 1, z >> 1)];
-    return q >= 0 && q < n_oct && !((refined[q] >> ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2))) & 1);
-  };
+  // this lane's core cell and whether it is a leaf of the tile
+  const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+  const int32_t q = t[G::slot(cx >> 1, cy >> 1, cz >> 1)];
+  const bool leaf = cx <= hb[0] && cy <= hb[1] && cz <= hb[2] && q >= 0 && q < n_oct &&
+                    !((refined[q] >> ((cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2))) & 1);
+  const uint64_t core = __ballot(leaf);   // bit x + 4y + 16z
+  const int32_t e = t[lane];
+  if (e < n_oct) return;
+  uint64_t w[8];
+#pragma unroll
+  for (int z = 0; z < 8; ++z) {
+    w[z] = 0;
+    if (z >= 2 && z <= 5)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) w[z] |= ((core >> (16 * (z - 2) + 4 * y)) & 0xFull) << (8 * (y + 2) + 2);
+  }
+  // this lane's ghost oct: cells at x 2sx..2sx+1 (shifted coordinates), etc.
+  const int sx = 2 * (lane & 3), sy = 2 * ((lane >> 2) & 3), sz = 2 * (lane >> 4);
   uint32_t m = 0;
-  for (int c = 0; c < 8; ++c) {
-    const int p[3] = {2 * sx + (c & 1), 2 * sy + ((c >> 1) & 1), 2 * sz + (c >> 2)};
-    bool rd = false;
-    for (int d = 0; d < 3 && !rd; ++d)
-      for (int st = -2; st <= 2 && !rd; ++st) {
-        if (st == 0) continue;
-        int q[3] = {p[0], p[1], p[2]};
-        q[d] += st;
-        rd = leaf(q[0], q[1], q[2]);
-      }
-    for (int d = 0; d < 3 && !rd; ++d)
-      for (int d2 = d + 1; d2 < 3 && !rd; ++d2)
-        for (int s1 = -1; s1 <= 1 && !rd; s1 += 2)
-          for (int s2 = -1; s2 <= 1 && !rd; s2 += 2) {
-            int q[3] = {p[0], p[1], p[2]};
-            q[d] += s1;
-            q[d2] += s2;
-            rd = leaf(q[0], q[1], q[2]);
-          }
-    if (rd) m |= 1u << c;
+#pragma unroll
+  for (int z = 0; z < 8; ++z) {
+    const uint64_t v = w[z];
+    const uint64_t a1 = (z >= 1 ? w[z - 1] : 0) | (z <= 6 ? w[z + 1] : 0);   // one step along z
+    const uint64_t a2 = (z >= 2 ? w[z - 2] : 0) | (z <= 5 ? w[z + 2] : 0);   // two steps along z
+    const uint64_t r = (v << 1) | (v >> 1) | (v << 2) | (v >> 2)             // x
+                       | (v << 8) | (v >> 8) | (v << 16) | (v >> 16)         // y
+                       | (v << 9) | (v >> 9) | (v << 7) | (v >> 7)           // x and y
+                       | a1 | a2 | (a1 << 1) | (a1 >> 1) | (a1 << 8) | (a1 >> 8);   // z; x and z; y and z
+    if (z == sz || z == sz + 1) {
+      const int bz = z - sz;
+#pragma unroll
+      for (int by = 0; by < 2; ++by)
+#pragma unroll
+        for (int bx = 0; bx < 2; ++bx)
+          if ((r >> ((sx + bx) + 8 * (sy + by))) & 1ull) m |= 1u << (bx | (by << 1) | (bz << 2));
+    }
   }
   if (m) atomicOr(gread + (e - n_oct), m);
 }

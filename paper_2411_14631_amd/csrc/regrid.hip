@@ -29,22 +29,85 @@ __device__ __forceinline__ int64_t find_key(const uint64_t* __restrict__ key, in
   return (lo < n && key[lo] == k) ? lo : -1;
 }
 
+// Packed oct position, 21 bits per axis.
+__device__ __forceinline__ uint64_t pack_pos(int64_t x, int64_t y, int64_t z) {
+  return uint64_t(x) | (uint64_t(y) << 21) | (uint64_t(z) << 42);
+}
+
+// MurmurHash3's 64-bit finaliser (xor-shift / multiply, two rounds).
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+// Position hash of a level: open addressing with linear probing, entries
+// {packed position, oct index}, an empty entry's key all ones (no packed
+// position has bit 63 set).  At most half the entries are used, so every
+// probe sequence ends at the key or at an empty entry.
+constexpr unsigned long long kEmptyPos = ~0ull;
+
+__device__ __forceinline__ ulonglong2 hash_entry(const unsigned long long* tab, uint64_t s) {
+  return *reinterpret_cast<const ulonglong2*>(tab + 2 * s);
+}
+
+// The rest of a probe sequence whose entry at slot s held e.
+__device__ __forceinline__ int64_t hash_probe_on(const unsigned long long* tab, uint64_t mask, uint64_t k, uint64_t s,
+                                                 ulonglong2 e) {
+  while (e.x != k && e.x != kEmptyPos) {
+    s = (s + 1) & mask;
+    e = hash_entry(tab, s);
+  }
+  return e.x == k ? int64_t(e.y) : -1;
+}
+
+__device__ __forceinline__ int64_t hash_lookup(const unsigned long long* tab, uint64_t mask, uint64_t k) {
+  const uint64_t s = fmix64(k) & mask;
+  return hash_probe_on(tab, mask, k, s, hash_entry(tab, s));
+}
+
+__global__ void pos_hash_insert_kernel(const int32_t* __restrict__ oc, int64_t n, unsigned long long* tab,
+                                       uint64_t mask) {
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const unsigned long long k = pack_pos(oc[3 * o], oc[3 * o + 1], oc[3 * o + 2]);
+  uint64_t s = fmix64(k) & mask;
+  while (atomicCAS(&tab[2 * s], kEmptyPos, k) != kEmptyPos) s = (s + 1) & mask;
+  tab[2 * s + 1] = (unsigned long long)o;   // read by later launches only
+}
+
+// Integer oct position q of a level after the boundary rule (periodic
+// wrap); false when q lies outside an outflow face.
+__device__ __forceinline__ bool wrap_oct(const LevelView& L, const int32_t* bc, int64_t q[3]) {
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = L.noct[a];
+    if (q[a] < 0) {
+      if (bc[2 * a] != RY_BC_PERIODIC) return false;
+      q[a] = ((q[a] % n) + n) % n;
+    } else if (q[a] >= n) {
+      if (bc[2 * a + 1] != RY_BC_PERIODIC) return false;
+      q[a] = q[a] % n;
+    }
+  }
+  return true;
+}
+
+// Index of the oct at an in-domain position, -1 when there is none.
+__device__ __forceinline__ int64_t find_oct(const LevelView& L, int64_t x, int64_t y, int64_t z) {
+  if (L.hash) return hash_lookup(L.hash, L.hmask, pack_pos(x, y, z));
+  return find_key(L.key, L.n, hilbert3(L.bits, uint32_t(x), uint32_t(y), uint32_t(z)));
+}
+
 // Oct at integer oct position q of a level after the boundary rule: returns
 // its index, -1 when it does not exist, or -2 when q lies outside an
 // outflow face (such positions count as existing; the caller clamps).
 __device__ __forceinline__ int64_t oct_at(const LevelView& L, const int32_t* bc, int64_t qx, int64_t qy, int64_t qz) {
   int64_t q[3] = {qx, qy, qz};
-  for (int a = 0; a < 3; ++a) {
-    const int64_t n = L.noct[a];
-    if (q[a] < 0) {
-      if (bc[2 * a] != RY_BC_PERIODIC) return -2;
-      q[a] = ((q[a] % n) + n) % n;
-    } else if (q[a] >= n) {
-      if (bc[2 * a + 1] != RY_BC_PERIODIC) return -2;
-      q[a] = q[a] % n;
-    }
-  }
-  return find_key(L.key, L.n, hilbert3(L.bits, uint32_t(q[0]), uint32_t(q[1]), uint32_t(q[2])));
+  if (!wrap_oct(L, bc, q)) return -2;
+  return find_oct(L, q[0], q[1], q[2]);
 }
 
 __device__ __forceinline__ int cell_bits(int64_t x, int64_t y, int64_t z) {
@@ -60,60 +123,114 @@ __device__ __forceinline__ int64_t cell_at(const LevelView& L, const int32_t* bc
     if (p[a] < 0) p[a] = (bc[2 * a] == RY_BC_PERIODIC) ? ((p[a] % n) + n) % n : 0;
     else if (p[a] >= n) p[a] = (bc[2 * a + 1] == RY_BC_PERIODIC) ? p[a] % n : n - 1;
   }
-  const int64_t o = find_key(L.key, L.n, hilbert3(L.bits, uint32_t(p[0] >> 1), uint32_t(p[1] >> 1),
-                                                   uint32_t(p[2] >> 1)));
+  const int64_t o = find_oct(L, p[0] >> 1, p[1] >> 1, p[2] >> 1);
   return o < 0 ? -1 : o * 8 + cell_bits(p[0], p[1], p[2]);
+}
+
+// The 27 octs around oct o at (ox, oy, oz), entry (dx+1) + 3(dy+1) + 9(dz+1):
+// as oct_at.  With a hash, the first probes of a layer's nine lookups are
+// all issued before any is used.
+__device__ __forceinline__ void neighbours27(const LevelView& L, const int32_t* bc, int64_t o, int64_t ox, int64_t oy,
+                                             int64_t oz, int32_t nb[27]) {
+  if (!L.hash) {
+#pragma unroll
+    for (int j = 0; j < 27; ++j)
+      nb[j] = int32_t(j == 13 ? o : oct_at(L, bc, ox + j % 3 - 1, oy + (j / 3) % 3 - 1, oz + j / 9 - 1));
+    return;
+  }
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz) {
+    uint64_t key[9], slot[9];
+    ulonglong2 e[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      int64_t q[3] = {ox + m % 3 - 1, oy + m / 3 - 1, oz + dz - 1};
+      key[m] = wrap_oct(L, bc, q) ? pack_pos(q[0], q[1], q[2]) : kEmptyPos;   // all ones: outside
+      slot[m] = fmix64(key[m]) & L.hmask;
+    }
+#pragma unroll
+    for (int m = 0; m < 9; ++m) e[m] = hash_entry(L.hash, slot[m]);
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      const int j = m + 9 * dz;
+      if (j == 13) nb[j] = int32_t(o);
+      else if (key[m] == kEmptyPos) nb[j] = -2;
+      else nb[j] = int32_t(hash_probe_on(L.hash, L.hmask, key[m], slot[m], e[m]));
+    }
+  }
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
 }
 
 // ---------------------------------------------------------------------------
 // Flags: the build's criterion under the 26-neighbour rule.
 // ---------------------------------------------------------------------------
-__global__ void regrid_flag_kernel(LevelView L, RegridDom D, int l, const double* __restrict__ rho,
+__global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom D, int l, const double* __restrict__ rho,
                                    uint8_t* __restrict__ flag, int32_t* __restrict__ cnt) {
   const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (o >= L.n) return;
-  const int64_t ox = L.oc[3 * o], oy = L.oc[3 * o + 1], oz = L.oc[3 * o + 2];
   const double mass_thr = D.refine_param * ldexp(1.0, 3 * (l - D.lmin));
-  uint32_t have = 0;
-  bool known = false;
+  double rc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) rc[c] = rho[8 * o + c];
+  uint32_t cand = 0;   // cells the criterion looks at further
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (D.refine == RY_REFINE_MASS ? rc[c] > mass_thr : D.refine == RY_REFINE_GRAD) cand |= 1u << c;
   uint8_t f = 0;
-  for (int c = 0; c < 8; ++c) {
-    const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
-    const double rc = rho[8 * o + c];
-    if (D.refine == RY_REFINE_MASS && !(rc > mass_thr)) continue;
-    if (D.refine != RY_REFINE_MASS && D.refine != RY_REFINE_GRAD) continue;
-    if (!known) {
-      known = true;
-      for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int64_t e = (dx | dy | dz) ? oct_at(L, D.bc, ox + dx, oy + dy, oz + dz) : o;
-            if (e != -1) have |= 1u << ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
-          }
-    }
-    const int sx = bx ? 1 : -1, sy = by ? 1 : -1, sz = bz ? 1 : -1;
-    bool ok = true;
-    for (int k = 1; k < 8 && ok; ++k) {
-      const int dx = (k & 1) ? sx : 0, dy = (k & 2) ? sy : 0, dz = (k & 4) ? sz : 0;
-      if (!((have >> ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1))) & 1u)) ok = false;
-    }
-    if (!ok) continue;
-    bool want = true;
-    if (D.refine == RY_REFINE_GRAD) {
+  if (cand) {
+    const int64_t ox = L.oc[3 * o], oy = L.oc[3 * o + 1], oz = L.oc[3 * o + 2];
+    int32_t nb[27];
+    neighbours27(L, D.bc, o, ox, oy, oz, nb);
+    uint32_t have = 0;
+#pragma unroll
+    for (int j = 0; j < 27; ++j)
+      if (nb[j] != -1) have |= 1u << j;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (!((cand >> c) & 1u)) continue;
+      const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
+      // the rule: the 2x2x2 octs at the cell's outer corner all exist
+      uint32_t need = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int dx = (k & 1) ? (bx ? 1 : -1) : 0, dy = (k & 2) ? (by ? 1 : -1) : 0,
+                  dz = (k & 4) ? (bz ? 1 : -1) : 0;
+        need |= 1u << ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+      }
+      if ((have & need) != need) continue;
+      bool want = true;
+      if (D.refine == RY_REFINE_GRAD) {
 #pragma clang fp contract(off)
-      const int64_t x = 2 * ox + bx, y = 2 * oy + by, z = 2 * oz + bz;
-      // the six cells lie in octs the rule just found; checked anyway
-      const int64_t xp = cell_at(L, D.bc, x + 1, y, z), xm = cell_at(L, D.bc, x - 1, y, z);
-      const int64_t yp = cell_at(L, D.bc, x, y + 1, z), ym = cell_at(L, D.bc, x, y - 1, z);
-      const int64_t zp = cell_at(L, D.bc, x, y, z + 1), zm = cell_at(L, D.bc, x, y, z - 1);
-      if ((xp | xm | yp | ym | zp | zm) < 0) continue;
-      const double gx = 0.5 * (rho[xp] - rho[xm]);
-      const double gy = 0.5 * (rho[yp] - rho[ym]);
-      const double gz = 0.5 * (rho[zp] - rho[zm]);
-      const double th = D.refine_param;
-      want = gx * gx + gy * gy + gz * gz > (th * rc) * (th * rc);
+        // the six face-neighbour cells (-1 and +1 along x, y, z): the other
+        // cell of the oct along that axis, or a cell of the face-neighbour
+        // oct on the cell's side (the cell itself past an outflow face)
+        int64_t nc[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const int b = (c >> a) & 1;
+            if (b != s) {
+              nc[2 * a + s] = 8 * o + (c ^ (1 << a));
+            } else {
+              const int32_t e = nb[13 + (s ? 1 : -1) * (a == 0 ? 1 : a == 1 ? 3 : 9)];
+              nc[2 * a + s] = e >= 0 ? 8 * int64_t(e) + (c ^ (1 << a)) : (e == -2 ? 8 * o + c : -1);
+            }
+          }
+        if ((nc[0] | nc[1] | nc[2] | nc[3] | nc[4] | nc[5]) < 0) continue;
+        const double gx = 0.5 * (rho[nc[1]] - rho[nc[0]]);
+        const double gy = 0.5 * (rho[nc[3]] - rho[nc[2]]);
+        const double gz = 0.5 * (rho[nc[5]] - rho[nc[4]]);
+        const double th = D.refine_param;
+        want = gx * gx + gy * gy + gz * gz > (th * rc[c]) * (th * rc[c]);
+      }
+      if (want) f |= uint8_t(1u << c);
     }
-    if (want) f |= uint8_t(1u << c);
   }
   flag[o] = f;
   cnt[o] = __popc(uint32_t(f));
@@ -123,17 +240,16 @@ __global__ void regrid_flag_kernel(LevelView L, RegridDom D, int l, const double
 // Children of the refined cells (level l+1) in Hilbert order, their
 // mapping to the old level l+1 and the interpolation sources of new octs.
 // ---------------------------------------------------------------------------
-__global__ void regrid_children_kernel(LevelView C, LevelView Fold, RegridDom D, int fbits,
-                                       const uint8_t* __restrict__ flag, const int32_t* __restrict__ off,
-                                       uint64_t* __restrict__ nkey, int32_t* __restrict__ noc,
-                                       int32_t* __restrict__ parent, int32_t* __restrict__ child,
-                                       int32_t* __restrict__ src_old, int32_t* __restrict__ src7,
-                                       int32_t* __restrict__ err) {
-  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (o >= C.n) return;
+// Children of oct o; returns how many were found in the old level.
+__device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const LevelView& Fold, const RegridDom& D,
+                                           int fbits, const uint8_t* __restrict__ flag,
+                                           const int32_t* __restrict__ off, uint64_t* __restrict__ nkey,
+                                           int32_t* __restrict__ noc, int32_t* __restrict__ parent,
+                                           int32_t* __restrict__ child, int32_t* __restrict__ src_old,
+                                           int32_t* __restrict__ src7, int32_t* __restrict__ err) {
   const uint8_t f = flag[o];
   for (int c = 0; c < 8; ++c) child[8 * o + c] = -1;
-  if (!f) return;
+  if (!f) return 0;
   const int64_t ox = C.oc[3 * o], oy = C.oc[3 * o + 1], oz = C.oc[3 * o + 2];
   uint64_t k8[8];
   int c8[8];
@@ -153,6 +269,7 @@ __global__ void regrid_children_kernel(LevelView C, LevelView Fold, RegridDom D,
     c8[j] = c;
   }
   const int64_t base = off[o];
+  int kept = 0;
   for (int j = 0; j < m; ++j) {
     const int c = c8[j];
     const int64_t k = base + j;
@@ -163,9 +280,12 @@ __global__ void regrid_children_kernel(LevelView C, LevelView Fold, RegridDom D,
     noc[3 * k + 2] = int32_t(z);
     parent[k] = int32_t(o * 8 + c);
     child[8 * o + c] = int32_t(k);
-    const int64_t so = find_key(Fold.key, Fold.n, k8[j]);
+    const int64_t so = Fold.n ? find_oct(Fold, x, y, z) : -1;
     src_old[k] = int32_t(so);
-    if (so >= 0) continue;
+    if (so >= 0) {
+      ++kept;
+      continue;
+    }
     // parent cell Q = (x, y, z) of level l and its six face neighbours
     src7[7 * k] = int32_t(o * 8 + c);
     for (int a = 0; a < 3; ++a)
@@ -180,6 +300,20 @@ __global__ void regrid_children_kernel(LevelView C, LevelView Fold, RegridDom D,
         src7[7 * k + 1 + 2 * a + s] = int32_t(r);
       }
   }
+  return kept;
+}
+
+__global__ __launch_bounds__(256) void regrid_children_kernel(LevelView C, LevelView Fold, RegridDom D, int fbits,
+                                       const uint8_t* __restrict__ flag, const int32_t* __restrict__ off,
+                                       uint64_t* __restrict__ nkey, int32_t* __restrict__ noc,
+                                       int32_t* __restrict__ parent, int32_t* __restrict__ child,
+                                       int32_t* __restrict__ src_old, int32_t* __restrict__ src7,
+                                       int32_t* __restrict__ err, unsigned long long* __restrict__ kept) {
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int n = 0;
+  if (o < C.n) n = children_of(o, C, Fold, D, fbits, flag, off, nkey, noc, parent, child, src_old, src7, err);
+  n = wave_sum(n);   // every lane of the wavefront takes part (blocks of whole wavefronts)
+  if ((threadIdx.x & 63) == 0 && n) atomicAdd(kept, (unsigned long long)n);
 }
 
 // ---------------------------------------------------------------------------
@@ -307,9 +441,6 @@ __global__ void tile_table_kernel(LevelView L, RegridDom D, const int32_t* __res
 }
 
 // Missing entries in (tile, slot) order: their wrapped oct positions.
-__device__ __forceinline__ uint64_t pack_pos(int64_t x, int64_t y, int64_t z) {
-  return uint64_t(x) | (uint64_t(y) << 21) | (uint64_t(z) << 42);
-}
 
 __global__ void missing_list_kernel(LevelView L, const int32_t* __restrict__ first, int32_t n_tile,
                                     const int32_t* __restrict__ miss, const int32_t* __restrict__ midx,
@@ -442,6 +573,21 @@ int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const dou
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+uint64_t pos_hash_entries(int64_t n) {
+  uint64_t e = 64;
+  while (e < 2 * uint64_t(n)) e <<= 1;
+  return e;
+}
+
+int launch_pos_hash(const int32_t* oc, int64_t n, unsigned long long* tab, uint64_t entries, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks(int64_t(2 * entries))), dim3(256), 0, s, tab, int64_t(2 * entries),
+                     kEmptyPos);
+  if (n > 0)
+    hipLaunchKernelGGL(pos_hash_insert_kernel, dim3(blocks(n)), dim3(256), 0, s, oc, n, tab, entries - 1);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int scan_tmp_ints(int64_t n) { return int((n + SCAN_BLOCK - 1) / SCAN_BLOCK) + 2; }
 
 int launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, void* stream) {
@@ -460,10 +606,11 @@ int launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, void* 
 
 int launch_regrid_children(const LevelView& C, const LevelView& Fold, const RegridDom& D, int fbits,
                            const uint8_t* flag, const int32_t* off, uint64_t* nkey, int32_t* noc, int32_t* parent,
-                           int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err, void* stream) {
+                           int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err,
+                           unsigned long long* kept, void* stream) {
   if (C.n == 0) return 0;
   hipLaunchKernelGGL(regrid_children_kernel, dim3(blocks(C.n)), dim3(256), 0, (hipStream_t)stream, C, Fold, D, fbits,
-                     flag, off, nkey, noc, parent, child, src_old, src7, err);
+                     flag, off, nkey, noc, parent, child, src_old, src7, err, kept);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

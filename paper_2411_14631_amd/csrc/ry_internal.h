@@ -273,7 +273,18 @@ struct LevelView {
   int64_t n;
   int32_t bits;                      // Hilbert bits per axis at this level
   int32_t noct[3];                   // octs per axis at this level
+  // optional position hash of the level's octs (launch_pos_hash); null:
+  // octs are found by binary search of their key
+  const unsigned long long* hash;
+  uint64_t hmask;                    // hash entries - 1 (a power of two minus one)
 };
+// Hash entries (16 bytes each) for n octs: a power of two >= 2n, so that
+// at most half the entries are used.
+uint64_t pos_hash_entries(int64_t n);
+// Position hash of a level's n octs (oc: 3 int32 per oct): tab holds
+// pos_hash_entries(n) entries of two unsigned long long {packed position,
+// oct index}; cleared and filled on the stream.
+int launch_pos_hash(const int32_t* oc, int64_t n, unsigned long long* tab, uint64_t entries, void* stream);
 struct RegridDom {
   int32_t bc[6];
   int32_t lmin;
@@ -286,9 +297,12 @@ int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const dou
 // tmp[scan_tmp_ints(n) - 1])
 int scan_tmp_ints(int64_t n);
 int launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, void* stream);
+// Children of level C's flagged cells (one thread per oct of C); kept gets
+// the number of children found in the old child level Fold added.
 int launch_regrid_children(const LevelView& C, const LevelView& Fold, const RegridDom& D, int fbits,
                            const uint8_t* flag, const int32_t* off, uint64_t* nkey, int32_t* noc, int32_t* parent,
-                           int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err, void* stream);
+                           int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err,
+                           unsigned long long* kept, void* stream);
 int launch_tile_starts(const uint64_t* key, int64_t n, int32_t* start, void* stream);
 int launch_tile_first(const int32_t* start, const int32_t* tid, int64_t n, int32_t n_tile, int32_t* first,
                       void* stream);
