@@ -1010,13 +1010,39 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
   };
   std::vector<NewLevel> N(nl);
   std::vector<unsigned long long*> H(nl, nullptr);   // position hash of each new level
+  std::vector<std::vector<LevelView>> coarse_views;   // host sources of async copies, kept to the end
   std::vector<uint64_t> HE(nl, 0);                    // its entries
   std::vector<void*> fresh, temps;   // new level arrays / scratch of this call
   bool ok = true;
+  // new level arrays: one allocation each (they outlive the call); scratch:
+  // 256-byte-aligned pieces of a few large chunks (64 MiB, then doubling),
+  // all released at the end
+  struct Chunk {
+    char* base;
+    size_t size, used;
+  };
+  std::vector<Chunk> chunks;
   auto A = [&](size_t bytes, bool temp) -> void* {
-    void* p = dalloc(c, bytes);
-    if (!p) ok = false;
-    else (temp ? temps : fresh).push_back(p);
+    if (!temp) {
+      void* p = dalloc(c, bytes);
+      if (!p) ok = false;
+      else fresh.push_back(p);
+      return p;
+    }
+    bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+    if (chunks.empty() || chunks.back().used + bytes > chunks.back().size) {
+      const size_t sz = std::max(bytes, chunks.empty() ? size_t(64) << 20 : 2 * chunks.back().size);
+      void* p = dalloc(c, sz);
+      if (!p) {
+        ok = false;
+        return nullptr;
+      }
+      temps.push_back(p);
+      chunks.push_back({static_cast<char*>(p), sz, 0});
+    }
+    Chunk& ch = chunks.back();
+    void* p = ch.base + ch.used;
+    ch.used += bytes;
     return p;
   };
   auto release = [&](std::vector<void*>& v) {
@@ -1103,6 +1129,11 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     RG_TRY(ok, RY_ENOMEM, "allocation failed");
     RG_TRY(!launch_pos_hash(L.oc, L.n, H[k], HE[k], st), RY_EHIP, "position hash kernel");
     const LevelView V = view(k);
+    // what the flag kernel reads of the tiles (refined levels) or of a
+    // complete level (the base level, when it holds every position)
+    FlagTiles FT{};
+    FT.n_oct = L.n;
+    FT.complete = k == 0 && L.n == c->dom.noct(l, 0) * c->dom.noct(l, 1) * c->dom.noct(l, 2);
     if (k > 0) {
       // tiles: octs sharing key >> 3
       int32_t* start = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
@@ -1120,10 +1151,15 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
       L.tflag = static_cast<uint32_t*>(A(sizeof(uint32_t) * nt, false));
       int32_t* miss = static_cast<int32_t*>(A(sizeof(int32_t) * nslot, true));
       int32_t* midx = static_cast<int32_t*>(A(sizeof(int32_t) * nslot, true));
+      auto* pres = static_cast<unsigned long long*>(A(sizeof(unsigned long long) * nt, true));
       RG_TRY(ok, RY_ENOMEM, "allocation failed");
+      FT.start = start;
+      FT.tid = tid;
+      FT.pres = pres;
+      FT.tab = L.tab;
       int64_t nm = 0;
       RG_TRY(!launch_tile_first(start, tid, L.n, L.n_tile, first, st) &&
-                 !launch_tile_table(V, RD, first, L.n_tile, L.tab, L.tflag, miss, st) &&
+                 !launch_tile_table(V, RD, first, L.n_tile, L.tab, L.tflag, miss, pres, st) &&
                  scan_total(miss, midx, nslot, nm),
              RY_EHIP, "tile table kernels");
       // ghost octs: numbered by first use over (tile, slot)
@@ -1152,14 +1188,14 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
         L.n_ghost = h;
       }
       if (L.n_ghost > 0) {
-        std::vector<LevelView> cv(k);
+        coarse_views.emplace_back(k);
+        std::vector<LevelView>& cv = coarse_views.back();
         for (int j = 0; j < k; ++j) cv[j] = view(k - 1 - j);
         LevelView* d_cv = static_cast<LevelView*>(A(sizeof(LevelView) * k, true));
         L.gsrc = static_cast<int64_t*>(A(sizeof(int64_t) * 7 * L.n_ghost, false));
         RG_TRY(ok, RY_ENOMEM, "allocation failed");
         RG_TRY(hipMemcpyAsync(d_cv, cv.data(), sizeof(LevelView) * k, hipMemcpyHostToDevice, st) == hipSuccess &&
-                   !launch_ghost_sources(d_cv, k, RD, gpos, L.n_ghost, L.gsrc, d_err, st) &&
-                   hipStreamSynchronize(st) == hipSuccess,
+                   !launch_ghost_sources(d_cv, k, RD, gpos, L.n_ghost, L.gsrc, d_err, st),
                RY_EHIP, "ghost source kernel");
       }
       // state: kept octs copied, new octs interpolated from level l-1
@@ -1189,7 +1225,7 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
       int32_t* cnt = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
       int32_t* off = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
       RG_TRY(ok, RY_ENOMEM, "allocation failed");
-      RG_TRY(!launch_regrid_flags(V, RD, l, L.U[0], L.flag, cnt, st) && scan_total(cnt, off, L.n, n_fine), RY_EHIP,
+      RG_TRY(!launch_regrid_flags(V, RD, l, L.U[0], FT, L.flag, cnt, st) && scan_total(cnt, off, L.n, n_fine), RY_EHIP,
              "regrid flag kernel");
       NewLevel& F = N[k + 1];
       F.n = n_fine;

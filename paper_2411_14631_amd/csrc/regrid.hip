@@ -82,6 +82,7 @@ __global__ void pos_hash_insert_kernel(const int32_t* __restrict__ oc, int64_t n
 // Integer oct position q of a level after the boundary rule (periodic
 // wrap); false when q lies outside an outflow face.
 __device__ __forceinline__ bool wrap_oct(const LevelView& L, const int32_t* bc, int64_t q[3]) {
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int64_t n = L.noct[a];
     if (q[a] < 0) {
@@ -118,6 +119,7 @@ __device__ __forceinline__ int cell_bits(int64_t x, int64_t y, int64_t z) {
 // rule (periodic wrap, outflow clamp); -1 when its oct does not exist.
 __device__ __forceinline__ int64_t cell_at(const LevelView& L, const int32_t* bc, int64_t x, int64_t y, int64_t z) {
   int64_t p[3] = {x, y, z};
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int64_t n = 2 * int64_t(L.noct[a]);
     if (p[a] < 0) p[a] = (bc[2 * a] == RY_BC_PERIODIC) ? ((p[a] % n) + n) % n : 0;
@@ -127,37 +129,34 @@ __device__ __forceinline__ int64_t cell_at(const LevelView& L, const int32_t* bc
   return o < 0 ? -1 : o * 8 + cell_bits(p[0], p[1], p[2]);
 }
 
-// The 27 octs around oct o at (ox, oy, oz), entry (dx+1) + 3(dy+1) + 9(dz+1):
-// as oct_at.  With a hash, the first probes of a layer's nine lookups are
-// all issued before any is used.
-__device__ __forceinline__ void neighbours27(const LevelView& L, const int32_t* bc, int64_t o, int64_t ox, int64_t oy,
-                                             int64_t oz, int32_t nb[27]) {
+// The six face-neighbour octs of oct o (-x, +x, -y, +y, -z, +z), as oct_at:
+// index, -1 absent, -2 outside an outflow face.  With a hash, the six first
+// probes are issued together.
+__device__ __forceinline__ void face_neighbours(const LevelView& L, const int32_t* bc, int64_t ox, int64_t oy,
+                                                int64_t oz, int32_t nb[6]) {
   if (!L.hash) {
 #pragma unroll
-    for (int j = 0; j < 27; ++j)
-      nb[j] = int32_t(j == 13 ? o : oct_at(L, bc, ox + j % 3 - 1, oy + (j / 3) % 3 - 1, oz + j / 9 - 1));
+    for (int m = 0; m < 6; ++m) {
+      const int64_t st = (m & 1) ? 1 : -1;
+      nb[m] = int32_t(oct_at(L, bc, ox + (m >> 1 == 0 ? st : 0), oy + (m >> 1 == 1 ? st : 0),
+                             oz + (m >> 1 == 2 ? st : 0)));
+    }
     return;
   }
+  uint64_t key[6], slot[6];
+  ulonglong2 e[6];
 #pragma unroll
-  for (int dz = 0; dz < 3; ++dz) {
-    uint64_t key[9], slot[9];
-    ulonglong2 e[9];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-      int64_t q[3] = {ox + m % 3 - 1, oy + m / 3 - 1, oz + dz - 1};
-      key[m] = wrap_oct(L, bc, q) ? pack_pos(q[0], q[1], q[2]) : kEmptyPos;   // all ones: outside
-      slot[m] = fmix64(key[m]) & L.hmask;
-    }
-#pragma unroll
-    for (int m = 0; m < 9; ++m) e[m] = hash_entry(L.hash, slot[m]);
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-      const int j = m + 9 * dz;
-      if (j == 13) nb[j] = int32_t(o);
-      else if (key[m] == kEmptyPos) nb[j] = -2;
-      else nb[j] = int32_t(hash_probe_on(L.hash, L.hmask, key[m], slot[m], e[m]));
-    }
+  for (int m = 0; m < 6; ++m) {
+    const int64_t st = (m & 1) ? 1 : -1;
+    int64_t q[3] = {ox + (m >> 1 == 0 ? st : 0), oy + (m >> 1 == 1 ? st : 0), oz + (m >> 1 == 2 ? st : 0)};
+    key[m] = wrap_oct(L, bc, q) ? pack_pos(q[0], q[1], q[2]) : kEmptyPos;   // all ones: outside
+    slot[m] = fmix64(key[m]) & L.hmask;
   }
+#pragma unroll
+  for (int m = 0; m < 6; ++m) e[m] = hash_entry(L.hash, slot[m]);
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+    nb[m] = key[m] == kEmptyPos ? -2 : int32_t(hash_probe_on(L.hash, L.hmask, key[m], slot[m], e[m]));
 }
 
 __device__ __forceinline__ int wave_sum(int v) {
@@ -169,8 +168,9 @@ __device__ __forceinline__ int wave_sum(int v) {
 // ---------------------------------------------------------------------------
 // Flags: the build's criterion under the 26-neighbour rule.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom D, int l, const double* __restrict__ rho,
-                                   uint8_t* __restrict__ flag, int32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom D, int l,
+                                                          const double* __restrict__ rho, FlagTiles T,
+                                                          uint8_t* __restrict__ flag, int32_t* __restrict__ cnt) {
   const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (o >= L.n) return;
   const double mass_thr = D.refine_param * ldexp(1.0, 3 * (l - D.lmin));
@@ -184,12 +184,40 @@ __global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom
   uint8_t f = 0;
   if (cand) {
     const int64_t ox = L.oc[3 * o], oy = L.oc[3 * o + 1], oz = L.oc[3 * o + 2];
-    int32_t nb[27];
-    neighbours27(L, D.bc, o, ox, oy, oz, nb);
+    const bool grad = D.refine == RY_REFINE_GRAD;
+    // have: bit (dx+1) + 3(dy+1) + 9(dz+1) when the oct position at that
+    // offset holds an oct or lies outside an outflow face; nb6: the face
+    // neighbours (-x, +x, -y, +y, -z, +z) as oct_at, for the gradient
     uint32_t have = 0;
+    int32_t nb6[6] = {-1, -1, -1, -1, -1, -1};
+    if (T.pres) {
+      // the oct sits at (1 + (ox & 1), ...) in its tile's 4x4x4 table
+      const int32_t t = T.tid[o] + T.start[o] - 1;
+      const int px = 1 + int(ox & 1), py = 1 + int(oy & 1), pz = 1 + int(oz & 1);
+      const unsigned long long q = T.pres[t] >> ((px - 1) + 4 * (py - 1) + 16 * (pz - 1));
 #pragma unroll
-    for (int j = 0; j < 27; ++j)
-      if (nb[j] != -1) have |= 1u << j;
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) have |= uint32_t((q >> (4 * dy + 16 * dz)) & 7u) << (3 * dy + 9 * dz);
+      if (grad) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          const int st = (m & 1) ? 1 : -1, a = m >> 1;
+          const int32_t v = T.tab[int64_t(t) * TILE_TAB + (px + (a == 0 ? st : 0)) + 4 * (py + (a == 1 ? st : 0)) +
+                                  16 * (pz + (a == 2 ? st : 0))];
+          // a present oct's face neighbours are all in the table: the oct,
+          // a ghost / missing entry, or -1 outside an outflow face
+          nb6[m] = (v >= 0 && v < T.n_oct) ? v : (v == -1 ? -2 : -1);
+        }
+      }
+    } else if (T.complete) {
+      have = (1u << 27) - 1;
+      if (grad) face_neighbours(L, D.bc, ox, oy, oz, nb6);
+    } else {   // a base level that does not hold every position: one lookup after another
+      for (int j = 0; j < 27; ++j)
+        if (j == 13 || oct_at(L, D.bc, ox + j % 3 - 1, oy + (j / 3) % 3 - 1, oz + j / 9 - 1) != -1) have |= 1u << j;
+      if (grad) face_neighbours(L, D.bc, ox, oy, oz, nb6);
+    }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       if (!((cand >> c) & 1u)) continue;
@@ -204,7 +232,7 @@ __global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom
       }
       if ((have & need) != need) continue;
       bool want = true;
-      if (D.refine == RY_REFINE_GRAD) {
+      if (grad) {
 #pragma clang fp contract(off)
         // the six face-neighbour cells (-1 and +1 along x, y, z): the other
         // cell of the oct along that axis, or a cell of the face-neighbour
@@ -218,7 +246,7 @@ __global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom
             if (b != s) {
               nc[2 * a + s] = 8 * o + (c ^ (1 << a));
             } else {
-              const int32_t e = nb[13 + (s ? 1 : -1) * (a == 0 ? 1 : a == 1 ? 3 : 9)];
+              const int32_t e = nb6[2 * a + s];
               nc[2 * a + s] = e >= 0 ? 8 * int64_t(e) + (c ^ (1 << a)) : (e == -2 ? 8 * o + c : -1);
             }
           }
@@ -240,6 +268,44 @@ __global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom
 // Children of the refined cells (level l+1) in Hilbert order, their
 // mapping to the old level l+1 and the interpolation sources of new octs.
 // ---------------------------------------------------------------------------
+// Last key digits of the 8 children of the oct at (px, py, pz), bits 3c..3c+2
+// for child c (x + 2y + 4z), for a child level of `bits` bits per axis.  A
+// child's key is its parent's key followed by one digit, so only the digit
+// is missing.  In the transpose algorithm every decision (which axes swap,
+// which flip) reads bits above the lowest one, and the lowest bit only
+// moves between the axes or flips; so one pass over the parent's bits, with
+// the lowest bit of each axis replaced by an 8-bit mask of its value in the
+// 8 children (x: 0xAA, y: 0xCC, z: 0xF0) and the parent's bits shifted
+// above it, carries all 8 children at once.  Needs bits + 7 <= 32.
+__device__ __forceinline__ uint32_t child_digits(int bits, uint32_t px, uint32_t py, uint32_t pz) {
+  uint32_t a[3] = {(px << 8) | 0xAAu, (py << 8) | 0xCCu, (pz << 8) | 0xF0u};
+  const uint32_t top = 1u << (bits + 6);   // the parent's top bit
+  for (uint32_t q = top; q > 0x80u; q >>= 1) {
+    const uint32_t low = q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (a[i] & q) {
+        a[0] ^= low;
+      } else {
+        const uint32_t swap = (a[0] ^ a[i]) & low;
+        a[0] ^= swap;
+        a[i] ^= swap;
+      }
+    }
+  }
+  a[1] ^= a[0];
+  a[2] ^= a[1];
+  uint32_t flip = 0;
+  for (uint32_t q = top; q > 0x80u; q >>= 1)
+    if (a[2] & q) flip ^= q - 1;
+  uint32_t d = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    d |= (((((a[0] ^ flip) >> c) & 1u) << 2) | ((((a[1] ^ flip) >> c) & 1u) << 1) | (((a[2] ^ flip) >> c) & 1u))
+         << (3 * c);
+  return d;
+}
+
+
 // Children of oct o; returns how many were found in the old level.
 __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const LevelView& Fold, const RegridDom& D,
                                            int fbits, const uint8_t* __restrict__ flag,
@@ -251,54 +317,84 @@ __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const 
   for (int c = 0; c < 8; ++c) child[8 * o + c] = -1;
   if (!f) return 0;
   const int64_t ox = C.oc[3 * o], oy = C.oc[3 * o + 1], oz = C.oc[3 * o + 2];
-  uint64_t k8[8];
-  int c8[8];
-  int m = 0;
-  for (int c = 0; c < 8; ++c) {
-    if (!((f >> c) & 1)) continue;
-    const uint32_t x = uint32_t(2 * ox + (c & 1)), y = uint32_t(2 * oy + ((c >> 1) & 1)),
-                   z = uint32_t(2 * oz + ((c >> 2) & 1));
-    const uint64_t k = hilbert3(fbits, x, y, z);
-    int j = m++;
-    while (j > 0 && k8[j - 1] > k) {   // insertion sort by key
-      k8[j] = k8[j - 1];
-      c8[j] = c8[j - 1];
-      --j;
+  const uint64_t pkey = C.key[o];
+  const uint32_t dg = child_digits(fbits, uint32_t(ox), uint32_t(oy), uint32_t(oz));
+  uint32_t fd = 0;   // digits of the flagged children: a child's rank among them is its output slot
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if ((f >> c) & 1) fd |= 1u << ((dg >> (3 * c)) & 7u);
+  // the flagged children in the old level (-1: new): first probes issued together
+  int32_t so8[8];
+  if (Fold.hash) {
+    uint64_t fk[8], fs[8];
+    ulonglong2 fe[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      fk[c] = pack_pos(2 * ox + (c & 1), 2 * oy + ((c >> 1) & 1), 2 * oz + (c >> 2));
+      fs[c] = fmix64(fk[c]) & Fold.hmask;
     }
-    k8[j] = k;
-    c8[j] = c;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) fe[c] = hash_entry(Fold.hash, fs[c]);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      so8[c] = ((f >> c) & 1) ? int32_t(hash_probe_on(Fold.hash, Fold.hmask, fk[c], fs[c], fe[c])) : -1;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      so8[c] = ((f >> c) & 1) && Fold.n ? int32_t(find_oct(Fold, 2 * ox + (c & 1), 2 * oy + ((c >> 1) & 1),
+                                                          2 * oz + (c >> 2)))
+                                        : -1;
   }
   const int64_t base = off[o];
   int kept = 0;
-  for (int j = 0; j < m; ++j) {
-    const int c = c8[j];
-    const int64_t k = base + j;
+  uint32_t fresh = 0;   // children not in the old level
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (!((f >> c) & 1)) continue;
+    const uint32_t d = (dg >> (3 * c)) & 7u;
+    const int64_t k = base + __popc(fd & ((1u << d) - 1u));
     const int64_t x = 2 * ox + (c & 1), y = 2 * oy + ((c >> 1) & 1), z = 2 * oz + ((c >> 2) & 1);
-    nkey[k] = k8[j];
+    nkey[k] = (pkey << 3) | uint64_t(d);
     noc[3 * k] = int32_t(x);
     noc[3 * k + 1] = int32_t(y);
     noc[3 * k + 2] = int32_t(z);
     parent[k] = int32_t(o * 8 + c);
     child[8 * o + c] = int32_t(k);
-    const int64_t so = Fold.n ? find_oct(Fold, x, y, z) : -1;
-    src_old[k] = int32_t(so);
-    if (so >= 0) {
-      ++kept;
-      continue;
-    }
-    // parent cell Q = (x, y, z) of level l and its six face neighbours
-    src7[7 * k] = int32_t(o * 8 + c);
-    for (int a = 0; a < 3; ++a)
-      for (int s = 0; s < 2; ++s) {
-        int64_t p[3] = {x, y, z};
-        p[a] += s ? 1 : -1;
-        int64_t r = cell_at(C, D.bc, p[0], p[1], p[2]);
-        if (r < 0) {             // excluded by the neighbour rule; reported, read kept in bounds
-          atomicOr(err, 1);
-          r = o * 8 + c;
+    src_old[k] = so8[c];
+    if (so8[c] >= 0) ++kept;
+    else fresh |= 1u << c;
+  }
+  // interpolation sources of the new children: the parent cell Q and its
+  // six face neighbours (cell_at's rule), each the other cell of the oct
+  // along that axis or a cell of the face-neighbour oct on Q's side (Q
+  // itself past an outflow face)
+  if (fresh) {
+    int32_t nb[6];
+    face_neighbours(C, D.bc, ox, oy, oz, nb);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (!((fresh >> c) & 1)) continue;
+      const int64_t k = base + __popc(fd & ((1u << ((dg >> (3 * c)) & 7u)) - 1u));
+      const int64_t q = o * 8 + c;
+      src7[7 * k] = int32_t(q);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          int64_t r;
+          if (((c >> a) & 1) != s) {
+            r = o * 8 + (c ^ (1 << a));
+          } else {
+            const int32_t e = nb[2 * a + s];
+            r = e >= 0 ? 8 * int64_t(e) + (c ^ (1 << a)) : (e == -2 ? q : -1);
+          }
+          if (r < 0) {   // excluded by the neighbour rule; reported, read kept in bounds
+            atomicOr(err, 1);
+            r = q;
+          }
+          src7[7 * k + 1 + 2 * a + s] = int32_t(r);
         }
-        src7[7 * k + 1 + 2 * a + s] = int32_t(r);
-      }
+    }
   }
   return kept;
 }
@@ -397,14 +493,18 @@ __global__ void tile_first_kernel(const int32_t* __restrict__ start, const int32
   if (o == 0) first[n_tile] = int32_t(n);
 }
 
-// One thread per (tile, slot): the tile's 4x4x4 oct neighbourhood.  tab
-// gets the oct index, -1 (not needed, or outside an outflow face) or -2
-// (missing: a ghost oct, numbered later); miss = 1 for missing entries.
+// One wavefront per tile, one lane per slot: the tile's 4x4x4 oct
+// neighbourhood.  tab gets the oct index, -1 (not needed, or outside an
+// outflow face) or -2 (missing: a ghost oct, numbered later); miss = 1 for
+// missing entries; pres gets bit slot set when the position holds an oct or
+// lies outside an outflow face (every slot looked up, needed or not: the
+// refinement flags' neighbour rule reads the corners too).
 __global__ void tile_table_kernel(LevelView L, RegridDom D, const int32_t* __restrict__ first, int32_t n_tile,
                                   int32_t* __restrict__ tab, uint32_t* __restrict__ tflag,
-                                  int32_t* __restrict__ miss) {
+                                  int32_t* __restrict__ miss, unsigned long long* __restrict__ pres) {
+  static_assert(TILE_TAB == 64, "one wavefront per tile");
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= int64_t(n_tile) * TILE_TAB) return;
+  if (i >= int64_t(n_tile) * TILE_TAB) return;   // whole wavefronts: blocks of whole wavefronts, 64 slots a tile
   const int t = int(i / TILE_TAB), slot = int(i % TILE_TAB);
   const int rx = slot % 4 - 1, ry_ = (slot / 4) % 4 - 1, rz = slot / 16 - 1;
   const int64_t o0 = first[t], o1 = first[t + 1];
@@ -427,9 +527,11 @@ __global__ void tile_table_kernel(LevelView L, RegridDom D, const int32_t* __res
     if (bz + 2 == L.noct[2] && D.bc[5] == RY_BC_OUTFLOW) fl |= CL_HIZ;
     tflag[t] = fl;
   }
+  const int64_t e = oct_at(L, D.bc, bx + rx, by + ry_, bz + rz);
+  const unsigned long long p = __ballot(e != -1);
+  if (slot == 0) pres[t] = p;
   int32_t v = -1, m = 0;
   if (needed) {
-    const int64_t e = oct_at(L, D.bc, bx + rx, by + ry_, bz + rz);
     if (e >= 0) v = int32_t(e);
     else if (e == -1) {
       v = -2;
@@ -565,10 +667,11 @@ inline unsigned blocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b
 }  // namespace
 
 // ------------------------------------------------------------- launchers
-int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const double* rho, uint8_t* flag, int32_t* cnt,
-                        void* stream) {
+int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const double* rho, const FlagTiles& T,
+                        uint8_t* flag, int32_t* cnt, void* stream) {
   if (L.n == 0) return 0;
-  hipLaunchKernelGGL(regrid_flag_kernel, dim3(blocks(L.n)), dim3(256), 0, (hipStream_t)stream, L, D, l, rho, flag,
+  if (T.pres && (!T.start || !T.tid || !T.tab)) return -1;
+  hipLaunchKernelGGL(regrid_flag_kernel, dim3(blocks(L.n)), dim3(256), 0, (hipStream_t)stream, L, D, l, rho, T, flag,
                      cnt);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -609,6 +712,7 @@ int launch_regrid_children(const LevelView& C, const LevelView& Fold, const Regr
                            int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err,
                            unsigned long long* kept, void* stream) {
   if (C.n == 0) return 0;
+  if (fbits < 1 || fbits > 25) return -1;   // child_digits' range
   hipLaunchKernelGGL(regrid_children_kernel, dim3(blocks(C.n)), dim3(256), 0, (hipStream_t)stream, C, Fold, D, fbits,
                      flag, off, nkey, noc, parent, child, src_old, src7, err, kept);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -629,10 +733,10 @@ int launch_tile_first(const int32_t* start, const int32_t* tid, int64_t n, int32
 }
 
 int launch_tile_table(const LevelView& L, const RegridDom& D, const int32_t* first, int32_t n_tile, int32_t* tab,
-                      uint32_t* tflag, int32_t* miss, void* stream) {
+                      uint32_t* tflag, int32_t* miss, unsigned long long* pres, void* stream) {
   if (n_tile == 0) return 0;
   hipLaunchKernelGGL(tile_table_kernel, dim3(blocks(int64_t(n_tile) * TILE_TAB)), dim3(256), 0, (hipStream_t)stream,
-                     L, D, first, n_tile, tab, tflag, miss);
+                     L, D, first, n_tile, tab, tflag, miss, pres);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

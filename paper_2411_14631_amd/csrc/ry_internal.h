@@ -291,8 +291,22 @@ struct RegridDom {
   int32_t refine;
   double refine_param;
 };
-int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const double* rho, uint8_t* flag, int32_t* cnt,
-                        void* stream);
+// Refinement flags of level l (rho: the density plane).  The neighbour rule
+// reads the level's tile presence masks when given (pres; oct o's tile is
+// tid[o] + start[o] - 1: tid the exclusive scan of the tile-start flags
+// start), else takes every position as holding an oct when complete != 0,
+// else looks the octs up; the gradient criterion takes the face neighbours
+// from the tile tables (tab, n_oct) when given, else looks them up.
+struct FlagTiles {
+  const int32_t* start;
+  const int32_t* tid;
+  const unsigned long long* pres;
+  const int32_t* tab;
+  int64_t n_oct;
+  int32_t complete;
+};
+int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const double* rho, const FlagTiles& T,
+                        uint8_t* flag, int32_t* cnt, void* stream);
 // exclusive scan of n int32 (tmp: scan_tmp_ints(n) ints; the total lands in
 // tmp[scan_tmp_ints(n) - 1])
 int scan_tmp_ints(int64_t n);
@@ -306,8 +320,10 @@ int launch_regrid_children(const LevelView& C, const LevelView& Fold, const Regr
 int launch_tile_starts(const uint64_t* key, int64_t n, int32_t* start, void* stream);
 int launch_tile_first(const int32_t* start, const int32_t* tid, int64_t n, int32_t n_tile, int32_t* first,
                       void* stream);
+// pres: per tile, bit slot set when the slot's position holds an oct or lies
+// outside an outflow face
 int launch_tile_table(const LevelView& L, const RegridDom& D, const int32_t* first, int32_t n_tile, int32_t* tab,
-                      uint32_t* tflag, int32_t* miss, void* stream);
+                      uint32_t* tflag, int32_t* miss, unsigned long long* pres, void* stream);
 int launch_missing_list(const LevelView& L, const int32_t* first, int32_t n_tile, const int32_t* miss,
                         const int32_t* midx, uint64_t* mpos, int32_t* mentry, void* stream);
 int launch_ghost_numbering(const uint64_t* mpos, const int32_t* mentry, int64_t nm, unsigned long long* hkey,
