@@ -278,6 +278,31 @@ def run_zoom_only(precision, steps, warmup, tune, fixed, eager):
     return out
 
 
+def run_regrid_only(steps, warmup, tune, fixed):
+    """The zoom hierarchy's device regrid alone (for profiling): `warmup`
+    coarse steps, then `steps` rounds of one coarse step and one timed
+    regrid."""
+    import torch
+    import workloads as W
+    h, _ = make(W.zoom(), "fp64", tune, fixed)
+    h.set_regrid_device(True)
+    h.advance(max(1, warmup))
+    times, counts = [], []
+    for _ in range(steps):
+        h.advance(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        created, destroyed = h.regrid()
+        times.append(time.perf_counter() - t0)
+        counts.append((created, destroyed))
+        log(f"bench: regrid {1e3 * times[-1]:.2f} ms, created {created}, destroyed {destroyed}")
+    out = {"workload": "zoom AMR levels 7-12, device regrid", "steps": steps,
+           "octs": sum(h.level_info(lv)[0] for lv in h.levels),
+           "regrid_ms": [round(1e3 * t, 3) for t in times], "created_destroyed": counts}
+    h.close()
+    return out
+
+
 def leaf_fields(h):
     """Leaf-cell density, pressure and cell volume of every level."""
     import numpy as np
@@ -523,7 +548,7 @@ def main():
     ap.add_argument("--tuning", type=str, default="",
                     help="fixed hydro tuning tiles_per_wg,persistent,waves_per_cu,batch,waves_per_tile[,tile_cells]")
     ap.add_argument("--only", choices=["fp64", "mixed", "poisson", "zoom", "zoom-mixed", "batch", "batch-mixed",
-                                       "twolevel", "twolevel-mixed"], default=None)
+                                       "twolevel", "twolevel-mixed", "regrid"], default=None)
     ap.add_argument("--eager-only", action="store_true",
                     help="with --only: every step launched eagerly with HIP events (for profiling)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -586,6 +611,10 @@ def main():
         print(json.dumps({"workload": "two-level theta 0.70", "precision": prec, "tunings": level_tunings(h),
                           "value": cups * args.steps / med, "ms_per_coarse_step": 1e3 * med / args.steps}), flush=True)
         h.close()
+        return
+    if args.only == "regrid":
+        log("bench: zoom device regrid only")
+        print(json.dumps(run_regrid_only(args.steps, args.warmup, tune, fixed)), flush=True)
         return
     if args.only in ("zoom", "zoom-mixed"):
         prec = "mixed" if args.only == "zoom-mixed" else "fp64"
