@@ -1071,15 +1071,6 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     v.hmask = HE[k] ? HE[k] - 1 : 0;
     return v;
   };
-  auto old_view = [&](int k) {
-    LevelView v{};
-    v.key = c->lev[k].dkey;
-    v.oc = c->lev[k].doc;
-    v.n = c->lev[k].n_oct;
-    v.bits = c->dom.hbits0 + k;
-    for (int a = 0; a < 3; ++a) v.noct[a] = int32_t(c->dom.noct(lmin + k, a));
-    return v;
-  };
   // exclusive scan of n counts; returns the total (stream synchronised)
   auto scan_total = [&](const int32_t* in, int32_t* out, int64_t n, int64_t& total) -> bool {
     const int nt = scan_tmp_ints(n);
@@ -1237,19 +1228,16 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
         F.oc = static_cast<int32_t*>(A(sizeof(int32_t) * 3 * n_fine, false));
         F.parent = static_cast<int32_t*>(A(sizeof(int32_t) * n_fine, false));
         L.child = static_cast<int32_t*>(A(sizeof(int32_t) * 8 * L.n, false));
+        // the old tree: level l's octs in the old level (its remap sources;
+        // the base level is unchanged) and the old level l's child map
+        OldTree OT{};
+        OT.old_of = k == 0 ? nullptr : src_old;
+        OT.old_child = n_old > 0 ? c->lev[k].child : nullptr;
+        RG_TRY(n_old == 0 || OT.old_child, RY_EINVAL, "old level without a child map");
         src_old = static_cast<int32_t*>(A(sizeof(int32_t) * n_fine, true));
         src7 = static_cast<int32_t*>(A(sizeof(int32_t) * 7 * n_fine, true));
-        // the old child level's octs, found by position
-        LevelView Fo = old_view(k + 1);
-        if (n_old > 0) {
-          const uint64_t he = pos_hash_entries(n_old);
-          auto* ho = static_cast<unsigned long long*>(A(16 * he, true));
-          RG_TRY(ok, RY_ENOMEM, "allocation failed");
-          RG_TRY(!launch_pos_hash(Fo.oc, n_old, ho, he, st), RY_EHIP, "position hash kernel");
-          Fo.hash = ho;
-          Fo.hmask = he - 1;
-        }
-        RG_TRY(!launch_regrid_children(V, Fo, RD, c->dom.hbits0 + k + 1, L.flag, off, F.key, F.oc, F.parent,
+        RG_TRY(ok, RY_ENOMEM, "allocation failed");
+        RG_TRY(!launch_regrid_children(V, OT, RD, c->dom.hbits0 + k + 1, L.flag, off, F.key, F.oc, F.parent,
                                        L.child, src_old, src7, d_err, d_kept + k + 1, st),
                RY_EHIP, "regrid children kernel");
       }

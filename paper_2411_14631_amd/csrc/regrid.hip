@@ -307,7 +307,7 @@ __device__ __forceinline__ uint32_t child_digits(int bits, uint32_t px, uint32_t
 
 
 // Children of oct o; returns how many were found in the old level.
-__device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const LevelView& Fold, const RegridDom& D,
+__device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const OldTree& T, const RegridDom& D,
                                            int fbits, const uint8_t* __restrict__ flag,
                                            const int32_t* __restrict__ off, uint64_t* __restrict__ nkey,
                                            int32_t* __restrict__ noc, int32_t* __restrict__ parent,
@@ -323,27 +323,19 @@ __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const 
 #pragma unroll
   for (int c = 0; c < 8; ++c)
     if ((f >> c) & 1) fd |= 1u << ((dg >> (3 * c)) & 7u);
-  // the flagged children in the old level (-1: new): first probes issued together
+  // the flagged children in the old level (-1: new): an old child at this
+  // position has an old parent at the parent's position, and is that old
+  // parent's child at the same cell
   int32_t so8[8];
-  if (Fold.hash) {
-    uint64_t fk[8], fs[8];
-    ulonglong2 fe[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      fk[c] = pack_pos(2 * ox + (c & 1), 2 * oy + ((c >> 1) & 1), 2 * oz + (c >> 2));
-      fs[c] = fmix64(fk[c]) & Fold.hmask;
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) fe[c] = hash_entry(Fold.hash, fs[c]);
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      so8[c] = ((f >> c) & 1) ? int32_t(hash_probe_on(Fold.hash, Fold.hmask, fk[c], fs[c], fe[c])) : -1;
+  const int64_t op = T.old_of ? T.old_of[o] : o;
+  if (op >= 0 && T.old_child) {
+    const int4 a = *reinterpret_cast<const int4*>(T.old_child + 8 * op);
+    const int4 b = *reinterpret_cast<const int4*>(T.old_child + 8 * op + 4);
+    so8[0] = a.x; so8[1] = a.y; so8[2] = a.z; so8[3] = a.w;
+    so8[4] = b.x; so8[5] = b.y; so8[6] = b.z; so8[7] = b.w;
   } else {
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-      so8[c] = ((f >> c) & 1) && Fold.n ? int32_t(find_oct(Fold, 2 * ox + (c & 1), 2 * oy + ((c >> 1) & 1),
-                                                          2 * oz + (c >> 2)))
-                                        : -1;
+    for (int c = 0; c < 8; ++c) so8[c] = -1;
   }
   const int64_t base = off[o];
   int kept = 0;
@@ -399,7 +391,7 @@ __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const 
   return kept;
 }
 
-__global__ __launch_bounds__(256) void regrid_children_kernel(LevelView C, LevelView Fold, RegridDom D, int fbits,
+__global__ __launch_bounds__(256) void regrid_children_kernel(LevelView C, OldTree T, RegridDom D, int fbits,
                                        const uint8_t* __restrict__ flag, const int32_t* __restrict__ off,
                                        uint64_t* __restrict__ nkey, int32_t* __restrict__ noc,
                                        int32_t* __restrict__ parent, int32_t* __restrict__ child,
@@ -407,7 +399,7 @@ __global__ __launch_bounds__(256) void regrid_children_kernel(LevelView C, Level
                                        int32_t* __restrict__ err, unsigned long long* __restrict__ kept) {
   const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int n = 0;
-  if (o < C.n) n = children_of(o, C, Fold, D, fbits, flag, off, nkey, noc, parent, child, src_old, src7, err);
+  if (o < C.n) n = children_of(o, C, T, D, fbits, flag, off, nkey, noc, parent, child, src_old, src7, err);
   n = wave_sum(n);   // every lane of the wavefront takes part (blocks of whole wavefronts)
   if ((threadIdx.x & 63) == 0 && n) atomicAdd(kept, (unsigned long long)n);
 }
@@ -707,13 +699,13 @@ int launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, void* 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_regrid_children(const LevelView& C, const LevelView& Fold, const RegridDom& D, int fbits,
+int launch_regrid_children(const LevelView& C, const OldTree& T, const RegridDom& D, int fbits,
                            const uint8_t* flag, const int32_t* off, uint64_t* nkey, int32_t* noc, int32_t* parent,
                            int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err,
                            unsigned long long* kept, void* stream) {
   if (C.n == 0) return 0;
   if (fbits < 1 || fbits > 25) return -1;   // child_digits' range
-  hipLaunchKernelGGL(regrid_children_kernel, dim3(blocks(C.n)), dim3(256), 0, (hipStream_t)stream, C, Fold, D, fbits,
+  hipLaunchKernelGGL(regrid_children_kernel, dim3(blocks(C.n)), dim3(256), 0, (hipStream_t)stream, C, T, D, fbits,
                      flag, off, nkey, noc, parent, child, src_old, src7, err, kept);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -311,9 +311,17 @@ int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const dou
 // tmp[scan_tmp_ints(n) - 1])
 int scan_tmp_ints(int64_t n);
 int launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, void* stream);
+// The old tree around level C: old_of[o] the index in the old level of C's
+// oct o, or -1 when it is new (null: C's octs are the old ones, unchanged);
+// old_child the old level's child map (8 per oct: the child oct or -1; null
+// when the old level had no children).
+struct OldTree {
+  const int32_t* old_of;
+  const int32_t* old_child;
+};
 // Children of level C's flagged cells (one thread per oct of C); kept gets
-// the number of children found in the old child level Fold added.
-int launch_regrid_children(const LevelView& C, const LevelView& Fold, const RegridDom& D, int fbits,
+// the number of children found in the old child level added.
+int launch_regrid_children(const LevelView& C, const OldTree& T, const RegridDom& D, int fbits,
                            const uint8_t* flag, const int32_t* off, uint64_t* nkey, int32_t* noc, int32_t* parent,
                            int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err,
                            unsigned long long* kept, void* stream);

@@ -198,6 +198,33 @@ def test_gradient_criterion_regrid_matches_oracle(ry, theta):
     compare(g, o)
 
 
+@pytest.mark.parametrize("bc", [(W.BC_PERIODIC,) * 6, (W.BC_OUTFLOW,) * 6])
+def test_gradient_criterion_on_refined_levels(ry, bc):
+    """The gradient criterion on a refined level (levels 3-5: the device flag
+    kernel reads the neighbour rule from the tile presence masks and the
+    face neighbours from the tile tables): after two coarse steps and two
+    threshold changes, the device regrid gives the oracle's counts and
+    states, and the host-flag path's mesh and state bit for bit."""
+    prob = cases.analytic_problem("gblob3-5", 3, 5, cases.blob_state, theta=0.05, bc=bc)
+    g, o, h = ry.Hydro(prob), Oracle(prob), ry.Hydro(prob)
+    h.set_regrid_device(False)
+    for _ in range(2):   # all three with the oracle's time step
+        dt = o.cfl_dt()
+        for x in (o, g, h):
+            x.coarse_step(dt)
+    for theta in (None, 0.03, 0.08):
+        if theta is not None:
+            for x in (g, o, h):
+                x.set_refine_param(theta)
+        counts = g.regrid()
+        assert counts == o.regrid() == h.regrid(), theta
+        assert g.level_info(5)[0] > 0
+        compare(g, o)
+        same_mesh_and_state(g, h)
+    step_both(g, o, 1)
+    compare(g, o)
+
+
 def test_regrid_between_multi_step_graph_runs(ry):
     """Runs long enough for the multi-step graphs (9 = 8 + 1 steps), a regrid that reallocates
     every refined level, and another such run: the graphs captured on the
