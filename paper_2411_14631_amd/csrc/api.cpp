@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ry_internal.h"
+#include "regrid.h"
 
 using namespace ry;
 

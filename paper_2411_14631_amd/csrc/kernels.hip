@@ -9,6 +9,7 @@
 
 #include "hydro_tile.h"
 #include "ry_internal.h"
+#include "regrid.h"
 
 namespace ry {
 

@@ -14,6 +14,7 @@
 #include <cstdint>
 
 #include "ry_internal.h"
+#include "regrid.h"
 
 namespace ry {
 
