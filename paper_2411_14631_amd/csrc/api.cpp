@@ -1004,6 +1004,8 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     int32_t* child = nullptr;
     int32_t* tab = nullptr;
     uint32_t* tflag = nullptr;
+    int32_t* tile_of = nullptr;        // refined levels: each oct's tile and each tile's
+    int32_t* tfirst = nullptr;         // first oct (from the parent level's children kernel)
     uint8_t* refined = nullptr;
     int64_t* gsrc = nullptr;
     double* reg = nullptr;
@@ -1084,6 +1086,22 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     total = h;
     return true;
   };
+  // two exclusive scans of n counts and both totals in one round trip
+  auto scan_totals = [&](const int32_t* in1, int32_t* out1, const int32_t* in2, int32_t* out2, int64_t n,
+                         int64_t& total1, int64_t& total2) -> bool {
+    const int nt = scan_tmp_ints(n);
+    int32_t* tmp1 = static_cast<int32_t*>(A(sizeof(int32_t) * nt, true));
+    int32_t* tmp2 = static_cast<int32_t*>(A(sizeof(int32_t) * nt, true));
+    if (!tmp1 || !tmp2 || launch_scan(in1, out1, n, tmp1, st) || launch_scan(in2, out2, n, tmp2, st)) return false;
+    int32_t h[2] = {0, 0};
+    if (hipMemcpyAsync(&h[0], tmp1 + nt - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&h[1], tmp2 + nt - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return false;
+    total1 = h[0];
+    total2 = h[1];
+    return true;
+  };
   int32_t* d_err = static_cast<int32_t*>(A(sizeof(int32_t), true));
   // per level: children of the new level found in the old one
   auto* d_kept = static_cast<unsigned long long*>(A(sizeof(unsigned long long) * nl, true));
@@ -1127,17 +1145,10 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     FT.n_oct = L.n;
     FT.complete = k == 0 && L.n == c->dom.noct(l, 0) * c->dom.noct(l, 1) * c->dom.noct(l, 2);
     if (k > 0) {
-      // tiles: octs sharing key >> 3
-      int32_t* start = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
-      int32_t* tid = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
-      RG_TRY(ok, RY_ENOMEM, "allocation failed");
-      int64_t nt = 0;
-      RG_TRY(!launch_tile_starts(L.key, L.n, start, st) && scan_total(start, tid, L.n, nt), RY_EHIP,
-             "tile kernels");
-      RG_TRY(nt * TILE_TAB < (int64_t(1) << 31), RY_EINVAL,
-             "level too large for the device regrid (use the host path)");
-      L.n_tile = int32_t(nt);
-      int32_t* first = static_cast<int32_t*>(A(sizeof(int32_t) * (nt + 1), true));
+      // tiles: octs sharing key >> 3, the children of one parent oct (listed
+      // by the parent level's children kernel)
+      const int64_t nt = L.n_tile;
+      int32_t* first = L.tfirst;
       const int64_t nslot = nt * TILE_TAB;
       L.tab = static_cast<int32_t*>(A(sizeof(int32_t) * nslot, false));
       L.tflag = static_cast<uint32_t*>(A(sizeof(uint32_t) * nt, false));
@@ -1145,13 +1156,11 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
       int32_t* midx = static_cast<int32_t*>(A(sizeof(int32_t) * nslot, true));
       auto* pres = static_cast<unsigned long long*>(A(sizeof(unsigned long long) * nt, true));
       RG_TRY(ok, RY_ENOMEM, "allocation failed");
-      FT.start = start;
-      FT.tid = tid;
+      FT.tile_of = L.tile_of;
       FT.pres = pres;
       FT.tab = L.tab;
       int64_t nm = 0;
-      RG_TRY(!launch_tile_first(start, tid, L.n, L.n_tile, first, st) &&
-                 !launch_tile_table(V, RD, first, L.n_tile, L.tab, L.tflag, miss, pres, st) &&
+      RG_TRY(!launch_tile_table(V, RD, first, L.n_tile, L.tab, L.tflag, miss, pres, st) &&
                  scan_total(miss, midx, nslot, nm),
              RY_EHIP, "tile table kernels");
       // ghost octs: numbered by first use over (tile, slot)
@@ -1216,11 +1225,20 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     if (k + 1 < nl) {
       int32_t* cnt = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
       int32_t* off = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
+      int32_t* has = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
+      int32_t* toff = static_cast<int32_t*>(A(sizeof(int32_t) * L.n, true));
       RG_TRY(ok, RY_ENOMEM, "allocation failed");
-      RG_TRY(!launch_regrid_flags(V, RD, l, L.U[0], FT, L.flag, cnt, st) && scan_total(cnt, off, L.n, n_fine), RY_EHIP,
-             "regrid flag kernel");
+      // child octs and child tiles (parents with children): both counts in
+      // one round trip
+      int64_t n_ctile = 0;
+      RG_TRY(!launch_regrid_flags(V, RD, l, L.U[0], FT, L.flag, cnt, has, st) &&
+                 scan_totals(cnt, off, has, toff, L.n, n_fine, n_ctile),
+             RY_EHIP, "regrid flag kernel");
+      RG_TRY(n_ctile * TILE_TAB < (int64_t(1) << 31), RY_EINVAL,
+             "level too large for the device regrid (use the host path)");
       NewLevel& F = N[k + 1];
       F.n = n_fine;
+      F.n_tile = int32_t(n_ctile);
       const int64_t n_old = c->lev[k + 1].n_oct;
       n_new[k + 1] = n_fine;
       n_prev[k + 1] = n_old;
@@ -1237,8 +1255,11 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
         RG_TRY(n_old == 0 || OT.old_child, RY_EINVAL, "old level without a child map");
         src_old = static_cast<int32_t*>(A(sizeof(int32_t) * n_fine, true));
         src7 = static_cast<int32_t*>(A(sizeof(int32_t) * 7 * n_fine, true));
+        F.tile_of = static_cast<int32_t*>(A(sizeof(int32_t) * n_fine, true));
+        F.tfirst = static_cast<int32_t*>(A(sizeof(int32_t) * (n_ctile + 1), true));
         RG_TRY(ok, RY_ENOMEM, "allocation failed");
-        RG_TRY(!launch_regrid_children(V, OT, RD, c->dom.hbits0 + k + 1, L.flag, off, F.key, F.oc, F.parent,
+        const ChildTiles CT{toff, int32_t(n_ctile), F.tile_of, F.tfirst};
+        RG_TRY(!launch_regrid_children(V, OT, RD, c->dom.hbits0 + k + 1, L.flag, off, CT, F.key, F.oc, F.parent,
                                        L.child, src_old, src7, d_err, d_kept + k + 1, st),
                RY_EHIP, "regrid children kernel");
       }

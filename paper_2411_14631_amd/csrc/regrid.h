@@ -35,22 +35,21 @@ struct RegridDom {
   int32_t refine;
   double refine_param;
 };
-// Refinement flags of level l (rho: the density plane).  The neighbour rule
-// reads the level's tile presence masks when given (pres; oct o's tile is
-// tid[o] + start[o] - 1: tid the exclusive scan of the tile-start flags
-// start), else takes every position as holding an oct when complete != 0,
-// else looks the octs up; the gradient criterion takes the face neighbours
-// from the tile tables (tab, n_oct) when given, else looks them up.
+// Refinement flags of level l (rho: the density plane), their counts (cnt)
+// and has = 1 where an oct has a flagged cell.  The neighbour rule reads the
+// level's tile presence masks when given (pres; tile_of: each oct's tile),
+// else takes every position as holding an oct when complete != 0, else
+// looks the octs up; the gradient criterion takes the face neighbours from
+// the tile tables (tab, n_oct) when given, else looks them up.
 struct FlagTiles {
-  const int32_t* start;
-  const int32_t* tid;
+  const int32_t* tile_of;
   const unsigned long long* pres;
   const int32_t* tab;
   int64_t n_oct;
   int32_t complete;
 };
 int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const double* rho, const FlagTiles& T,
-                        uint8_t* flag, int32_t* cnt, void* stream);
+                        uint8_t* flag, int32_t* cnt, int32_t* has, void* stream);
 // exclusive scan of n int32 (tmp: scan_tmp_ints(n) ints; the total lands in
 // tmp[scan_tmp_ints(n) - 1])
 int scan_tmp_ints(int64_t n);
@@ -63,15 +62,22 @@ struct OldTree {
   const int32_t* old_of;
   const int32_t* old_child;
 };
+// The child level's tiles (one per parent oct with children): toff the
+// exclusive scan of the flag kernel's has (a parent's tile), n_tile their
+// number; written: tile_of (the tile of each child oct) and tfirst (each
+// tile's first child oct, n_tile + 1 entries).
+struct ChildTiles {
+  const int32_t* toff;
+  int32_t n_tile;
+  int32_t* tile_of;
+  int32_t* tfirst;
+};
 // Children of level C's flagged cells (one thread per oct of C); kept gets
 // the number of children found in the old child level added.
 int launch_regrid_children(const LevelView& C, const OldTree& T, const RegridDom& D, int fbits,
-                           const uint8_t* flag, const int32_t* off, uint64_t* nkey, int32_t* noc, int32_t* parent,
-                           int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err,
-                           unsigned long long* kept, void* stream);
-int launch_tile_starts(const uint64_t* key, int64_t n, int32_t* start, void* stream);
-int launch_tile_first(const int32_t* start, const int32_t* tid, int64_t n, int32_t n_tile, int32_t* first,
-                      void* stream);
+                           const uint8_t* flag, const int32_t* off, const ChildTiles& CT, uint64_t* nkey,
+                           int32_t* noc, int32_t* parent, int32_t* child, int32_t* src_old, int32_t* src7,
+                           int32_t* err, unsigned long long* kept, void* stream);
 // pres: per tile, bit slot set when the slot's position holds an oct or lies
 // outside an outflow face
 int launch_tile_table(const LevelView& L, const RegridDom& D, const int32_t* first, int32_t n_tile, int32_t* tab,

@@ -171,7 +171,8 @@ __device__ __forceinline__ int wave_sum(int v) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom D, int l,
                                                           const double* __restrict__ rho, FlagTiles T,
-                                                          uint8_t* __restrict__ flag, int32_t* __restrict__ cnt) {
+                                                          uint8_t* __restrict__ flag, int32_t* __restrict__ cnt,
+                                                          int32_t* __restrict__ has) {
   const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (o >= L.n) return;
   const double mass_thr = D.refine_param * ldexp(1.0, 3 * (l - D.lmin));
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom
     int32_t nb6[6] = {-1, -1, -1, -1, -1, -1};
     if (T.pres) {
       // the oct sits at (1 + (ox & 1), ...) in its tile's 4x4x4 table
-      const int32_t t = T.tid[o] + T.start[o] - 1;
+      const int32_t t = T.tile_of[o];
       const int px = 1 + int(ox & 1), py = 1 + int(oy & 1), pz = 1 + int(oz & 1);
       const unsigned long long q = T.pres[t] >> ((px - 1) + 4 * (py - 1) + 16 * (pz - 1));
 #pragma unroll
@@ -263,6 +264,7 @@ __global__ __launch_bounds__(256) void regrid_flag_kernel(LevelView L, RegridDom
   }
   flag[o] = f;
   cnt[o] = __popc(uint32_t(f));
+  has[o] = f != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -310,7 +312,8 @@ __device__ __forceinline__ uint32_t child_digits(int bits, uint32_t px, uint32_t
 // Children of oct o; returns how many were found in the old level.
 __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const OldTree& T, const RegridDom& D,
                                            int fbits, const uint8_t* __restrict__ flag,
-                                           const int32_t* __restrict__ off, uint64_t* __restrict__ nkey,
+                                           const int32_t* __restrict__ off, const ChildTiles& CT,
+                                           uint64_t* __restrict__ nkey,
                                            int32_t* __restrict__ noc, int32_t* __restrict__ parent,
                                            int32_t* __restrict__ child, int32_t* __restrict__ src_old,
                                            int32_t* __restrict__ src7, int32_t* __restrict__ err) {
@@ -339,6 +342,11 @@ __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const 
     for (int c = 0; c < 8; ++c) so8[c] = -1;
   }
   const int64_t base = off[o];
+  // the children are one tile of the child level: its first oct, and the
+  // tile of each
+  const int32_t tile = CT.toff[o];
+  CT.tfirst[tile] = int32_t(base);
+  if (tile + 1 == CT.n_tile) CT.tfirst[tile + 1] = int32_t(base + __popc(uint32_t(f)));
   int kept = 0;
   uint32_t fresh = 0;   // children not in the old level
 #pragma unroll
@@ -348,6 +356,7 @@ __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const 
     const int64_t k = base + __popc(fd & ((1u << d) - 1u));
     const int64_t x = 2 * ox + (c & 1), y = 2 * oy + ((c >> 1) & 1), z = 2 * oz + ((c >> 2) & 1);
     nkey[k] = (pkey << 3) | uint64_t(d);
+    CT.tile_of[k] = tile;
     noc[3 * k] = int32_t(x);
     noc[3 * k + 1] = int32_t(y);
     noc[3 * k + 2] = int32_t(z);
@@ -394,13 +403,14 @@ __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const 
 
 __global__ __launch_bounds__(256) void regrid_children_kernel(LevelView C, OldTree T, RegridDom D, int fbits,
                                        const uint8_t* __restrict__ flag, const int32_t* __restrict__ off,
+                                       ChildTiles CT,
                                        uint64_t* __restrict__ nkey, int32_t* __restrict__ noc,
                                        int32_t* __restrict__ parent, int32_t* __restrict__ child,
                                        int32_t* __restrict__ src_old, int32_t* __restrict__ src7,
                                        int32_t* __restrict__ err, unsigned long long* __restrict__ kept) {
   const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int n = 0;
-  if (o < C.n) n = children_of(o, C, T, D, fbits, flag, off, nkey, noc, parent, child, src_old, src7, err);
+  if (o < C.n) n = children_of(o, C, T, D, fbits, flag, off, CT, nkey, noc, parent, child, src_old, src7, err);
   n = wave_sum(n);   // every lane of the wavefront takes part (blocks of whole wavefronts)
   if ((threadIdx.x & 63) == 0 && n) atomicAdd(kept, (unsigned long long)n);
 }
@@ -472,20 +482,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_add_kernel(int32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Tiles: octs sharing key >> 3.
+// Tiles: octs sharing key >> 3 (on a refined level, the children of one
+// parent oct: the children kernel lists them).
 // ---------------------------------------------------------------------------
-__global__ void tile_start_kernel(const uint64_t* __restrict__ key, int64_t n, int32_t* __restrict__ start) {
-  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (o < n) start[o] = (o == 0 || (key[o] >> 3) != (key[o - 1] >> 3)) ? 1 : 0;
-}
-
-__global__ void tile_first_kernel(const int32_t* __restrict__ start, const int32_t* __restrict__ tid, int64_t n,
-                                  int32_t n_tile, int32_t* __restrict__ first) {
-  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (o < n && start[o]) first[tid[o]] = int32_t(o);
-  if (o == 0) first[n_tile] = int32_t(n);
-}
-
 // One wavefront per tile, one lane per slot: the tile's 4x4x4 oct
 // neighbourhood.  tab gets the oct index, -1 (not needed, or outside an
 // outflow face) or -2 (missing: a ghost oct, numbered later); miss = 1 for
@@ -661,11 +660,11 @@ inline unsigned blocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b
 
 // ------------------------------------------------------------- launchers
 int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const double* rho, const FlagTiles& T,
-                        uint8_t* flag, int32_t* cnt, void* stream) {
+                        uint8_t* flag, int32_t* cnt, int32_t* has, void* stream) {
   if (L.n == 0) return 0;
-  if (T.pres && (!T.start || !T.tid || !T.tab)) return -1;
+  if (T.pres && (!T.tile_of || !T.tab)) return -1;
   hipLaunchKernelGGL(regrid_flag_kernel, dim3(blocks(L.n)), dim3(256), 0, (hipStream_t)stream, L, D, l, rho, T, flag,
-                     cnt);
+                     cnt, has);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -701,27 +700,14 @@ int launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, void* 
 }
 
 int launch_regrid_children(const LevelView& C, const OldTree& T, const RegridDom& D, int fbits,
-                           const uint8_t* flag, const int32_t* off, uint64_t* nkey, int32_t* noc, int32_t* parent,
-                           int32_t* child, int32_t* src_old, int32_t* src7, int32_t* err,
-                           unsigned long long* kept, void* stream) {
+                           const uint8_t* flag, const int32_t* off, const ChildTiles& CT, uint64_t* nkey,
+                           int32_t* noc, int32_t* parent, int32_t* child, int32_t* src_old, int32_t* src7,
+                           int32_t* err, unsigned long long* kept, void* stream) {
   if (C.n == 0) return 0;
   if (fbits < 1 || fbits > 25) return -1;   // child_digits' range
+  if (!CT.toff || !CT.tile_of || !CT.tfirst) return -1;
   hipLaunchKernelGGL(regrid_children_kernel, dim3(blocks(C.n)), dim3(256), 0, (hipStream_t)stream, C, T, D, fbits,
-                     flag, off, nkey, noc, parent, child, src_old, src7, err, kept);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-int launch_tile_starts(const uint64_t* key, int64_t n, int32_t* start, void* stream) {
-  if (n == 0) return 0;
-  hipLaunchKernelGGL(tile_start_kernel, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, key, n, start);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-int launch_tile_first(const int32_t* start, const int32_t* tid, int64_t n, int32_t n_tile, int32_t* first,
-                      void* stream) {
-  if (n == 0) return 0;
-  hipLaunchKernelGGL(tile_first_kernel, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, start, tid, n, n_tile,
-                     first);
+                     flag, off, CT, nkey, noc, parent, child, src_old, src7, err, kept);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
