@@ -3,12 +3,16 @@
 // interpolation sources, and the per-level device tables (tiles, the 4x4x4
 // oct neighbourhood of each tile, ghost octs and their sources).
 //
-// Octs of a level are looked up by binary search of their Hilbert key in
-// the level's sorted key array.  Children of a level-l oct occupy a
-// contiguous, ordered run of level-l+1 keys (key_{l+1} >> 3 == key_l), so the
-// child level comes out sorted from a scan over the parent octs: no global
-// sort.  Ghost octs are numbered in the order the host builder numbers them
-// (first use over tiles and slots), found with a device hash of positions.
+// Octs of a level are looked up in a hash of their positions built at the
+// start of the level's turn (binary search of the sorted Hilbert keys when a
+// level has no hash); the refinement flags read most of what they need from
+// the tile tables instead.  Children of a level-l oct occupy a contiguous,
+// ordered run of level-l+1 keys (key_{l+1} >> 3 == key_l), so the child level
+// comes out sorted from a scan over the parent octs: no global sort, and each
+// parent's children are one tile of the child level.  Surviving children are
+// read from the old tree (the old parent's child map).  Ghost octs are
+// numbered in the order the host builder numbers them (first use over tiles
+// and slots), found with a device hash of positions.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -308,7 +312,6 @@ __device__ __forceinline__ uint32_t child_digits(int bits, uint32_t px, uint32_t
   return d;
 }
 
-
 // Children of oct o; returns how many were found in the old level.
 __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const OldTree& T, const RegridDom& D,
                                            int fbits, const uint8_t* __restrict__ flag,
@@ -550,20 +553,14 @@ __global__ void missing_list_kernel(LevelView L, const int32_t* __restrict__ fir
   mentry[midx[i]] = int32_t(i);
 }
 
-// Open-addressing hash of positions -> the first (smallest) list index.
-__device__ __forceinline__ uint64_t mix_pos(uint64_t k) {
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdull;
-  k ^= k >> 33;
-  return k;
-}
-
+// Open-addressing hash of positions -> the first (smallest) list index
+// (the same mixer as the oct position hash).
 __global__ void hash_insert_kernel(const uint64_t* __restrict__ mpos, int64_t nm, unsigned long long* hkey,
                                    int32_t* hval, uint64_t mask) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nm) return;
   const unsigned long long k = mpos[i];
-  uint64_t s = mix_pos(k) & mask;
+  uint64_t s = fmix64(k) & mask;
   while (true) {
     const unsigned long long prev = atomicCAS(&hkey[s], ~0ull, k);
     if (prev == ~0ull || prev == k) {
@@ -575,7 +572,7 @@ __global__ void hash_insert_kernel(const uint64_t* __restrict__ mpos, int64_t nm
 }
 
 __device__ __forceinline__ int64_t hash_find(const unsigned long long* hkey, uint64_t mask, uint64_t k) {
-  uint64_t s = mix_pos(k) & mask;
+  uint64_t s = fmix64(k) & mask;
   while (hkey[s] != k) s = (s + 1) & mask;
   return int64_t(s);
 }
