@@ -1134,10 +1134,11 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     // the device regrid counts cells (8 per oct) and tile slots (64 per tile)
     // in 32-bit integers
     RG_TRY(L.n < (int64_t(1) << 28), RY_EINVAL, "level too large for the device regrid (use the host path)");
-    HE[k] = pos_hash_entries(L.n);
-    H[k] = static_cast<unsigned long long*>(A(16 * HE[k], true));
+    // the level's aligned 2x2x2 blocks of octs are its tiles
+    HE[k] = pos_hash_entries(std::max<int64_t>(L.n_tile, (L.n + 7) / 8));
+    H[k] = static_cast<unsigned long long*>(A(64 * HE[k], true));
     RG_TRY(ok, RY_ENOMEM, "allocation failed");
-    RG_TRY(!launch_pos_hash(L.oc, L.n, H[k], HE[k], st), RY_EHIP, "position hash kernel");
+    RG_TRY(!launch_pos_hash(L.key, L.oc, L.n, H[k], HE[k], d_err, st), RY_EHIP, "position hash kernel");
     const LevelView V = view(k);
     // what the flag kernel reads of the tiles (refined levels) or of a
     // complete level (the base level, when it holds every position)
@@ -1282,7 +1283,8 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     created += n_new[k] - int64_t(kept[k]);
     destroyed += n_prev[k] - int64_t(kept[k]);
   }
-  RG_TRY(herr == 0, RY_EINVAL, herr & 1 ? "interpolation source missing" : "ghost source missing");
+  RG_TRY(herr == 0, RY_EINVAL,
+         herr & 4 ? "position hash full" : herr & 1 ? "interpolation source missing" : "ghost source missing");
 #undef RG_TRY
   // install: release the old arrays (level lmin keeps state, keys, tables)
   for (int k = 0; k < nl; ++k) {

@@ -22,13 +22,16 @@ struct LevelView {
   const unsigned long long* hash;
   uint64_t hmask;                    // hash entries - 1 (a power of two minus one)
 };
-// Hash entries (16 bytes each) for n octs: a power of two >= 2n, so that
-// at most half the entries are used.
-uint64_t pos_hash_entries(int64_t n);
-// Position hash of a level's n octs (oc: 3 int32 per oct): tab holds
-// pos_hash_entries(n) entries of two unsigned long long {packed position,
-// oct index}; cleared and filled on the stream.
-int launch_pos_hash(const int32_t* oc, int64_t n, unsigned long long* tab, uint64_t entries, void* stream);
+// Hash entries (64 bytes each, one per aligned 2x2x2 block of oct positions
+// holding an oct) for n_blocks such blocks: a power of two >= 2 n_blocks, so
+// that at most half the entries are used.
+uint64_t pos_hash_entries(int64_t n_blocks);
+// Position hash of a level's n octs (key: their sorted Hilbert keys; oc: 3
+// int32 per oct): tab holds pos_hash_entries(blocks) entries of 8 unsigned
+// long long; cleared and filled on the stream.  A table too small for the
+// level's blocks sets bit 4 of *err.
+int launch_pos_hash(const uint64_t* key, const int32_t* oc, int64_t n, unsigned long long* tab, uint64_t entries,
+                    int32_t* err, void* stream);
 struct RegridDom {
   int32_t bc[6];
   int32_t lmin;

@@ -49,39 +49,89 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   return k;
 }
 
-// Position hash of a level: open addressing with linear probing, entries
-// {packed position, oct index}, an empty entry's key all ones (no packed
-// position has bit 63 set).  At most half the entries are used, so every
-// probe sequence ends at the key or at an empty entry.
+// Position hash of a level: one 64-byte entry per aligned 2x2x2 block of
+// oct positions that holds an oct, {packed block position, the indices of
+// the 8 octs at child position (x & 1) + 2 (y & 1) + 4 (z & 1), -1 where
+// absent}; an empty entry is all ones (no packed position has bit 63 set).
+// Open addressing with linear probing; at most half the entries are used,
+// so a probe sequence ends at the block or at an empty entry (the loops
+// also stop after visiting every entry, and report a full table).
 constexpr unsigned long long kEmptyPos = ~0ull;
+constexpr int kBlockWords = 8;   // unsigned long long per entry
 
-__device__ __forceinline__ ulonglong2 hash_entry(const unsigned long long* tab, uint64_t s) {
-  return *reinterpret_cast<const ulonglong2*>(tab + 2 * s);
+struct alignas(64) BlockEntry {
+  unsigned long long key;
+  int32_t oct[8];
+  unsigned long long pad[3];
+};
+static_assert(sizeof(BlockEntry) == kBlockWords * 8, "one 64-byte entry per block");
+
+__device__ __forceinline__ const BlockEntry* block_entry(const unsigned long long* tab, uint64_t s) {
+  return reinterpret_cast<const BlockEntry*>(tab) + s;
 }
 
-// The rest of a probe sequence whose entry at slot s held e.
-__device__ __forceinline__ int64_t hash_probe_on(const unsigned long long* tab, uint64_t mask, uint64_t k, uint64_t s,
-                                                 ulonglong2 e) {
-  while (e.x != k && e.x != kEmptyPos) {
+// The rest of a probe sequence for block key k, child position c, whose
+// entry at slot s held key ek and oct eo.
+__device__ __forceinline__ int64_t hash_probe_on(const unsigned long long* tab, uint64_t mask, uint64_t k, int c,
+                                                 uint64_t s, unsigned long long ek, int32_t eo) {
+  for (uint64_t p = 0; ek != k && ek != kEmptyPos && p <= mask; ++p) {
     s = (s + 1) & mask;
-    e = hash_entry(tab, s);
+    ek = block_entry(tab, s)->key;
+    eo = block_entry(tab, s)->oct[c];
   }
-  return e.x == k ? int64_t(e.y) : -1;
+  return ek == k ? int64_t(eo) : -1;
 }
 
-__device__ __forceinline__ int64_t hash_lookup(const unsigned long long* tab, uint64_t mask, uint64_t k) {
+__device__ __forceinline__ uint64_t block_key(int64_t x, int64_t y, int64_t z) {
+  return pack_pos(x >> 1, y >> 1, z >> 1);
+}
+__device__ __forceinline__ int child_pos(int64_t x, int64_t y, int64_t z) {
+  return int((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+}
+
+__device__ __forceinline__ int64_t hash_lookup(const unsigned long long* tab, uint64_t mask, int64_t x, int64_t y,
+                                               int64_t z) {
+  const uint64_t k = block_key(x, y, z);
+  const int c = child_pos(x, y, z);
   const uint64_t s = fmix64(k) & mask;
-  return hash_probe_on(tab, mask, k, s, hash_entry(tab, s));
+  return hash_probe_on(tab, mask, k, c, s, block_entry(tab, s)->key, block_entry(tab, s)->oct[c]);
 }
 
-__global__ void pos_hash_insert_kernel(const int32_t* __restrict__ oc, int64_t n, unsigned long long* tab,
-                                       uint64_t mask) {
+// Build, first pass: the first oct of each block (in key order; siblings
+// share key >> 3) enters the block's key.
+__global__ void pos_hash_key_kernel(const uint64_t* __restrict__ key, const int32_t* __restrict__ oc, int64_t n,
+                                    unsigned long long* tab, uint64_t mask, int32_t* __restrict__ err) {
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o >= n || (o > 0 && (key[o] >> 3) == (key[o - 1] >> 3))) return;
+  const unsigned long long k = block_key(oc[3 * o], oc[3 * o + 1], oc[3 * o + 2]);
+  uint64_t s = fmix64(k) & mask;
+  for (uint64_t p = 0; p <= mask; ++p) {
+    const unsigned long long prev = atomicCAS(&tab[kBlockWords * s], kEmptyPos, k);
+    if (prev == kEmptyPos || prev == k) return;
+    s = (s + 1) & mask;
+  }
+  atomicOr(err, 4);   // table full
+}
+
+// Build, second pass: every oct writes its index into its block's entry
+// (read by later launches only).
+__global__ void pos_hash_oct_kernel(const int32_t* __restrict__ oc, int64_t n, unsigned long long* tab,
+                                    uint64_t mask, int32_t* __restrict__ err) {
   const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (o >= n) return;
-  const unsigned long long k = pack_pos(oc[3 * o], oc[3 * o + 1], oc[3 * o + 2]);
+  const int64_t x = oc[3 * o], y = oc[3 * o + 1], z = oc[3 * o + 2];
+  const unsigned long long k = block_key(x, y, z);
   uint64_t s = fmix64(k) & mask;
-  while (atomicCAS(&tab[2 * s], kEmptyPos, k) != kEmptyPos) s = (s + 1) & mask;
-  tab[2 * s + 1] = (unsigned long long)o;   // read by later launches only
+  for (uint64_t p = 0; p <= mask; ++p) {
+    const unsigned long long e = tab[kBlockWords * s];
+    if (e == k) {
+      reinterpret_cast<BlockEntry*>(tab)[s].oct[child_pos(x, y, z)] = int32_t(o);
+      return;
+    }
+    if (e == kEmptyPos) break;
+    s = (s + 1) & mask;
+  }
+  atomicOr(err, 4);   // block not entered
 }
 
 // Integer oct position q of a level after the boundary rule (periodic
@@ -103,7 +153,7 @@ __device__ __forceinline__ bool wrap_oct(const LevelView& L, const int32_t* bc, 
 
 // Index of the oct at an in-domain position, -1 when there is none.
 __device__ __forceinline__ int64_t find_oct(const LevelView& L, int64_t x, int64_t y, int64_t z) {
-  if (L.hash) return hash_lookup(L.hash, L.hmask, pack_pos(x, y, z));
+  if (L.hash) return hash_lookup(L.hash, L.hmask, x, y, z);
   return find_key(L.key, L.n, hilbert3(L.bits, uint32_t(x), uint32_t(y), uint32_t(z)));
 }
 
@@ -149,19 +199,27 @@ __device__ __forceinline__ void face_neighbours(const LevelView& L, const int32_
     return;
   }
   uint64_t key[6], slot[6];
-  ulonglong2 e[6];
+  int cp[6];
+  unsigned long long ek[6];
+  int32_t eo[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
     const int64_t st = (m & 1) ? 1 : -1;
     int64_t q[3] = {ox + (m >> 1 == 0 ? st : 0), oy + (m >> 1 == 1 ? st : 0), oz + (m >> 1 == 2 ? st : 0)};
-    key[m] = wrap_oct(L, bc, q) ? pack_pos(q[0], q[1], q[2]) : kEmptyPos;   // all ones: outside
+    const bool in = wrap_oct(L, bc, q);
+    key[m] = in ? block_key(q[0], q[1], q[2]) : kEmptyPos;   // all ones: outside
+    cp[m] = child_pos(q[0], q[1], q[2]);
     slot[m] = fmix64(key[m]) & L.hmask;
   }
 #pragma unroll
-  for (int m = 0; m < 6; ++m) e[m] = hash_entry(L.hash, slot[m]);
+  for (int m = 0; m < 6; ++m) {
+    ek[m] = block_entry(L.hash, slot[m])->key;
+    eo[m] = block_entry(L.hash, slot[m])->oct[cp[m]];
+  }
 #pragma unroll
   for (int m = 0; m < 6; ++m)
-    nb[m] = key[m] == kEmptyPos ? -2 : int32_t(hash_probe_on(L.hash, L.hmask, key[m], slot[m], e[m]));
+    nb[m] = key[m] == kEmptyPos ? -2
+                                : int32_t(hash_probe_on(L.hash, L.hmask, key[m], cp[m], slot[m], ek[m], eo[m]));
 }
 
 __device__ __forceinline__ int wave_sum(int v) {
@@ -665,18 +723,21 @@ int launch_regrid_flags(const LevelView& L, const RegridDom& D, int l, const dou
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-uint64_t pos_hash_entries(int64_t n) {
+uint64_t pos_hash_entries(int64_t n_blocks) {
   uint64_t e = 64;
-  while (e < 2 * uint64_t(n)) e <<= 1;
+  while (e < 2 * uint64_t(n_blocks)) e <<= 1;
   return e;
 }
 
-int launch_pos_hash(const int32_t* oc, int64_t n, unsigned long long* tab, uint64_t entries, void* stream) {
+int launch_pos_hash(const uint64_t* key, const int32_t* oc, int64_t n, unsigned long long* tab, uint64_t entries,
+                    int32_t* err, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks(int64_t(2 * entries))), dim3(256), 0, s, tab, int64_t(2 * entries),
-                     kEmptyPos);
-  if (n > 0)
-    hipLaunchKernelGGL(pos_hash_insert_kernel, dim3(blocks(n)), dim3(256), 0, s, oc, n, tab, entries - 1);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks(int64_t(kBlockWords * entries))), dim3(256), 0, s, tab,
+                     int64_t(kBlockWords * entries), kEmptyPos);
+  if (n > 0) {
+    hipLaunchKernelGGL(pos_hash_key_kernel, dim3(blocks(n)), dim3(256), 0, s, key, oc, n, tab, entries - 1, err);
+    hipLaunchKernelGGL(pos_hash_oct_kernel, dim3(blocks(n)), dim3(256), 0, s, oc, n, tab, entries - 1, err);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
