@@ -148,6 +148,26 @@ def test_device_and_host_regrid_paths_bit_identical(ry, bc):
     same_mesh_and_state(a, b)
 
 
+@pytest.mark.parametrize("bc", [(W.BC_PERIODIC,) * 6, (W.BC_OUTFLOW,) * 6])
+def test_mixed_form_device_and_host_regrid_paths_bit_identical(ry, bc):
+    """The mixed form through both regrid paths (all on the device, and host
+    flags with the device remap): the same meshes and states bit for bit
+    over three rounds of a coarse step and a regrid, and the same solution
+    after two more steps."""
+    prob = cases.with_scalars(cases.amr_blob(bc=bc), 1)
+    a, b = ry.Hydro(prob, "mixed"), ry.Hydro(prob, "mixed")
+    b.set_regrid_device(False)
+    for _ in range(3):
+        a.advance(1)
+        b.advance(1)
+        assert a.regrid() == b.regrid()
+        same_mesh_and_state(a, b)
+    assert a.level_info(a.levels[-1])[0] > 0
+    a.advance(2)
+    b.advance(2)
+    same_mesh_and_state(a, b)
+
+
 def test_device_regrid_empties_and_regrows_levels(ry):
     """Thresholds that remove every refined level, then restore them: counts,
     meshes and states against the oracle on the way down and back up."""
