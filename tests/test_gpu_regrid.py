@@ -245,6 +245,34 @@ def test_gradient_criterion_on_refined_levels(ry, bc):
     compare(g, o)
 
 
+@pytest.mark.parametrize("bc", [(W.BC_PERIODIC,) * 6, (W.BC_OUTFLOW,) * 6])
+def test_regrid_on_base_side_2_mod_4(ry, bc):
+    """A base of 18 cells per side (9 octs per axis: blocks and tiles of the
+    base cut by the domain's high side) under the gradient criterion: after
+    two coarse steps and a threshold change, the device regrid gives the
+    oracle's counts and states, and the host-flag path's mesh and state bit
+    for bit."""
+    import dataclasses
+    prob = dataclasses.replace(W.twolevel(36, 0.5), bc=bc)
+    g, o, h = ry.Hydro(prob), Oracle(prob), ry.Hydro(prob)
+    h.set_regrid_device(False)
+    for _ in range(2):   # all three with the oracle's time step
+        dt = o.cfl_dt()
+        for x in (o, g, h):
+            x.coarse_step(dt)
+    for theta in (None, 0.35):
+        if theta is not None:
+            for x in (g, o, h):
+                x.set_refine_param(theta)
+        counts = g.regrid()
+        assert counts == o.regrid() == h.regrid(), theta
+        assert g.level_info(prob.level_max)[0] > 0
+        compare(g, o)
+        same_mesh_and_state(g, h)
+    step_both(g, o, 1)
+    compare(g, o)
+
+
 def test_regrid_between_multi_step_graph_runs(ry):
     """Runs long enough for the multi-step graphs (9 = 8 + 1 steps), a regrid that reallocates
     every refined level, and another such run: the graphs captured on the
