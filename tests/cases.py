@@ -70,6 +70,22 @@ def amr_blob(level_min=3, level_max=5, rho_thr=1.5, bc=(W.BC_PERIODIC,) * 6, **k
                             lambda pos: blob_state(pos, **kw), rho_thr=rho_thr, bc=bc)
 
 
+def noncubic_blob(bc=(W.BC_PERIODIC,) * 6, level_min=3, level_max=5, nbase=(8, 16, 12), gamma=1.4):
+    """AMR blob on a box of different cell counts per axis (cubic cells,
+    dx = 1 / nbase[0] at the base level), refined by the mass threshold."""
+    def values(level, ijk):
+        n = nbase[0] << (level - level_min)
+        pos = (ijk.astype(np.float64) + 0.5) / n
+        rho, vx, vy, vz, p = blob_state(pos, centre=(0.3, 1.4, 0.9), lshape=False)
+        return W.conserved(rho, vx, vy, vz, p, gamma)
+
+    idx = np.indices((nbase[2], nbase[1], nbase[0]))
+    ijk = np.stack([idx[2].ravel(), idx[1].ravel(), idx[0].ravel()], axis=1).astype(np.int32)
+    Ub = values(level_min, ijk).reshape(5, nbase[2], nbase[1], nbase[0])
+    return W.Problem("ncblob", level_min, level_max, tuple(nbase), gamma, Ub, bc=bc, refine=W.REFINE_MASS,
+                     refine_param=1.5, fill=values)
+
+
 def rel_err(a, b, floor_frac=1e-3):
     """Per-variable relative error |a-b| / max(|b|, floor_frac * max|b_v|)."""
     a = np.asarray(a)

@@ -273,6 +273,25 @@ def test_regrid_on_base_side_2_mod_4(ry, bc):
     compare(g, o)
 
 
+@pytest.mark.parametrize("bc", [(W.BC_PERIODIC,) * 6, (W.BC_OUTFLOW,) * 6])
+def test_regrid_on_non_cubic_box(ry, bc):
+    """A box of 8 x 16 x 12 base cells (levels 3-5, mass threshold): three
+    rounds of a coarse step and a regrid, the device regrid giving the
+    oracle's counts and states and the host-flag path's mesh and state bit
+    for bit."""
+    prob = cases.noncubic_blob(bc)
+    g, o, h = ry.Hydro(prob), Oracle(prob), ry.Hydro(prob)
+    h.set_regrid_device(False)
+    for _ in range(3):
+        dt = o.cfl_dt()
+        for x in (o, g, h):
+            x.coarse_step(dt)
+        assert g.regrid() == o.regrid() == h.regrid()
+        assert g.level_info(prob.level_max)[0] > 0
+        compare(g, o)
+        same_mesh_and_state(g, h)
+
+
 def test_regrid_between_multi_step_graph_runs(ry):
     """Runs long enough for the multi-step graphs (9 = 8 + 1 steps), a regrid that reallocates
     every refined level, and another such run: the graphs captured on the
