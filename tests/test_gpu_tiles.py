@@ -239,6 +239,20 @@ def test_base_side_2_mod_4_amr(ry, n_fine, bc):
         compare_levels(g, o)
 
 
+@pytest.mark.parametrize("level_max", [3, 5])
+@pytest.mark.parametrize("bc", ["periodic", "outflow"])
+def test_non_cubic_box(ry, level_max, bc):
+    """A box of 8 x 16 x 12 base cells (4 x 8 x 6 octs: 8^3-cell tiles cut
+    along z), uniform and with two refined levels, on every tile shape,
+    against the oracle."""
+    prob = cases.noncubic_blob(bc=(W.BC_OUTFLOW if bc == "outflow" else W.BC_PERIODIC,) * 6, level_max=level_max)
+    o = Oracle(prob)
+    o.advance(3)
+    for t in (SMALL, BIG, BIG4):
+        g = run(ry, prob, 3, tuning=t)
+        compare_levels(g, o)
+
+
 def test_batch_accepts_sides_2_mod_4(ry):
     boxes = [W.batch_box(30, 18, 1.0, 1.5), W.batch_box(31, 30, 0.7, 0.8), W.batch_box(32, 16, 1.2, 2.0),
              W.batch_box(33, 6, 0.5, 1.0)]
