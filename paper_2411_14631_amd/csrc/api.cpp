@@ -64,6 +64,8 @@ struct ry_ctx {
   std::vector<HostLevel> host;            // topology of the current mesh (no state)
   bool host_valid = true;                 // false after a device-side regrid
   bool regrid_device = true;              // build regrid flags / tables on the device
+  bool means_valid = true;                // every refined cell holds its children's ordered mean
+                                          // (the builder and every step restrict; an upload may not)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int num_cu = 256;
@@ -792,6 +794,7 @@ ry_status ry_amr_build(ry_ctx* c, const double* U_base, ry_fill_fn fill, void* u
   for (auto& h : H) std::vector<double>().swap(h.U);
   c->host = std::move(H);
   c->host_valid = true;
+  c->means_valid = true;   // the builder restricts every refined cell
   c->built = true;
   return RY_OK;
   RY_ABI_CATCH
@@ -841,7 +844,7 @@ ry_status refresh_host_topology(ry_ctx* c) {
   return RY_OK;
 }
 
-ry_status finish_regrid(ry_ctx* c);
+ry_status finish_regrid(ry_ctx* c, const std::vector<uint8_t*>* dirty = nullptr);
 
 // Regrid with flags and tables built on the host (the state stays on the
 // device).
@@ -945,7 +948,10 @@ ry_status regrid_host(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
 
 // Common tail of both regrid paths: CFL partial slots for the new tile
 // counts, restriction bottom-up, CFL data; graphs and subcycle counters reset.
-ry_status finish_regrid(ry_ctx* c) {
+// dirty (device regrid): per level, the octs whose state changed (new, or a
+// cell restricted again), filled bottom-up by the restriction; null: every
+// refined cell is restricted.
+ry_status finish_regrid(ry_ctx* c, const std::vector<uint8_t*>* dirty) {
   const int nl = c->nlev, nv = c->dom.nv;
   ry_status s;
   dfree(c, c->d_part);
@@ -961,14 +967,18 @@ ry_status finish_regrid(ry_ctx* c) {
   }
   HIPCHK(c, hipMemcpyAsync(c->d_segoff, c->seg_off.data(), sizeof(int64_t) * c->seg_off.size(),
                            hipMemcpyHostToDevice, c->stream));
-  // refined cells = ordered 8-child means, bottom-up
+  // refined cells = ordered 8-child means, bottom-up (after a device
+  // regrid only those above changed octs: the others hold these means)
   for (int k = nl - 2; k >= 0; --k) {
     DevLevel& L = c->lev[k];
     DevLevel& F = c->lev[k + 1];
     if (F.n_oct == 0) continue;
-    if (launch_restrict(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur], L.plane(), nv, nullptr,
-                        err_ptr(c), c->stream))
-      return fail(c, RY_EHIP, "restrict kernel");
+    const int rc = dirty ? launch_restrict_dirty(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur],
+                                                 L.plane(), nv, (*dirty)[k + 1], k > 0 ? (*dirty)[k] : nullptr,
+                                                 err_ptr(c), c->stream)
+                         : launch_restrict(F.U[F.cur], F.plane(), F.n_oct, F.parent_cell, L.U[L.cur], L.plane(),
+                                           nv, nullptr, err_ptr(c), c->stream);
+    if (rc) return fail(c, RY_EHIP, "restrict kernel");
   }
   drop_graphs(c);
   drop_super(c);
@@ -977,7 +987,9 @@ ry_status finish_regrid(ry_ctx* c) {
   if ((s = build_ghost_read(c))) return s;
   if ((s = ensure_super(c))) return s;
   if ((s = enqueue_cfl_all(c))) return s;
-  return sync_and_check(c);
+  if ((s = sync_and_check(c))) return s;
+  c->means_valid = true;
+  return RY_OK;
 }
 
 // Regrid with the mesh work on the device: per level, refinement flags from
@@ -1006,6 +1018,7 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     uint32_t* tflag = nullptr;
     int32_t* tile_of = nullptr;        // refined levels: each oct's tile and each tile's
     int32_t* tfirst = nullptr;         // first oct (from the parent level's children kernel)
+    uint8_t* fresh = nullptr;          // refined levels: 1 for octs not in the old level
     uint8_t* refined = nullptr;
     int64_t* gsrc = nullptr;
     double* reg = nullptr;
@@ -1258,8 +1271,9 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
         src7 = static_cast<int32_t*>(A(sizeof(int32_t) * 7 * n_fine, true));
         F.tile_of = static_cast<int32_t*>(A(sizeof(int32_t) * n_fine, true));
         F.tfirst = static_cast<int32_t*>(A(sizeof(int32_t) * (n_ctile + 1), true));
+        F.fresh = static_cast<uint8_t*>(A(n_fine, true));
         RG_TRY(ok, RY_ENOMEM, "allocation failed");
-        const ChildTiles CT{toff, int32_t(n_ctile), F.tile_of, F.tfirst};
+        const ChildTiles CT{toff, int32_t(n_ctile), F.tile_of, F.tfirst, F.fresh};
         RG_TRY(!launch_regrid_children(V, OT, RD, c->dom.hbits0 + k + 1, L.flag, off, CT, F.key, F.oc, F.parent,
                                        L.child, src_old, src7, d_err, d_kept + k + 1, st),
                RY_EHIP, "regrid children kernel");
@@ -1322,9 +1336,14 @@ ry_status regrid_device(ry_ctx* c, int64_t* n_created, int64_t* n_destroyed) {
     }
   }
   fresh.clear();
-  release(temps);
   c->host_valid = false;
-  ry_status s = finish_regrid(c);
+  // the restriction reads the new-oct marks (scratch): released after it;
+  // all refined cells are restricted when an upload may have left means
+  // out of date
+  std::vector<uint8_t*> dirty(nl, nullptr);
+  for (int k = 1; k < nl; ++k) dirty[k] = N[k].fresh;
+  ry_status s = finish_regrid(c, c->means_valid ? &dirty : nullptr);
+  release(temps);
   if (s) return s;
   if (n_created) *n_created = created;
   if (n_destroyed) *n_destroyed = destroyed;
@@ -1566,6 +1585,7 @@ ry_status ry_upload(ry_ctx* c, int32_t level, const double* U) {
   if (!D.n_oct) return RY_OK;
   ry_status s = upload_level_state(c, D, U);
   if (s) return s;
+  c->means_valid = false;
   HIPCHK(c, hipMemsetAsync(err_ptr(c), 0, sizeof(int32_t), c->stream));
   if ((s = enqueue_cfl_all(c))) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -219,21 +219,52 @@ int launch_ghost(const GhostArgs& a, void* stream) {
 // ---------------------------------------------------------------------------
 // Restriction: refined cell of level l = mean of its 8 children.
 // ---------------------------------------------------------------------------
+// The ordered mean of fine oct k's 8 cells in plane v (64 contiguous bytes,
+// as four 16-byte loads).
+__device__ __forceinline__ double child_mean(const double* __restrict__ Uf, int64_t pf, int v, int64_t k) {
+  const double2* s = reinterpret_cast<const double2*>(Uf + v * pf + 8 * k);
+  const double2 a = s[0], b = s[1], c = s[2], d = s[3];
+  return 0.125 * (((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y)));
+}
+
 __global__ void restrict_kernel(const double* __restrict__ Uf, int64_t pf, int64_t nf,
                                 const int32_t* __restrict__ parent, double* __restrict__ Uc, int64_t pc, int nv,
                                 const int32_t* skip, int32_t* err) {
   if (skip && *skip) return;
   // variable-major: consecutive threads read consecutive octs of one plane
-  // (64 contiguous bytes each, as four 16-byte loads)
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nf * nv) return;
   const int v = int(i / nf);
   const int64_t k = i - int64_t(v) * nf;
-  const double2* s = reinterpret_cast<const double2*>(Uf + v * pf + 8 * k);
-  const double2 a = s[0], b = s[1], c = s[2], d = s[3];
   const int32_t q = parent[k];
   if (!debug_in_bounds(q >= 0 && q < pc, err)) return;
-  Uc[v * pc + q] = 0.125 * (((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y)));
+  Uc[v * pc + q] = child_mean(Uf, pf, v, k);
+}
+
+// The same restriction for the fine octs marked in dirty_f only; each marks
+// its parent oct in dirty_c (when given).
+__global__ void restrict_dirty_kernel(const double* __restrict__ Uf, int64_t pf, int64_t nf,
+                                      const int32_t* __restrict__ parent, double* __restrict__ Uc, int64_t pc, int nv,
+                                      const uint8_t* __restrict__ dirty_f, uint8_t* __restrict__ dirty_c,
+                                      int32_t* err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nf * nv) return;
+  const int v = int(i / nf);
+  const int64_t k = i - int64_t(v) * nf;
+  if (!dirty_f[k]) return;
+  const int32_t q = parent[k];
+  if (!debug_in_bounds(q >= 0 && q < pc, err)) return;
+  Uc[v * pc + q] = child_mean(Uf, pf, v, k);
+  if (v == 0 && dirty_c) dirty_c[q >> 3] = 1;
+}
+
+int launch_restrict_dirty(const double* Uf, int64_t pf, int64_t nf, const int32_t* parent, double* Uc, int64_t pc,
+                          int nv, const uint8_t* dirty_f, uint8_t* dirty_c, int32_t* err, void* stream) {
+  if (nf == 0) return 0;
+  const int64_t n = nf * nv;
+  hipLaunchKernelGGL(restrict_dirty_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, Uf,
+                     pf, nf, parent, Uc, pc, nv, dirty_f, dirty_c, err);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_restrict(const double* Uf, int64_t pf, int64_t nf, const int32_t* parent, double* Uc, int64_t pc,

@@ -67,13 +67,15 @@ struct OldTree {
 };
 // The child level's tiles (one per parent oct with children): toff the
 // exclusive scan of the flag kernel's has (a parent's tile), n_tile their
-// number; written: tile_of (the tile of each child oct) and tfirst (each
-// tile's first child oct, n_tile + 1 entries).
+// number; written: tile_of (the tile of each child oct), tfirst (each
+// tile's first child oct, n_tile + 1 entries) and fresh (1 for a child oct
+// not in the old level, else 0).
 struct ChildTiles {
   const int32_t* toff;
   int32_t n_tile;
   int32_t* tile_of;
   int32_t* tfirst;
+  uint8_t* fresh;
 };
 // Children of level C's flagged cells (one thread per oct of C); kept gets
 // the number of children found in the old child level added.
@@ -94,6 +96,12 @@ int launch_ghost_sources(const LevelView* coarse_dev, int ncoarse, const RegridD
                          int64_t n_ghost, int64_t* gsrc, int32_t* err, void* stream);
 int launch_refined_ext(const uint8_t* flag, int64_t n, int64_t n_ext, uint8_t* out, void* stream);
 
+// Restriction after a regrid of the fine octs marked in dirty_f only (the
+// same ordered 8-child means as launch_restrict); each marks its parent oct
+// in dirty_c when given.  A refined cell whose children neither are new nor
+// had a cell restricted again keeps the mean it already holds.
+int launch_restrict_dirty(const double* Uf, int64_t pf, int64_t nf, const int32_t* parent, double* Uc, int64_t pc,
+                          int nv, const uint8_t* dirty_f, uint8_t* dirty_c, int32_t* err, void* stream);
 // Regrid state remap of one level: for new oct k, cell c, variable v: a kept
 // oct copies Uold[v*pold + 8*src_old[k] + c]; a new one takes the MinMod-
 // linear interpolation of the level-l cells src7[7k..7k+6] of Uc (plane pc).

@@ -424,6 +424,7 @@ __device__ __forceinline__ int children_of(int64_t o, const LevelView& C, const 
     parent[k] = int32_t(o * 8 + c);
     child[8 * o + c] = int32_t(k);
     src_old[k] = so8[c];
+    CT.fresh[k] = so8[c] < 0;
     if (so8[c] >= 0) ++kept;
     else fresh |= 1u << c;
   }
@@ -763,7 +764,7 @@ int launch_regrid_children(const LevelView& C, const OldTree& T, const RegridDom
                            int32_t* err, unsigned long long* kept, void* stream) {
   if (C.n == 0) return 0;
   if (fbits < 1 || fbits > 25) return -1;   // child_digits' range
-  if (!CT.toff || !CT.tile_of || !CT.tfirst) return -1;
+  if (!CT.toff || !CT.tile_of || !CT.tfirst || !CT.fresh) return -1;
   hipLaunchKernelGGL(regrid_children_kernel, dim3(blocks(C.n)), dim3(256), 0, (hipStream_t)stream, C, T, D, fbits,
                      flag, off, CT, nkey, noc, parent, child, src_old, src7, err, kept);
   return hipGetLastError() == hipSuccess ? 0 : -1;

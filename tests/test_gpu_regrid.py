@@ -292,6 +292,32 @@ def test_regrid_on_non_cubic_box(ry, bc):
         same_mesh_and_state(g, h)
 
 
+@pytest.mark.parametrize("bc", [(W.BC_PERIODIC,) * 6, (W.BC_OUTFLOW,) * 6])
+def test_regrid_after_upload_restricts_every_refined_cell(ry, bc):
+    """A state uploaded to a refined level leaves its parents' means out of
+    date; the next device regrid restricts every refined cell (after a step
+    or the build only the cells above new octs need it): counts and states
+    as the oracle's, mesh and state as the host-flag path's bit for bit."""
+    prob = cases.amr_blob(bc=bc)
+    g, o, h = ry.Hydro(prob), Oracle(prob), ry.Hydro(prob)
+    h.set_regrid_device(False)
+    dt = o.cfl_dt()
+    for x in (o, g, h):
+        x.coarse_step(dt)
+    lv = prob.level_min + 1
+    U = g.download(lv).copy()
+    U[0] *= 1.01   # density and energy up by 1%: positive, and means change
+    U[4] *= 1.01
+    for x in (g, o, h):
+        x.upload(lv, U)
+    counts = g.regrid()
+    assert counts == o.regrid() == h.regrid()
+    compare(g, o)
+    same_mesh_and_state(g, h)
+    step_both(g, o, 1)
+    compare(g, o)
+
+
 def test_regrid_between_multi_step_graph_runs(ry):
     """Runs long enough for the multi-step graphs (9 = 8 + 1 steps), a regrid that reallocates
     every refined level, and another such run: the graphs captured on the
